@@ -1,0 +1,430 @@
+"""Seeded synthetic workloads for LDPC decoding over GF(2^p).
+
+This module only *generates inputs*: random sparse parity-check matrices,
+codewords whose information symbols follow an i.i.d. or first-order Markov
+source, and their images through the binary symmetric, binary erasure and
+binary-input AWGN channels.  It holds none of the decoder's arithmetic and is
+shared, as the single source of inputs, by the decoder library's tests and
+benchmarks and by the reference decoder's tests.
+
+Conventions (Section 2 of the paper: symbols of GF(q) are sent as their binary
+representation, and channel noise is added bitwise):
+
+* GF(2^p) is taken in the polynomial basis of a fixed primitive polynomial
+  (``DEFAULT_POLY``); bit b of a symbol is the coefficient of x^b and is
+  transmitted b-th (least significant bit first).
+* BPSK maps bit 0 to +1 and bit 1 to -1; sigma is the noise standard deviation.
+* After :func:`systematic` the columns are ordered [information | parity] so
+  that the information symbols are columns 0..K-1 in source order.
+
+All randomness comes from ``numpy.random.default_rng([seed, stream])`` with a
+distinct stream number per purpose, drawn with the frame index as the leading
+array axis, so frame f of a workload does not depend on how many frames are
+generated after it.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+DEFAULT_POLY = {1: 0b11, 2: 0b111, 3: 0b1011, 4: 0b10011, 5: 0b100101, 6: 0b1000011}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libgfsynth.so"
+
+# Markov transition matrices printed in the paper's results section (footnote
+# to Table 1): the 2-state matrix, and the 4-state matrix whose rows sum to 1
+# only to about 5e-7 (they are renormalised in double precision).
+PAPER_MARKOV_2S = np.array([[0.89, 0.11], [0.11, 0.89]], dtype=np.float64)
+PAPER_MARKOV_4S_RAW = np.array(
+    [
+        [0.808022, 0.0883281, 0.0130689, 0.0905813],
+        [0.128676, 0.0514706, 0.0772059, 0.742647],
+        [0.755814, 0.108527, 0.0116279, 0.124031],
+        [0.866667, 0.0151111, 0.091556, 0.0266659],
+    ],
+    dtype=np.float64,
+)
+PAPER_MARKOV_4S = PAPER_MARKOV_4S_RAW / PAPER_MARKOV_4S_RAW.sum(axis=1, keepdims=True)
+
+
+# --------------------------------------------------------------------------
+# native encoder
+# --------------------------------------------------------------------------
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = os.path.join(_HERE, _LIBNAME)
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')"
+        )
+    lib = ctypes.CDLL(path)
+    lib.synth_encoder_build.restype = ctypes.c_void_p
+    lib.synth_encoder_build.argtypes = [
+        ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.c_int,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+    ]
+    lib.synth_encoder_info.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.synth_encoder_encode.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.synth_encoder_free.argtypes = [ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def build_native(verbose: bool = False) -> str:
+    """Compile the encoder helper with gcc into this directory."""
+    import subprocess
+
+    src = os.path.join(_HERE, "_encoder.c")
+    out = os.path.join(_HERE, _LIBNAME)
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
+# --------------------------------------------------------------------------
+# codes
+# --------------------------------------------------------------------------
+@dataclass
+class Code:
+    """A parity-check matrix H over GF(q) in compressed-row form.
+
+    Edges (nonzeros of H) are numbered row by row; within a row by increasing
+    column.  ``n_info`` columns 0..n_info-1 are information symbols when the
+    code came from :func:`systematic`.
+    """
+
+    q: int
+    n: int
+    m: int
+    row_ptr: np.ndarray  # int32 [m+1]
+    col: np.ndarray  # int32 [E]
+    coef: np.ndarray  # uint8 [E]
+    poly: int = 0
+    n_info: int = 0
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.poly == 0:
+            self.poly = DEFAULT_POLY[self.p]
+
+    @property
+    def p(self) -> int:
+        return int(round(math.log2(self.q)))
+
+    @property
+    def E(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def row_of_edge(self) -> np.ndarray:
+        return np.repeat(np.arange(self.m, dtype=np.int32), np.diff(self.row_ptr))
+
+    def dense(self) -> np.ndarray:
+        H = np.zeros((self.m, self.n), dtype=np.uint8)
+        H[self.row_of_edge(), self.col] = self.coef
+        return H
+
+    def col_degrees(self) -> np.ndarray:
+        return np.bincount(self.col, minlength=self.n)
+
+    def row_degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr)
+
+
+def _four_cycle_edges(var: np.ndarray, chk: np.ndarray, n: int, m: int) -> np.ndarray:
+    """Indices of edges to move so that no two checks share two variables and
+    no (check, variable) pair repeats.  ``var``/``chk`` list the edges."""
+    order = np.lexsort((chk, var))
+    v_s, c_s = var[order], chk[order]
+    starts = np.searchsorted(v_s, np.arange(n))
+    ends = np.searchsorted(v_s, np.arange(n), side="right")
+    deg = ends - starts
+    bad = []
+    # multi-edges: consecutive equal (var, chk)
+    dup = np.nonzero((v_s[1:] == v_s[:-1]) & (c_s[1:] == c_s[:-1]))[0]
+    bad.extend(order[dup + 1].tolist())
+    # 4-cycles: pairs of checks of a variable repeated across variables
+    keys, owner = [], []
+    dmax = int(deg.max()) if n else 0
+    for a in range(dmax):
+        for b in range(a + 1, dmax):
+            ok = deg > b
+            vi = np.nonzero(ok)[0]
+            ca = c_s[starts[vi] + a]
+            cb = c_s[starts[vi] + b]
+            keys.append(ca.astype(np.int64) * m + cb)
+            owner.append(order[starts[vi] + b])
+    if keys:
+        keys = np.concatenate(keys)
+        owner = np.concatenate(owner)
+        srt = np.argsort(keys, kind="stable")
+        k_s = keys[srt]
+        rep = np.nonzero(k_s[1:] == k_s[:-1])[0]
+        bad.extend(owner[srt[rep + 1]].tolist())
+    return np.unique(np.asarray(bad, dtype=np.int64))
+
+
+def make_code(n: int, m: int, d_v: int, q: int, seed: int, reject_4cycles: bool = True,
+              max_rounds: int = 20000) -> Code:
+    """Random column-regular code: every column has weight ``d_v``; row weights
+    are as equal as possible (floor/ceil of n*d_v/m).  Configuration model,
+    then random edge swaps until there are no repeated edges (and, if asked, no
+    4-cycles).  Nonzero coefficients are uniform on GF(q) minus {0}."""
+    rng = np.random.default_rng([seed, 0xC0DE])
+    E = n * d_v
+    base, extra = divmod(E, m)
+    rdeg = np.full(m, base, dtype=np.int64)
+    rdeg[rng.permutation(m)[:extra]] += 1
+    var = np.repeat(np.arange(n, dtype=np.int64), d_v)
+    chk = np.repeat(np.arange(m, dtype=np.int64), rdeg)[rng.permutation(E)]
+    for _ in range(max_rounds):
+        if reject_4cycles:
+            bad = _four_cycle_edges(var, chk, n, m)
+        else:
+            order = np.lexsort((chk, var))
+            dup = np.nonzero((var[order][1:] == var[order][:-1]) & (chk[order][1:] == chk[order][:-1]))[0]
+            bad = order[dup + 1]
+        if len(bad) == 0:
+            break
+        partners = rng.integers(0, E, size=len(bad))
+        for e1, e2 in zip(bad.tolist(), partners.tolist()):
+            chk[e1], chk[e2] = chk[e2], chk[e1]
+    else:
+        raise RuntimeError("code construction did not converge; relax the constraints")
+    order = np.lexsort((var, chk))
+    chk, var = chk[order], var[order]
+    row_ptr = np.zeros(m + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(np.bincount(chk, minlength=m))
+    coef = rng.integers(1, q, size=E).astype(np.uint8)
+    return Code(q=q, n=n, m=m, row_ptr=row_ptr, col=var.astype(np.int32), coef=coef, seed=seed,
+                meta={"d_v": d_v, "reject_4cycles": reject_4cycles})
+
+
+class Encoder:
+    """Systematic encoder of a code whose columns are [information | parity]."""
+
+    def __init__(self, handle, n_info: int, rank: int, p: int):
+        self._h = handle
+        self.n_info = n_info
+        self.rank = rank
+        self.p = p
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.synth_encoder_free(self._h)
+            self._h = None
+
+    def encode(self, s: np.ndarray) -> np.ndarray:
+        """Codewords [F][n] (information symbols first) for sources s [F][K]."""
+        s = np.ascontiguousarray(s, dtype=np.uint8)
+        F = s.shape[0]
+        assert s.shape[1] == self.n_info
+        par = np.zeros((F, self.rank), dtype=np.uint8)
+        _load().synth_encoder_encode(self._h, F, s.ctypes.data, par.ctypes.data)
+        return np.concatenate([s, par], axis=1)
+
+
+def systematic(code: Code) -> tuple[Code, Encoder]:
+    """Permute the columns of ``code`` to [information | parity] (keeping the
+    relative order inside each part) and return it with its encoder."""
+    lib = _load()
+    order = np.zeros(code.n, dtype=np.int32)
+    rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(code.col, dtype=np.int32)
+    cf = np.ascontiguousarray(code.coef, dtype=np.uint8)
+    h = lib.synth_encoder_build(code.p, code.poly, code.m, code.n, rp.ctypes.data, cl.ctypes.data,
+                                cf.ctypes.data, order.ctypes.data)
+    if not h:
+        raise RuntimeError("encoder construction failed")
+    k = ctypes.c_int32()
+    r = ctypes.c_int32()
+    lib.synth_encoder_info(h, ctypes.byref(k), ctypes.byref(r))
+    newpos = np.empty(code.n, dtype=np.int32)
+    newpos[order] = np.arange(code.n, dtype=np.int32)
+    col = newpos[code.col]
+    # re-sort edges inside each row by the new column index
+    row = code.row_of_edge()
+    srt = np.lexsort((col, row))
+    out = Code(q=code.q, n=code.n, m=code.m, row_ptr=code.row_ptr.copy(), col=col[srt].astype(np.int32),
+               coef=code.coef[srt].copy(), poly=code.poly, n_info=int(k.value), seed=code.seed,
+               meta=dict(code.meta, rank=int(r.value)))
+    return out, Encoder(h, int(k.value), int(r.value), code.p)
+
+
+def regular_code(n: int, d_v: int, d_c: int, q: int, seed: int) -> tuple[Code, Encoder]:
+    """Systematic (d_v, d_c)-regular code with no 4-cycles."""
+    assert (n * d_v) % d_c == 0
+    return systematic(make_code(n, n * d_v // d_c, d_v, q, seed))
+
+
+# --------------------------------------------------------------------------
+# sources and channels
+# --------------------------------------------------------------------------
+def self_transition_matrix(q: int, stay: float) -> np.ndarray:
+    M = np.full((q, q), (1.0 - stay) / (q - 1), dtype=np.float64)
+    np.fill_diagonal(M, stay)
+    return M
+
+
+def stationary(M: np.ndarray) -> np.ndarray:
+    w, v = np.linalg.eig(M.T)
+    i = int(np.argmin(np.abs(w - 1.0)))
+    pi = np.real(v[:, i])
+    pi = np.abs(pi) / np.abs(pi).sum()
+    return pi
+
+
+def iid_source(F: int, K: int, q: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng([seed, 1])
+    return rng.integers(0, q, size=(F, K)).astype(np.uint8)
+
+
+def markov_source(F: int, K: int, M: np.ndarray, pi: np.ndarray, seed: int) -> np.ndarray:
+    """First-order Markov chain: s_0 ~ pi, s_k | s_{k-1}=a ~ M[a, :]."""
+    rng = np.random.default_rng([seed, 1])
+    u = rng.random((F, K))
+    cumM = np.cumsum(M, axis=1)
+    cumM[:, -1] = 1.0
+    cumpi = np.cumsum(pi)
+    cumpi[-1] = 1.0
+    s = np.zeros((F, K), dtype=np.int64)
+    if K == 0:
+        return s.astype(np.uint8)
+    s[:, 0] = np.searchsorted(cumpi, u[:, 0], side="right")
+    for k in range(1, K):
+        rows = cumM[s[:, k - 1]]
+        s[:, k] = (u[:, k:k + 1] >= rows).sum(axis=1)
+    return np.minimum(s, M.shape[0] - 1).astype(np.uint8)
+
+
+def symbol_bits(c: np.ndarray, p: int) -> np.ndarray:
+    """[..., n] symbols -> [..., n, p] bits (bit b = coefficient of x^b)."""
+    return ((c[..., None].astype(np.int64) >> np.arange(p)) & 1).astype(np.uint8)
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    p = bits.shape[-1]
+    return (bits.astype(np.int64) << np.arange(p)).sum(axis=-1).astype(np.uint8)
+
+
+def bsc(c: np.ndarray, p: int, f, seed: int) -> np.ndarray:
+    """Received symbols: each bit flipped independently with probability f."""
+    rng = np.random.default_rng([seed, 2])
+    f = np.broadcast_to(np.asarray(f, dtype=np.float64).reshape(-1, 1, 1), (c.shape[0], 1, 1))
+    flips = rng.random(c.shape + (p,)) < f
+    return (c ^ pack_bits(flips)).astype(np.uint8)
+
+
+def bec(c: np.ndarray, p: int, eps, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """(received symbols with erased bits set to 0, erased-bit masks)."""
+    rng = np.random.default_rng([seed, 2])
+    eps = np.broadcast_to(np.asarray(eps, dtype=np.float64).reshape(-1, 1, 1), (c.shape[0], 1, 1))
+    er = pack_bits(rng.random(c.shape + (p,)) < eps)
+    return (c & ~er).astype(np.uint8), er.astype(np.uint8)
+
+
+def biawgn(c: np.ndarray, p: int, sigma, seed: int) -> np.ndarray:
+    """y = (1 - 2 bit) + sigma * n, float32 [F][n][p]."""
+    rng = np.random.default_rng([seed, 2])
+    sigma = np.broadcast_to(np.asarray(sigma, dtype=np.float64).reshape(-1, 1, 1), (c.shape[0], 1, 1))
+    x = 1.0 - 2.0 * symbol_bits(c, p).astype(np.float64)
+    return (x + sigma * rng.standard_normal(x.shape)).astype(np.float32)
+
+
+def sigma_from_ebn0(ebn0_db: float, rate: float) -> float:
+    """Noise std for unit-energy BPSK at Eb/N0 (dB) and code rate R:
+    sigma^2 = 1 / (2 R 10^(Eb/N0 / 10))."""
+    return math.sqrt(1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0)))
+
+
+def biawgn_capacity(sigma: float, npts: int = 4001) -> float:
+    """Capacity (bits/use) of the BPSK-input AWGN channel, by quadrature."""
+    y = np.linspace(-1.0 - 12 * sigma, 1.0 + 12 * sigma, npts)
+    dy = y[1] - y[0]
+    g = lambda m: np.exp(-((y - m) ** 2) / (2 * sigma * sigma)) / math.sqrt(2 * math.pi * sigma * sigma)
+    p0, p1 = g(1.0), g(-1.0)
+    py = 0.5 * (p0 + p1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t0 = np.where(p0 > 0, p0 * np.log2(p0 / py), 0.0)
+    return float(np.sum(t0) * dy)
+
+
+def h2(x: float) -> float:
+    if x <= 0 or x >= 1:
+        return 0.0
+    return -x * math.log2(x) - (1 - x) * math.log2(1 - x)
+
+
+def bsc_matching(cap: float) -> float:
+    """Crossover f with 1 - h2(f) = cap (0 <= f <= 1/2)."""
+    lo, hi = 0.0, 0.5
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if 1 - h2(mid) > cap:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@dataclass
+class Frames:
+    """One batch of received frames for one code and one channel kind."""
+
+    channel: str  # "bsc" | "bec" | "biawgn"
+    param: np.ndarray  # float64 [F]: f, eps or sigma
+    codeword: np.ndarray  # uint8 [F][n]
+    rx: np.ndarray | None = None  # uint8 [F][n]
+    erasure: np.ndarray | None = None  # uint8 [F][n]
+    y: np.ndarray | None = None  # float32 [F][n][p]
+    syndrome: np.ndarray | None = None  # uint8 [F][m] (None means z = 0)
+
+    @property
+    def F(self) -> int:
+        return int(self.codeword.shape[0])
+
+    def subset(self, idx) -> "Frames":
+        g = lambda a: None if a is None else np.ascontiguousarray(a[idx])
+        return Frames(self.channel, self.param[idx].copy(), g(self.codeword), g(self.rx), g(self.erasure),
+                      g(self.y), g(self.syndrome))
+
+
+def make_frames(code: Code, enc: Encoder, F: int, seed: int, channel: str, param,
+                source: str = "iid", markov: np.ndarray | None = None,
+                pi: np.ndarray | None = None) -> Frames:
+    """Encode F source blocks and pass them through the channel."""
+    K = code.n_info
+    if source == "iid":
+        s = iid_source(F, K, code.q, seed)
+    elif source == "markov":
+        assert markov is not None
+        s = markov_source(F, K, markov, stationary(markov) if pi is None else pi, seed)
+    elif source == "zero":
+        s = np.zeros((F, K), dtype=np.uint8)
+    else:
+        raise ValueError(source)
+    c = enc.encode(s)
+    prm = np.broadcast_to(np.asarray(param, dtype=np.float64), (F,)).copy()
+    p = code.p
+    if channel == "bsc":
+        return Frames("bsc", prm, c, rx=bsc(c, p, prm, seed))
+    if channel == "bec":
+        rx, er = bec(c, p, prm, seed)
+        return Frames("bec", prm, c, rx=rx, erasure=er)
+    if channel == "biawgn":
+        return Frames("biawgn", prm, c, y=biawgn(c, p, prm, seed))
+    raise ValueError(channel)

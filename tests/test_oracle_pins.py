@@ -1,0 +1,491 @@
+"""Pins for the reference decoder (CPU only).
+
+Each test ties the reference decoder to something other than itself: textbook
+field values and field axioms, the paper's closed-form BSC noise prior,
+brute-force enumeration of Eq. (eq_r), the textbook binary tanh rule, exact
+marginals of cycle-free graphs by enumeration of all solutions of H x = z, the
+forward-pass exactness of one sequential sweep on a chain, Eq. (eq_prior1)
+enumerated against the implemented Eq. (prior2), and invariants of the two
+schedules.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0605069_amd import workloads as wl
+from tests import _gf
+
+POLY = wl.DEFAULT_POLY
+
+
+# ------------------------------------------------------------------ field
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_field_matches_independent_multiplication(p):
+    q = 1 << p
+    for a in range(q):
+        for b in range(q):
+            assert oracle.gf_mul(p, POLY[p], a, b) == _gf.mul(a, b, p)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+def test_field_axioms(p):
+    q = 1 << p
+    T = np.array([[oracle.gf_mul(p, POLY[p], a, b) for b in range(q)] for a in range(q)])
+    assert (T == T.T).all()
+    assert (T[1] == np.arange(q)).all() and (T[0] == 0).all()
+    # distributive over addition (XOR) and associative
+    A = np.arange(q)
+    for a in range(q):
+        for b in range(q):
+            assert (T[a, A ^ b] == (T[a, A] ^ T[a, b])).all()
+            assert (T[T[a, b], A] == T[a, T[b, A]]).all()
+    # nonzero products form a Latin square; inverses exist
+    nz = T[1:, 1:]
+    for r in nz:
+        assert sorted(r.tolist()) == list(range(1, q))
+    for a in range(1, q):
+        assert T[a, oracle.gf_inv(p, POLY[p], a)] == 1
+    # x (= 2) is primitive: its powers run through all q-1 nonzero elements
+    seen, v = set(), 1
+    for _ in range(q - 1):
+        seen.add(v)
+        v = T[v, 2]
+    assert len(seen) == q - 1 and v == 1
+
+
+def test_field_textbook_values():
+    # GF(4) = F2[x]/(x^2+x+1): x*x = x+1, x*(x+1) = 1, (x+1)^2 = x
+    assert oracle.gf_mul(2, POLY[2], 2, 2) == 3
+    assert oracle.gf_mul(2, POLY[2], 2, 3) == 1
+    assert oracle.gf_mul(2, POLY[2], 3, 3) == 2
+    # GF(8) = F2[x]/(x^3+x+1): x * x^2 = x + 1, x^2 * x^2 = x^2 + x
+    assert oracle.gf_mul(3, POLY[3], 2, 4) == 3
+    assert oracle.gf_mul(3, POLY[3], 4, 4) == 6
+
+
+# ------------------------------------------------------------------ likelihoods
+@pytest.mark.parametrize("p", [1, 2, 3, 6])
+def test_bsc_likelihood_is_papers_noise_prior(p):
+    """Section 2: the BSC noise prior f^L (1-f)^(p-L), L = number of ones in the
+    bits of the noise symbol; about a received symbol the noise is a XOR rx."""
+    f = 0.17
+    for rx in [0, (1 << p) - 1, 1]:
+        L = oracle.likelihood(p, "bsc", f, rx=rx)
+        for a in range(1 << p):
+            ones = bin(a ^ rx).count("1")
+            assert L[a] == pytest.approx(f ** ones * (1 - f) ** (p - ones), rel=1e-14)
+        assert L.sum() == pytest.approx(1.0, abs=1e-14)
+
+
+def test_bec_likelihood_dyadic():
+    p = 3
+    for er in range(8):
+        for rx in range(8):
+            rx &= ~er
+            L = oracle.likelihood(p, "bec", 0.3, rx=rx, er=er)
+            e = bin(er).count("1")
+            for a in range(8):
+                agrees = (a & ~er) == rx
+                assert L[a] == (2.0 ** -e if agrees else 0.0)
+
+
+def test_biawgn_binary_llr_closed_form():
+    for sigma in [0.5, 0.9, 1.6]:
+        for y in [-2.0, -0.3, 0.0, 0.7, 1.9]:
+            L = oracle.likelihood(1, "biawgn", sigma, y=[y])
+            assert math.log(L[0] / L[1]) == pytest.approx(2 * np.float32(y) / sigma ** 2, rel=1e-12, abs=1e-12)
+            assert L.sum() == pytest.approx(1.0, abs=1e-15)
+
+
+def test_biawgn_symbol_likelihood_factorises():
+    p, sigma = 3, 0.8
+    y = np.array([0.3, -1.1, 0.05], dtype=np.float32)
+    L = oracle.likelihood(p, "biawgn", sigma, y=y)
+    bit = [oracle.likelihood(1, "biawgn", sigma, y=[v]) for v in y]
+    for a in range(8):
+        want = np.prod([bit[b][(a >> b) & 1] for b in range(p)])
+        assert L[a] == pytest.approx(want, rel=1e-14)
+
+
+# ------------------------------------------------------------------ check node
+def _brute_force_r(p, h, z, qin):
+    """Eq. (eq_r) enumerated literally: for every target d and value a, sum the
+    product of sibling messages over all sibling configurations with
+    h_d a + sum h_s x_s = z."""
+    q = 1 << p
+    dc = len(h)
+    r = np.zeros((dc, q))
+    for d in range(dc):
+        sib = [s for s in range(dc) if s != d]
+        for a in range(q):
+            tot = 0.0
+            for xs in itertools.product(range(q), repeat=len(sib)):
+                acc = _gf.mul(int(h[d]), a, p)
+                w = 1.0
+                for s, x in zip(sib, xs):
+                    acc ^= _gf.mul(int(h[s]), x, p)
+                    w *= qin[s, x]
+                if acc == z:
+                    tot += w
+            r[d, a] = tot
+    return r
+
+
+@pytest.mark.parametrize("p,dc", [(1, 3), (2, 3), (2, 4), (3, 3), (3, 4)])
+def test_check_update_equals_enumeration(p, dc):
+    rng = np.random.default_rng(100 + 10 * p + dc)
+    q = 1 << p
+    for trial in range(3):
+        h = rng.integers(1, q, size=dc)
+        z = int(rng.integers(0, q))
+        qin = rng.random((dc, q)) + 0.05
+        qin /= qin.sum(axis=1, keepdims=True)
+        got = oracle.check_update(p, POLY[p], h, z, qin)
+        want = _brute_force_r(p, h, z, qin)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(got.sum(axis=1), 1.0, atol=1e-13)
+
+
+def test_check_update_binary_tanh_rule():
+    """q = 2: tanh(lambda_r / 2) = (-1)^z prod tanh(lambda_q / 2), lambda = log(P0/P1)."""
+    rng = np.random.default_rng(7)
+    for dc in [2, 3, 6, 9]:
+        for z in [0, 1]:
+            p0 = rng.uniform(0.05, 0.95, size=dc)
+            qin = np.stack([p0, 1 - p0], axis=1)
+            r = oracle.check_update(1, POLY[1], np.ones(dc), z, qin)
+            lam = np.log(p0 / (1 - p0))
+            for d in range(dc):
+                t = (-1) ** z * np.prod(np.tanh(np.delete(lam, d) / 2))
+                assert math.log(r[d, 0] / r[d, 1]) == pytest.approx(2 * math.atanh(t), rel=1e-10, abs=1e-12)
+
+
+# ------------------------------------------------------------------ small codes
+def _code(q, n, rows, coef_seed=0):
+    """Code with the given rows (lists of columns) and random nonzero coefficients."""
+    rng = np.random.default_rng(coef_seed)
+    row_ptr = np.zeros(len(rows) + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([c for r in rows for c in sorted(r)], dtype=np.int32)
+    coef = rng.integers(1, q, size=len(col)).astype(np.uint8)
+    return wl.Code(q=q, n=n, m=len(rows), row_ptr=row_ptr, col=col, coef=coef)
+
+
+def _exact_marginals(code, L, z):
+    """Q_j(a) = sum over all x with H x = z and x_j = a of prod_j' L_j'(x_j'), normalised."""
+    q, n, p = code.q, code.n, code.p
+    X = np.indices((q,) * n).reshape(n, -1).T
+    T = _gf.mul_table(p)
+    H = code.dense()
+    ok = np.ones(len(X), dtype=bool)
+    for i in range(code.m):
+        s = np.zeros(len(X), dtype=np.int64)
+        for j in range(n):
+            if H[i, j]:
+                s ^= T[H[i, j], X[:, j]]
+        ok &= s == z[i]
+    w = np.prod(L[np.arange(n), X], axis=1) * ok
+    Q = np.zeros((n, q))
+    for j in range(n):
+        Q[j] = np.bincount(X[:, j], weights=w, minlength=q)
+    return Q / Q.sum(axis=1, keepdims=True)
+
+
+TREES = [
+    (2, 9, [[0, 1, 2], [2, 3, 4], [4, 5, 6], [6, 7, 8]]),
+    (4, 7, [[0, 1, 2], [2, 3, 4], [4, 5, 6]]),
+    (8, 6, [[0, 1, 2], [2, 3], [3, 4, 5]]),
+    (4, 7, [[0, 1], [1, 2, 3], [1, 4], [4, 5, 6]]),
+]
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+@pytest.mark.parametrize("tree", range(len(TREES)))
+def test_tree_posteriors_are_exact_marginals(tree, schedule):
+    q, n, rows = TREES[tree]
+    code = _code(q, n, rows, coef_seed=tree)
+    rng = np.random.default_rng(50 + tree)
+    for trial in range(2):
+        L = rng.random((n, q)) ** 2 + 0.01
+        z = rng.integers(0, q, size=code.m).astype(np.uint8)
+        want = _exact_marginals(code, L, z)
+        out = oracle.decode(code, likelihoods=L[None], syndrome=z[None], schedule=schedule, max_iter=2 * n,
+                            early_stop=False, posterior=True)
+        np.testing.assert_allclose(out["posterior"][0], want, rtol=0, atol=1e-12)
+
+
+def test_one_sequential_sweep_is_a_forward_pass_on_a_chain():
+    """On a chain (check k joins columns k and k+1), one sweep in column order
+    carries the evidence of every earlier column into the last one, so after a
+    single SUS iteration the last column's posterior is exact; one PUS iteration
+    only reaches its neighbour."""
+    q, n = 4, 8
+    code = _code(q, n, [[k, k + 1] for k in range(n - 1)], coef_seed=3)
+    rng = np.random.default_rng(4)
+    L = rng.random((n, q)) + 0.05
+    z = rng.integers(0, q, size=n - 1).astype(np.uint8)
+    want = _exact_marginals(code, L, z)
+    sus = oracle.decode(code, likelihoods=L[None], syndrome=z[None], schedule=oracle.SUS, max_iter=1,
+                        early_stop=False, posterior=True)["posterior"][0]
+    pus = oracle.decode(code, likelihoods=L[None], syndrome=z[None], schedule=oracle.PUS, max_iter=1,
+                        early_stop=False, posterior=True)["posterior"][0]
+    np.testing.assert_allclose(sus[n - 1], want[n - 1], atol=1e-13)
+    assert np.abs(pus[n - 1] - want[n - 1]).max() > 1e-3
+    assert np.abs(sus[0] - want[0]).max() > 1e-3  # the sweep has not yet come back to column 0
+
+
+# ------------------------------------------------------------------ binary BP, textbook LLR form
+def _binary_bp_llr(code, llr, z, iters, schedule):
+    E = code.E
+    rows = code.row_of_edge()
+    col = code.col
+    col_edges = [np.nonzero(col == j)[0] for j in range(code.n)]
+    row_edges = [np.arange(code.row_ptr[i], code.row_ptr[i + 1]) for i in range(code.m)]
+    lq = llr[col].astype(np.float64)
+    lr = np.zeros(E)
+
+    def r_of(e):
+        i = rows[e]
+        sib = [s for s in row_edges[i] if s != e]
+        t = (-1.0) ** z[i] * np.prod(np.tanh(lq[sib] / 2))
+        return 2 * np.arctanh(t)
+
+    def q_of(j):
+        tot = llr[j] + lr[col_edges[j]].sum()
+        lq[col_edges[j]] = tot - lr[col_edges[j]]
+
+    for _ in range(iters):
+        if schedule == oracle.PUS:
+            lr = np.array([r_of(e) for e in range(E)])
+            for j in range(code.n):
+                q_of(j)
+        else:
+            for j in range(code.n):
+                for e in col_edges[j]:
+                    lr[e] = r_of(e)
+                q_of(j)
+    post = llr + np.array([lr[col_edges[j]].sum() for j in range(code.n)])
+    return 1.0 / (1.0 + np.exp(-post))
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_binary_decoder_matches_textbook_llr_bp(schedule):
+    code = wl.make_code(48, 24, 3, 2, seed=11, reject_4cycles=False)
+    rng = np.random.default_rng(12)
+    p0 = rng.uniform(0.2, 0.8, size=code.n)
+    L = np.stack([p0, 1 - p0], axis=1)
+    z = rng.integers(0, 2, size=code.m).astype(np.uint8)
+    for iters in [1, 2, 4]:
+        want = _binary_bp_llr(code, np.log(p0 / (1 - p0)), z, iters, schedule)
+        got = oracle.decode(code, likelihoods=L[None], syndrome=z[None], schedule=schedule, max_iter=iters,
+                            early_stop=False, posterior=True)["posterior"][0]
+        np.testing.assert_allclose(got[:, 0], want, rtol=0, atol=1e-9)
+
+
+# ------------------------------------------------------------------ whole-decoder invariants
+@pytest.fixture(scope="module")
+def c1_small():
+    code, enc = wl.regular_code(96, 3, 6, 4, seed=21)
+    return code, enc
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.0), ("bec", 0.0), ("biawgn", 0.05)])
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_noiseless_channels_decode_in_one_iteration(c1_small, channel, param, schedule):
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 6, 31, channel, param)
+    out = oracle.decode(code, fr, schedule=schedule, max_iter=10)
+    assert (out["iters"] == 1).all() and out["converged"].all()
+    assert (out["xhat"] == fr.codeword).all()
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_messages_are_distributions(c1_small, schedule):
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 4, 32, "bsc", 0.12)
+    for it in [1, 3]:
+        out = oracle.decode(code, fr, schedule=schedule, max_iter=it, early_stop=False, snap_iter=it)
+        np.testing.assert_allclose(out["snap_q"].sum(-1), 1.0, atol=1e-12)
+        np.testing.assert_allclose(out["snap_r"].sum(-1), 1.0, atol=1e-12)
+        np.testing.assert_allclose(out["snap_Q"].sum(-1), 1.0, atol=1e-12)
+        assert (out["snap_r"] >= 0).all()
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_codeword_shift_equivariance(c1_small, schedule):
+    """Decoding c + noise equals decoding 0 + noise shifted by c (i.i.d. prior)."""
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 8, 33, "bsc", 0.10)
+    zero = wl.Frames("bsc", fr.param, np.zeros_like(fr.codeword), rx=fr.rx ^ fr.codeword)
+    a = oracle.decode(code, fr, schedule=schedule, max_iter=40, posterior=True, early_stop=False)
+    b = oracle.decode(code, zero, schedule=schedule, max_iter=40, posterior=True, early_stop=False)
+    assert (a["iters"] == b["iters"]).all()
+    assert ((a["xhat"] ^ fr.codeword) == b["xhat"]).all()
+    q = code.q
+    shifted = np.take_along_axis(b["posterior"], (np.arange(q)[None, None, :] ^ fr.codeword[:, :, None]), axis=2)
+    np.testing.assert_allclose(a["posterior"], shifted, atol=1e-9)
+
+
+def _permute_rows(code, perm):
+    rows = [list(code.col[code.row_ptr[i]:code.row_ptr[i + 1]]) for i in range(code.m)]
+    coefs = [list(code.coef[code.row_ptr[i]:code.row_ptr[i + 1]]) for i in range(code.m)]
+    row_ptr = np.zeros(code.m + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum([len(rows[i]) for i in perm])
+    col = np.array([c for i in perm for c in rows[i]], dtype=np.int32)
+    coef = np.array([h for i in perm for h in coefs[i]], dtype=np.uint8)
+    return wl.Code(q=code.q, n=code.n, m=code.m, row_ptr=row_ptr, col=col, coef=coef, n_info=code.n_info)
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_row_permutation_invariance(c1_small, schedule):
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 6, 34, "bsc", 0.10)
+    perm = np.random.default_rng(3).permutation(code.m)
+    a = oracle.decode(code, fr, schedule=schedule, max_iter=30, posterior=True, early_stop=False)
+    b = oracle.decode(_permute_rows(code, perm), fr, schedule=schedule, max_iter=30, posterior=True,
+                      early_stop=False)
+    assert (a["iters"] == b["iters"]).all() and (a["xhat"] == b["xhat"]).all()
+    np.testing.assert_allclose(a["posterior"], b["posterior"], atol=1e-9)
+
+
+def _swap_columns(code, j):
+    col = code.col.copy()
+    a, b = col == j, col == j + 1
+    col[a], col[b] = j + 1, j
+    return wl.Code(q=code.q, n=code.n, m=code.m, row_ptr=code.row_ptr.copy(), col=col, coef=code.coef.copy(),
+                   n_info=code.n_info)
+
+
+def test_sequential_order_only_matters_between_columns_sharing_a_check(c1_small):
+    """Swapping two adjacent columns that share no check leaves SUS bitwise
+    unchanged; swapping two that share a check changes the trajectory."""
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 8, 35, "bsc", 0.12)
+    rows = code.row_of_edge()
+    share = lambda j: bool(set(rows[code.col == j]) & set(rows[code.col == j + 1]))
+    free_j = next(j for j in range(code.n - 1) if not share(j))
+    tied_j = next((j for j in range(code.n - 1) if share(j)), None)
+    base = oracle.decode(code, fr, schedule=oracle.SUS, max_iter=3, early_stop=False, posterior=True)
+
+    def swapped(j):
+        perm = np.arange(code.n)
+        perm[[j, j + 1]] = perm[[j + 1, j]]
+        f2 = wl.Frames("bsc", fr.param, fr.codeword[:, perm], rx=fr.rx[:, perm])
+        out = oracle.decode(_swap_columns(code, j), f2, schedule=oracle.SUS, max_iter=3, early_stop=False,
+                            posterior=True)
+        return out["posterior"][:, perm]
+
+    assert np.array_equal(swapped(free_j), base["posterior"])
+    if tied_j is None:
+        # build a pair that shares a check by construction: columns of one row
+        pytest.skip("no adjacent columns share a check")
+    assert not np.array_equal(swapped(tied_j), base["posterior"])
+
+
+# ------------------------------------------------------------------ Markov prior
+def test_markov_prior_matches_eq_prior1_enumerated():
+    """The implemented factorised form (prior2) against the double sum (eq_prior1)."""
+    rng = np.random.default_rng(9)
+    for q in [2, 4, 8]:
+        K = 7
+        M = rng.random((q, q)) + 0.1
+        M /= M.sum(1, keepdims=True)
+        pi = wl.stationary(M)
+        Q = rng.random((K, q))
+        Q /= Q.sum(1, keepdims=True)
+        P = oracle.markov_prior(Q, M, pi)
+        for k in range(1, K - 1):
+            want = np.array([sum(Q[k - 1, a] * M[a, b] * M[b, c] * Q[k + 1, c] for a in range(q) for c in range(q))
+                             for b in range(q)])
+            np.testing.assert_allclose(P[k], want / want.sum(), rtol=1e-13)
+        left = pi * (M @ Q[1])
+        right = Q[K - 2] @ M
+        np.testing.assert_allclose(P[0], left / left.sum(), rtol=1e-13)
+        np.testing.assert_allclose(P[K - 1], right / right.sum(), rtol=1e-13)
+
+
+def test_markov_prior_degenerate_cases():
+    rng = np.random.default_rng(10)
+    q, K = 8, 9
+    Q = rng.random((K, q))
+    Q /= Q.sum(1, keepdims=True)
+    pi = rng.random(q)
+    pi /= pi.sum()
+    # identical rows (memoryless source): the prior is the static marginal
+    P = oracle.markov_prior(Q, np.tile(pi, (q, 1)), pi)
+    np.testing.assert_allclose(P, np.tile(pi, (K, 1)), rtol=1e-13)
+    # uniform transitions: uniform prior
+    P = oracle.markov_prior(Q, np.full((q, q), 1.0 / q), np.full(q, 1.0 / q))
+    np.testing.assert_allclose(P, 1.0 / q, rtol=1e-13)
+
+
+def _lik(code, fr):
+    """Channel likelihoods of all frames, from the single-symbol routine."""
+    F, n, q = fr.F, code.n, code.q
+    out = np.zeros((F, n, q))
+    for f in range(F):
+        for j in range(n):
+            out[f, j] = oracle.likelihood(code.p, fr.channel, fr.param[f], rx=fr.rx[f, j],
+                                          er=0 if fr.erasure is None else fr.erasure[f, j])
+    return out
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_markov_prior_with_memoryless_matrix_is_a_static_prior(c1_small, schedule):
+    code, enc = c1_small
+    q = code.q
+    fr = wl.make_frames(code, enc, 4, 36, "bsc", 0.14)
+    pi = np.array([0.4, 0.3, 0.2, 0.1])
+    a = oracle.decode(code, fr, schedule=schedule, max_iter=20, prior="markov", markov_M=np.tile(pi, (q, 1)),
+                      markov_pi=pi, posterior=True, early_stop=False)
+    L = _lik(code, fr)
+    L[:, :code.n_info] *= pi
+    b = oracle.decode(code, likelihoods=L, schedule=schedule, max_iter=20, posterior=True, early_stop=False)
+    assert (a["xhat"] == b["xhat"]).all() and (a["iters"] == b["iters"]).all()
+    np.testing.assert_allclose(a["posterior"], b["posterior"], atol=1e-12)
+
+
+def test_markov_prior_refresh_timing_pus(c1_small):
+    """Iteration 2 of PUS uses the prior re-estimated from iteration 1's
+    posteriors: Q2_j = norm(L_j * P_j * prod_i r2_ij), with r2 from the
+    q-messages of iteration 1 (recomputed here with the pinned check update)."""
+    code, enc = c1_small
+    q = code.q
+    M = wl.self_transition_matrix(q, 0.7)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 2, 37, "bsc", 0.2, source="markov", markov=M)
+    one = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=1, early_stop=False, prior="markov", markov_M=M,
+                        markov_pi=pi, snap_iter=1)
+    two = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=2, early_stop=False, prior="markov", markov_M=M,
+                        markov_pi=pi, snap_iter=2)
+    L = _lik(code, fr)
+    K = code.n_info
+    for f in range(fr.F):
+        P = oracle.markov_prior(one["snap_Q"][f][:K], M, pi)
+        prior = L[f].copy()
+        prior[:K] *= P
+        r2 = np.zeros((code.E, q))
+        for i in range(code.m):
+            s, e = code.row_ptr[i], code.row_ptr[i + 1]
+            r2[s:e] = oracle.check_update(code.p, code.poly, code.coef[s:e], 0, one["snap_q"][f][s:e])
+        Q2 = prior.copy()
+        for e in range(code.E):
+            Q2[code.col[e]] *= r2[e]
+        Q2 /= Q2.sum(1, keepdims=True)
+        np.testing.assert_allclose(two["snap_Q"][f], Q2, atol=1e-12)
+
+
+# ------------------------------------------------------------------ schedules' headline behaviour
+def test_sequential_schedule_needs_fewer_iterations():
+    """Context for the paper's headline (Abstract, Table 1): SUS converges in
+    fewer iterations than PUS on the same frames."""
+    code, enc = wl.regular_code(504, 3, 6, 4, seed=0xC0DE0001)
+    fr = wl.make_frames(code, enc, 48, 0xDA7A0001, "bsc", 0.075)
+    pus = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=200)
+    sus = oracle.decode(code, fr, schedule=oracle.SUS, max_iter=200)
+    both = (pus["converged"] == 1) & (sus["converged"] == 1)
+    assert both.sum() > 30
+    assert sus["iters"][both].mean() < 0.85 * pus["iters"][both].mean()
