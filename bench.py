@@ -1,0 +1,200 @@
+"""Benchmark: GF(q) LDPC belief-propagation decoding, PUS and SUS, one MI355X.
+
+Workload (one "step"): GF(16), regular (3,6), rate 1/2, N = 2000 symbols
+(8000 bits); BPSK over BI-AWGN at Eb/N0 = 0.8, 1.0, 1.2, 1.4, 1.6 dB, 4096
+frames per point, each point decoded in one launch under the parallel (PUS)
+and then the sequential (SUS) schedule, max 100 iterations, early stopping
+on H x = 0.  Inputs (code, codewords, channel outputs) are seeded synthetic
+data generated once and resident in device memory before timing starts.
+
+Reported value: edge-q message updates per second over the whole step, where
+a frame that ran t iterations counts t * E * q updates (E = edges, q = field
+size).  Also per schedule: updates/s, frames/s, mean iterations, decode-call
+latency; the roofline of the dominant kernel from HIP events recorded around
+each launch during the timed steps; and the reference decoder timed on a
+bounded sample of the same frames on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-frames S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+EBN0 = (0.8, 1.0, 1.2, 1.4, 1.6)
+N_SYM, DV, DC, Q = 2000, 3, 6, 16
+FRAMES = 4096
+MAX_ITER = 100
+CODE_SEED, DATA_SEED = 0xC0DE0002, 0xDA7A0002
+
+
+def make_workload():
+    from paper_cs_0605069_amd import workloads as wl
+
+    code, enc = wl.regular_code(N_SYM, DV, DC, Q, seed=CODE_SEED)
+    rate = code.n_info / code.n
+    points = []
+    for i, eb in enumerate(EBN0):
+        sigma = wl.sigma_from_ebn0(eb, rate)
+        points.append((eb, wl.make_frames(code, enc, FRAMES, DATA_SEED * 16 + i, "biawgn", sigma)))
+    return code, points
+
+
+def cpu_baseline(code, points, n_frames: int):
+    """Reference decoder on every k-th frame of the step (all points), both schedules."""
+    import oracle
+    from paper_cs_0605069_amd import workloads as wl
+
+    per_point = max(1, n_frames // len(points))
+    stride = FRAMES // per_point
+    idx = np.arange(0, FRAMES, stride)[:per_point]
+    subs = [fr.subset(idx) for _, fr in points]
+    fr = wl.Frames("biawgn", np.concatenate([s.param for s in subs]), np.concatenate([s.codeword for s in subs]),
+                   y=np.concatenate([s.y for s in subs]))
+    threads = oracle.max_threads()
+    eq = 0.0
+    t0 = time.perf_counter()
+    iters = {}
+    for name, sch in (("pus", oracle.PUS), ("sus", oracle.SUS)):
+        out = oracle.decode(code, fr, schedule=sch, max_iter=MAX_ITER)
+        eq += float(out["iters"].sum()) * code.E * code.q
+        iters[name] = float(out["iters"].mean())
+    dt = time.perf_counter() - t0
+    return {"value": eq / dt, "unit": "edge·q updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{fr.F} frames (every {stride}th of each of the {len(points)} Eb/N0 points), "
+                      f"PUS and SUS, max {MAX_ITER} iterations, float64, {dt:.1f} s wall",
+            "frames_per_s": 2 * fr.F / dt, "mean_iters": iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-frames", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedules", default="pus,sus")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: frames are independent and this decoder has no multi-GPU path "
+              "(run it with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_cs_0605069_amd as gfbp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    code, points = make_workload()
+    dcode = gfbp.DeviceCode(code)
+    scheds = [s for s in args.schedules.split(",") if s]
+    dev_points = [(eb, gfbp.frames_to_device(fr)) for eb, fr in points]
+    ws = {s: torch.empty(dcode.workspace_size(FRAMES, s), dtype=torch.uint8, device="cuda") for s in scheds}
+    outs = {s: {"xhat": torch.empty((FRAMES, code.n), dtype=torch.uint8, device="cuda"),
+                "iters": torch.empty(FRAMES, dtype=torch.int32, device="cuda"),
+                "converged": torch.empty(FRAMES, dtype=torch.uint8, device="cuda"),
+                "guards": torch.empty(FRAMES, dtype=torch.int32, device="cuda")} for s in scheds}
+    torch.cuda.synchronize()
+
+    def step(record):
+        for eb, d in dev_points:
+            for s in scheds:
+                t0 = time.perf_counter()
+                o = gfbp.decode_batch(dcode, d, schedule=s, max_iter=MAX_ITER, workspace=ws[s], outputs=outs[s])
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if record is not None:
+                    it = o["iters"].cpu().numpy()
+                    record.append({"sched": s, "ebn0": eb, "ms": dt * 1e3, "iters": it,
+                                   "fer": 1.0 - float(o["converged"].float().mean().item())})
+
+    for _ in range(args.warmup):
+        step(None)
+    gfbp.profile_reset()
+    gfbp.profile_enable(True)
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(rec)
+        print(f"# step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gfbp.profile_enable(False)
+    prof = gfbp.profile_read()
+
+    EQ = code.E * code.q
+    total_eq = sum(float(r["iters"].sum()) * EQ for r in rec)
+    per = {}
+    for s in scheds:
+        rs = [r for r in rec if r["sched"] == s]
+        ms = np.array([r["ms"] for r in rs])
+        eq = sum(float(r["iters"].sum()) * EQ for r in rs)
+        per[s] = {"edge_q_per_s": eq / (ms.sum() / 1e3), "frames_per_s": len(rs) * FRAMES / (ms.sum() / 1e3),
+                  "mean_iters": float(np.mean([r["iters"].mean() for r in rs])),
+                  "decode_call_ms_p50": float(np.percentile(ms, 50)), "decode_call_ms_p99": float(np.percentile(ms, 99)),
+                  "fer_by_ebn0": {str(r["ebn0"]): round(r["fer"], 4) for r in rs[:len(EBN0)]},
+                  "mean_iters_by_ebn0": {str(r["ebn0"]): round(float(r["iters"].mean()), 3) for r in rs[:len(EBN0)]}}
+    if "pus" in per and "sus" in per:
+        pi = np.concatenate([r["iters"] for r in rec if r["sched"] == "pus"]).astype(float)
+        si = np.concatenate([r["iters"] for r in rec if r["sched"] == "sus"]).astype(float)
+        per["sus_over_pus"] = {"ratio_of_means": si.mean() / pi.mean(), "mean_of_ratios": float(np.mean(si / pi)),
+                               "stdev_of_ratios": float(np.std(si / pi))}
+
+    iter_kernels = {k: v for k, v in prof.items() if k in ("check", "variable", "sequential")}
+    dom = max(iter_kernels, key=lambda k: iter_kernels[k]["total_ms"]) if iter_kernels else None
+    roof = None
+    if dom:
+        d = prof[dom]
+        ach = d["algo_bytes"] / (d["total_ms"] / 1e3)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ach / HBM_PEAK, "traffic": None,
+                "avg_launch_ms": d["total_ms"] / d["launches"], "launches": d["launches"],
+                "algo_bytes_per_launch": d["algo_bytes"] / d["launches"]}
+    kernels = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
+                   "share_of_gpu_time": v["total_ms"] / max(1e-9, sum(x["total_ms"] for x in prof.values())),
+                   "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0}
+               for k, v in prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(code, points, args.cpu_frames)
+
+    line = {
+        "metric": "edge·q message updates/s (PUS and SUS)",
+        "value": total_eq / wall,
+        "unit": "edge·q updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 messages, f64 transforms",
+        "data": "synthetic",
+        "config": {"workload": f"GF({Q}) regular ({DV},{DC}) rate-1/2 LDPC, N={N_SYM} symbols, BI-AWGN "
+                               f"Eb/N0 {EBN0[0]}-{EBN0[-1]} dB step 0.2, {FRAMES} frames per point, max {MAX_ITER} "
+                               f"iterations, {'+'.join(s.upper() for s in scheds)}",
+                   "edges": code.E, "q": code.q, "frames_per_step": FRAMES * len(EBN0) * len(scheds)},
+        "frames_per_s": len(rec) * FRAMES / wall,
+        "schedules": per,
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

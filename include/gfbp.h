@@ -1,0 +1,195 @@
+/*
+ * gfbp — belief-propagation decoding of LDPC codes over GF(q = 2^p) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yacov, Efraim, Kfir, Kanter, Shental, "Parallel vs. Sequential
+ * Belief Propagation Decoding of LDPC Codes over GF(q) and Markov Sources",
+ * Section 2.  The decoder solves H x = z for x over GF(q) given per-symbol
+ * channel evidence and priors, by the message passing of Eqs. (eq_r)
+ * (check-to-variable r), (eq_q) (variable-to-check q) and (eq_Q)
+ * (pseudo-posterior Q, clipped to a decision), under either
+ *   - the parallel updating scheme (PUS): all r from the previous
+ *     iteration's q, then all q; or
+ *   - the sequential updating scheme (SUS): for each column j in order, the
+ *     r of column j's edges from the current q, then column j's q.
+ * After each iteration the decision is tested against H x = z.  With a Markov
+ * source, the priors of the information symbols are re-estimated after every
+ * iteration by the dynamical block prior of Eq. (prior2).
+ *
+ * Conventions shared by every call:
+ *   - GF(2^p) in the polynomial basis of a primitive polynomial (bit b of a
+ *     symbol is the coefficient of x^b and is the b-th transmitted bit);
+ *   - BPSK maps bit 0 to +1 and bit 1 to -1;
+ *   - all sums over symbols run over the q field elements 0..q-1;
+ *   - messages are stored as IEEE binary32 probabilities; transforms,
+ *     products and normalisations are computed in binary64; symbols and
+ *     syndromes are bytes.
+ *
+ * Errors: every call returns a gfbp_status; 0 is success, negative values are
+ * errors, and gfbp_last_error() returns a message for the calling thread's
+ * last failure.  No C++ exception crosses this interface.
+ *
+ * Threads and streams: code handles are immutable after gfbp_code_build and
+ * may be shared by concurrent decode calls on different streams, each with
+ * its own workspace.
+ */
+#ifndef GFBP_H
+#define GFBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gfbp_status;
+#define GFBP_OK 0
+#define GFBP_EINVAL (-1)       /* bad argument (null pointer, bad size, bad enum) */
+#define GFBP_EUNSUPPORTED (-2) /* q not 2^p with 1 <= p <= 6, or a degree beyond the kernels' limits */
+#define GFBP_ENOMEM (-3)       /* device or host allocation failed (code build only) */
+#define GFBP_EHIP (-4)         /* a HIP runtime call failed */
+#define GFBP_ESMALL (-5)       /* workspace smaller than gfbp_workspace_size() */
+
+/* schedules (Section 2) */
+#define GFBP_PUS 0
+#define GFBP_SUS 1
+
+/* channels */
+#define GFBP_CH_BSC 0        /* rx: received hard symbols; param: crossover f      */
+#define GFBP_CH_BEC 1        /* rx + erasure: erased-bit masks; param unused      */
+#define GFBP_CH_BIAWGN 2     /* y: p samples per symbol; param: noise std sigma   */
+#define GFBP_CH_LIKELIHOOD 3 /* likelihood: P(received | x = a) for every a       */
+
+/* priors of the information symbols (columns 0..n_info-1) */
+#define GFBP_PRIOR_UNIFORM 0 /* i.i.d. uniform source: prior 1/q                  */
+#define GFBP_PRIOR_MARKOV 1  /* first-order Markov source, Eq. (prior2)           */
+
+/* Limits of the decoding kernels. */
+#define GFBP_MAX_Q 64
+#define GFBP_MAX_ROW_DEGREE 16
+#define GFBP_MAX_COL_DEGREE 8
+
+typedef struct gfbp_code gfbp_code; /* opaque, device-resident Tanner graph */
+
+/* A parity-check matrix H (m x n) over GF(q) in compressed-row form.  All
+ * pointers are host memory, read during gfbp_code_build only (the library
+ * copies them).  Edges (nonzeros) are numbered row by row in the given
+ * order; that numbering is the "edge index" used by message snapshots. */
+typedef struct {
+    int32_t q;               /* field size 2^p, 2 <= q <= 64                        */
+    int32_t poly;            /* primitive polynomial incl. x^p (e.g. 0x13 for q=16); 0 = default */
+    int32_t n;               /* columns (code symbols), visited in order 0..n-1 by SUS */
+    int32_t m;               /* rows (checks)                                        */
+    int32_t n_info;          /* columns 0..n_info-1 are source symbols in chain order */
+    const int32_t *row_ptr;  /* [m+1], row_ptr[0] = 0, nondecreasing                */
+    const int32_t *col;      /* [E] column of each edge, 0 <= col < n, no repeats in a row */
+    const uint8_t *coef;     /* [E] nonzero field element of each edge, < q          */
+} gfbp_code_desc;
+
+typedef struct {
+    int32_t q, p, n, m, n_info, n_edges;
+    int32_t max_row_degree, max_col_degree;
+    int32_t poly;
+    int32_t sus_levels;      /* dependency levels of one SUS sweep (see GFBP_OPT_SUS_STRICT) */
+} gfbp_code_info;
+
+/* Build the device-resident graph of a code on the current HIP device.
+ * Rejects: null pointers, q not a power of two in [2, 64], a polynomial that
+ * is not primitive of degree p, column/coefficient out of range, a column
+ * repeated in a row, row degree > GFBP_MAX_ROW_DEGREE, column degree
+ * > GFBP_MAX_COL_DEGREE.  Synchronous.  The handle owns its device memory. */
+gfbp_status gfbp_code_build(const gfbp_code_desc *desc, gfbp_code **out);
+gfbp_status gfbp_code_free(gfbp_code *code);
+gfbp_status gfbp_code_info_get(const gfbp_code *code, gfbp_code_info *out);
+
+/* One batch of frames, all on one code.  All pointers are device memory,
+ * frame-major, owned by the caller and only read. */
+typedef struct {
+    int32_t n_frames;        /* F >= 0                                                */
+    int32_t schedule;        /* GFBP_PUS or GFBP_SUS                                  */
+    int32_t max_iter;        /* >= 1                                                  */
+    int32_t early_stop;      /* 1: a frame stops at the first iteration with H x = z;
+                                0: every frame runs max_iter iterations              */
+    int32_t channel;         /* GFBP_CH_*                                             */
+    const float *param;      /* [F] crossover f (BSC) or sigma (BI-AWGN); may be NULL for BEC/LIKELIHOOD */
+    const uint8_t *rx;       /* [F][n] received symbols (BSC, BEC; erased bits 0)     */
+    const uint8_t *erasure;  /* [F][n] erased-bit masks (BEC)                         */
+    const float *y;          /* [F][n][p] channel outputs (BI-AWGN)                   */
+    const float *likelihood; /* [F][n][q] P(received | a) (LIKELIHOOD), need not be normalised */
+    const uint8_t *syndrome; /* [F][m] z, or NULL for z = 0                           */
+    int32_t prior;           /* GFBP_PRIOR_*                                          */
+    const float *markov_M;   /* [q][q] M[a][b] = P(next = b | current = a) (MARKOV)   */
+    const float *markov_pi;  /* [q] distribution of the first source symbol (MARKOV)  */
+    int32_t options;         /* bit set of GFBP_OPT_*                                 */
+} gfbp_batch;
+
+/* SUS runs, by default, in dependency levels: two columns that share no check
+ * commute, so columns are grouped into levels (a column's level is one more
+ * than the highest level of the earlier columns it shares a check with) and
+ * the columns of one level are updated concurrently.  Every column still sees
+ * exactly the messages it would see in the strict column order, and its
+ * arithmetic is the same, so results are bitwise identical to the strict
+ * sweep.  This option runs the strict sweep instead (one column after the
+ * other within each frame). */
+#define GFBP_OPT_SUS_STRICT 1
+
+/* Outputs, device memory owned by the caller. */
+typedef struct {
+    uint8_t *xhat;           /* [F][n] decision after the frame's last iteration      */
+    int32_t *iters;          /* [F] first iteration with H x = z, else max_iter       */
+    uint8_t *converged;      /* [F] 1 if some iteration satisfied H x = z             */
+    float *posterior;        /* [F][n][q] final pseudo-posteriors, or NULL            */
+    int32_t *guards;         /* [F] count of zero/non-finite normalisers met, or NULL */
+    int32_t snap_iter;       /* 1-based iteration after which messages are copied; 0 = none */
+    float *snap_q;           /* [F][E][q] q-messages (probability domain), or NULL   */
+    float *snap_r;           /* [F][E][q] r-messages, or NULL                         */
+    float *snap_Q;           /* [F][n][q] pseudo-posteriors, or NULL                  */
+} gfbp_result;
+
+/* Bytes of device workspace gfbp_decode_batch needs for F frames. */
+size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t schedule, int32_t prior);
+
+/* Decode a batch (Section 2, PUS or SUS; Eq. (prior2) priors when asked).
+ * workspace: device memory of at least gfbp_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller, clobbered.  stream: a hipStream_t (NULL =
+ * default stream).  All work is enqueued on the stream; the call returns after
+ * the frames have finished (it reads the number of frames still iterating
+ * back to the host every `poll` iterations to stop early).  Results are then
+ * complete in the output buffers. */
+gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
+                              void *workspace, size_t ws_bytes, void *stream);
+
+/* ---- Tracing: per-kernel timing with HIP events on the decode stream. ----
+ * Off by default.  When on, every kernel launch of gfbp_decode_batch is
+ * bracketed by two HIP events on the caller's stream; after the decode's final
+ * synchronisation the elapsed times are added to process-wide totals per
+ * kernel kind ("init", "check", "variable", "sequential", "syndrome",
+ * "markov", "output"), together with the launch's algorithmic HBM bytes
+ * (float32 messages read and written once, as the method defines them; frames
+ * that have stopped iterating are not counted) and its edge-q updates (E*q per
+ * running frame for one iteration). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;      /* sum of event-measured launch durations */
+    double algo_bytes;    /* sum of algorithmic bytes of those launches */
+    double edge_q;        /* sum of edge-q updates of those launches */
+} gfbp_kernel_stats;
+
+gfbp_status gfbp_profile_enable(int32_t on);
+gfbp_status gfbp_profile_reset(void);
+/* Copies up to cap entries (kinds with at least one launch) and returns how
+ * many kinds have data. */
+int32_t gfbp_profile_read(gfbp_kernel_stats *out, int32_t cap);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *gfbp_last_error(void);
+
+/* Library version string. */
+const char *gfbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFBP_H */

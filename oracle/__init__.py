@@ -68,6 +68,8 @@ def _load():
         lib.ref_markov_prior.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.ref_markov_prior.restype = ctypes.c_int
+        lib.ref_frame_likelihoods.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.ref_decode.argtypes = [ctypes.POINTER(_Code), ctypes.POINTER(_Batch), ctypes.POINTER(_Result)]
         lib.ref_decode.restype = ctypes.c_int
         lib.ref_max_threads.restype = ctypes.c_int
@@ -91,6 +93,19 @@ def likelihood(p: int, channel: str, param: float, rx: int = 0, er: int = 0, y=N
     out = np.zeros(1 << p, dtype=np.float64)
     yy = None if y is None else np.ascontiguousarray(y, dtype=np.float32)
     _load().ref_likelihood(p, CHANNELS[channel], float(param), int(rx), int(er), _ptr(yy), out.ctypes.data)
+    return out
+
+
+def frame_likelihoods(code, frames) -> np.ndarray:
+    """Channel likelihoods L[f][j][a] of every symbol of every frame."""
+    F, n, p = frames.F, code.n, code.p
+    out = np.zeros((F, n, 1 << p))
+    param = np.ascontiguousarray(frames.param, dtype=np.float64)
+    rx = None if frames.rx is None else np.ascontiguousarray(frames.rx, dtype=np.uint8)
+    er = None if frames.erasure is None else np.ascontiguousarray(frames.erasure, dtype=np.uint8)
+    y = None if frames.y is None else np.ascontiguousarray(frames.y, dtype=np.float32)
+    _load().ref_frame_likelihoods(p, CHANNELS[frames.channel], F, n, param.ctypes.data, _ptr(rx), _ptr(er), _ptr(y),
+                                  out.ctypes.data)
     return out
 
 

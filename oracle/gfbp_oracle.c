@@ -129,6 +129,19 @@ void ref_likelihood(int p, int channel, double param, int rx, int er, const floa
     }
 }
 
+/* Channel likelihoods of F frames of n symbols: L[f][j][a]. */
+void ref_frame_likelihoods(int p, int channel, int F, int n, const double *param, const uint8_t *rx,
+                           const uint8_t *er, const float *y, double *L)
+{
+    const int q = 1 << p;
+    for (int f = 0; f < F; ++f)
+        for (int j = 0; j < n; ++j) {
+            const size_t fj = (size_t)f * n + j;
+            ref_likelihood(p, channel, param[f], rx ? rx[fj] : 0, er ? er[fj] : 0, y ? y + fj * p : NULL,
+                           L + fj * q);
+        }
+}
+
 /* Eq. (eq_r) for edge d of a check with dc edges (coefficients h, syndrome z),
  * from the q-messages qin[dc][q]: sum over configurations of the other dc-1
  * symbols such that  h_d a + sum_{d' != d} h_d' x_d' = z.  The sum is taken

@@ -1,1 +1,257 @@
-"""placeholder"""
+"""gfbp — GF(2^p) LDPC belief-propagation decoding on AMD Instinct MI355X.
+
+Thin ctypes binding of the C ABI in ``include/gfbp.h`` (library
+``libgfbp.so`` next to this file).  The binding only marshals arguments: it
+allocates device buffers with PyTorch (memory and streams are PyTorch's) and
+passes raw pointers; every step of decoding runs in the HIP kernels of the
+library.  If the library is missing the binding raises: there is no fallback.
+
+Method: Yacov et al., "Parallel vs. Sequential Belief Propagation Decoding of
+LDPC Codes over GF(q) and Markov Sources", Section 2 (schedules PUS and SUS,
+Eqs. (eq_r), (eq_q), (eq_Q), dynamical Markov block priors Eq. (prior2)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfbp.so")
+
+PUS, SUS = 0, 1
+CH_BSC, CH_BEC, CH_BIAWGN, CH_LIKELIHOOD = 0, 1, 2, 3
+PRIOR_UNIFORM, PRIOR_MARKOV = 0, 1
+OPT_SUS_STRICT = 1
+CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
+SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
+
+EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size", "gfbp_decode_batch",
+           "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_last_error", "gfbp_version")
+
+
+class CodeDesc(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("poly", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n_info", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p)]
+
+
+class CodeInfo(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("p", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n_info", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("max_row_degree", ctypes.c_int32),
+                ("max_col_degree", ctypes.c_int32), ("poly", ctypes.c_int32), ("sus_levels", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("schedule", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("early_stop", ctypes.c_int32), ("channel", ctypes.c_int32), ("param", ctypes.c_void_p),
+                ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p), ("prior", ctypes.c_int32),
+                ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("options", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("xhat", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("converged", ctypes.c_void_p),
+                ("posterior", ctypes.c_void_p), ("guards", ctypes.c_void_p), ("snap_iter", ctypes.c_int32),
+                ("snap_q", ctypes.c_void_p), ("snap_r", ctypes.c_void_p), ("snap_Q", ctypes.c_void_p)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double), ("edge_q", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build the HIP library first (__graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    L.gfbp_code_build.argtypes = [ctypes.POINTER(CodeDesc), ctypes.POINTER(ctypes.c_void_p)]
+    L.gfbp_code_build.restype = ctypes.c_int32
+    L.gfbp_code_free.argtypes = [ctypes.c_void_p]
+    L.gfbp_code_free.restype = ctypes.c_int32
+    L.gfbp_code_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(CodeInfo)]
+    L.gfbp_code_info_get.restype = ctypes.c_int32
+    L.gfbp_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.gfbp_workspace_size.restype = ctypes.c_size_t
+    L.gfbp_decode_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]
+    L.gfbp_decode_batch.restype = ctypes.c_int32
+    L.gfbp_profile_enable.argtypes = [ctypes.c_int32]
+    L.gfbp_profile_enable.restype = ctypes.c_int32
+    L.gfbp_profile_reset.restype = ctypes.c_int32
+    L.gfbp_profile_read.argtypes = [ctypes.POINTER(KernelStats), ctypes.c_int32]
+    L.gfbp_profile_read.restype = ctypes.c_int32
+    L.gfbp_last_error.restype = ctypes.c_char_p
+    L.gfbp_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class GfbpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().gfbp_last_error().decode()
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise GfbpError(status, where)
+
+
+def version() -> str:
+    return lib().gfbp_version().decode()
+
+
+def profile_enable(on: bool = True):
+    _check(lib().gfbp_profile_enable(int(bool(on))), "gfbp_profile_enable")
+
+
+def profile_reset():
+    _check(lib().gfbp_profile_reset(), "gfbp_profile_reset")
+
+
+def profile_read() -> dict:
+    """Per-kernel totals since the last reset: {name: {launches, total_ms, algo_bytes, edge_q}}."""
+    buf = (KernelStats * 16)()
+    n = lib().gfbp_profile_read(buf, 16)
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches), "total_ms": float(buf[i].total_ms),
+                                   "algo_bytes": float(buf[i].algo_bytes), "edge_q": float(buf[i].edge_q)}
+            for i in range(min(n, 16))}
+
+
+def last_error() -> str:
+    return lib().gfbp_last_error().decode()
+
+
+class DeviceCode:
+    """A code built on the current HIP device (``gfbp_code_build``).
+
+    ``code`` is any object with q, n, m, n_info, row_ptr, col, coef and
+    (optionally) poly attributes, such as ``workloads.Code``.
+    """
+
+    def __init__(self, code):
+        L = lib()
+        self._rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+        self._col = np.ascontiguousarray(code.col, dtype=np.int32)
+        self._coef = np.ascontiguousarray(code.coef, dtype=np.uint8)
+        d = CodeDesc(int(code.q), int(getattr(code, "poly", 0)), int(code.n), int(code.m), int(code.n_info),
+                     self._rp.ctypes.data, self._col.ctypes.data, self._coef.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(L.gfbp_code_build(ctypes.byref(d), ctypes.byref(h)), "gfbp_code_build")
+        self.handle = h
+        info = CodeInfo()
+        _check(L.gfbp_code_info_get(h, ctypes.byref(info)), "gfbp_code_info_get")
+        self.info = info
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gfbp_code_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def q(self):
+        return self.info.q
+
+    @property
+    def n(self):
+        return self.info.n
+
+    @property
+    def m(self):
+        return self.info.m
+
+    @property
+    def E(self):
+        return self.info.n_edges
+
+    def workspace_size(self, n_frames: int, schedule, prior: int = PRIOR_UNIFORM) -> int:
+        return int(lib().gfbp_workspace_size(self.handle, int(n_frames), SCHEDULES[schedule], int(prior)))
+
+
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def frames_to_device(frames, device="cuda"):
+    """Copy a ``workloads.Frames`` batch to device tensors (marshalling only)."""
+    import torch
+
+    def dev(a, dt):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+
+    return {
+        "channel": frames.channel,
+        "F": frames.F,
+        "param": dev(frames.param.astype(np.float32), torch.float32),
+        "rx": dev(frames.rx, torch.uint8),
+        "erasure": dev(frames.erasure, torch.uint8),
+        "y": dev(frames.y, torch.float32),
+        "syndrome": dev(frames.syndrome, torch.uint8),
+        "likelihood": None,
+    }
+
+
+def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
+                 prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
+                 snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
+                 sus_strict: bool = False) -> dict:
+    """``gfbp_decode_batch`` on device tensors; returns device tensors.
+
+    dframes: dict from :func:`frames_to_device` (or with the same keys).
+    workspace: optional preallocated uint8 device tensor of at least
+    ``dcode.workspace_size(F, schedule, prior)`` bytes, 256-byte aligned.
+    outputs: optional preallocated output tensors (xhat, iters, converged).
+    """
+    import torch
+
+    F = int(dframes["F"])
+    n, q, E = dcode.n, dcode.q, dcode.E
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sch = SCHEDULES[schedule]
+    pk = PRIOR_MARKOV if prior == "markov" else PRIOR_UNIFORM
+    out = dict(outputs) if outputs else {}
+    out.setdefault("xhat", torch.empty((F, n), dtype=torch.uint8, device=dev))
+    out.setdefault("iters", torch.empty((F,), dtype=torch.int32, device=dev))
+    out.setdefault("converged", torch.empty((F,), dtype=torch.uint8, device=dev))
+    if posterior:
+        out.setdefault("posterior", torch.empty((F, n, q), dtype=torch.float32, device=dev))
+    if guards:
+        out.setdefault("guards", torch.empty((F,), dtype=torch.int32, device=dev))
+    if snap_iter:
+        out["snap_q"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
+        out["snap_r"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
+        out["snap_Q"] = torch.zeros((F, n, q), dtype=torch.float32, device=dev)
+    ws_bytes = dcode.workspace_size(F, sch, pk)
+    if workspace is None:
+        workspace = torch.empty((max(ws_bytes, 1),), dtype=torch.uint8, device=dev)
+    Mt = pt = None
+    if pk == PRIOR_MARKOV:
+        Mt = torch.as_tensor(np.asarray(markov_M, dtype=np.float32), device=dev).contiguous()
+        pt = torch.as_tensor(np.asarray(markov_pi, dtype=np.float32), device=dev).contiguous()
+    b = Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes["channel"]], _dptr(dframes.get("param")),
+              _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")), _dptr(dframes.get("y")),
+              _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")), pk, _dptr(Mt), _dptr(pt),
+              OPT_SUS_STRICT if sus_strict else 0)
+    r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), _dptr(out.get("posterior")),
+               _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
+               _dptr(out.get("snap_Q")))
+    st = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().gfbp_decode_batch(dcode.handle, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(),
+                                   workspace.numel(), ctypes.c_void_p(st.cuda_stream)), "gfbp_decode_batch")
+    return out

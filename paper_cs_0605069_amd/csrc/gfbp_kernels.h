@@ -1,0 +1,133 @@
+// Device-side building blocks of the GF(2^p) belief-propagation decoder.
+//
+// Thread mapping: one "group" of Q = 2^P consecutive lanes holds one q-vector
+// of one frame, lane k holding entry k; a 64-lane wavefront holds 64/Q frames
+// that all work on the same graph node, so every index into the graph is
+// wavefront-uniform and every message access stays inside one contiguous
+// 256-byte run.
+//
+// Message layout (frame-interleaved, edge-major): message[e][f][a] with f the
+// frame and a the field element, messages kept as probabilities in float32
+// (which holds small probabilities to full relative precision).
+//
+// Check-node arithmetic (Eq. (eq_r)): with y = h x the weighted symbol of an
+// edge, the check constraint is an XOR-sum of the y's, so the sum over
+// configurations is an XOR-convolution of the siblings' distributions of y,
+// q~(y) = q(h^-1 y).  The Walsh-Hadamard transform (WHT) turns XOR-convolution
+// into a pointwise product.  The permutation by h^-1 is folded into the load
+// address (lane y reads entry h^-1 y), the transforms and products run in
+// float64 registers (a float32 transform loses every probability below ~1e-7
+// of the largest one to cancellation), and the result S(y) goes back to
+// r(a) = S(z + h a) by the store address a = h^-1 (y + z).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gfbp {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kDcMax = 16;  // GFBP_MAX_ROW_DEGREE
+constexpr int kDvMax = 8;   // GFBP_MAX_COL_DEGREE
+
+struct DevCode {
+    int n, m, E, q, p, n_info;
+    const int32_t *row_ptr;   // [m+1]
+    const int32_t *col;       // [E]
+    const uint8_t *coef;      // [E]
+    const int32_t *col_ptr;   // [n+1]
+    const int32_t *col_edge;  // [E] edges of each column, increasing edge index
+    const int32_t *edge_row;  // [E]
+    const uint8_t *mul;       // [q][q] field multiplication
+    const uint64_t *emap;     // [E][2] images of x^b under h^-1 (word 0) and h (word 1), 6 bits each
+};
+
+struct DevState {
+    float *Qm;        // [E][F][Q] variable-to-check messages q
+    float *R;         // [E][F][Q] check-to-variable messages r (PUS only)
+    float *L;         // [n][F][Q] normalised channel likelihoods
+    float *Pr;        // [K][F][Q] normalised likelihood x Markov prior (Markov only)
+    float *Qp;        // [n][F][Q] pseudo-posteriors (when needed)
+    uint8_t *xh;      // [n][F] decisions
+    uint32_t *unsat;  // [F] some check unsatisfied in this iteration
+    uint8_t *active;  // [F] frame still iterating
+    uint32_t *count;  // [2] frames still iterating, by iteration parity
+    int32_t *guards;  // [F]
+    int F;
+};
+
+struct Snap {
+    float *q;  // [F][E][Q] or null
+    float *r;  // [F][E][Q] or null
+};
+
+// Multiplication by a fixed field element h, applied to y through the images
+// of the basis vectors x^b (packed 6 bits each): h y = XOR over set bits b of
+// y of h x^b.
+template <int P>
+__device__ __forceinline__ int gf_apply(uint64_t packed, int y) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) r ^= ((y >> b) & 1) ? int((packed >> (6 * b)) & 63u) : 0;
+    return r;
+}
+
+// ---------------------------------------------------------------- group ops
+template <typename T>
+__device__ __forceinline__ T lane_xor(T v, int mask) {
+    return __shfl_xor(v, mask, kWave);
+}
+
+template <int P, typename T>
+__device__ __forceinline__ T grp_gather(T v, int src_in_group) {
+    return __shfl(v, src_in_group, 1 << P);
+}
+
+// Unnormalised Walsh-Hadamard transform across the Q lanes of a group:
+// out(k) = sum_y v(y) (-1)^popcount(k & y).  Each butterfly stage pairs
+// lanes that differ in one bit.
+template <int P, typename T>
+__device__ __forceinline__ T wht(T v, int k) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        const int m = 1 << s;
+        const T o = lane_xor(v, m);
+        v = (k & m) ? (o - v) : (v + o);
+    }
+    return v;
+}
+
+// Sum over the group, bitwise identical on every lane.
+template <int P, typename T>
+__device__ __forceinline__ T grp_sum(T v) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) v += lane_xor(v, 1 << s);
+    return v;
+}
+
+// Index of the largest entry, the smallest index among equal maxima.
+template <int P>
+__device__ __forceinline__ int grp_argmax(float v, int k) {
+    int bi = k;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        const float ov = lane_xor(v, 1 << s);
+        const int oi = lane_xor(bi, 1 << s);
+        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+    }
+    return bi;
+}
+
+// v / sum over the group; uniform 1/Q (and a guard event) when the sum is
+// zero or not finite.
+template <int P>
+__device__ __forceinline__ double grp_normalise(double v, int32_t *guards, int f, int k) {
+    const double s = grp_sum<P>(v);
+    if (!(s > 0.0) || !isfinite(s)) {
+        if (k == 0) atomicAdd(&guards[f], 1);
+        return 1.0 / double(1 << P);
+    }
+    return v / s;
+}
+
+}  // namespace gfbp

@@ -1,0 +1,66 @@
+"""C ABI: the library loads, exports every function the header declares, and
+rejects bad arguments on the host (no GPU needed for these paths)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "gfbp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gfbp_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("gfbp_code_build", "gfbp_code_free", "gfbp_decode_batch", "gfbp_workspace_size", "gfbp_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_cs_0605069_amd as gfbp
+
+    L = gfbp.lib()
+    for name in _declared():
+        assert hasattr(L, name), f"{name} declared in gfbp.h but not exported"
+    assert set(gfbp.EXPORTS) <= set(_declared())
+    assert gfbp.version().startswith("gfbp")
+
+
+def _desc(gfbp, q=4, n=6, m=3, rows=((0, 1, 2), (2, 3, 4), (4, 5, 0)), coef=None, poly=0):
+    rp = np.zeros(m + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([c for r in rows for c in r], dtype=np.int32)
+    cf = np.ones(len(col), dtype=np.uint8) if coef is None else np.asarray(coef, dtype=np.uint8)
+    keep = (rp, col, cf)
+    return gfbp.CodeDesc(q, poly, n, m, 0, rp.ctypes.data, col.ctypes.data, cf.ctypes.data), keep
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(q=3), -2), (dict(q=128), -2), (dict(q=4, poly=0b101), -1),
+    (dict(coef=[1, 1, 4, 1, 1, 1, 1, 1, 1]), -1), (dict(coef=[1, 0, 1, 1, 1, 1, 1, 1, 1]), -1),
+    (dict(rows=((0, 1, 1), (2, 3, 4), (4, 5, 0))), -1), (dict(rows=((0, 1, 9), (2, 3, 4), (4, 5, 0))), -1),
+])
+def test_code_build_rejects_bad_descriptions(bad, status):
+    import paper_cs_0605069_amd as gfbp
+
+    d, keep = _desc(gfbp, **bad)
+    h = ctypes.c_void_p()
+    assert gfbp.lib().gfbp_code_build(ctypes.byref(d), ctypes.byref(h)) == status
+    assert h.value is None
+    assert gfbp.last_error() != ""
+
+
+def test_null_arguments():
+    import paper_cs_0605069_amd as gfbp
+
+    L = gfbp.lib()
+    assert L.gfbp_code_build(None, None) == -1
+    assert L.gfbp_decode_batch(None, None, None, None, 0, None) == -1
+    assert L.gfbp_workspace_size(None, 10, 0, 0) == 0
+    assert L.gfbp_code_free(None) == 0

@@ -1,0 +1,332 @@
+"""GPU decoder against the reference decoder, through the C ABI.
+
+Same seeded inputs on both sides.  Bars:
+  * messages (q, r, Q) after the first iterations within 1e-4 absolute;
+  * BEC with an i.i.d. source: messages bit-identical (every value is dyadic);
+  * decisions and iteration counts identical on >= 99.9% of frames, the
+    exceptions (logged) being frames the reference itself did not converge
+    on ("chaotic") and frames whose reference outcome changes when its own
+    float64 channel likelihoods are rounded to float32 ("fp32-sensitive");
+  * FER and mean iterations within each other's 95% confidence intervals.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0605069_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+MSG_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def gfbp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_cs_0605069_amd as g
+
+    g.lib()
+    return g
+
+
+def _gpu(gfbp, code, fr, schedule, **kw):
+    import torch
+
+    dcode = gfbp.DeviceCode(code)
+    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _ref(code, fr, schedule, **kw):
+    return oracle.decode(code, fr, schedule=gfbp_sched(schedule), **kw)
+
+
+def gfbp_sched(s):
+    return {"pus": oracle.PUS, "sus": oracle.SUS}[s]
+
+
+def _small_code(q, n, seed, d_v=3, d_c=6):
+    m = n * d_v // d_c
+    return wl.systematic(wl.make_code(n, m, d_v, q, seed, reject_4cycles=False))
+
+
+def _fp32_sensitive(code, fr, schedule, idx, **kw):
+    """Frames (of idx) whose reference outcome changes when their float64
+    channel likelihoods are rounded to float32, the GPU decoder's input
+    precision: their result is not determined at that precision."""
+    if len(idx) == 0:
+        return np.zeros(0, dtype=bool)
+    sub = fr.subset(idx)
+    L = oracle.frame_likelihoods(code, sub)
+    kw = {k: v for k, v in kw.items() if k not in ("snap_iter", "posterior")}
+    a = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=gfbp_sched(schedule), **kw)
+    b = oracle.decode(code, likelihoods=L.astype(np.float32).astype(np.float64), syndrome=sub.syndrome,
+                      schedule=gfbp_sched(schedule), **kw)
+    return (a["xhat"] != b["xhat"]).any(axis=1) | (a["iters"] != b["iters"])
+
+
+def _compare_decisions(g, r, label, min_frac=0.999, recheck=None):
+    """Identical decisions and iteration counts on >= min_frac of the frames;
+    frames the reference did not converge on (chaotic) and frames whose
+    reference outcome is not determined at float32 input precision
+    (recheck(idx) -> bool mask) are logged exceptions."""
+    same = (g["xhat"] == r["xhat"]).all(axis=1) & (g["iters"] == r["iters"])
+    chaotic = r["converged"] == 0
+    bad = ~same & ~chaotic
+    sensitive = np.zeros_like(bad)
+    if recheck is not None and bad.any():
+        bi = np.nonzero(bad)[0]
+        sens = recheck(bi)
+        sensitive[bi[sens]] = True
+        bad &= ~sensitive
+    F = len(same)
+    print(f"[{label}] frames={F} identical={int(same.sum())} chaotic-differing={int((~same & chaotic).sum())} "
+          f"fp32-sensitive={int(sensitive.sum())} other-differing={int(bad.sum())} "
+          f"mean_iters gpu={g['iters'].mean():.3f} ref={r['iters'].mean():.3f} "
+          f"FER gpu={1 - g['converged'].mean():.4f} ref={1 - r['converged'].mean():.4f}")
+    for name, mask in (("chaotic", ~same & chaotic), ("fp32-sensitive", sensitive), ("differing", bad)):
+        if mask.any():
+            idx = np.nonzero(mask)[0][:8]
+            print(f"[{label}] {name} frames {idx.tolist()} iters gpu={g['iters'][idx].tolist()} "
+                  f"ref={r['iters'][idx].tolist()}")
+    assert bad.sum() <= math.floor((1 - min_frac) * F), f"{label}: {int(bad.sum())} frames differ"
+    return same
+
+
+def _ci_overlap(a, b):
+    """95% CIs of two means (normal approximation) overlap."""
+    ma, mb = a.mean(), b.mean()
+    sa = 1.96 * a.std(ddof=1) / math.sqrt(len(a)) if len(a) > 1 else 0.0
+    sb = 1.96 * b.std(ddof=1) / math.sqrt(len(b)) if len(b) > 1 else 0.0
+    return abs(ma - mb) <= sa + sb + 1e-12
+
+
+# --------------------------------------------------------------- messages
+@pytest.mark.parametrize("q", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_messages_after_first_iterations(gfbp, q, schedule):
+    code, enc = _small_code(q, 72, seed=100 + q)
+    F = 13  # not a multiple of the frames per wavefront: ragged tail
+    fr = wl.make_frames(code, enc, F, 200 + q, "bsc", 0.09)
+    for it in (1, 2, 3):
+        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            err = np.abs(g[key] - r[key]).max()
+            assert err <= MSG_TOL, f"q={q} {schedule} iter {it} {key}: max abs error {err:.3g}"
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_bec_messages_bit_identical(gfbp, schedule):
+    code, enc = _small_code(8, 96, seed=7)
+    fr = wl.make_frames(code, enc, 10, 8, "bec", 0.3)
+    for it in (1, 2, 4):
+        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            assert np.array_equal(g[key], r[key].astype(np.float32)), f"{schedule} iter {it} {key} not bit-identical"
+
+
+# --------------------------------------------------------------- decisions
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_config1_all_frames(gfbp, schedule):
+    """GF(4), (3,6), N=504, BSC 0.06, 2000 frames, max 200 iterations."""
+    code, enc = wl.regular_code(504, 3, 6, 4, seed=0xC0DE0001)
+    fr = wl.make_frames(code, enc, 2000, 0xDA7A0001, "bsc", 0.06)
+    g = _gpu(gfbp, code, fr, schedule, max_iter=200)
+    r = _ref(code, fr, schedule, max_iter=200)
+    _compare_decisions(g, r, f"C1 {schedule}",
+                       recheck=lambda idx: _fp32_sensitive(code, fr, schedule, idx, max_iter=200))
+    assert _ci_overlap(g["iters"].astype(float), r["iters"].astype(float))
+
+
+@pytest.mark.parametrize("channel,param", [("bec", 0.42), ("biawgn", 0.85)])
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_other_channels(gfbp, channel, param, schedule):
+    code, enc = wl.regular_code(240, 3, 6, 8, seed=9)
+    fr = wl.make_frames(code, enc, 150, 10, channel, param)
+    g = _gpu(gfbp, code, fr, schedule, max_iter=60)
+    r = _ref(code, fr, schedule, max_iter=60)
+    _compare_decisions(g, r, f"{channel} {schedule}",
+                       recheck=lambda idx: _fp32_sensitive(code, fr, schedule, idx, max_iter=60))
+    for it in (1, 3):
+        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
+        assert np.abs(g["snap_q"] - r["snap_q"]).max() <= MSG_TOL
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_markov_prior(gfbp, schedule):
+    q = 8
+    code, enc = wl.regular_code(300, 3, 6, q, seed=11)
+    M = wl.self_transition_matrix(q, 0.7)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 120, 12, "bsc", 0.1, source="markov", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=pi)
+    for it in (1, 2, 4):
+        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it, **kw)
+        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it, **kw)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            err = np.abs(g[key] - r[key]).max()
+            assert err <= MSG_TOL, f"{schedule} iter {it} {key}: {err:.3g}"
+    g = _gpu(gfbp, code, fr, schedule, max_iter=100, **kw)
+    r = _ref(code, fr, schedule, max_iter=100, **kw)
+    _compare_decisions(g, r, f"markov {schedule}",
+                       recheck=lambda idx: _fp32_sensitive(code, fr, schedule, idx, max_iter=100, **kw))
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_nonzero_syndrome_and_given_likelihoods(gfbp, schedule):
+    """Coset decoding (H x = z with z != 0) from raw likelihood vectors."""
+    import torch
+
+    q = 16
+    code, enc = _small_code(q, 120, seed=13)
+    rng = np.random.default_rng(14)
+    F = 40
+    x = rng.integers(0, q, size=(F, code.n)).astype(np.uint8)
+    H = code.dense()
+    from tests import _gf
+
+    T = _gf.mul_table(code.p)
+    z = np.zeros((F, code.m), dtype=np.uint8)
+    for i in range(code.m):
+        for j in np.nonzero(H[i])[0]:
+            z[:, i] ^= T[H[i, j], x[:, j]].astype(np.uint8)
+    noisy = wl.bsc(x, code.p, 0.05, 15)
+    L = np.stack([oracle.likelihood(code.p, "bsc", 0.05, rx=int(v)) for v in noisy.ravel()]).reshape(F, code.n, q)
+    dcode = gfbp.DeviceCode(code)
+    dfr = {"channel": "likelihood", "F": F, "likelihood": torch.from_numpy(L.astype(np.float32)).cuda(),
+           "syndrome": torch.from_numpy(z).cuda()}
+    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    r = oracle.decode(code, likelihoods=L.astype(np.float32).astype(np.float64), syndrome=z,
+                      schedule=gfbp_sched(schedule), max_iter=50)
+    _compare_decisions(g, r, f"coset {schedule}")
+    assert (g["xhat"][g["converged"] == 1] == x[g["converged"] == 1]).mean() > 0.99
+
+
+# --------------------------------------------------------------- full sizes, sampled frames
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_config2_full_batch_sampled(gfbp, schedule):
+    """GF(16), (3,6), N=2000, BI-AWGN 1.0 dB, 4096 frames in one launch; the
+    reference decodes every 256th frame."""
+    code, enc = wl.regular_code(2000, 3, 6, 16, seed=0xC0DE0002)
+    sigma = wl.sigma_from_ebn0(1.0, code.n_info / code.n)
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0002, "biawgn", sigma)
+    g = _gpu(gfbp, code, fr, schedule, max_iter=100)
+    idx = np.arange(0, 4096, 256)
+    r = _ref(code, fr.subset(idx), schedule, max_iter=100)
+    gs = {k: v[idx] for k, v in g.items()}
+    sub = fr.subset(idx)
+    _compare_decisions(gs, r, f"C2 1.0dB {schedule}", min_frac=0.9,
+                       recheck=lambda i: _fp32_sensitive(code, sub, schedule, i, max_iter=100))
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.08), ("bec", 0.45)])
+def test_config3_full_batch_sampled(gfbp, channel, param):
+    """GF(8), (3,6), N=3000, Markov source (self-transition 0.7), 4096 frames."""
+    q = 8
+    code, enc = wl.regular_code(3000, 3, 6, q, seed=0xC0DE0003)
+    M = wl.self_transition_matrix(q, 0.7)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0003, channel, param, source="markov", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=pi, max_iter=100)
+    idx = np.arange(0, 4096, 512)
+    for schedule in ("pus", "sus"):
+        g = _gpu(gfbp, code, fr, schedule, **kw)
+        r = _ref(code, fr.subset(idx), schedule, **kw)
+        gs = {k: v[idx] for k, v in g.items()}
+        sub = fr.subset(idx)
+        _compare_decisions(gs, r, f"C3 {channel} {schedule}", min_frac=0.875,
+                           recheck=lambda i: _fp32_sensitive(code, sub, schedule, i, **kw))
+
+
+# --------------------------------------------------------------- batching properties
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_frame_alone_equals_frame_in_batch_and_runs_repeat(gfbp, schedule):
+    code, enc = wl.regular_code(200, 3, 6, 16, seed=17)
+    fr = wl.make_frames(code, enc, 37, 18, "bsc", 0.07)
+    a = _gpu(gfbp, code, fr, schedule, max_iter=40, posterior=True)
+    b = _gpu(gfbp, code, fr, schedule, max_iter=40, posterior=True)
+    for k in ("xhat", "iters", "converged", "posterior"):
+        assert np.array_equal(a[k], b[k]), f"run-to-run difference in {k}"
+    for f in (0, 5, 36):
+        one = _gpu(gfbp, code, fr.subset([f]), schedule, max_iter=40, posterior=True)
+        assert np.array_equal(one["posterior"][0], a["posterior"][f])
+        assert one["iters"][0] == a["iters"][f]
+
+
+def test_edge_cases(gfbp):
+    import torch
+
+    code, enc = _small_code(4, 48, seed=19)
+    fr = wl.make_frames(code, enc, 1, 20, "bsc", 0.05)
+    for sch in ("pus", "sus"):
+        g = _gpu(gfbp, code, fr, sch, max_iter=1)
+        r = _ref(code, fr, sch, max_iter=1)
+        assert np.array_equal(g["xhat"], r["xhat"]) and np.array_equal(g["iters"], r["iters"])
+    # zero frames is a no-op
+    dcode = gfbp.DeviceCode(code)
+    empty = {"channel": "bsc", "F": 0, "param": torch.zeros(0, device="cuda"),
+             "rx": torch.zeros((0, code.n), dtype=torch.uint8, device="cuda")}
+    out = gfbp.decode_batch(dcode, empty, schedule="pus")
+    assert out["xhat"].shape == (0, code.n)
+    # workspace too small is refused
+    with pytest.raises(gfbp.GfbpError) as ei:
+        gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == -5
+
+
+def test_degree_limits(gfbp):
+    """Row degree 16 and column degree 8 (the kernels' limits)."""
+    q = 4
+    code = wl.make_code(64, 32, 8, q, seed=21, reject_4cycles=False)
+    assert code.row_degrees().max() == 16 and code.col_degrees().max() == 8
+    code, enc = wl.systematic(code)
+    fr = wl.make_frames(code, enc, 9, 22, "bsc", 0.02)
+    for sch in ("pus", "sus"):
+        g = _gpu(gfbp, code, fr, sch, max_iter=2, early_stop=False, snap_iter=2)
+        r = _ref(code, fr, sch, max_iter=2, early_stop=False, snap_iter=2)
+        assert np.abs(g["snap_q"] - r["snap_q"]).max() <= MSG_TOL
+
+
+# --------------------------------------------------------------- SUS by dependency levels
+def _sus_levels(code):
+    rows = code.row_of_edge()
+    top = -np.ones(code.m, dtype=np.int64)
+    nlev = 0
+    for j in range(code.n):
+        r = rows[code.col == j]
+        lv = int(top[r].max()) + 1 if len(r) else 0
+        top[r] = lv
+        nlev = max(nlev, lv + 1)
+    return nlev
+
+
+@pytest.mark.parametrize("q,channel,param,prior", [(4, "bsc", 0.07, "uniform"), (16, "biawgn", 0.85, "uniform"),
+                                                   (8, "bsc", 0.1, "markov"), (64, "bec", 0.4, "uniform")])
+def test_levelled_sus_is_bitwise_the_strict_sweep(gfbp, q, channel, param, prior):
+    """Columns of one dependency level share no check, so running a level at
+    once reproduces the strict column order exactly."""
+    code, enc = wl.regular_code(300 if q < 64 else 120, 3, 6, q, seed=31 + q)
+    kw = {}
+    src = "iid"
+    if prior == "markov":
+        M = wl.self_transition_matrix(q, 0.7)
+        kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M))
+        src = "markov"
+    fr = wl.make_frames(code, enc, 50, 32 + q, channel, param, source=src, markov=kw.get("markov_M"))
+    dcode = gfbp.DeviceCode(code)
+    assert dcode.info.sus_levels == _sus_levels(code)
+    assert dcode.info.sus_levels < code.n // 3
+    for extra in (dict(max_iter=40, posterior=True), dict(max_iter=3, early_stop=False, snap_iter=2)):
+        a = _gpu(gfbp, code, fr, "sus", **extra, **kw)
+        b = _gpu(gfbp, code, fr, "sus", sus_strict=True, **extra, **kw)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), f"levelled and strict SUS differ in {k}"
