@@ -151,7 +151,7 @@ def main():
         per["sus_over_pus"] = {"ratio_of_means": si.mean() / pi.mean(), "mean_of_ratios": float(np.mean(si / pi)),
                                "stdev_of_ratios": float(np.std(si / pi))}
 
-    iter_kernels = {k: v for k, v in prof.items() if k in ("check", "variable", "sequential")}
+    iter_kernels = {k: v for k, v in prof.items() if k in ("check", "variable", "sequential", "sus_level")}
     dom = max(iter_kernels, key=lambda k: iter_kernels[k]["total_ms"]) if iter_kernels else None
     roof = None
     if dom:

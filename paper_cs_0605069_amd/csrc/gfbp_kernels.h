@@ -73,9 +73,47 @@ __device__ __forceinline__ int gf_apply(uint64_t packed, int y) {
 }
 
 // ---------------------------------------------------------------- group ops
-template <typename T>
-__device__ __forceinline__ T lane_xor(T v, int mask) {
-    return __shfl_xor(v, mask, kWave);
+// Exchange with lane (lane ^ MASK) without the LDS crossbar: DPP quad
+// permutes for masks 1 and 2, half-row mirror followed by a quad reversal for
+// 4, a 16-lane row rotation by 8 for 8, and the gfx950 row swaps
+// v_permlane16_swap / v_permlane32_swap for 16 and 32.
+template <int MASK>
+__device__ __forceinline__ uint32_t xchg_u32(uint32_t v) {
+    const int x = int(v);
+    if constexpr (MASK == 1) {
+        return uint32_t(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    } else if constexpr (MASK == 2) {
+        return uint32_t(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    } else if constexpr (MASK == 4) {
+        const int t = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);      // row_half_mirror: i -> 7-i
+        return uint32_t(__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false));   // quad_perm [3,2,1,0]
+    } else if constexpr (MASK == 8) {
+        return uint32_t(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));  // row_ror:8
+    } else if constexpr (MASK == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        static_assert(MASK == 32, "exchange mask");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    }
+}
+
+template <int MASK>
+__device__ __forceinline__ float xchg(float v) {
+    return __uint_as_float(xchg_u32<MASK>(__float_as_uint(v)));
+}
+
+template <int MASK>
+__device__ __forceinline__ int xchg(int v) {
+    return int(xchg_u32<MASK>(uint32_t(v)));
+}
+
+template <int MASK>
+__device__ __forceinline__ double xchg(double v) {
+    const uint64_t u = uint64_t(__double_as_longlong(v));
+    const uint32_t lo = xchg_u32<MASK>(uint32_t(u)), hi = xchg_u32<MASK>(uint32_t(u >> 32));
+    return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
 }
 
 template <int P, typename T>
@@ -84,38 +122,40 @@ __device__ __forceinline__ T grp_gather(T v, int src_in_group) {
 }
 
 // Unnormalised Walsh-Hadamard transform across the Q lanes of a group:
-// out(k) = sum_y v(y) (-1)^popcount(k & y).  Each butterfly stage pairs
-// lanes that differ in one bit.
-template <int P, typename T>
+// out(k) = sum_y v(y) (-1)^popcount(k & y).  Stage S pairs lanes that differ
+// in bit S.
+template <int P, int S = 0, typename T>
 __device__ __forceinline__ T wht(T v, int k) {
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-        const int m = 1 << s;
-        const T o = lane_xor(v, m);
-        v = (k & m) ? (o - v) : (v + o);
+    if constexpr (S < P) {
+        const T o = xchg<(1 << S)>(v);
+        v = (k & (1 << S)) ? (o - v) : (v + o);
+        return wht<P, S + 1>(v, k);
+    } else {
+        return v;
     }
-    return v;
 }
 
 // Sum over the group, bitwise identical on every lane.
-template <int P, typename T>
+template <int P, int S = 0, typename T>
 __device__ __forceinline__ T grp_sum(T v) {
-#pragma unroll
-    for (int s = 0; s < P; ++s) v += lane_xor(v, 1 << s);
-    return v;
+    if constexpr (S < P) {
+        return grp_sum<P, S + 1>(v + xchg<(1 << S)>(v));
+    } else {
+        return v;
+    }
 }
 
 // Index of the largest entry, the smallest index among equal maxima.
-template <int P>
+template <int P, int S = 0>
 __device__ __forceinline__ int grp_argmax(float v, int k) {
-    int bi = k;
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-        const float ov = lane_xor(v, 1 << s);
-        const int oi = lane_xor(bi, 1 << s);
-        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+    if constexpr (S < P) {
+        const float ov = xchg<(1 << S)>(v);
+        const int oi = xchg<(1 << S)>(k);
+        const bool take = ov > v || (ov == v && oi < k);
+        return grp_argmax<P, S + 1>(take ? ov : v, take ? oi : k);
+    } else {
+        return k;
     }
-    return bi;
 }
 
 // v / sum over the group; uniform 1/Q (and a guard event) when the sum is

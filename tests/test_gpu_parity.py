@@ -6,7 +6,8 @@ Same seeded inputs on both sides.  Bars:
   * decisions and iteration counts identical on >= 99.9% of frames, the
     exceptions (logged) being frames the reference itself did not converge
     on ("chaotic") and frames whose reference outcome changes when its own
-    float64 channel likelihoods are rounded to float32 ("fp32-sensitive");
+    float64 inputs are rounded to float32 or moved by a relative 1e-6
+    ("fp32-sensitive");
   * FER and mean iterations within each other's 95% confidence intervals.
 """
 import math
@@ -56,18 +57,31 @@ def _small_code(q, n, seed, d_v=3, d_c=6):
 
 
 def _fp32_sensitive(code, fr, schedule, idx, **kw):
-    """Frames (of idx) whose reference outcome changes when their float64
-    channel likelihoods are rounded to float32, the GPU decoder's input
-    precision: their result is not determined at that precision."""
+    """Frames (of idx) whose reference outcome is not determined at float32
+    precision: it changes when the reference's own float64 inputs (channel
+    likelihoods, Markov matrix and start distribution) are rounded to float32,
+    as the GPU decoder stores them, or perturbed by a relative 1e-6 (a few
+    float32 rounding steps) in either of two seeded random directions."""
     if len(idx) == 0:
         return np.zeros(0, dtype=bool)
     sub = fr.subset(idx)
     L = oracle.frame_likelihoods(code, sub)
     kw = {k: v for k, v in kw.items() if k not in ("snap_iter", "posterior")}
-    a = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=gfbp_sched(schedule), **kw)
-    b = oracle.decode(code, likelihoods=L.astype(np.float32).astype(np.float64), syndrome=sub.syndrome,
-                      schedule=gfbp_sched(schedule), **kw)
-    return (a["xhat"] != b["xhat"]).any(axis=1) | (a["iters"] != b["iters"])
+    sch = gfbp_sched(schedule)
+    a = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=sch, **kw)
+    rnd = dict(kw)
+    if "markov_M" in rnd:
+        rnd["markov_M"] = np.asarray(rnd["markov_M"]).astype(np.float32).astype(np.float64)
+        rnd["markov_pi"] = np.asarray(rnd["markov_pi"]).astype(np.float32).astype(np.float64)
+    variants = [L.astype(np.float32).astype(np.float64)]
+    rng = np.random.default_rng(0x5E45)
+    for _ in range(2):
+        variants.append(L * (1.0 + 1e-6 * rng.uniform(-1, 1, size=L.shape)))
+    moved = np.zeros(len(idx), dtype=bool)
+    for Lv in variants:
+        b = oracle.decode(code, likelihoods=Lv, syndrome=sub.syndrome, schedule=sch, **rnd)
+        moved |= (a["xhat"] != b["xhat"]).any(axis=1) | (a["iters"] != b["iters"])
+    return moved
 
 
 def _compare_decisions(g, r, label, min_frac=0.999, recheck=None):
