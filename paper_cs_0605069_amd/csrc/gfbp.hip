@@ -16,6 +16,7 @@
 
 #include "../../include/gfbp.h"
 #include "gfbp_kernels.h"
+#include "gfbp_tiled.h"
 
 using namespace gfbp;
 
@@ -135,228 +136,15 @@ thread_local std::vector<hipEvent_t> Tracer::pool;
 // ======================================================================= kernels
 namespace {
 
-struct BatchArgs {
-    int channel;
-    const float *param;
-    const uint8_t *rx;
-    const uint8_t *erasure;
-    const float *y;
-    const float *lik;
-    const uint8_t *z;
-    int markov;
-    const float *M;
-    const float *pi;
-};
-
 __global__ void k_state_init(DevState s, int32_t *iters, uint8_t *conv) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < 2 && blockIdx.x == 0) s.count[f] = 0;
+    if (f < 4 && blockIdx.x == 0) s.count[f] = 0;
     if (f >= s.F) return;
     s.active[f] = 1;
     s.unsat[f] = 0;
     iters[f] = 0;
     conv[f] = 0;
     s.guards[f] = 0;
-}
-
-// A1 channel likelihood and A2 initialisation for column j of frame f:
-// L_j(a) = P(received | x_j = a) as a product over the p transmitted bits;
-// p_j = L_j (times the stationary Markov marginal pi for source symbols);
-// every edge of column j starts with q_e = p_j.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, BatchArgs b) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F;
-    const int nchunk = (F + GPB - 1) / GPB;
-    const int j = blockIdx.x / nchunk;
-    const int f = (blockIdx.x % nchunk) * GPB + threadIdx.x / Q;
-    const int a = threadIdx.x % Q;
-    if (f >= F) return;
-    const size_t fj = size_t(f) * c.n + j;
-    double v = 1.0;
-    if (b.channel == GFBP_CH_BSC) {
-        const int rx = b.rx[fj];
-        const double fl = b.param[f];
-#pragma unroll
-        for (int t = 0; t < P; ++t) v *= (((a ^ rx) >> t) & 1) ? fl : (1.0 - fl);
-    } else if (b.channel == GFBP_CH_BEC) {
-        const int rx = b.rx[fj], er = b.erasure[fj];
-#pragma unroll
-        for (int t = 0; t < P; ++t) v *= ((er >> t) & 1) ? 0.5 : ((((a ^ rx) >> t) & 1) ? 0.0 : 1.0);
-    } else if (b.channel == GFBP_CH_BIAWGN) {
-        const double sg = b.param[f];
-        const double g = 2.0 / (sg * sg);
-#pragma unroll
-        for (int t = 0; t < P; ++t) {
-            const double yb = b.y[fj * P + t];
-            v *= ((a >> t) & 1) ? 1.0 / (1.0 + exp(g * yb)) : 1.0 / (1.0 + exp(-g * yb));
-        }
-    } else {
-        v = b.lik[fj * Q + a];
-    }
-    const double Lv = grp_normalise<P>(v, s.guards, f, a);
-    s.L[(size_t(j) * F + f) * Q + a] = float(Lv);
-    double pv = Lv;
-    if (b.markov && j < c.n_info) {
-        pv = grp_normalise<P>(double(float(Lv)) * double(b.pi[a]), s.guards, f, a);
-        s.Pr[(size_t(j) * F + f) * Q + a] = float(pv);
-    }
-    const float pf = float(pv);
-    for (int t = c.col_ptr[j]; t < c.col_ptr[j + 1]; ++t) s.Qm[(size_t(c.col_edge[t]) * F + f) * Q + a] = pf;
-}
-
-// Transform of the weighted-symbol distribution q~(y) = q(h^-1 y) of one
-// edge, read straight from the permuted address.
-template <int P>
-__device__ __forceinline__ double load_transformed(const float *Qm, size_t vec, uint64_t hinv, int y) {
-    return wht<P>(double(Qm[vec + gf_apply<P>(hinv, y)]), y);
-}
-
-// A3, parallel schedule: all r of check i from the previous iteration's q.
-// Lane y ends with S(y), the XOR-convolution of the other siblings'
-// weighted-symbol distributions, and stores it as r(a) at a = h^-1 (y + z).
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const uint8_t *z, Snap snap) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F;
-    const int nchunk = (F + GPB - 1) / GPB;
-    const int i = blockIdx.x / nchunk;
-    const int f = (blockIdx.x % nchunk) * GPB + threadIdx.x / Q;
-    const int y = threadIdx.x % Q;
-    if (f >= F || !s.active[f]) return;
-    const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
-    const int zi = z ? z[size_t(f) * c.m + i] : 0;
-    double W[kDcMax], pre[kDcMax];
-#pragma unroll
-    for (int d = 0; d < kDcMax; ++d)
-        if (d < dc) W[d] = load_transformed<P>(s.Qm, (size_t(rs + d) * F + f) * Q, c.emap[2 * (rs + d)], y);
-    double acc = 1.0;
-#pragma unroll
-    for (int d = 0; d < kDcMax; ++d)
-        if (d < dc) { pre[d] = acc; acc *= W[d]; }
-    double suf = 1.0;
-#pragma unroll
-    for (int d = kDcMax - 1; d >= 0; --d) {
-        if (d < dc) {
-            const double S = wht<P>(pre[d] * suf, y) * (1.0 / double(Q));
-            suf *= W[d];
-            const float r = float(fmax(S, 0.0));
-            const int a = gf_apply<P>(c.emap[2 * (rs + d)], y ^ zi);
-            s.R[(size_t(rs + d) * F + f) * Q + a] = r;
-            if (snap.r) snap.r[(size_t(f) * c.E + rs + d) * Q + a] = r;
-        }
-    }
-}
-
-// A4 variable-node update of column j from its r-messages r[0..dv): the
-// pseudo-posterior Q_j (Eq. eq_Q) and its decision, then each edge's q
-// (Eq. eq_q), normalised.  Products in float64, stored as float32.
-template <int P>
-__device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, int j, int f, int a,
-                                                const double *r, int cs, int dv, int markov, int wantQ,
-                                                const Snap &snap) {
-    constexpr int Q = 1 << P;
-    const int F = s.F;
-    const size_t jf = (size_t(j) * F + f) * Q + a;
-    const double pv = (markov && j < c.n_info) ? s.Pr[jf] : s.L[jf];
-    double pre[kDvMax];
-    double acc = pv;
-#pragma unroll
-    for (int d = 0; d < kDvMax; ++d)
-        if (d < dv) { pre[d] = acc; acc *= r[d]; }
-    const float Qf = float(grp_normalise<P>(acc, s.guards, f, a));
-    if (wantQ) s.Qp[jf] = Qf;
-    const int x = grp_argmax<P>(Qf, a);
-    if (a == 0) s.xh[size_t(j) * F + f] = uint8_t(x);
-    double suf = 1.0;
-#pragma unroll
-    for (int d = kDvMax - 1; d >= 0; --d) {
-        if (d < dv) {
-            const float qn = float(grp_normalise<P>(pre[d] * suf, s.guards, f, a));
-            suf *= r[d];
-            const int e = c.col_edge[cs + d];
-            s.Qm[(size_t(e) * F + f) * Q + a] = qn;
-            if (snap.q) snap.q[(size_t(f) * c.E + e) * Q + a] = qn;
-        }
-    }
-}
-
-// A4, parallel schedule: every column from this iteration's r.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int markov, int wantQ, Snap snap) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F;
-    const int nchunk = (F + GPB - 1) / GPB;
-    const int j = blockIdx.x / nchunk;
-    const int f = (blockIdx.x % nchunk) * GPB + threadIdx.x / Q;
-    const int a = threadIdx.x % Q;
-    if (f >= F || !s.active[f]) return;
-    const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
-    double r[kDvMax];
-#pragma unroll
-    for (int d = 0; d < kDvMax; ++d)
-        if (d < dv) r[d] = s.R[(size_t(c.col_edge[cs + d]) * F + f) * Q + a];
-    variable_update<P>(c, s, j, f, a, r, cs, dv, markov, wantQ, snap);
-}
-
-// A6 sequential schedule, the step for one column j of frame f: the r of
-// column j's edges from the siblings' current q (partial horizontal pass),
-// then column j's q and pseudo-posterior (partial vertical pass).
-template <int P>
-__device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, int j, int f,
-                                           int k, int markov, int wantQ, const Snap &snap) {
-    constexpr int Q = 1 << P;
-    const int F = s.F;
-    const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
-    double r[kDvMax];
-#pragma unroll
-    for (int d = 0; d < kDvMax; ++d) {
-        if (d < dv) {
-            const int e = c.col_edge[cs + d];
-            const int i = c.edge_row[e];
-            const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
-            const int zi = z ? z[size_t(f) * c.m + i] : 0;
-            double acc = 1.0;
-#pragma unroll
-            for (int t = 0; t < kDcMax; ++t)
-                if (t < dc && rs + t != e)
-                    acc *= load_transformed<P>(s.Qm, (size_t(rs + t) * F + f) * Q, c.emap[2 * (rs + t)], k);
-            const double S = wht<P>(acc, k) * (1.0 / double(Q));
-            // r(a) = S(z + h a): lane a reads lane z ^ (h a)
-            const double rv = fmax(grp_gather<P>(S, zi ^ gf_apply<P>(c.emap[2 * e + 1], k)), 0.0);
-            r[d] = double(float(rv));
-            if (snap.r) snap.r[(size_t(f) * c.E + e) * Q + k] = float(rv);
-        }
-    }
-    variable_update<P>(c, s, j, f, k, r, cs, dv, markov, wantQ, snap);
-}
-
-// A6, strict order: one iteration for the frames of this group, columns in
-// order 0..n-1.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
-                                                       int wantQ, Snap snap) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F;
-    const int f = blockIdx.x * GPB + threadIdx.x / Q;
-    const int k = threadIdx.x % Q;
-    if (f >= F || !s.active[f]) return;
-    for (int j = 0; j < c.n; ++j) sus_column<P>(c, s, z, j, f, k, markov, wantQ, snap);
-}
-
-// A6, one dependency level: the columns cols[0..ncols) share no check, so
-// their steps commute; each runs exactly as in the strict order.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov, int wantQ,
-                                                      Snap snap, const int32_t *cols) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F;
-    const int nchunk = (F + GPB - 1) / GPB;
-    const int j = cols[blockIdx.x / nchunk];
-    const int f = (blockIdx.x % nchunk) * GPB + threadIdx.x / Q;
-    const int k = threadIdx.x % Q;
-    if (f >= F || !s.active[f]) return;
-    sus_column<P>(c, s, z, j, f, k, markov, wantQ, snap);
 }
 
 // A5 convergence test: check i of frame f against z_i.
@@ -368,14 +156,14 @@ __global__ __launch_bounds__(kBlock) void k_syndrome(DevCode c, DevState s, cons
     if (f >= F || !s.active[f]) return;
     int acc = 0;
     for (int e = c.row_ptr[i]; e < c.row_ptr[i + 1]; ++e)
-        acc ^= c.mul[c.coef[e] * c.q + s.xh[size_t(c.col[e]) * F + f]];
+        acc ^= c.mul[c.coef[e] * c.q + s.xh[size_t(c.col[e]) * s.Fp + f]];
     if (acc != (z ? z[size_t(f) * c.m + i] : 0)) s.unsat[f] = 1;
 }
 
 // A5 retirement after iteration t.
 __global__ void k_retire(DevState s, int t, int max_iter, int early_stop, int32_t *iters, uint8_t *conv) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f == 0) s.count[(t + 1) & 1] = 0;
+    if (f == 0) s.count[2 * ((t + 1) & 1)] = 0;
     if (f >= s.F) return;
     if (s.active[f]) {
         const bool ok = s.unsat[f] == 0;
@@ -384,7 +172,7 @@ __global__ void k_retire(DevState s, int t, int max_iter, int early_stop, int32_
             s.active[f] = 0;
             if (!conv[f]) iters[f] = max_iter;
         } else {
-            atomicAdd(&s.count[t & 1], 1u);
+            atomicAdd(&s.count[2 * (t & 1)], 1u);
         }
     }
     s.unsat[f] = 0;
@@ -420,29 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
     s.Pr[kf] = float(grp_normalise<P>(double(s.L[kf]) * Pk, s.guards, f, b));
 }
 
-__global__ void k_out_xhat(const uint8_t *xh, int n, int F, uint8_t *out) {
+__global__ void k_out_xhat(const uint8_t *xh, int n, int F, int Fp, uint8_t *out) {
     const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= size_t(n) * F) return;
     const int f = int(t / n), j = int(t % n);
-    out[t] = xh[size_t(j) * F + f];
-}
-
-__global__ void k_out_vectors(const float *src, int n, int F, int Q, float *out) {
-    // src [n][F][Q] -> out [F][n][Q]
-    const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= size_t(n) * F * Q) return;
-    const int a = int(t % Q);
-    const size_t fj = t / Q;
-    const int f = int(fj / n), j = int(fj % n);
-    out[t] = src[(size_t(j) * F + f) * Q + a];
+    out[t] = xh[size_t(j) * Fp + f];
 }
 
 // ---------------------------------------------------------------- dispatch
-inline unsigned nblocks_nodes(int nodes, int F, int Q) {
-    const int GPB = kBlock / Q;
-    return unsigned(nodes) * unsigned((F + GPB - 1) / GPB);
-}
-
 // Algorithmic HBM bytes per frame of each iteration kernel (float32 messages).
 struct Bytes {
     double check, variable, sequential, syndrome, markov;
@@ -460,24 +233,94 @@ Bytes bytes_per_frame(const gfbp_code *code, int needQ, int has_z) {
     return b;
 }
 
-template <int P>
+// Kernel shape for a code: entries per lane EL = min(q, 8), or min(q, 4) for
+// rows longer than 8 (the check keeps every sibling's transform in
+// registers); DCM / DVM bound the row / column degree.
+struct Shape {
+    int lg, dcm, dvm;
+};
+
+inline Shape shape_of(const gfbp_code *code) {
+    const int p = code->info.p, dc = code->info.max_row_degree, dv = code->info.max_col_degree;
+    Shape sh;
+    sh.dcm = dc <= 6 ? 6 : (dc <= 8 ? 8 : 16);
+    sh.dvm = dv <= 4 ? 4 : 8;
+    if (sh.dcm == 6 && sh.dvm == 8) sh.dcm = 8;
+    const int lel = std::min(p, sh.dcm == 16 ? 2 : 3);
+    sh.lg = p - lel;
+    return sh;
+}
+
+// Frame stride of the workspace arrays: whole 64-frame tiles.
+inline int frame_stride(int F) { return (F + kWave - 1) / kWave * kWave; }
+
+inline unsigned tiled_blocks(int nodes, const DevState &s) {
+    const long long waves = (long long)nodes * s.nact;
+    return unsigned(std::max<long long>(1, (waves + (kBlock / kWave) - 1) / (kBlock / kWave)));
+}
+
+template <int P, int LG, int DCM, int DVM>
+struct TiledLaunch {
+    static void init(hipStream_t st, const DevCode &c, const DevState &s, const gfbp_batch *b) {
+        tiled::Chan ch{b->channel, b->prior == GFBP_PRIOR_MARKOV, b->rx, b->erasure, b->y, b->likelihood, b->param,
+                       b->markov_pi};
+        hipLaunchKernelGGL((tiled::k_init<P, LG>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
+    }
+    static void check(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, Snap sn) {
+        hipLaunchKernelGGL((tiled::k_check<P, LG, DCM>), dim3(tiled_blocks(c.m, s)), dim3(kBlock), 0, st, c, s,
+                           z, sn);
+    }
+    static void variable(hipStream_t st, const DevCode &c, const DevState &s, int markov, int wantQ, Snap sn) {
+        hipLaunchKernelGGL((tiled::k_variable<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c,
+                           s, markov, wantQ, sn);
+    }
+    static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+                          Snap sn, const int32_t *cols, int nc) {
+        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DVM>), dim3(tiled_blocks(nc, s)), dim3(kBlock), 0, st, c,
+                           s, z, markov, wantQ, sn, cols, nc);
+    }
+    static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
+                           int wantQ, Snap sn) {
+        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DVM>), dim3(tiled_blocks(1, s)), dim3(kBlock), 0, st, c,
+                           s, z, markov, wantQ, sn);
+    }
+    static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
+        hipLaunchKernelGGL((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
+                           M, pi);
+    }
+    static constexpr int TF = kWave >> LG;
+    static void tiles(hipStream_t st, const DevState &s, int t) {
+        hipLaunchKernelGGL(tiled::k_tiles, dim3(1), dim3(1024), 0, st, s, TF, t);
+    }
+    static void vectors(hipStream_t st, const float *src, int n, const DevState &s, float *out) {
+        const size_t tot = size_t(n) * s.F * (1 << P);
+        hipLaunchKernelGGL((tiled::k_out_vectors<P, LG>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, src, n,
+                           s.F, s.Fp, out);
+    }
+};
+
+template <int P, class K>
 gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s,
                       hipStream_t st, int needQ) {
     constexpr int Q = 1 << P;
     const DevCode &c = code->dev;
     const int F = s.F;
-    BatchArgs args{b->channel, b->param, b->rx, b->erasure, b->y, b->likelihood, b->syndrome,
-                   b->prior == GFBP_PRIOR_MARKOV, b->markov_M, b->markov_pi};
     const unsigned fb = unsigned((F + kBlock - 1) / kBlock);
     const Bytes bpf = bytes_per_frame(code, needQ, b->syndrome != nullptr);
     const double eq_frame = double(c.E) * Q;
     Tracer tr(st);
     hipLaunchKernelGGL(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, out->iters, out->converged);
+    const int ntiles = s.Fp / K::TF;
+    K::tiles(st, s, 0);
+    // k_tiles(0) lists exactly the tiles holding a frame: ceil(F / TF) of them
+    // (ntiles can be larger: the stride is padded to whole 64-frame tiles).
+    s.act = s.tiles;
+    s.nact = (F + K::TF - 1) / K::TF;
     tr.begin();
-    hipLaunchKernelGGL(k_init<P>, dim3(nblocks_nodes(c.n, F, Q)), dim3(kBlock), 0, st, c, s, args);
+    K::init(st, c, s, b);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
     HIP_TRY(hipGetLastError());
-    const int markov = args.markov && c.n_info > 0;
+    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
     uint32_t running = uint32_t(F);
     for (int t = 1; t <= b->max_iter; ++t) {
         const bool snap_now = (t == out->snap_iter);
@@ -486,36 +329,27 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         const double Fa = running;
         if (b->schedule == GFBP_PUS) {
             tr.begin();
-            hipLaunchKernelGGL(k_check<P>, dim3(nblocks_nodes(c.m, F, Q)), dim3(kBlock), 0, st, c, s,
-                               b->syndrome, sn);
+            K::check(st, c, s, b->syndrome, sn);
             tr.end(K_CHECK, Fa * bpf.check, Fa * eq_frame);
             tr.begin();
-            hipLaunchKernelGGL(k_variable<P>, dim3(nblocks_nodes(c.n, F, Q)), dim3(kBlock), 0, st, c, s, markov,
-                               wantQ, sn);
+            K::variable(st, c, s, markov, wantQ, sn);
             tr.end(K_VARIABLE, Fa * bpf.variable, Fa * eq_frame);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
-            const int GPB = kBlock / Q;
             tr.begin();
-            hipLaunchKernelGGL(k_sequential<P>, dim3((F + GPB - 1) / GPB), dim3(kBlock), 0, st, c, s, b->syndrome,
-                               markov, wantQ, sn);
+            K::sequential(st, c, s, b->syndrome, markov, wantQ, sn);
             tr.end(K_SEQUENTIAL, Fa * bpf.sequential, Fa * eq_frame);
         } else {
             const int nlev = int(code->level_ptr.size()) - 1;
             for (int l = 0; l < nlev; ++l) {
                 const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
                 tr.begin();
-                hipLaunchKernelGGL(k_sus_level<P>, dim3(nblocks_nodes(nc, F, Q)), dim3(kBlock), 0, st, c, s,
-                                   b->syndrome, markov, wantQ, sn, code->level_cols + c0);
+                K::sus_level(st, c, s, b->syndrome, markov, wantQ, sn, code->level_cols + c0, nc);
                 tr.end(K_SUS_LEVEL,
                        Fa * (4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1)),
                        Fa * code->level_edges[l] * Q);
             }
         }
-        if (snap_now && out->snap_Q) {
-            const size_t tot = size_t(c.n) * F * Q;
-            hipLaunchKernelGGL(k_out_vectors, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, s.Qp, c.n, F, Q,
-                               out->snap_Q);
-        }
+        if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
         tr.begin();
         hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, b->syndrome);
         tr.end(K_SYNDROME, Fa * bpf.syndrome, 0);
@@ -523,28 +357,28 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                            out->converged);
         HIP_TRY(hipGetLastError());
         if (t == b->max_iter) break;
-        uint32_t left = 0;
-        HIP_TRY(hipMemcpyAsync(&left, s.count + (t & 1), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        K::tiles(st, s, t);
+        uint32_t cnt[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(cnt, s.count + 2 * (t & 1), sizeof cnt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        const uint32_t left = cnt[0];
         running = left;
         if (left == 0) break;
+        s.act = s.tiles + size_t(t & 1) * ntiles;
+        s.nact = int(cnt[1]);
         if (markov) {
             tr.begin();
-            hipLaunchKernelGGL(k_markov<P>, dim3(nblocks_nodes(c.n_info, F, Q)), dim3(kBlock), 0, st, c, s,
-                               b->markov_M, b->markov_pi);
+            K::markov(st, c, s, b->markov_M, b->markov_pi);
             tr.end(K_MARKOV, double(left) * bpf.markov, 0);
         }
     }
     tr.begin();
     {
         const size_t tot = size_t(c.n) * F;
-        hipLaunchKernelGGL(k_out_xhat, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, s.xh, c.n, F, out->xhat);
+        hipLaunchKernelGGL(k_out_xhat, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, s.xh, c.n, F, s.Fp,
+                           out->xhat);
     }
-    if (out->posterior) {
-        const size_t tot = size_t(c.n) * F * Q;
-        hipLaunchKernelGGL(k_out_vectors, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, s.Qp, c.n, F, Q,
-                           out->posterior);
-    }
+    if (out->posterior) K::vectors(st, s.Qp, c.n, s, out->posterior);
     tr.end(K_OUTPUT, double(F) * c.n * (2.0 + (out->posterior ? 8.0 * Q : 0.0)), 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
@@ -552,13 +386,25 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     return GFBP_OK;
 }
 
+template <int P>
+gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
+                    int needQ) {
+    const Shape sh = shape_of(code);
+    constexpr int L3 = P > 3 ? P - 3 : 0, L2 = P > 2 ? P - 2 : 0;
+    if (sh.dcm == 6) return run_batch<P, TiledLaunch<P, L3, 6, 4>>(code, b, out, s, st, needQ);
+    if (sh.dcm == 8 && sh.dvm == 4) return run_batch<P, TiledLaunch<P, L3, 8, 4>>(code, b, out, s, st, needQ);
+    if (sh.dcm == 8) return run_batch<P, TiledLaunch<P, L3, 8, 8>>(code, b, out, s, st, needQ);
+    return run_batch<P, TiledLaunch<P, L2, 16, 8>>(code, b, out, s, st, needQ);
+}
+
 // Workspace carving, shared by size query and decode.
 struct Carve {
-    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, guards, total;
+    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, total;
 };
 
-Carve carve(const gfbp_code *code, int F, int schedule, int prior) {
+Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     const size_t E = code->info.n_edges, n = code->info.n, K = code->info.n_info, Q = code->info.q;
+    const size_t F = size_t(frame_stride(F_));
     Carve c{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -568,10 +414,11 @@ Carve carve(const gfbp_code *code, int F, int schedule, int prior) {
     c.Pr = take(prior == GFBP_PRIOR_MARKOV ? K * F * Q * 4 : 0);
     c.Qp = take(n * F * Q * 4);
     c.xh = take(n * F);
-    c.unsat = take(size_t(F) * 4);
-    c.active = take(size_t(F));
-    c.count = take(8);
-    c.guards = take(size_t(F) * 4);
+    c.unsat = take(size_t(F_) * 4);
+    c.active = take(size_t(F_));
+    c.count = take(16);
+    c.tiles = take(2 * F * 4);
+    c.guards = take(size_t(F_) * 4);
     c.total = off;
     return c;
 }
@@ -804,17 +651,19 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
     s.unsat = reinterpret_cast<uint32_t *>(w + cv.unsat);
     s.active = reinterpret_cast<uint8_t *>(w + cv.active);
     s.count = reinterpret_cast<uint32_t *>(w + cv.count);
+    s.tiles = reinterpret_cast<int32_t *>(w + cv.tiles);
     s.guards = out->guards ? out->guards : reinterpret_cast<int32_t *>(w + cv.guards);
     s.F = F;
+    s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (code->info.p) {
-        case 1: return run_batch<1>(code, b, out, s, st, needQ);
-        case 2: return run_batch<2>(code, b, out, s, st, needQ);
-        case 3: return run_batch<3>(code, b, out, s, st, needQ);
-        case 4: return run_batch<4>(code, b, out, s, st, needQ);
-        case 5: return run_batch<5>(code, b, out, s, st, needQ);
-        case 6: return run_batch<6>(code, b, out, s, st, needQ);
+        case 1: return run_any<1>(code, b, out, s, st, needQ);
+        case 2: return run_any<2>(code, b, out, s, st, needQ);
+        case 3: return run_any<3>(code, b, out, s, st, needQ);
+        case 4: return run_any<4>(code, b, out, s, st, needQ);
+        case 5: return run_any<5>(code, b, out, s, st, needQ);
+        case 6: return run_any<6>(code, b, out, s, st, needQ);
         default: return fail(GFBP_EUNSUPPORTED, "bad field");
     }
 }

@@ -51,9 +51,13 @@ struct DevState {
     uint8_t *xh;      // [n][F] decisions
     uint32_t *unsat;  // [F] some check unsatisfied in this iteration
     uint8_t *active;  // [F] frame still iterating
-    uint32_t *count;  // [2] frames still iterating, by iteration parity
+    uint32_t *count;  // [2][2] by iteration parity: frames still iterating, tiles holding them
     int32_t *guards;  // [F]
-    int F;
+    int32_t *tiles;   // [2][ntiles] tiles with a running frame, by iteration parity
+    int F;            // frames
+    int Fp;           // frame stride (whole 64-frame tiles)
+    int nact;         // length of the current tile list
+    const int32_t *act;  // current tile list
 };
 
 struct Snap {
