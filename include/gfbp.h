@@ -5,8 +5,8 @@
  * Method: Yacov, Efraim, Kfir, Kanter, Shental, "Parallel vs. Sequential
  * Belief Propagation Decoding of LDPC Codes over GF(q) and Markov Sources",
  * Section 2.  The decoder solves H x = z for x over GF(q) given per-symbol
- * channel evidence and priors, by the message passing of Eqs. (eq_r)
- * (check-to-variable r), (eq_q) (variable-to-check q) and (eq_Q)
+ * channel evidence and priors, by the message passing of Eqs. (3)
+ * (check-to-variable r), (4) (variable-to-check q) and (5)
  * (pseudo-posterior Q, clipped to a decision), under either
  *   - the parallel updating scheme (PUS): all r from the previous
  *     iteration's q, then all q; or
@@ -14,7 +14,7 @@
  *     r of column j's edges from the current q, then column j's q.
  * After each iteration the decision is tested against H x = z.  With a Markov
  * source, the priors of the information symbols are re-estimated after every
- * iteration by the dynamical block prior of Eq. (prior2).
+ * iteration by the dynamical block prior of Eq. (7).
  *
  * Conventions shared by every call:
  *   - GF(2^p) in the polynomial basis of a primitive polynomial (bit b of a
@@ -63,7 +63,7 @@ typedef int32_t gfbp_status;
 
 /* priors of the information symbols (columns 0..n_info-1) */
 #define GFBP_PRIOR_UNIFORM 0 /* i.i.d. uniform source: prior 1/q                  */
-#define GFBP_PRIOR_MARKOV 1  /* first-order Markov source, Eq. (prior2)           */
+#define GFBP_PRIOR_MARKOV 1  /* first-order Markov source, Eq. (7)           */
 
 /* Limits of the decoding kernels. */
 #define GFBP_MAX_Q 64
@@ -150,7 +150,7 @@ typedef struct {
 /* Bytes of device workspace gfbp_decode_batch needs for F frames. */
 size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t schedule, int32_t prior);
 
-/* Decode a batch (Section 2, PUS or SUS; Eq. (prior2) priors when asked).
+/* Decode a batch (Section 2, PUS or SUS; Eq. (7) priors when asked).
  * workspace: device memory of at least gfbp_workspace_size() bytes, 256-byte
  * aligned, owned by the caller, clobbered.  stream: a hipStream_t (NULL =
  * default stream).  All work is enqueued on the stream; the call returns after

@@ -110,7 +110,7 @@ def frame_likelihoods(code, frames) -> np.ndarray:
 
 
 def check_update(p: int, poly: int, h, z: int, qin: np.ndarray) -> np.ndarray:
-    """All r-messages of one check (Eq. eq_r) from its q-messages qin[dc][q]."""
+    """All r-messages of one check (Eq. (3)) from its q-messages qin[dc][q]."""
     h = np.ascontiguousarray(h, dtype=np.uint8)
     qin = np.ascontiguousarray(qin, dtype=np.float64)
     out = np.zeros_like(qin)

@@ -17,23 +17,23 @@
  *   ref_likelihood .......... BSC noise prior f^L (1-f)^(p-L) of Section 2,
  *                             taken about the received symbol; BEC and BI-AWGN
  *                             as bit-wise products (Section 3 channels)
- *   check update ............ Eq. (eq_r): sum, over sibling configurations
+ *   check update ............ Eq. (3): sum, over sibling configurations
  *                             that satisfy check i with x_j = a, of the
  *                             product of sibling q-messages, accumulated one
  *                             sibling at a time (distributivity only)
- *   variable update ......... Eq. (eq_q), normalised
- *   pseudo-posterior ........ Eq. (eq_Q), normalised, then clipped (argmax)
+ *   variable update ......... Eq. (4), normalised
+ *   pseudo-posterior ........ Eq. (5), normalised, then clipped (argmax)
  *   parallel schedule ....... Section 2, PUS: all r from the previous
  *                             iteration's q, then all q
  *   sequential schedule ..... Section 2, SUS steps 1-4: per column, partial
  *                             horizontal pass then partial vertical pass
  *   stopping ................ Section 2: test H x = z after each iteration
- *   Markov prior ............ Eq. (prior2), the paper's O(q) form of
- *                             Eq. (eq_prior1), refreshed after each iteration
+ *   Markov prior ............ Eq. (7), the paper's O(q) form of
+ *                             Eq. (6), refreshed after each iteration
  *
  * Readings taken where the paper is silent (also listed in the design notes):
  *   - all sums over symbols run over the q field elements 0..q-1;
- *   - r is left unnormalised, as Eq. (eq_r) states it;
+ *   - r is left unnormalised, as Eq. (3) states it;
  *   - a zero or non-finite normaliser makes the vector uniform and counts a
  *     guard event;
  *   - the clipping decision is taken on the posterior rounded to float32
@@ -142,7 +142,7 @@ void ref_frame_likelihoods(int p, int channel, int F, int n, const double *param
         }
 }
 
-/* Eq. (eq_r) for edge d of a check with dc edges (coefficients h, syndrome z),
+/* Eq. (3) for edge d of a check with dc edges (coefficients h, syndrome z),
  * from the q-messages qin[dc][q]: sum over configurations of the other dc-1
  * symbols such that  h_d a + sum_{d' != d} h_d' x_d' = z.  The sum is taken
  * one sibling at a time: D(y) is the total weight of the siblings handled so
@@ -186,7 +186,7 @@ static int normalise(double *v, int q)
     return 0;
 }
 
-/* Eq. (prior2) over a chain of K source symbols: P_k(b) is proportional to
+/* Eq. (7) over a chain of K source symbols: P_k(b) is proportional to
  * [sum_a Q_{k-1}(a) M(a,b)] [sum_c M(b,c) Q_{k+1}(c)], with pi in place of the
  * left factor at k = 0 and 1 in place of the right factor at k = K-1. */
 int ref_markov_prior(int q, int K, const double *Q, const double *M, const double *pi, double *P)
@@ -294,7 +294,7 @@ static void update_r(const ref_field *F, const ref_code *C, const ref_graph *G, 
     check_edge(F, dc, scratch_h, z ? z[i] : 0, scratch_q, e - rs, rm + (size_t)e * q);
 }
 
-/* q-message of edge e, Eq. (eq_q) */
+/* q-message of edge e, Eq. (4) */
 static int update_q(int q, const ref_graph *G, int j, int e, const double *pj, const double *rm, double *qm)
 {
     double *out = qm + (size_t)e * q;
@@ -309,7 +309,7 @@ static int update_q(int q, const ref_graph *G, int j, int e, const double *pj, c
     return normalise(out, q);
 }
 
-/* pseudo-posterior of column j, Eq. (eq_Q) */
+/* pseudo-posterior of column j, Eq. (5) */
 static int posterior(int q, const ref_graph *G, int j, const double *pj, const double *rm, double *Q)
 {
     double *out = Q + (size_t)j * q;

@@ -8,7 +8,7 @@ library.  If the library is missing the binding raises: there is no fallback.
 
 Method: Yacov et al., "Parallel vs. Sequential Belief Propagation Decoding of
 LDPC Codes over GF(q) and Markov Sources", Section 2 (schedules PUS and SUS,
-Eqs. (eq_r), (eq_q), (eq_Q), dynamical Markov block priors Eq. (prior2)).
+Eqs. (3), (4), (5), dynamical Markov block priors Eq. (7)).
 """
 from __future__ import annotations
 

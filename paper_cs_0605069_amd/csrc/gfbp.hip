@@ -178,36 +178,6 @@ __global__ void k_retire(DevState s, int t, int max_iter, int early_stop, int32_
     s.unsat[f] = 0;
 }
 
-// A7 dynamical block prior (Eq. prior2) for source symbol k of frame f, from
-// this iteration's pseudo-posteriors of its chain neighbours; the result is
-// multiplied into the channel likelihood for the next iteration.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi) {
-    constexpr int Q = 1 << P, GPB = kBlock / Q;
-    const int F = s.F, K = c.n_info;
-    const int nchunk = (F + GPB - 1) / GPB;
-    const int k = blockIdx.x / nchunk;
-    const int f = (blockIdx.x % nchunk) * GPB + threadIdx.x / Q;
-    const int b = threadIdx.x % Q;
-    if (f >= F || !s.active[f]) return;
-    double u = 0.0, v = 0.0;
-    if (k == 0) {
-        u = pi[b];
-    } else {
-        const float *Qm1 = s.Qp + (size_t(k - 1) * F + f) * Q;
-        for (int a = 0; a < Q; ++a) u += double(Qm1[a]) * double(M[a * Q + b]);
-    }
-    if (k == K - 1) {
-        v = 1.0;
-    } else {
-        const float *Qp1 = s.Qp + (size_t(k + 1) * F + f) * Q;
-        for (int cc = 0; cc < Q; ++cc) v += double(M[b * Q + cc]) * double(Qp1[cc]);
-    }
-    const double Pk = grp_normalise<P>(u * v, s.guards, f, b);
-    const size_t kf = (size_t(k) * F + f) * Q + b;
-    s.Pr[kf] = float(grp_normalise<P>(double(s.L[kf]) * Pk, s.guards, f, b));
-}
-
 __global__ void k_out_xhat(const uint8_t *xh, int n, int F, int Fp, uint8_t *out) {
     const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= size_t(n) * F) return;
@@ -455,7 +425,7 @@ extern "C" {
 
 const char *gfbp_last_error(void) { return g_err.c_str(); }
 
-const char *gfbp_version(void) { return "gfbp 0.3 (gfx950)"; }
+const char *gfbp_version(void) { return "gfbp 0.4 (gfx950)"; }
 
 gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (!d || !out) return fail(GFBP_EINVAL, "null argument");

@@ -10,7 +10,7 @@
 // frame and a the field element, messages kept as probabilities in float32
 // (which holds small probabilities to full relative precision).
 //
-// Check-node arithmetic (Eq. (eq_r)): with y = h x the weighted symbol of an
+// Check-node arithmetic (Eq. (3)): with y = h x the weighted symbol of an
 // edge, the check constraint is an XOR-sum of the y's, so the sum over
 // configurations is an XOR-convolution of the siblings' distributions of y,
 // q~(y) = q(h^-1 y).  The Walsh-Hadamard transform (WHT) turns XOR-convolution

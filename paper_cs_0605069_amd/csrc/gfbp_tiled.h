@@ -17,7 +17,7 @@
 // so that, for a fixed entry a, the TF frames of a wavefront are adjacent.
 // Loads and stores of entry a for a wavefront touch G runs of TF*4 bytes.
 //
-// Check node (Eq. (eq_r)).  With y = h x the weighted symbol of an edge, a
+// Check node (Eq. (3)).  With y = h x the weighted symbol of an edge, a
 // check constrains the XOR-sum of the y's, so the sum over configurations is
 // the XOR-convolution of the siblings' distributions q~(y) = q(h^-1 y).  The
 // Walsh-Hadamard transform (WHT) turns that into a pointwise product.  The
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
 }
 
 // A4 variable-node update of column j from its r-messages r[d][.]: the
-// pseudo-posterior Q_j (Eq. eq_Q) and its decision, then each edge's q
-// (Eq. eq_q), normalised.
+// pseudo-posterior Q_j (Eq. (5)) and its decision, then each edge's q
+// (Eq. (4)), normalised.
 template <int P, int LG, int DVM>
 __device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, const Item &it, int ntiles,
                                                 int j, const float (*r)[Geo<P, LG>::EL], int cs, int dv, int markov,
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_sequential(DevCode c, DevState s, co
     for (int j = 0; j < c.n; ++j) sus_column<P, LG, DVM>(c, s, z, it, ntiles, j, markov, wantQ, snap, mine);
 }
 
-// A7 dynamical block prior (Eq. prior2) for source symbol k: from this
+// A7 dynamical block prior (Eq. (7)) for source symbol k: from this
 // iteration's pseudo-posteriors of its chain neighbours, multiplied into the
 // channel likelihood for the next iteration.
 template <int P, int LG>

@@ -2,10 +2,10 @@
 
 Each test ties the reference decoder to something other than itself: textbook
 field values and field axioms, the paper's closed-form BSC noise prior,
-brute-force enumeration of Eq. (eq_r), the textbook binary tanh rule, exact
+brute-force enumeration of Eq. (3), the textbook binary tanh rule, exact
 marginals of cycle-free graphs by enumeration of all solutions of H x = z, the
-forward-pass exactness of one sequential sweep on a chain, Eq. (eq_prior1)
-enumerated against the implemented Eq. (prior2), and invariants of the two
+forward-pass exactness of one sequential sweep on a chain, Eq. (6)
+enumerated against the implemented Eq. (7), and invariants of the two
 schedules.
 """
 import itertools
@@ -112,7 +112,7 @@ def test_biawgn_symbol_likelihood_factorises():
 
 # ------------------------------------------------------------------ check node
 def _brute_force_r(p, h, z, qin):
-    """Eq. (eq_r) enumerated literally: for every target d and value a, sum the
+    """Eq. (3) enumerated literally: for every target d and value a, sum the
     product of sibling messages over all sibling configurations with
     h_d a + sum h_s x_s = z."""
     q = 1 << p
@@ -386,8 +386,8 @@ def test_sequential_order_only_matters_between_columns_sharing_a_check(c1_small)
 
 
 # ------------------------------------------------------------------ Markov prior
-def test_markov_prior_matches_eq_prior1_enumerated():
-    """The implemented factorised form (prior2) against the double sum (eq_prior1)."""
+def test_markov_prior_matches_eq6_enumerated():
+    """The implemented factorised form (7) against the double sum (6)."""
     rng = np.random.default_rng(9)
     for q in [2, 4, 8]:
         K = 7
