@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="pus,sus")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shape instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: frames are independent and this decoder has no multi-GPU path "
@@ -104,6 +105,13 @@ def main():
                 "iters": torch.empty(FRAMES, dtype=torch.int32, device="cuda"),
                 "converged": torch.empty(FRAMES, dtype=torch.uint8, device="cuda"),
                 "guards": torch.empty(FRAMES, dtype=torch.int32, device="cuda")} for s in scheds}
+    shapes = {}
+    if not args.no_tune:
+        eb, d = dev_points[len(dev_points) // 2]
+        for s in scheds:
+            shapes[s] = gfbp.tune(dcode, d, schedule=s, trial_iters=3, workspace=ws[s], outputs=outs[s])
+    else:
+        shapes = {s: dcode.shape(s) for s in scheds}
     torch.cuda.synchronize()
 
     def step(record):
@@ -186,7 +194,8 @@ def main():
         "config": {"workload": f"GF({Q}) regular ({DV},{DC}) rate-1/2 LDPC, N={N_SYM} symbols, BI-AWGN "
                                f"Eb/N0 {EBN0[0]}-{EBN0[-1]} dB step 0.2, {FRAMES} frames per point, max {MAX_ITER} "
                                f"iterations, {'+'.join(s.upper() for s in scheds)}",
-                   "edges": code.E, "q": code.q, "frames_per_step": FRAMES * len(EBN0) * len(scheds)},
+                   "edges": code.E, "q": code.q, "frames_per_step": FRAMES * len(EBN0) * len(scheds),
+                   "entries_per_lane": shapes},
         "frames_per_s": len(rec) * FRAMES / wall,
         "schedules": per,
         "roofline": roof,

@@ -160,6 +160,23 @@ size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t sche
 gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- Kernel shape and its autotuner. ----
+ * The decoding kernels spread one frame's q-vector over G lanes with
+ * q/G "entries per lane" in registers (EL): a larger EL makes more of the
+ * Walsh-Hadamard butterflies register arithmetic, a smaller EL uses fewer
+ * registers (more wavefronts per compute unit).  EL in {2, 4, 8} (at most q;
+ * at most 4 for codes with rows longer than 6 or columns longer than 4).
+ * gfbp_code_set_shape fixes EL for one schedule (0 = default, the largest
+ * allowed); gfbp_code_get_shape returns the EL in use.  gfbp_tune times
+ * trial_iters fixed iterations of `batch` (same buffers and workspace as a
+ * decode; outputs are overwritten) with every allowed EL and keeps the
+ * fastest for batch->schedule, returned in *chosen.  These calls change the
+ * code handle: do not run them concurrently with decodes on the same code. */
+gfbp_status gfbp_code_set_shape(gfbp_code *code, int32_t schedule, int32_t entries_per_lane);
+int32_t gfbp_code_get_shape(const gfbp_code *code, int32_t schedule);
+gfbp_status gfbp_tune(gfbp_code *code, const gfbp_batch *batch, gfbp_result *out, void *workspace, size_t ws_bytes,
+                      void *stream, int32_t trial_iters, int32_t *chosen);
+
 /* ---- Tracing: per-kernel timing with HIP events on the decode stream. ----
  * Off by default.  When on, every kernel launch of gfbp_decode_batch is
  * bracketed by two HIP events on the caller's stream; after the decode's final

@@ -28,7 +28,8 @@ CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
 EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size", "gfbp_decode_batch",
-           "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_last_error", "gfbp_version")
+           "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
+           "gfbp_code_get_shape", "gfbp_tune", "gfbp_last_error", "gfbp_version")
 
 
 class CodeDesc(ctypes.Structure):
@@ -89,6 +90,13 @@ def lib():
     L.gfbp_profile_reset.restype = ctypes.c_int32
     L.gfbp_profile_read.argtypes = [ctypes.POINTER(KernelStats), ctypes.c_int32]
     L.gfbp_profile_read.restype = ctypes.c_int32
+    L.gfbp_code_set_shape.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    L.gfbp_code_set_shape.restype = ctypes.c_int32
+    L.gfbp_code_get_shape.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.gfbp_code_get_shape.restype = ctypes.c_int32
+    L.gfbp_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
+                            ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.gfbp_tune.restype = ctypes.c_int32
     L.gfbp_last_error.restype = ctypes.c_char_p
     L.gfbp_version.restype = ctypes.c_char_p
     _lib = L
@@ -180,6 +188,12 @@ class DeviceCode:
     def E(self):
         return self.info.n_edges
 
+    def set_shape(self, schedule, entries_per_lane: int):
+        _check(lib().gfbp_code_set_shape(self.handle, SCHEDULES[schedule], int(entries_per_lane)), "gfbp_code_set_shape")
+
+    def shape(self, schedule) -> int:
+        return int(lib().gfbp_code_get_shape(self.handle, SCHEDULES[schedule]))
+
     def workspace_size(self, n_frames: int, schedule, prior: int = PRIOR_UNIFORM) -> int:
         return int(lib().gfbp_workspace_size(self.handle, int(n_frames), SCHEDULES[schedule], int(prior)))
 
@@ -210,7 +224,7 @@ def frames_to_device(frames, device="cuda"):
 def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
-                 sus_strict: bool = False) -> dict:
+                 sus_strict: bool = False, tune_iters: int = 0) -> dict:
     """``gfbp_decode_batch`` on device tensors; returns device tensors.
 
     dframes: dict from :func:`frames_to_device` (or with the same keys).
@@ -252,6 +266,18 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
                _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
                _dptr(out.get("snap_Q")))
     st = torch.cuda.current_stream() if stream is None else stream
+    if tune_iters:
+        chosen = ctypes.c_int32(0)
+        _check(lib().gfbp_tune(dcode.handle, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(), workspace.numel(),
+                               ctypes.c_void_p(st.cuda_stream), int(tune_iters), ctypes.byref(chosen)), "gfbp_tune")
+        out["entries_per_lane"] = int(chosen.value)
+        return out
     _check(lib().gfbp_decode_batch(dcode.handle, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(),
                                    workspace.numel(), ctypes.c_void_p(st.cuda_stream)), "gfbp_decode_batch")
     return out
+
+
+def tune(dcode: DeviceCode, dframes: dict, schedule="pus", trial_iters: int = 3, **kw) -> int:
+    """``gfbp_tune``: time every allowed kernel shape on this batch and keep the
+    fastest for the schedule; returns the chosen entries per lane."""
+    return decode_batch(dcode, dframes, schedule=schedule, tune_iters=trial_iters, **kw)["entries_per_lane"]

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -49,6 +50,7 @@ struct gfbp_code {
     std::vector<double> level_sibs;   // per level: sibling vectors read (sum over its edges of d_c - 1)
     std::vector<double> level_edges;  // per level: edges
     const int32_t *level_cols = nullptr;  // device [n]
+    int el[2] = {0, 0};   // entries per lane chosen for PUS / SUS (0 = default)
     void *mem = nullptr;  // one device allocation holding every array of dev
 };
 
@@ -203,21 +205,38 @@ Bytes bytes_per_frame(const gfbp_code *code, int needQ, int has_z) {
     return b;
 }
 
-// Kernel shape for a code: entries per lane EL = min(q, 8), or min(q, 4) for
-// rows longer than 8 (the check keeps every sibling's transform in
-// registers); DCM / DVM bound the row / column degree.
+// Kernel shape for a code and schedule.  Degree class "small" (rows <= 6,
+// columns <= 4) keeps up to 6 siblings' transforms in registers and allows
+// EL = 2, 4 or 8 entries per lane; the general class (rows <= 16, columns <= 8)
+// allows EL = 2 or 4.  The default is the largest allowed EL (at most q);
+// gfbp_code_set_shape / gfbp_tune choose another.
 struct Shape {
-    int lg, dcm, dvm;
+    bool small;
+    int lel;  // log2 of entries per lane
 };
 
-inline Shape shape_of(const gfbp_code *code) {
-    const int p = code->info.p, dc = code->info.max_row_degree, dv = code->info.max_col_degree;
+inline bool small_class(const gfbp_code *code) {
+    return code->info.max_row_degree <= 6 && code->info.max_col_degree <= 4;
+}
+
+inline int max_lel(const gfbp_code *code) { return std::min(code->info.p, small_class(code) ? 3 : 2); }
+
+inline bool allowed_el(const gfbp_code *code, int el) {
+    if (el == 0) return true;
+    for (int l = 1; l <= max_lel(code); ++l)
+        if (el == (1 << l)) return true;
+    return false;
+}
+
+inline Shape shape_of(const gfbp_code *code, int schedule) {
     Shape sh;
-    sh.dcm = dc <= 6 ? 6 : (dc <= 8 ? 8 : 16);
-    sh.dvm = dv <= 4 ? 4 : 8;
-    if (sh.dcm == 6 && sh.dvm == 8) sh.dcm = 8;
-    const int lel = std::min(p, sh.dcm == 16 ? 2 : 3);
-    sh.lg = p - lel;
+    sh.small = small_class(code);
+    const int el = code->el[schedule == GFBP_SUS ? 1 : 0];
+    int lel = max_lel(code);
+    if (el > 0)
+        for (int l = 1; l <= max_lel(code); ++l)
+            if (el == (1 << l)) lel = l;
+    sh.lel = lel;
     return sh;
 }
 
@@ -246,12 +265,12 @@ struct TiledLaunch {
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                           Snap sn, const int32_t *cols, int nc) {
-        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DVM>), dim3(tiled_blocks(nc, s)), dim3(kBlock), 0, st, c,
-                           s, z, markov, wantQ, sn, cols, nc);
+        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(unsigned(nc) * unsigned(s.nact)),
+                           dim3(DVM * kWave), 0, st, c, s, z, markov, wantQ, sn, cols, nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DVM>), dim3(tiled_blocks(1, s)), dim3(kBlock), 0, st, c,
+        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(unsigned(s.nact)), dim3(DVM * kWave), 0, st, c,
                            s, z, markov, wantQ, sn);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
@@ -356,15 +375,28 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     return GFBP_OK;
 }
 
+template <int P, int LEL>
+gfbp_status run_lel(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
+                    int needQ, bool small) {
+    if constexpr (LEL <= 3 && LEL <= P) {
+        if (small) return run_batch<P, TiledLaunch<P, P - LEL, 6, 4>>(code, b, out, s, st, needQ);
+    }
+    if constexpr (LEL <= 2 && LEL <= P) {
+        if (!small) return run_batch<P, TiledLaunch<P, P - LEL, 16, 8>>(code, b, out, s, st, needQ);
+    }
+    return fail(GFBP_EUNSUPPORTED, "no kernel for this shape");
+}
+
 template <int P>
 gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
                     int needQ) {
-    const Shape sh = shape_of(code);
-    constexpr int L3 = P > 3 ? P - 3 : 0, L2 = P > 2 ? P - 2 : 0;
-    if (sh.dcm == 6) return run_batch<P, TiledLaunch<P, L3, 6, 4>>(code, b, out, s, st, needQ);
-    if (sh.dcm == 8 && sh.dvm == 4) return run_batch<P, TiledLaunch<P, L3, 8, 4>>(code, b, out, s, st, needQ);
-    if (sh.dcm == 8) return run_batch<P, TiledLaunch<P, L3, 8, 8>>(code, b, out, s, st, needQ);
-    return run_batch<P, TiledLaunch<P, L2, 16, 8>>(code, b, out, s, st, needQ);
+    const Shape sh = shape_of(code, b->schedule);
+    switch (sh.lel) {
+        case 1: return run_lel<P, 1>(code, b, out, s, st, needQ, sh.small);
+        case 2: return run_lel<P, 2>(code, b, out, s, st, needQ, sh.small);
+        case 3: return run_lel<P, 3>(code, b, out, s, st, needQ, sh.small);
+        default: return fail(GFBP_EUNSUPPORTED, "bad shape");
+    }
 }
 
 // Workspace carving, shared by size query and decode.
@@ -636,6 +668,56 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
         case 6: return run_any<6>(code, b, out, s, st, needQ);
         default: return fail(GFBP_EUNSUPPORTED, "bad field");
     }
+}
+
+gfbp_status gfbp_code_set_shape(gfbp_code *c, int32_t schedule, int32_t entries_per_lane) {
+    if (!c) return fail(GFBP_EINVAL, "null code");
+    if (schedule != GFBP_PUS && schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
+    if (!allowed_el(c, entries_per_lane)) return fail(GFBP_EUNSUPPORTED, "entries per lane not available for this code");
+    c->el[schedule == GFBP_SUS ? 1 : 0] = entries_per_lane;
+    return GFBP_OK;
+}
+
+int32_t gfbp_code_get_shape(const gfbp_code *c, int32_t schedule) {
+    if (!c || (schedule != GFBP_PUS && schedule != GFBP_SUS)) return 0;
+    return 1 << shape_of(c, schedule).lel;
+}
+
+gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void *workspace, size_t ws_bytes,
+                      void *stream, int32_t trial_iters, int32_t *chosen) {
+    if (!c || !b || !out) return fail(GFBP_EINVAL, "null argument");
+    if (trial_iters < 1) return fail(GFBP_EINVAL, "trial_iters < 1");
+    const int slot = b->schedule == GFBP_SUS ? 1 : 0;
+    const int keep = c->el[slot];
+    gfbp_batch tb = *b;
+    tb.max_iter = trial_iters;
+    tb.early_stop = 0;
+    gfbp_result to = *out;
+    to.posterior = nullptr;
+    to.snap_iter = 0;
+    to.snap_q = to.snap_r = to.snap_Q = nullptr;
+    double best_t = 1e300;
+    int best = 0;
+    for (int l = 1; l <= max_lel(c); ++l) {
+        c->el[slot] = 1 << l;
+        double t = 0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run warms up, the second is timed
+            const auto t0 = std::chrono::steady_clock::now();
+            const gfbp_status st = gfbp_decode_batch(c, &tb, &to, workspace, ws_bytes, stream);
+            if (st != GFBP_OK) {
+                c->el[slot] = keep;
+                return st;
+            }
+            t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (t < best_t) {
+            best_t = t;
+            best = 1 << l;
+        }
+    }
+    c->el[slot] = best;
+    if (chosen) *chosen = best;
+    return GFBP_OK;
 }
 
 gfbp_status gfbp_profile_enable(int32_t on) {

@@ -169,17 +169,26 @@ __device__ __forceinline__ void syndrome_signs(int z, int g, double *v) {
     for (int r = 0; r < Gm::EL; ++r) v[r] = (__popc(z & (g * Gm::EL + r)) & 1) ? -1.0 : 1.0;
 }
 
-// Transform of edge e's weighted-symbol distribution q~(y) = q(h^-1 y).
+// Edge e's weighted-symbol distribution q~(y) = q(h^-1 y) at this lane's
+// positions (loads only; all the loads of a check are issued before any
+// transform so that their latencies overlap).
 template <int P, int LG>
-__device__ __forceinline__ void load_transformed(const float *Qm, size_t e, const Item &it, int ntiles, uint64_t hinv,
-                                                 double *v) {
+__device__ __forceinline__ void load_permuted(const float *Qm, size_t e, const Item &it, int ntiles, uint64_t hinv,
+                                              float *v) {
     using Gm = Geo<P, LG>;
     const float *base = vec_base<P, LG>(Qm, e, it.tile, ntiles);
     int pos[Gm::EL];
     gf_positions<P, LG>(hinv, it.g, pos);
 #pragma unroll
-    for (int r = 0; r < Gm::EL; ++r) v[r] = double(base[pos[r] * Gm::TF + it.fw]);
-    wht<P, LG>(v, it.g);
+    for (int r = 0; r < Gm::EL; ++r) v[r] = base[pos[r] * Gm::TF + it.fw];
+}
+
+template <int P, int LG>
+__device__ __forceinline__ void transform(const float *raw, double *v, int g) {
+    using Gm = Geo<P, LG>;
+#pragma unroll
+    for (int r = 0; r < Gm::EL; ++r) v[r] = double(raw[r]);
+    wht<P, LG>(v, g);
 }
 
 struct Chan {
@@ -275,10 +284,14 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
     const int i = it.node, f = it.f;
     const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
     const int zi = z ? z[size_t(f) * c.m + i] : 0;
+    float raw[DCM][Gm::EL];
+#pragma unroll
+    for (int d = 0; d < DCM; ++d)
+        if (d < dc) load_permuted<P, LG>(s.Qm, size_t(rs + d), it, ntiles, c.emap[2 * (rs + d)], raw[d]);
     double W[DCM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DCM; ++d)
-        if (d < dc) load_transformed<P, LG>(s.Qm, size_t(rs + d), it, ntiles, c.emap[2 * (rs + d)], W[d]);
+        if (d < dc) transform<P, LG>(raw[d], W[d], it.g);
 #pragma unroll
     for (int d = 0; d < DCM; ++d) {
         if (d < dc) {
@@ -382,77 +395,161 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
     variable_update<P, LG, DVM>(c, s, it, ntiles, j, r, cs, dv, markov, wantQ, snap);
 }
 
-// A6 sequential schedule, the step of column j for one frame: the r of
-// column j's edges from the siblings' current q (partial horizontal pass),
-// then column j's q and pseudo-posterior (partial vertical pass).  lds is the
-// wavefront's Q x TF buffer used to apply r(a) = T(h a): position y is
-// written to entry h^-1 y and entries are read back in order; only the lanes
-// of the same frame exchange data through it.
-template <int P, int LG, int DVM>
+// A6 sequential schedule, the step of column j for one tile of frames, done
+// by a workgroup: wavefront d (< column degree) computes the r of the
+// column's d-th edge from the siblings' current q (partial horizontal pass);
+// after a workgroup barrier, wavefront d combines the column's r into its
+// edge's q and wavefront 0 into the pseudo-posterior and decision (partial
+// vertical pass).  `live`: this lane's frame is still iterating.  perm is the
+// wavefront's Q x TF buffer that applies r(a) = T(h a) (position y written to
+// entry h^-1 y, entries read back in order); rsh holds the column's r as
+// [d][register][lane].
+template <int P, int LG, int DCM, int DVM>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
-                                           int ntiles, int j, int markov, int wantQ, const Snap &snap, float *lds) {
+                                           bool live, int ntiles, int j, int markov, int wantQ, const Snap &snap,
+                                           float *perm, float *rsh) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
+    const int d = int(threadIdx.x) / kWave, lane = int(threadIdx.x) % kWave;
     const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
-    float r[DVM][Gm::EL];
+    const bool mine = live && d < dv;
+    size_t e = 0;
+    if (d < dv) e = size_t(c.col_edge[cs + d]);
+    if (mine) {
+        const int i = c.edge_row[e];
+        const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
+        const int self = int(e) - rs;
+        float raw[DCM][Gm::EL];
 #pragma unroll
-    for (int d = 0; d < DVM; ++d) {
-        if (d < dv) {
-            const size_t e = size_t(c.col_edge[cs + d]);
-            const int i = c.edge_row[e];
-            const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
-            double acc[Gm::EL];
-            syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + i] : 0, it.g, acc);
-            for (int t = 0; t < dc; ++t) {
-                if (size_t(rs + t) == e) continue;
+        for (int t = 0; t < DCM; ++t)
+            if (t < dc && t != self)
+                load_permuted<P, LG>(s.Qm, size_t(rs + t), it, ntiles, c.emap[2 * (rs + t)], raw[t]);
+        double acc[Gm::EL];
+        syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + i] : 0, it.g, acc);
+#pragma unroll
+        for (int t = 0; t < DCM; ++t) {
+            if (t < dc && t != self) {
                 double w[Gm::EL];
-                load_transformed<P, LG>(s.Qm, size_t(rs + t), it, ntiles, c.emap[2 * (rs + t)], w);
+                transform<P, LG>(raw[t], w, it.g);
 #pragma unroll
                 for (int q = 0; q < Gm::EL; ++q) acc[q] *= w[q];
             }
-            wht<P, LG>(acc, it.g);
-            int pos[Gm::EL];
-            gf_positions<P, LG>(c.emap[2 * e], it.g, pos);
+        }
+        wht<P, LG>(acc, it.g);
+        int pos[Gm::EL];
+        gf_positions<P, LG>(c.emap[2 * e], it.g, pos);
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q)
-                lds[pos[q] * Gm::TF + it.fw] = float(fmax(acc[q] * (1.0 / double(Gm::Q)), 0.0));
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int q = 0; q < Gm::EL; ++q) perm[pos[q] * Gm::TF + it.fw] = float(fmax(acc[q] * (1.0 / double(Gm::Q)), 0.0));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) {
-                r[d][q] = lds[(it.g * Gm::EL + q) * Gm::TF + it.fw];
-                if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = r[d][q];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int q = 0; q < Gm::EL; ++q) {
+            const float rv = perm[(it.g * Gm::EL + q) * Gm::TF + it.fw];
+            rsh[(d * Gm::EL + q) * kWave + lane] = rv;
+            if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = rv;
         }
     }
-    variable_update<P, LG, DVM>(c, s, it, ntiles, j, r, cs, dv, markov, wantQ, snap);
+    __syncthreads();
+    if (mine) {
+        const float *pj = (markov && j < c.n_info) ? s.Pr : s.L;
+        const float *pb = vec_base<P, LG>(pj, size_t(j), it.tile, ntiles);
+        double pv[Gm::EL];
+#pragma unroll
+        for (int q = 0; q < Gm::EL; ++q) pv[q] = pb[(it.g * Gm::EL + q) * Gm::TF + it.fw];
+        if (d == 0) {
+            // A4/A5: pseudo-posterior (Eq. (5)) and decision
+            double acc[Gm::EL];
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) acc[q] = pv[q];
+#pragma unroll
+            for (int d2 = 0; d2 < DVM; ++d2)
+                if (d2 < dv) {
+#pragma unroll
+                    for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
+                }
+            normalise<P, LG>(acc, s.guards, f, it.g);
+            int best = it.g * Gm::EL;
+            float bv = float(acc[0]);
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) {
+                const float v = float(acc[q]);
+                if (wantQ) s.Qp[at<P, LG>(j, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = v;
+                if (v > bv) { bv = v; best = it.g * Gm::EL + q; }
+            }
+            best = lanes_argmax<LG>(bv, best);
+            if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
+        }
+        // Eq. (4) for this wavefront's edge
+        double qv[Gm::EL];
+#pragma unroll
+        for (int q = 0; q < Gm::EL; ++q) qv[q] = pv[q];
+#pragma unroll
+        for (int d2 = 0; d2 < DVM; ++d2)
+            if (d2 < dv && d2 != d) {
+#pragma unroll
+                for (int q = 0; q < Gm::EL; ++q) qv[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
+            }
+        normalise<P, LG>(qv, s.guards, f, it.g);
+        float *qb = vec_base<P, LG>(s.Qm, e, it.tile, ntiles);
+#pragma unroll
+        for (int q = 0; q < Gm::EL; ++q) {
+            const float qn = float(qv[q]);
+            qb[(it.g * Gm::EL + q) * Gm::TF + it.fw] = qn;
+            if (snap.q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn;
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup item: (node, tile) for the whole workgroup; each lane's frame.
+template <int P, int LG>
+__device__ __forceinline__ Item block_item(int nodes, const DevState &s) {
+    using Gm = Geo<P, LG>;
+    const int b = int(blockIdx.x);
+    const int lane = int(threadIdx.x) % kWave;
+    Item it;
+    it.node = b / s.nact;
+    it.ok = it.node < nodes;
+    it.tile = it.ok ? s.act[b % s.nact] : 0;
+    if (it.tile < 0 || it.tile >= s.Fp / Gm::TF) {
+        it.ok = false;
+        it.tile = 0;
+    }
+    it.fw = lane >> LG;
+    it.g = lane & (Gm::G - 1);
+    it.f = it.tile * Gm::TF + it.fw;
+    return it;
 }
 
 // A6, one dependency level: the columns cols[0..ncols) share no check, so
-// their steps commute; each runs exactly as in the strict order.
-template <int P, int LG, int DVM>
-__global__ __launch_bounds__(kBlock) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov, int wantQ,
-                                                      Snap snap, const int32_t *cols, int ncols) {
+// their steps commute; each runs exactly as in the strict order.  One
+// workgroup of DVM wavefronts per (column, tile).
+template <int P, int LG, int DCM, int DVM>
+__global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
+                                                          int wantQ, Snap snap, const int32_t *cols, int ncols) {
     using Gm = Geo<P, LG>;
-    __shared__ float lds[(kBlock / kWave) * Gm::Q * Gm::TF];
+    __shared__ float perm[DVM * Gm::Q * Gm::TF];
+    __shared__ float rsh[DVM * Gm::EL * kWave];
     const int ntiles = s.Fp / Gm::TF;
-    const Item it = item<P, LG>(ncols, s);
-    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
-    sus_column<P, LG, DVM>(c, s, z, it, ntiles, cols[it.node], markov, wantQ, snap,
-                           lds + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF);
+    const Item it = block_item<P, LG>(ncols, s);
+    if (!it.ok) return;  // uniform over the workgroup
+    const bool live = it.f < s.F && s.active[it.f];
+    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, ntiles, cols[it.node], markov, wantQ, snap,
+                                perm + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF, rsh);
 }
 
-// A6, strict order: columns 0..n-1 one after the other for each frame.
-template <int P, int LG, int DVM>
-__global__ __launch_bounds__(kBlock) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
-                                                       int wantQ, Snap snap) {
+// A6, strict order: columns 0..n-1 one after the other for each tile.
+template <int P, int LG, int DCM, int DVM>
+__global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
+                                                           int wantQ, Snap snap) {
     using Gm = Geo<P, LG>;
-    __shared__ float lds[(kBlock / kWave) * Gm::Q * Gm::TF];
+    __shared__ float perm[DVM * Gm::Q * Gm::TF];
+    __shared__ float rsh[DVM * Gm::EL * kWave];
     const int ntiles = s.Fp / Gm::TF;
-    const Item it = item<P, LG>(1, s);
-    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
-    float *mine = lds + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF;
-    for (int j = 0; j < c.n; ++j) sus_column<P, LG, DVM>(c, s, z, it, ntiles, j, markov, wantQ, snap, mine);
+    const Item it = block_item<P, LG>(1, s);
+    if (!it.ok) return;  // uniform over the workgroup
+    const bool live = it.f < s.F && s.active[it.f];
+    float *mine = perm + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF;
+    for (int j = 0; j < c.n; ++j) sus_column<P, LG, DCM, DVM>(c, s, z, it, live, ntiles, j, markov, wantQ, snap, mine, rsh);
 }
 
 // A7 dynamical block prior (Eq. (7)) for source symbol k: from this

@@ -344,3 +344,45 @@ def test_levelled_sus_is_bitwise_the_strict_sweep(gfbp, q, channel, param, prior
         b = _gpu(gfbp, code, fr, "sus", sus_strict=True, **extra, **kw)
         for k in a:
             assert np.array_equal(a[k], b[k]), f"levelled and strict SUS differ in {k}"
+
+
+# --------------------------------------------------------------- kernel shapes and the tuner
+@pytest.mark.parametrize("q", [2, 4, 16, 64])
+def test_every_kernel_shape_matches_the_reference(gfbp, q):
+    """Each allowed entries-per-lane choice (EL = 2, 4, 8) is a different
+    register/lane split of the same arithmetic; all must match the oracle."""
+    import torch
+
+    code, enc = _small_code(q, 72, seed=300 + q)
+    fr = wl.make_frames(code, enc, 13, 301 + q, "bsc", 0.08)
+    dcode = gfbp.DeviceCode(code)
+    dfr = gfbp.frames_to_device(fr)
+    for sch in ("pus", "sus"):
+        r = _ref(code, fr, sch, max_iter=2, early_stop=False, snap_iter=2)
+        for el in (2, 4, 8):
+            if el > q:
+                with pytest.raises(gfbp.GfbpError):
+                    dcode.set_shape(sch, el)
+                continue
+            dcode.set_shape(sch, el)
+            assert dcode.shape(sch) == el
+            out = gfbp.decode_batch(dcode, dfr, schedule=sch, max_iter=2, early_stop=False, snap_iter=2)
+            torch.cuda.synchronize()
+            for key in ("snap_q", "snap_r", "snap_Q"):
+                err = np.abs(out[key].cpu().numpy() - r[key]).max()
+                assert err <= MSG_TOL, f"q={q} {sch} EL={el} {key}: {err:.3g}"
+
+
+def test_tuner_keeps_an_allowed_shape_and_decodes_correctly(gfbp):
+    code, enc = wl.regular_code(240, 3, 6, 16, seed=41)
+    fr = wl.make_frames(code, enc, 200, 42, "bsc", 0.07)
+    dcode = gfbp.DeviceCode(code)
+    dfr = gfbp.frames_to_device(fr)
+    for sch in ("pus", "sus"):
+        el = gfbp.tune(dcode, dfr, schedule=sch, trial_iters=2)
+        assert el in (2, 4, 8) and dcode.shape(sch) == el
+        out = gfbp.decode_batch(dcode, dfr, schedule=sch, max_iter=50)
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        r = _ref(code, fr, sch, max_iter=50)
+        _compare_decisions(g, r, f"tuned EL={el} {sch}",
+                           recheck=lambda idx: _fp32_sensitive(code, fr, sch, idx, max_iter=50))
