@@ -160,6 +160,67 @@ size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t sche
 gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- Sessions: continuous batching with resident frame state. ----
+ * A session holds n_slots frame slots of one code on the device (message
+ * state, staged channel inputs, per-slot iteration counters).  Frames are
+ * admitted into free slots as they arrive; every step advances each running
+ * slot by a number of iterations of the session's schedule; a slot whose
+ * decision satisfies H x = z, or that reaches max_iter, finishes; poll hands
+ * back finished frames (decision, iterations, converged) and frees their
+ * slots.  A frame's arithmetic does not depend on the other frames, so its
+ * result is the same alone or in any mix (and equal to gfbp_decode_batch).
+ * Channel kind and prior are per frame.  The kernel shape is the code's shape
+ * for the schedule when the session is created.  Calls on one session must
+ * not overlap; different sessions may run on different streams. */
+typedef struct gfbp_session gfbp_session;
+
+typedef struct {
+    int32_t n_slots;         /* resident frames (rounded up to a multiple of 64)          */
+    int32_t schedule;        /* GFBP_PUS or GFBP_SUS                                      */
+    int32_t max_iter;        /* >= 1                                                      */
+    int32_t has_syndrome;    /* 1: frames may carry z (else z = 0)                        */
+    const float *markov_M;   /* host [q][q], or NULL: no frame uses a Markov prior        */
+    const float *markov_pi;  /* host [q] (with markov_M)                                  */
+    int32_t options;         /* GFBP_OPT_*                                                */
+} gfbp_session_desc;
+
+/* n frames to admit: device pointers, frame-major, read during the call. */
+typedef struct {
+    const uint8_t *channel;  /* [n] GFBP_CH_BSC, GFBP_CH_BEC or GFBP_CH_BIAWGN (required) */
+    const uint8_t *markov;   /* [n] 1: Markov prior on the source symbols, or NULL        */
+    const float *param;      /* [n] crossover f or sigma (unused for BEC)                  */
+    const uint8_t *rx;       /* [n][code n] received symbols, or NULL if no BSC/BEC frame  */
+    const uint8_t *erasure;  /* [n][code n] erased-bit masks, or NULL if no BEC frame      */
+    const float *y;          /* [n][code n][p] samples, or NULL if no BI-AWGN frame        */
+    const uint8_t *syndrome; /* [n][m], or NULL (z = 0)                                    */
+} gfbp_frames;
+
+typedef struct {
+    int64_t id;              /* the caller's id of the frame                               */
+    int32_t iters;           /* iterations run                                             */
+    int32_t converged;       /* 1 if the decision satisfies H x = z                        */
+} gfbp_retired;
+
+/* Device bytes a session would allocate (for admission by memory budget). */
+size_t gfbp_session_bytes(const gfbp_code *code, const gfbp_session_desc *desc);
+/* Allocates the session's device memory (synchronous). */
+gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *desc, gfbp_session **out);
+gfbp_status gfbp_session_destroy(gfbp_session *session);
+/* Admits the first *n_admitted of the n frames (as many as there are free
+ * slots; the caller offers the rest later) and initialises them on stream. */
+gfbp_status gfbp_session_admit(gfbp_session *session, int32_t n, const int64_t *ids, const gfbp_frames *frames,
+                               int32_t *n_admitted, void *stream);
+/* Enqueues `iters` iterations of every running slot; no host synchronisation. */
+gfbp_status gfbp_session_step(gfbp_session *session, int32_t iters, void *stream);
+/* Collects up to cap finished frames: out[0..*n_out) and, if xhat (host) is
+ * not NULL, their decisions xhat[r][code n]; frees their slots.  Synchronises
+ * the stream. */
+gfbp_status gfbp_session_poll(gfbp_session *session, gfbp_retired *out, uint8_t *xhat, int32_t cap, int32_t *n_out,
+                              void *stream);
+int32_t gfbp_session_free_slots(const gfbp_session *session);
+/* Frames admitted and not yet collected by poll. */
+int32_t gfbp_session_running(const gfbp_session *session);
+
 /* ---- Kernel shape and its autotuner. ----
  * The decoding kernels spread one frame's q-vector over G lanes with
  * q/G "entries per lane" in registers (EL): a larger EL makes more of the

@@ -29,7 +29,9 @@ SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
 EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size", "gfbp_decode_batch",
            "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
-           "gfbp_code_get_shape", "gfbp_tune", "gfbp_last_error", "gfbp_version")
+           "gfbp_code_get_shape", "gfbp_tune", "gfbp_session_bytes", "gfbp_session_create", "gfbp_session_destroy",
+           "gfbp_session_admit", "gfbp_session_step", "gfbp_session_poll", "gfbp_session_free_slots",
+           "gfbp_session_running", "gfbp_last_error", "gfbp_version")
 
 
 class CodeDesc(ctypes.Structure):
@@ -61,6 +63,22 @@ class Result(ctypes.Structure):
 class KernelStats(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("algo_bytes", ctypes.c_double), ("edge_q", ctypes.c_double)]
+
+
+class SessionDesc(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("schedule", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("has_syndrome", ctypes.c_int32), ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p),
+                ("options", ctypes.c_int32)]
+
+
+class FramesIn(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_void_p), ("markov", ctypes.c_void_p), ("param", ctypes.c_void_p),
+                ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("syndrome", ctypes.c_void_p)]
+
+
+class Retired(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +115,24 @@ def lib():
     L.gfbp_tune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.gfbp_tune.restype = ctypes.c_int32
+    L.gfbp_session_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(SessionDesc)]
+    L.gfbp_session_bytes.restype = ctypes.c_size_t
+    L.gfbp_session_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(SessionDesc), ctypes.POINTER(ctypes.c_void_p)]
+    L.gfbp_session_create.restype = ctypes.c_int32
+    L.gfbp_session_destroy.argtypes = [ctypes.c_void_p]
+    L.gfbp_session_destroy.restype = ctypes.c_int32
+    L.gfbp_session_admit.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(FramesIn),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+    L.gfbp_session_admit.restype = ctypes.c_int32
+    L.gfbp_session_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    L.gfbp_session_step.restype = ctypes.c_int32
+    L.gfbp_session_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(Retired), ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+    L.gfbp_session_poll.restype = ctypes.c_int32
+    L.gfbp_session_free_slots.argtypes = [ctypes.c_void_p]
+    L.gfbp_session_free_slots.restype = ctypes.c_int32
+    L.gfbp_session_running.argtypes = [ctypes.c_void_p]
+    L.gfbp_session_running.restype = ctypes.c_int32
     L.gfbp_last_error.restype = ctypes.c_char_p
     L.gfbp_version.restype = ctypes.c_char_p
     _lib = L
@@ -281,3 +317,112 @@ def tune(dcode: DeviceCode, dframes: dict, schedule="pus", trial_iters: int = 3,
     """``gfbp_tune``: time every allowed kernel shape on this batch and keep the
     fastest for the schedule; returns the chosen entries per lane."""
     return decode_batch(dcode, dframes, schedule=schedule, tune_iters=trial_iters, **kw)["entries_per_lane"]
+
+
+def _stream_ptr(stream):
+    import torch
+
+    st = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+class Session:
+    """``gfbp_session_*``: continuous batching on one code (resident frame slots).
+
+    Frames are admitted from device tensors (a dict with per-frame ``channel``
+    codes, optional ``markov`` flags, ``param``, ``rx``, ``erasure``, ``y``,
+    ``syndrome``), stepped, and collected by :meth:`poll`.
+    """
+
+    def __init__(self, dcode: DeviceCode, n_slots: int, schedule="pus", max_iter: int = 100,
+                 has_syndrome: bool = False, markov_M=None, markov_pi=None, sus_strict: bool = False):
+        self.dcode = dcode
+        self._M = None if markov_M is None else np.ascontiguousarray(markov_M, dtype=np.float32)
+        self._pi = None if markov_pi is None else np.ascontiguousarray(markov_pi, dtype=np.float32)
+        self.desc = SessionDesc(int(n_slots), SCHEDULES[schedule], int(max_iter), int(bool(has_syndrome)),
+                                None if self._M is None else self._M.ctypes.data,
+                                None if self._pi is None else self._pi.ctypes.data,
+                                OPT_SUS_STRICT if sus_strict else 0)
+        h = ctypes.c_void_p()
+        _check(lib().gfbp_session_create(dcode.handle, ctypes.byref(self.desc), ctypes.byref(h)), "gfbp_session_create")
+        self.handle = h
+        self.n = dcode.n
+
+    @staticmethod
+    def bytes_needed(dcode: DeviceCode, n_slots: int, schedule="pus", markov: bool = False,
+                     has_syndrome: bool = False) -> int:
+        q = dcode.q
+        M = np.zeros((q, q), np.float32)
+        d = SessionDesc(int(n_slots), SCHEDULES[schedule], 1, int(bool(has_syndrome)),
+                        M.ctypes.data if markov else None, M.ctypes.data if markov else None, 0)
+        return int(lib().gfbp_session_bytes(dcode.handle, ctypes.byref(d)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gfbp_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def free_slots(self) -> int:
+        return int(lib().gfbp_session_free_slots(self.handle))
+
+    @property
+    def running(self) -> int:
+        return int(lib().gfbp_session_running(self.handle))
+
+    def admit(self, ids, frames: dict, stream=None) -> int:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        fr = FramesIn(_dptr(frames["channel"]), _dptr(frames.get("markov")), _dptr(frames.get("param")),
+                      _dptr(frames.get("rx")), _dptr(frames.get("erasure")), _dptr(frames.get("y")),
+                      _dptr(frames.get("syndrome")))
+        k = ctypes.c_int32(0)
+        _check(lib().gfbp_session_admit(self.handle, len(ids), ids.ctypes.data, ctypes.byref(fr), ctypes.byref(k),
+                                        _stream_ptr(stream)), "gfbp_session_admit")
+        return int(k.value)
+
+    def step(self, iters: int = 1, stream=None):
+        _check(lib().gfbp_session_step(self.handle, int(iters), _stream_ptr(stream)), "gfbp_session_step")
+
+    def poll(self, cap: int | None = None, want_xhat: bool = True, stream=None):
+        """Finished frames: (ids int64[k], iters int32[k], converged uint8[k], xhat uint8[k][n] or None)."""
+        cap = int(cap or max(1, self.running))
+        out = (Retired * cap)()
+        xh = np.zeros((cap, self.n), dtype=np.uint8) if want_xhat else None
+        k = ctypes.c_int32(0)
+        _check(lib().gfbp_session_poll(self.handle, out, None if xh is None else xh.ctypes.data, cap, ctypes.byref(k),
+                                       _stream_ptr(stream)), "gfbp_session_poll")
+        k = int(k.value)
+        ids = np.array([out[i].id for i in range(k)], dtype=np.int64)
+        it = np.array([out[i].iters for i in range(k)], dtype=np.int32)
+        cv = np.array([out[i].converged for i in range(k)], dtype=np.uint8)
+        return ids, it, cv, (None if xh is None else xh[:k])
+
+
+def frames_for_session(frames_list, device="cuda"):
+    """Concatenate ``workloads.Frames`` batches (any channels) into the device
+    dict that :meth:`Session.admit` takes; frame order is preserved."""
+    import torch
+
+    kinds = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN}
+    F = sum(f.F for f in frames_list)
+    n = frames_list[0].codeword.shape[1]
+    ch = np.concatenate([np.full(f.F, kinds[f.channel], np.uint8) for f in frames_list])
+    param = np.concatenate([f.param.astype(np.float32) for f in frames_list])
+    need_rx = any(f.rx is not None for f in frames_list)
+    need_er = any(f.erasure is not None for f in frames_list)
+    need_y = any(f.y is not None for f in frames_list)
+    p = None
+    for f in frames_list:
+        if f.y is not None:
+            p = f.y.shape[2]
+    rx = np.concatenate([f.rx if f.rx is not None else np.zeros((f.F, n), np.uint8) for f in frames_list]) if need_rx else None
+    er = np.concatenate([f.erasure if f.erasure is not None else np.zeros((f.F, n), np.uint8) for f in frames_list]) if need_er else None
+    y = np.concatenate([f.y if f.y is not None else np.zeros((f.F, n, p), np.float32) for f in frames_list]) if need_y else None
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return {"F": F, "channel": dev(ch), "param": dev(param), "rx": dev(rx), "erasure": dev(er), "y": dev(y)}

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -244,7 +245,7 @@ inline Shape shape_of(const gfbp_code *code, int schedule) {
 inline int frame_stride(int F) { return (F + kWave - 1) / kWave * kWave; }
 
 inline unsigned tiled_blocks(int nodes, const DevState &s) {
-    const long long waves = (long long)nodes * s.nact;
+    const long long waves = (long long)nodes * s.nb;
     return unsigned(std::max<long long>(1, (waves + (kBlock / kWave) - 1) / (kBlock / kWave)));
 }
 
@@ -265,12 +266,12 @@ struct TiledLaunch {
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                           Snap sn, const int32_t *cols, int nc) {
-        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(unsigned(nc) * unsigned(s.nact)),
+        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
                            dim3(DVM * kWave), 0, st, c, s, z, markov, wantQ, sn, cols, nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(unsigned(s.nact)), dim3(DVM * kWave), 0, st, c,
+        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))), dim3(DVM * kWave), 0, st, c,
                            s, z, markov, wantQ, sn);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
@@ -278,8 +279,11 @@ struct TiledLaunch {
                            M, pi);
     }
     static constexpr int TF = kWave >> LG;
-    static void tiles(hipStream_t st, const DevState &s, int t) {
-        hipLaunchKernelGGL(tiled::k_tiles, dim3(1), dim3(1024), 0, st, s, TF, t);
+    static void tiles(hipStream_t st, const uint8_t *mask, int F, int Fp, int32_t *out, uint32_t *count) {
+        hipLaunchKernelGGL(tiled::k_tiles, dim3(1), dim3(1024), 0, st, mask, F, Fp, TF, out, count);
+    }
+    static void markov_any(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
+        markov(st, c, s, M, pi);
     }
     static void vectors(hipStream_t st, const float *src, int n, const DevState &s, float *out) {
         const size_t tot = size_t(n) * s.F * (1 << P);
@@ -300,11 +304,12 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     Tracer tr(st);
     hipLaunchKernelGGL(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, out->iters, out->converged);
     const int ntiles = s.Fp / K::TF;
-    K::tiles(st, s, 0);
-    // k_tiles(0) lists exactly the tiles holding a frame: ceil(F / TF) of them
-    // (ntiles can be larger: the stride is padded to whole 64-frame tiles).
+    K::tiles(st, s.active, F, s.Fp, s.tiles, s.count + 1);
+    // the first list holds exactly the tiles holding a frame: ceil(F / TF) of
+    // them (ntiles can be larger: the stride is padded to whole 64-frame tiles).
     s.act = s.tiles;
-    s.nact = (F + K::TF - 1) / K::TF;
+    s.nact = s.count + 1;
+    s.nb = (F + K::TF - 1) / K::TF;
     tr.begin();
     K::init(st, c, s, b);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
@@ -346,7 +351,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                            out->converged);
         HIP_TRY(hipGetLastError());
         if (t == b->max_iter) break;
-        K::tiles(st, s, t);
+        K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, s.count + 2 * (t & 1) + 1);
         uint32_t cnt[2] = {0, 0};
         HIP_TRY(hipMemcpyAsync(cnt, s.count + 2 * (t & 1), sizeof cnt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -354,7 +359,8 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         running = left;
         if (left == 0) break;
         s.act = s.tiles + size_t(t & 1) * ntiles;
-        s.nact = int(cnt[1]);
+        s.nact = s.count + 2 * (t & 1) + 1;
+        s.nb = int(cnt[1]);
         if (markov) {
             tr.begin();
             K::markov(st, c, s, b->markov_M, b->markov_pi);
@@ -399,6 +405,214 @@ gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out
     }
 }
 
+// ======================================================================= sessions
+// Continuous batching: a session holds S resident frame slots of one code;
+// frames are admitted into free slots as they arrive, every step advances all
+// running slots, finished slots are collected by poll and reused.
+}  // namespace
+
+// Device view of a session (trivially copyable: passed to kernels).
+struct SessDev {
+    DevState st;  // message state for S slots (F = S)
+    int S, max_iter;
+    uint8_t *rx, *er, *z, *chan, *mark;
+    float *y, *param;
+    int32_t *iters;
+    uint8_t *conv, *fresh, *done, *xout;
+    int32_t *pairs, *list, *res;
+};
+
+struct gfbp_session {
+    const gfbp_code *code = nullptr;
+    int S = 0, schedule = 0, max_iter = 0, has_z = 0, options = 0, markov = 0;
+    int tf = 0, ntiles = 0;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    SessDev dv{};
+    float *M = nullptr, *pi = nullptr;
+    int32_t *ftiles = nullptr;
+    uint32_t *aux = nullptr;  // [0] fresh tiles, [1] finished slots, [2..3] running tiles by parity
+    int parity = 0;
+    // host
+    std::vector<int64_t> id;
+    std::vector<int32_t> free_slots;  // sorted descending: back() is the lowest free slot
+    int running = 0;                  // admitted and not yet collected
+    void *pin = nullptr;              // pinned host staging
+    size_t pin_bytes = 0;
+    gfbp_status (*init_fn)(gfbp_session *, int, hipStream_t) = nullptr;
+    gfbp_status (*step_fn)(gfbp_session *, int, hipStream_t) = nullptr;
+};
+
+namespace {
+
+struct AdmitIn {
+    const float *param;
+    const uint8_t *rx, *erasure, *syndrome, *channel, *markov;
+    const float *y;
+};
+
+// Copy admitted frames' inputs into their slots and reset the slots' state.
+__global__ void k_admit(SessDev s, AdmitIn in, int n, int m, int p) {
+    const int k = blockIdx.x;
+    const int slot = s.pairs[2 * k], src = s.pairs[2 * k + 1];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        if (in.rx) s.rx[size_t(slot) * n + j] = in.rx[size_t(src) * n + j];
+        if (in.erasure) s.er[size_t(slot) * n + j] = in.erasure[size_t(src) * n + j];
+    }
+    if (in.y)
+        for (int t = threadIdx.x; t < n * p; t += blockDim.x) s.y[size_t(slot) * n * p + t] = in.y[size_t(src) * n * p + t];
+    if (s.z)
+        for (int i = threadIdx.x; i < m; i += blockDim.x)
+            s.z[size_t(slot) * m + i] = in.syndrome ? in.syndrome[size_t(src) * m + i] : 0;
+    if (threadIdx.x == 0) {
+        s.param[slot] = in.param ? in.param[src] : 0.0f;
+        s.chan[slot] = in.channel[src];
+        s.mark[slot] = in.markov ? in.markov[src] : 0;
+        s.fresh[slot] = 1;
+        s.st.active[slot] = 1;
+        s.st.unsat[slot] = 0;
+        s.st.guards[slot] = 0;
+        s.iters[slot] = 0;
+        s.conv[slot] = 0;
+        s.done[slot] = 0;
+    }
+}
+
+__global__ void k_clear_fresh(SessDev s, int k) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < k) s.fresh[s.pairs[2 * t]] = 0;
+}
+
+// Per-slot retirement after one more iteration of that slot.
+__global__ void k_session_retire(SessDev s) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= s.S) return;
+    if (s.st.active[f]) {
+        const int t = ++s.iters[f];
+        const bool ok = s.st.unsat[f] == 0;
+        if (ok) s.conv[f] = 1;
+        if (ok || t >= s.max_iter) {
+            s.st.active[f] = 0;
+            s.done[f] = 1;
+        }
+    }
+    s.st.unsat[f] = 0;
+}
+
+// Gather the decisions [k][n] and (iterations, converged) of listed slots.
+__global__ void k_collect(SessDev s, int k, int n) {
+    const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= size_t(k) * n) return;
+    const int r = int(t / n), j = int(t % n);
+    const int slot = s.list[r];
+    s.xout[t] = s.st.xh[size_t(j) * s.st.Fp + slot];
+    if (j == 0) {
+        s.res[2 * r] = s.iters[slot];
+        s.res[2 * r + 1] = s.conv[slot];
+        s.done[slot] = 0;
+    }
+}
+
+template <int P, class K>
+struct SessionRun {
+    // initialise the slots flagged fresh (k_admit), then rebuild the running list
+    static gfbp_status init(gfbp_session *ss, int nadm, hipStream_t st) {
+        const DevCode &c = ss->code->dev;
+        DevState s = ss->dv.st;
+        K::tiles(st, ss->dv.fresh, s.F, s.Fp, ss->ftiles, ss->aux + 0);
+        s.act = ss->ftiles;
+        s.nact = ss->aux + 0;
+        s.nb = std::min(ss->ntiles, nadm);
+        s.fresh = ss->dv.fresh;
+        gfbp_batch b{};
+        b.channel = GFBP_CH_BSC;  // per-slot channel kinds override this
+        b.param = ss->dv.param;
+        b.rx = ss->dv.rx;
+        b.erasure = ss->dv.er;
+        b.y = ss->dv.y;
+        b.prior = ss->markov ? GFBP_PRIOR_MARKOV : GFBP_PRIOR_UNIFORM;
+        b.markov_pi = ss->pi;
+        K::init(st, c, s, &b);
+        hipLaunchKernelGGL(k_clear_fresh, dim3((nadm + 255) / 256), dim3(256), 0, st, ss->dv, nadm);
+        K::tiles(st, s.active, s.F, s.Fp, ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles, ss->aux + 2 + ss->parity);
+        HIP_TRY(hipGetLastError());
+        return GFBP_OK;
+    }
+    // `iters` iterations of every running slot, no host synchronisation
+    static gfbp_status step(gfbp_session *ss, int iters, hipStream_t st) {
+        const gfbp_code *code = ss->code;
+        const DevCode &c = code->dev;
+        DevState s = ss->dv.st;
+        s.nb = std::min(ss->ntiles, ss->running);
+        if (s.nb == 0) return GFBP_OK;
+        const Snap sn{nullptr, nullptr};
+        const int needQ = ss->markov;
+        const uint8_t *z = ss->has_z ? ss->dv.z : nullptr;
+        const unsigned fb = unsigned((s.F + kBlock - 1) / kBlock);
+        for (int it = 0; it < iters; ++it) {
+            s.act = ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles;
+            s.nact = ss->aux + 2 + ss->parity;
+            if (ss->schedule == GFBP_PUS) {
+                K::check(st, c, s, z, sn);
+                K::variable(st, c, s, ss->markov, needQ, sn);
+            } else if (ss->options & GFBP_OPT_SUS_STRICT) {
+                K::sequential(st, c, s, z, ss->markov, needQ, sn);
+            } else {
+                const int nlev = int(code->level_ptr.size()) - 1;
+                for (int l = 0; l < nlev; ++l) {
+                    const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
+                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, code->level_cols + c0, nc);
+                }
+            }
+            hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
+            hipLaunchKernelGGL(k_session_retire, dim3(fb), dim3(kBlock), 0, st, ss->dv);
+            ss->parity ^= 1;
+            K::tiles(st, s.active, s.F, s.Fp, ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles, ss->aux + 2 + ss->parity);
+            if (ss->markov) {
+                s.act = ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles;
+                s.nact = ss->aux + 2 + ss->parity;
+                K::markov(st, c, s, ss->M, ss->pi);
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        return GFBP_OK;
+    }
+};
+
+template <int P, int LEL>
+bool session_bind_lel(gfbp_session *ss, bool small) {
+    if constexpr (LEL <= 3 && LEL <= P) {
+        if (small) {
+            using K = TiledLaunch<P, P - LEL, 6, 4>;
+            ss->init_fn = &SessionRun<P, K>::init;
+            ss->step_fn = &SessionRun<P, K>::step;
+            ss->tf = K::TF;
+            return true;
+        }
+    }
+    if constexpr (LEL <= 2 && LEL <= P) {
+        if (!small) {
+            using K = TiledLaunch<P, P - LEL, 16, 8>;
+            ss->init_fn = &SessionRun<P, K>::init;
+            ss->step_fn = &SessionRun<P, K>::step;
+            ss->tf = K::TF;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <int P>
+bool session_bind(gfbp_session *ss) {
+    const Shape sh = shape_of(ss->code, ss->schedule);
+    switch (sh.lel) {
+        case 1: return session_bind_lel<P, 1>(ss, sh.small);
+        case 2: return session_bind_lel<P, 2>(ss, sh.small);
+        case 3: return session_bind_lel<P, 3>(ss, sh.small);
+        default: return false;
+    }
+}
+
 // Workspace carving, shared by size query and decode.
 struct Carve {
     size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, total;
@@ -421,6 +635,53 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     c.count = take(16);
     c.tiles = take(2 * F * 4);
     c.guards = take(size_t(F_) * 4);
+    c.total = off;
+    return c;
+}
+
+// Device memory of a session, carved from one allocation.
+struct SessCarve {
+    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards;
+    size_t rx, er, y, param, z, chan, mark, iters, conv, fresh, done, xout, pairs, list, res, ftiles, aux, M, pi;
+    size_t total;
+};
+
+SessCarve session_carve(const gfbp_code *code, int S, int schedule, int markov, int has_z) {
+    const size_t E = code->info.n_edges, n = code->info.n, m = code->info.m, K = code->info.n_info,
+                 Q = code->info.q, p = code->info.p, F = size_t(S);
+    SessCarve c{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes ? bytes : 1); return o; };
+    c.Qm = take(E * Q * F * 4);
+    c.R = take(schedule == GFBP_PUS ? E * Q * F * 4 : 0);
+    c.L = take(n * Q * F * 4);
+    c.Pr = take(markov ? K * Q * F * 4 : 0);
+    c.Qp = take(markov ? n * Q * F * 4 : 0);
+    c.xh = take(n * F);
+    c.unsat = take(F * 4);
+    c.active = take(F);
+    c.count = take(16);
+    c.tiles = take(2 * F * 4);
+    c.guards = take(F * 4);
+    c.rx = take(n * F);
+    c.er = take(n * F);
+    c.y = take(n * p * F * 4);
+    c.param = take(F * 4);
+    c.z = take(has_z ? m * F : 0);
+    c.chan = take(F);
+    c.mark = take(F);
+    c.iters = take(F * 4);
+    c.conv = take(F);
+    c.fresh = take(F);
+    c.done = take(F);
+    c.xout = take(n * F);
+    c.pairs = take(2 * F * 4);
+    c.list = take(F * 4);
+    c.res = take(2 * F * 4);
+    c.ftiles = take(F * 4);
+    c.aux = take(64);
+    c.M = take(Q * Q * 4);
+    c.pi = take(Q * 4);
     c.total = off;
     return c;
 }
@@ -717,6 +978,202 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     }
     c->el[slot] = best;
     if (chosen) *chosen = best;
+    return GFBP_OK;
+}
+
+size_t gfbp_session_bytes(const gfbp_code *code, const gfbp_session_desc *d) {
+    if (!code || !d || d->n_slots < 1) return 0;
+    const int S = (d->n_slots + kWave - 1) / kWave * kWave;
+    return session_carve(code, S, d->schedule, d->markov_M != nullptr, d->has_syndrome).total;
+}
+
+gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *d, gfbp_session **out) {
+    if (!code || !d || !out) return fail(GFBP_EINVAL, "null argument");
+    *out = nullptr;
+    if (d->n_slots < 1) return fail(GFBP_EINVAL, "n_slots < 1");
+    if (d->schedule != GFBP_PUS && d->schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
+    if (d->max_iter < 1) return fail(GFBP_EINVAL, "max_iter < 1");
+    if ((d->markov_M == nullptr) != (d->markov_pi == nullptr)) return fail(GFBP_EINVAL, "markov_M and markov_pi go together");
+    gfbp_session *ss = new (std::nothrow) gfbp_session();
+    if (!ss) return fail(GFBP_ENOMEM, "host allocation");
+    ss->code = code;
+    ss->S = (d->n_slots + kWave - 1) / kWave * kWave;
+    ss->schedule = d->schedule;
+    ss->max_iter = d->max_iter;
+    ss->has_z = d->has_syndrome != 0;
+    ss->options = d->options;
+    ss->markov = d->markov_M != nullptr;
+    bool bound = false;
+    switch (code->info.p) {
+        case 1: bound = session_bind<1>(ss); break;
+        case 2: bound = session_bind<2>(ss); break;
+        case 3: bound = session_bind<3>(ss); break;
+        case 4: bound = session_bind<4>(ss); break;
+        case 5: bound = session_bind<5>(ss); break;
+        case 6: bound = session_bind<6>(ss); break;
+    }
+    if (!bound) {
+        delete ss;
+        return fail(GFBP_EUNSUPPORTED, "no kernel for this code's shape");
+    }
+    ss->ntiles = ss->S / ss->tf;
+    const SessCarve cv = session_carve(code, ss->S, ss->schedule, ss->markov, ss->has_z);
+    if (hipMalloc(&ss->mem, cv.total) != hipSuccess) {
+        delete ss;
+        return fail(GFBP_ENOMEM, "device allocation for the session");
+    }
+    ss->bytes = cv.total;
+    const size_t pin_bytes = size_t(ss->S) * 6 * 4 + 256;
+    if (hipHostMalloc(&ss->pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(ss->mem);
+        delete ss;
+        return fail(GFBP_ENOMEM, "pinned host allocation for the session");
+    }
+    ss->pin_bytes = pin_bytes;
+    if (hipMemset(ss->mem, 0, cv.total) != hipSuccess) {
+        (void)hipFree(ss->mem);
+        (void)hipHostFree(ss->pin);
+        delete ss;
+        return fail(GFBP_EHIP, "clearing session memory");
+    }
+    char *w = static_cast<char *>(ss->mem);
+    SessDev &v = ss->dv;
+    DevState &st = v.st;
+    st.Qm = reinterpret_cast<float *>(w + cv.Qm);
+    st.R = reinterpret_cast<float *>(w + cv.R);
+    st.L = reinterpret_cast<float *>(w + cv.L);
+    st.Pr = reinterpret_cast<float *>(w + cv.Pr);
+    st.Qp = reinterpret_cast<float *>(w + cv.Qp);
+    st.xh = reinterpret_cast<uint8_t *>(w + cv.xh);
+    st.unsat = reinterpret_cast<uint32_t *>(w + cv.unsat);
+    st.active = reinterpret_cast<uint8_t *>(w + cv.active);
+    st.count = reinterpret_cast<uint32_t *>(w + cv.count);
+    st.tiles = reinterpret_cast<int32_t *>(w + cv.tiles);
+    st.guards = reinterpret_cast<int32_t *>(w + cv.guards);
+    st.F = ss->S;
+    st.Fp = ss->S;
+    v.S = ss->S;
+    v.max_iter = ss->max_iter;
+    v.rx = reinterpret_cast<uint8_t *>(w + cv.rx);
+    v.er = reinterpret_cast<uint8_t *>(w + cv.er);
+    v.y = reinterpret_cast<float *>(w + cv.y);
+    v.param = reinterpret_cast<float *>(w + cv.param);
+    v.z = ss->has_z ? reinterpret_cast<uint8_t *>(w + cv.z) : nullptr;
+    v.chan = reinterpret_cast<uint8_t *>(w + cv.chan);
+    v.mark = reinterpret_cast<uint8_t *>(w + cv.mark);
+    v.iters = reinterpret_cast<int32_t *>(w + cv.iters);
+    v.conv = reinterpret_cast<uint8_t *>(w + cv.conv);
+    v.fresh = reinterpret_cast<uint8_t *>(w + cv.fresh);
+    v.done = reinterpret_cast<uint8_t *>(w + cv.done);
+    v.xout = reinterpret_cast<uint8_t *>(w + cv.xout);
+    v.pairs = reinterpret_cast<int32_t *>(w + cv.pairs);
+    v.list = reinterpret_cast<int32_t *>(w + cv.list);
+    v.res = reinterpret_cast<int32_t *>(w + cv.res);
+    st.chan = v.chan;
+    st.mark = v.mark;
+    ss->ftiles = reinterpret_cast<int32_t *>(w + cv.ftiles);
+    ss->aux = reinterpret_cast<uint32_t *>(w + cv.aux);
+    ss->M = reinterpret_cast<float *>(w + cv.M);
+    ss->pi = reinterpret_cast<float *>(w + cv.pi);
+    if (ss->markov) {
+        const int q = code->info.q;
+        if (hipMemcpy(ss->M, d->markov_M, sizeof(float) * q * q, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ss->pi, d->markov_pi, sizeof(float) * q, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(ss->mem);
+            (void)hipHostFree(ss->pin);
+            delete ss;
+            return fail(GFBP_EHIP, "copying the Markov source to the device");
+        }
+    }
+    ss->id.assign(ss->S, -1);
+    ss->free_slots.resize(ss->S);
+    for (int k = 0; k < ss->S; ++k) ss->free_slots[k] = ss->S - 1 - k;
+    *out = ss;
+    return GFBP_OK;
+}
+
+gfbp_status gfbp_session_destroy(gfbp_session *ss) {
+    if (!ss) return GFBP_OK;
+    hipError_t e1 = hipFree(ss->mem), e2 = hipHostFree(ss->pin);
+    delete ss;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(GFBP_EHIP, "freeing the session");
+    return GFBP_OK;
+}
+
+int32_t gfbp_session_free_slots(const gfbp_session *ss) { return ss ? int32_t(ss->free_slots.size()) : 0; }
+
+int32_t gfbp_session_running(const gfbp_session *ss) { return ss ? ss->running : 0; }
+
+gfbp_status gfbp_session_admit(gfbp_session *ss, int32_t n, const int64_t *ids, const gfbp_frames *fr,
+                               int32_t *n_admitted, void *stream) {
+    if (!ss || !fr || (n > 0 && !ids)) return fail(GFBP_EINVAL, "null argument");
+    if (n_admitted) *n_admitted = 0;
+    if (n <= 0) return GFBP_OK;
+    if (!fr->channel) return fail(GFBP_EINVAL, "frames need per-frame channel kinds");
+    if (fr->markov && !ss->markov) return fail(GFBP_EINVAL, "Markov frames need a session created with a Markov source");
+    if (fr->syndrome && !ss->has_z) return fail(GFBP_EINVAL, "syndromes need a session created with has_syndrome");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int k = std::min<int>(n, int(ss->free_slots.size()));
+    if (k == 0) return GFBP_OK;
+    int32_t *pairs = static_cast<int32_t *>(ss->pin);
+    for (int r = 0; r < k; ++r) {
+        const int slot = ss->free_slots.back();
+        ss->free_slots.pop_back();
+        pairs[2 * r] = slot;
+        pairs[2 * r + 1] = r;
+        ss->id[slot] = ids[r];
+    }
+    HIP_TRY(hipMemcpyAsync(ss->dv.pairs, pairs, sizeof(int32_t) * 2 * k, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the pinned staging is reused by the next call
+    AdmitIn in{fr->param, fr->rx, fr->erasure, fr->syndrome, fr->channel, fr->markov, fr->y};
+    hipLaunchKernelGGL(k_admit, dim3(k), dim3(256), 0, st, ss->dv, in, ss->code->info.n, ss->code->info.m,
+                       ss->code->info.p);
+    HIP_TRY(hipGetLastError());
+    ss->running += k;
+    const gfbp_status rs = ss->init_fn(ss, k, st);
+    if (rs != GFBP_OK) return rs;
+    if (n_admitted) *n_admitted = k;
+    return GFBP_OK;
+}
+
+gfbp_status gfbp_session_step(gfbp_session *ss, int32_t iters, void *stream) {
+    if (!ss) return fail(GFBP_EINVAL, "null session");
+    if (iters < 1) return fail(GFBP_EINVAL, "iters < 1");
+    return ss->step_fn(ss, iters, static_cast<hipStream_t>(stream));
+}
+
+gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat, int32_t cap, int32_t *n_out,
+                              void *stream) {
+    if (!ss || !out || !n_out) return fail(GFBP_EINVAL, "null argument");
+    *n_out = 0;
+    if (cap <= 0) return GFBP_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = ss->code->info.n;
+    hipLaunchKernelGGL(tiled::k_tiles, dim3(1), dim3(1024), 0, st, ss->dv.done, ss->S, ss->S, 1, ss->dv.list, ss->aux + 1);
+    uint32_t *hcount = static_cast<uint32_t *>(ss->pin);
+    HIP_TRY(hipMemcpyAsync(hcount, ss->aux + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int k = std::min<int>(int(*hcount), cap);
+    if (k == 0) return GFBP_OK;
+    const size_t tot = size_t(k) * n;
+    hipLaunchKernelGGL(k_collect, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, ss->dv, k, n);
+    int32_t *hlist = static_cast<int32_t *>(ss->pin);
+    int32_t *hres = hlist + ss->S;
+    HIP_TRY(hipMemcpyAsync(hlist, ss->dv.list, sizeof(int32_t) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hres, ss->dv.res, sizeof(int32_t) * 2 * k, hipMemcpyDeviceToHost, st));
+    if (xhat) HIP_TRY(hipMemcpyAsync(xhat, ss->dv.xout, tot, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int r = 0; r < k; ++r) {
+        const int slot = hlist[r];
+        out[r].id = ss->id[slot];
+        out[r].iters = hres[2 * r];
+        out[r].converged = hres[2 * r + 1];
+        ss->id[slot] = -1;
+        ss->free_slots.push_back(slot);
+    }
+    std::sort(ss->free_slots.begin(), ss->free_slots.end(), std::greater<int32_t>());
+    ss->running -= k;
+    *n_out = k;
     return GFBP_OK;
 }
 

@@ -54,10 +54,15 @@ struct DevState {
     uint32_t *count;  // [2][2] by iteration parity: frames still iterating, tiles holding them
     int32_t *guards;  // [F]
     int32_t *tiles;   // [2][ntiles] tiles with a running frame, by iteration parity
-    int F;            // frames
+    int F;            // frames (slots)
     int Fp;           // frame stride (whole 64-frame tiles)
-    int nact;         // length of the current tile list
-    const int32_t *act;  // current tile list
+    int nb;           // launch bound on the current tile list (grid = nodes x nb)
+    const int32_t *act;      // current tile list
+    const uint32_t *nact;    // its length, read on the device (<= nb)
+    // per-frame overrides, used by sessions (null: the batch-wide value)
+    const uint8_t *fresh;    // only these frames initialise
+    const uint8_t *chan;     // channel kind of each frame
+    const uint8_t *mark;     // 1 if the frame's source symbols take the Markov prior
 };
 
 struct Snap {

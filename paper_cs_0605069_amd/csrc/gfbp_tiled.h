@@ -48,17 +48,19 @@ struct Item {
     bool ok;
 };
 
-// Wavefront w works on node w / nact and on the (w % nact)-th tile of the
-// list of tiles that still hold a running frame.
+// Wavefront w works on node w / nb and on entry w % nb of the list of tiles
+// that still hold a running frame (entries past the list's current length,
+// read on the device, do nothing).
 template <int P, int LG>
 __device__ __forceinline__ Item item(int nodes, const DevState &s) {
     using Gm = Geo<P, LG>;
     const int w = int(blockIdx.x) * (kBlock / kWave) + int(threadIdx.x) / kWave;
     const int lane = int(threadIdx.x) % kWave;
     Item it;
-    it.node = w / s.nact;
-    it.ok = it.node < nodes;
-    it.tile = it.ok ? s.act[w % s.nact] : 0;
+    it.node = w / s.nb;
+    const int ti = w % s.nb;
+    it.ok = it.node < nodes && ti < int(*s.nact);
+    it.tile = it.ok ? s.act[ti] : 0;
     if (it.tile < 0 || it.tile >= s.Fp / Gm::TF) {  // the list only holds valid tiles; never index past it
         it.ok = false;
         it.tile = 0;
@@ -207,13 +209,16 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
     const int ntiles = s.Fp / Gm::TF;
     const Item it = item<P, LG>(c.n, s);
     if (!it.ok || it.f >= s.F) return;
+    if (s.fresh && !s.fresh[it.f]) return;
     const int j = it.node, f = it.f;
     const size_t fj = size_t(f) * c.n + j;
+    const int channel = s.chan ? int(s.chan[f]) : ch.channel;
+    const bool markov = s.mark ? s.mark[f] != 0 : ch.markov != 0;
     double L[Gm::EL];
-    if (ch.channel == GFBP_CH_BSC || ch.channel == GFBP_CH_BEC) {
+    if (channel == GFBP_CH_BSC || channel == GFBP_CH_BEC) {
         const int rx = ch.rx[fj];
-        const int er = ch.channel == GFBP_CH_BEC ? ch.erasure[fj] : 0;
-        const double fl = ch.channel == GFBP_CH_BSC ? double(ch.param[f]) : 0.0;
+        const int er = channel == GFBP_CH_BEC ? ch.erasure[fj] : 0;
+        const double fl = channel == GFBP_CH_BSC ? double(ch.param[f]) : 0.0;
 #pragma unroll
         for (int r = 0; r < Gm::EL; ++r) {
             const int a = it.g * Gm::EL + r;
@@ -221,12 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
 #pragma unroll
             for (int t = 0; t < P; ++t) {
                 const bool flip = ((a ^ rx) >> t) & 1;
-                if (ch.channel == GFBP_CH_BSC) v *= flip ? fl : (1.0 - fl);
+                if (channel == GFBP_CH_BSC) v *= flip ? fl : (1.0 - fl);
                 else v *= ((er >> t) & 1) ? 0.5 : (flip ? 0.0 : 1.0);
             }
             L[r] = v;
         }
-    } else if (ch.channel == GFBP_CH_BIAWGN) {
+    } else if (channel == GFBP_CH_BIAWGN) {
         const double sg = ch.param[f];
         const double gain = 2.0 / (sg * sg);
         double p0[P], p1[P];
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
         pf[r] = float(L[r]);
         s.L[at<P, LG>(j, it.tile, it.g * Gm::EL + r, it.fw, ntiles)] = pf[r];
     }
-    if (ch.markov && j < c.n_info) {
+    if (markov && j < c.n_info) {
         double pr[Gm::EL];
 #pragma unroll
         for (int r = 0; r < Gm::EL; ++r) pr[r] = double(pf[r]) * double(ch.pi[it.g * Gm::EL + r]);
@@ -327,7 +332,8 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
                                                 int wantQ, const Snap &snap) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
-    const float *pj = (markov && j < c.n_info) ? s.Pr : s.L;
+    const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
+    const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
     double pv[Gm::EL], acc[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
@@ -450,7 +456,8 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
     }
     __syncthreads();
     if (mine) {
-        const float *pj = (markov && j < c.n_info) ? s.Pr : s.L;
+        const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
+        const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
         const float *pb = vec_base<P, LG>(pj, size_t(j), it.tile, ntiles);
         double pv[Gm::EL];
 #pragma unroll
@@ -507,9 +514,10 @@ __device__ __forceinline__ Item block_item(int nodes, const DevState &s) {
     const int b = int(blockIdx.x);
     const int lane = int(threadIdx.x) % kWave;
     Item it;
-    it.node = b / s.nact;
-    it.ok = it.node < nodes;
-    it.tile = it.ok ? s.act[b % s.nact] : 0;
+    it.node = b / s.nb;
+    const int ti = b % s.nb;
+    it.ok = it.node < nodes && ti < int(*s.nact);
+    it.tile = it.ok ? s.act[ti] : 0;
     if (it.tile < 0 || it.tile >= s.Fp / Gm::TF) {
         it.ok = false;
         it.tile = 0;
@@ -561,6 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
     const int ntiles = s.Fp / Gm::TF;
     const Item it = item<P, LG>(c.n_info, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    if (s.mark && !s.mark[it.f]) return;
     const int k = it.node, K = c.n_info;
     double u[Gm::EL], v[Gm::EL];
 #pragma unroll
@@ -591,15 +600,15 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
     for (int q = 0; q < Gm::EL; ++q) s.Pr[at<P, LG>(k, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = float(u[q]);
 }
 
-// Ordered list of the tiles (of TF frames) that hold a frame still iterating
-// after iteration t, for iteration t + 1 (t = 0: before the first iteration).
-// One workgroup of 1024 threads; wavefront ballots and a workgroup scan keep
-// the list in increasing tile order.
-__global__ __launch_bounds__(1024) void k_tiles(DevState s, int TF, int t) {
+// Ordered list of the tiles (of TF frames) holding a frame whose mask byte is
+// set (frames still iterating; or frames just admitted), and its length.  One
+// workgroup of 1024 threads; wavefront ballots and a workgroup scan keep the
+// list in increasing tile order.
+__global__ __launch_bounds__(1024) void k_tiles(const uint8_t *mask, int F, int Fp, int TF, int32_t *out,
+                                                uint32_t *count) {
     __shared__ uint32_t wsum[1024 / kWave];
     __shared__ uint32_t base;
-    const int ntiles = s.Fp / TF;
-    int32_t *out = s.tiles + size_t(t & 1) * ntiles;
+    const int ntiles = Fp / TF;
     const int lane = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
     if (threadIdx.x == 0) base = 0;
     __syncthreads();
@@ -609,14 +618,14 @@ __global__ __launch_bounds__(1024) void k_tiles(DevState s, int TF, int t) {
         if (tile < ntiles)
             for (int fw = 0; fw < TF; ++fw) {
                 const int f = tile * TF + fw;
-                any |= f < s.F && s.active[f];
+                any |= f < F && mask[f];
             }
-        const uint64_t mask = __ballot(any);
-        if (lane == 0) wsum[wv] = uint32_t(__popcll(mask));
+        const uint64_t ballot = __ballot(any);
+        if (lane == 0) wsum[wv] = uint32_t(__popcll(ballot));
         __syncthreads();
         uint32_t off = base;
         for (int w = 0; w < wv; ++w) off += wsum[w];
-        if (any) out[off + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)))] = tile;
+        if (any) out[off + uint32_t(__popcll(ballot & ((uint64_t(1) << lane) - 1)))] = tile;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t tot = 0;
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_tiles(DevState s, int TF, int t) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) s.count[2 * (t & 1) + 1] = base;
+    if (threadIdx.x == 0) *count = base;
 }
 
 // [n][tile][Q][TF] -> [F][n][Q]
