@@ -221,6 +221,22 @@ int32_t gfbp_session_free_slots(const gfbp_session *session);
 /* Frames admitted and not yet collected by poll. */
 int32_t gfbp_session_running(const gfbp_session *session);
 
+/* ---- Batches of sessions as one HIP graph. ----
+ * gfbp_graph_capture records `iters` iterations (even, >= 2) of every session
+ * in sessions[0..n) -- possibly of different codes, fields and schedules --
+ * into one HIP graph, with launch grids covering every slot, so that the graph
+ * stays valid while frames finish and while new frames are admitted between
+ * launches.  gfbp_graph_launch replays it on a stream (no host
+ * synchronisation); gfbp_session_poll collects finished frames as usual.
+ * stream must be a created stream (not the default stream).  The sessions
+ * must outlive the graph; do not call gfbp_session_step on them between
+ * capture and destroy. */
+typedef struct gfbp_graph gfbp_graph;
+gfbp_status gfbp_graph_capture(gfbp_session *const *sessions, int32_t n, int32_t iters, void *stream,
+                               gfbp_graph **out);
+gfbp_status gfbp_graph_launch(gfbp_graph *graph, void *stream);
+gfbp_status gfbp_graph_destroy(gfbp_graph *graph);
+
 /* ---- Kernel shape and its autotuner. ----
  * The decoding kernels spread one frame's q-vector over G lanes with
  * q/G "entries per lane" in registers (EL): a larger EL makes more of the

@@ -31,7 +31,8 @@ EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_work
            "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
            "gfbp_code_get_shape", "gfbp_tune", "gfbp_session_bytes", "gfbp_session_create", "gfbp_session_destroy",
            "gfbp_session_admit", "gfbp_session_step", "gfbp_session_poll", "gfbp_session_free_slots",
-           "gfbp_session_running", "gfbp_last_error", "gfbp_version")
+           "gfbp_session_running", "gfbp_graph_capture", "gfbp_graph_launch", "gfbp_graph_destroy",
+           "gfbp_last_error", "gfbp_version")
 
 
 class CodeDesc(ctypes.Structure):
@@ -133,6 +134,13 @@ def lib():
     L.gfbp_session_free_slots.restype = ctypes.c_int32
     L.gfbp_session_running.argtypes = [ctypes.c_void_p]
     L.gfbp_session_running.restype = ctypes.c_int32
+    L.gfbp_graph_capture.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    L.gfbp_graph_capture.restype = ctypes.c_int32
+    L.gfbp_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.gfbp_graph_launch.restype = ctypes.c_int32
+    L.gfbp_graph_destroy.argtypes = [ctypes.c_void_p]
+    L.gfbp_graph_destroy.restype = ctypes.c_int32
     L.gfbp_last_error.restype = ctypes.c_char_p
     L.gfbp_version.restype = ctypes.c_char_p
     _lib = L
@@ -426,3 +434,30 @@ def frames_for_session(frames_list, device="cuda"):
     y = np.concatenate([f.y if f.y is not None else np.zeros((f.F, n, p), np.float32) for f in frames_list]) if need_y else None
     dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
     return {"F": F, "channel": dev(ch), "param": dev(param), "rx": dev(rx), "erasure": dev(er), "y": dev(y)}
+
+
+class Graph:
+    """``gfbp_graph_*``: `iters` iterations of several sessions as one HIP graph."""
+
+    def __init__(self, sessions, iters: int, stream):
+        arr = (ctypes.c_void_p * len(sessions))(*[x.handle.value for x in sessions])
+        h = ctypes.c_void_p()
+        _check(lib().gfbp_graph_capture(ctypes.cast(arr, ctypes.c_void_p), len(sessions), int(iters),
+                                        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), "gfbp_graph_capture")
+        self.handle = h
+        self.sessions = list(sessions)
+        self.iters = iters
+
+    def launch(self, stream):
+        _check(lib().gfbp_graph_launch(self.handle, ctypes.c_void_p(stream.cuda_stream)), "gfbp_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gfbp_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

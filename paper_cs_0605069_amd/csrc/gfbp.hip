@@ -411,6 +411,12 @@ gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out
 // running slots, finished slots are collected by poll and reused.
 }  // namespace
 
+struct gfbp_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int iters;
+};
+
 // Device view of a session (trivially copyable: passed to kernels).
 struct SessDev {
     DevState st;  // message state for S slots (F = S)
@@ -440,7 +446,7 @@ struct gfbp_session {
     void *pin = nullptr;              // pinned host staging
     size_t pin_bytes = 0;
     gfbp_status (*init_fn)(gfbp_session *, int, hipStream_t) = nullptr;
-    gfbp_status (*step_fn)(gfbp_session *, int, hipStream_t) = nullptr;
+    gfbp_status (*step_fn)(gfbp_session *, int, hipStream_t, bool) = nullptr;
 };
 
 namespace {
@@ -538,12 +544,14 @@ struct SessionRun {
         HIP_TRY(hipGetLastError());
         return GFBP_OK;
     }
-    // `iters` iterations of every running slot, no host synchronisation
-    static gfbp_status step(gfbp_session *ss, int iters, hipStream_t st) {
+    // `iters` iterations of every running slot, no host synchronisation.
+    // full: launch grids for every slot (for graph capture), not just for the
+    // slots running now.
+    static gfbp_status step(gfbp_session *ss, int iters, hipStream_t st, bool full) {
         const gfbp_code *code = ss->code;
         const DevCode &c = code->dev;
         DevState s = ss->dv.st;
-        s.nb = std::min(ss->ntiles, ss->running);
+        s.nb = full ? ss->ntiles : std::min(ss->ntiles, ss->running);
         if (s.nb == 0) return GFBP_OK;
         const Snap sn{nullptr, nullptr};
         const int needQ = ss->markov;
@@ -1139,7 +1147,7 @@ gfbp_status gfbp_session_admit(gfbp_session *ss, int32_t n, const int64_t *ids, 
 gfbp_status gfbp_session_step(gfbp_session *ss, int32_t iters, void *stream) {
     if (!ss) return fail(GFBP_EINVAL, "null session");
     if (iters < 1) return fail(GFBP_EINVAL, "iters < 1");
-    return ss->step_fn(ss, iters, static_cast<hipStream_t>(stream));
+    return ss->step_fn(ss, iters, static_cast<hipStream_t>(stream), false);
 }
 
 gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat, int32_t cap, int32_t *n_out,
@@ -1174,6 +1182,55 @@ gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat
     std::sort(ss->free_slots.begin(), ss->free_slots.end(), std::greater<int32_t>());
     ss->running -= k;
     *n_out = k;
+    return GFBP_OK;
+}
+
+gfbp_status gfbp_graph_capture(gfbp_session *const *sessions, int32_t n, int32_t iters, void *stream,
+                               gfbp_graph **out) {
+    if (!sessions || n < 1 || !out) return fail(GFBP_EINVAL, "null argument");
+    *out = nullptr;
+    if (iters < 2 || iters % 2) return fail(GFBP_EINVAL, "iters must be even and >= 2");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!st) return fail(GFBP_EINVAL, "graph capture needs a created stream, not the default stream");
+    for (int k = 0; k < n; ++k)
+        if (!sessions[k]) return fail(GFBP_EINVAL, "null session");
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    gfbp_status rs = GFBP_OK;
+    for (int k = 0; k < n && rs == GFBP_OK; ++k) rs = sessions[k]->step_fn(sessions[k], iters, st, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rs != GFBP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rs;
+    }
+    if (ec != hipSuccess) return fail(GFBP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(GFBP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    gfbp_graph *gr = new (std::nothrow) gfbp_graph{graph, exec, iters};
+    if (!gr) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(GFBP_ENOMEM, "host allocation");
+    }
+    *out = gr;
+    return GFBP_OK;
+}
+
+gfbp_status gfbp_graph_launch(gfbp_graph *g, void *stream) {
+    if (!g) return fail(GFBP_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return GFBP_OK;
+}
+
+gfbp_status gfbp_graph_destroy(gfbp_graph *g) {
+    if (!g) return GFBP_OK;
+    const hipError_t e1 = hipGraphExecDestroy(g->exec), e2 = hipGraphDestroy(g->graph);
+    delete g;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(GFBP_EHIP, "destroying the graph");
     return GFBP_OK;
 }
 

@@ -428,3 +428,87 @@ def make_frames(code: Code, enc: Encoder, F: int, seed: int, channel: str, param
     if channel == "biawgn":
         return Frames("biawgn", prm, c, y=biawgn(c, p, prm, seed))
     raise ValueError(channel)
+
+
+# --------------------------------------------------------------------------
+# syndrome-form frames and the mixed-shape pool
+# --------------------------------------------------------------------------
+def gf_mul_table(p: int, poly: int | None = None) -> np.ndarray:
+    """[q][q] products in GF(2^p) (carry-less multiplication, reduced)."""
+    poly = DEFAULT_POLY[p] if poly is None else poly
+    q = 1 << p
+    a = np.arange(q, dtype=np.int64)[:, None]
+    b = np.arange(q, dtype=np.int64)[None, :]
+    r = np.zeros((q, q), dtype=np.int64)
+    for i in range(p):
+        r ^= np.where((b >> i) & 1, a << i, 0)
+    for d in range(2 * p - 2, p - 1, -1):
+        r = np.where((r >> d) & 1, r ^ (poly << (d - p)), r)
+    return r.astype(np.uint8)
+
+
+def syndromes(code: Code, x: np.ndarray) -> np.ndarray:
+    """z = H x for every row of x [F][n]."""
+    T = gf_mul_table(code.p, code.poly)
+    prod = T[code.coef[None, :], x[:, code.col]]  # [F][E]
+    z = np.zeros((x.shape[0], code.m), dtype=np.uint8)
+    rows = code.row_of_edge()
+    for i0 in range(0, code.E, 1 << 16):
+        sl = slice(i0, min(code.E, i0 + (1 << 16)))
+        np.bitwise_xor.at(z.T, rows[sl], prod[:, sl].T)
+    return z
+
+
+def make_coset_frames(code: Code, F: int, seed: int, channel: str, param, source: str = "iid",
+                      markov: np.ndarray | None = None) -> Frames:
+    """Syndrome-form frames (the paper's Eq. (2) setting): x has source
+    symbols in columns 0..n_info-1 (i.i.d. or Markov) and uniform symbols
+    elsewhere; the decoder is given z = H x and the channel output of x."""
+    K = code.n_info
+    rng = np.random.default_rng([seed, 3])
+    x = rng.integers(0, code.q, size=(F, code.n)).astype(np.uint8)
+    if source == "markov":
+        x[:, :K] = markov_source(F, K, markov, stationary(markov), seed)
+    prm = np.broadcast_to(np.asarray(param, dtype=np.float64), (F,)).copy()
+    p = code.p
+    if channel == "bsc":
+        fr = Frames("bsc", prm, x, rx=bsc(x, p, prm, seed))
+    elif channel == "bec":
+        rx, er = bec(x, p, prm, seed)
+        fr = Frames("bec", prm, x, rx=rx, erasure=er)
+    elif channel == "biawgn":
+        fr = Frames("biawgn", prm, x, y=biawgn(x, p, prm, seed))
+    else:
+        raise ValueError(channel)
+    fr.syndrome = syndromes(code, x)
+    return fr
+
+
+def channel_for(kind: str, ebn0_db: float, rate: float) -> float:
+    """Channel parameter for a frame drawn at Eb/N0 (dB): sigma for BI-AWGN;
+    for BSC and BEC the parameter whose capacity equals the BI-AWGN capacity
+    at that sigma (1 - h2(f) = C, eps = 1 - C)."""
+    sigma = sigma_from_ebn0(ebn0_db, rate)
+    if kind == "biawgn":
+        return sigma
+    cap = biawgn_capacity(sigma)
+    return bsc_matching(cap) if kind == "bsc" else 1.0 - cap
+
+
+def mixed_pool(n_codes: int, seed: int, qs=(4, 16, 64), n_range=(256, 8000), q_weights=None) -> list[Code]:
+    """Codes for uneven batches: q from qs (optionally weighted), column weight
+    2 or 3, rate 1/3 or 1/2, n uniform in n_range (even), m = round((1-R) n),
+    row degrees balanced; n_info = n - m (source columns first)."""
+    rng = np.random.default_rng([seed, 7])
+    out = []
+    for k in range(n_codes):
+        q = int(rng.choice(qs, p=q_weights))
+        dv = int(rng.choice([2, 3]))
+        R = float(rng.choice([1 / 3, 1 / 2]))
+        n = int(rng.integers(n_range[0] // 2, n_range[1] // 2 + 1)) * 2
+        m = int(round((1 - R) * n))
+        c = make_code(n, m, dv, q, seed=seed * 1000 + k)
+        c.n_info = n - m
+        c.meta.update(rate=R, d_v=dv)
+        out.append(c)
+    return out
