@@ -1,0 +1,67 @@
+"""Serving loop: Poisson arrivals over several codes, one session per code.
+
+Every served frame must equal, bitwise, its gfbp_decode_batch result (decoded
+alone with its own channel group and prior), whatever it was batched with;
+converged frames must satisfy their syndrome; every request is answered once.
+"""
+import numpy as np
+import pytest
+
+from paper_cs_0605069_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gfbp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_cs_0605069_amd as g
+
+    g.lib()
+    return g
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_served_frames_equal_alone_decoding(gfbp, schedule):
+    import torch
+    from paper_cs_0605069_amd import serving
+
+    pool = wl.mixed_pool(4, seed=71, n_range=(256, 900))
+    queues, markov = serving.make_requests(pool, 500, rate=20000.0, seed=72)
+    srv = serving.Server(queues, slots=64, schedule=schedule, max_iter=40, budget_bytes=8 << 30, step_iters=3,
+                         markov=markov, keep_results=True)
+    st = srv.run()
+    assert st.done == 500 and len(st.results) == 500
+    assert len(st.latency) == 500 and min(st.latency) >= 0
+    for cq in queues:
+        M, pi = markov[cq.code.q]
+        for g, m, gids in cq.groups:
+            kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
+            out = gfbp.decode_batch(cq.dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40, **kw)
+            torch.cuda.synchronize()
+            it, cv, xh = out["iters"].cpu().numpy(), out["converged"].cpu().numpy(), out["xhat"].cpu().numpy()
+            for f, gid in enumerate(gids):
+                s_it, s_cv, s_xh = st.results[int(gid)]
+                assert s_it == it[f] and s_cv == cv[f] and np.array_equal(s_xh, xh[f]), \
+                    f"q={cq.code.q} n={cq.code.n} {g.channel} markov={m} frame {f}"
+                if s_cv:
+                    assert np.array_equal(wl.syndromes(cq.code, s_xh[None])[0], g.syndrome[f])
+
+
+def test_memory_budget_defers_sessions(gfbp):
+    from paper_cs_0605069_amd import serving
+
+    pool = wl.mixed_pool(3, seed=73, n_range=(256, 600))
+    queues, markov = serving.make_requests(pool, 150, rate=50000.0, seed=74)
+    dcodes = [gfbp.DeviceCode(cq.code) for cq in queues]
+    need = [gfbp.Session.bytes_needed(d, 64, "pus", markov=True, has_syndrome=True) for d in dcodes]
+    for cq, d in zip(queues, dcodes):
+        cq.dcode = d
+    # room for the largest session only: sessions run one after another
+    srv = serving.Server(queues, slots=64, schedule="pus", max_iter=30, budget_bytes=max(need), markov=markov,
+                         autotune=False)
+    st = srv.run()
+    assert st.done == 150
+    assert srv.refused > 0
