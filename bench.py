@@ -84,6 +84,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="pus,sus")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shape instead of autotuning")
+    ap.add_argument("--shapes", default="", help="fix entries per lane instead of autotuning, e.g. pus=8,sus=4")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_gf16_n2000_bi-awgn.txt"),
+                    help="measured HBM traffic summary to report beside the roofline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: frames are independent and this decoder has no multi-GPU path "
@@ -106,7 +111,12 @@ def main():
                 "converged": torch.empty(FRAMES, dtype=torch.uint8, device="cuda"),
                 "guards": torch.empty(FRAMES, dtype=torch.int32, device="cuda")} for s in scheds}
     shapes = {}
-    if not args.no_tune:
+    if args.shapes:
+        for kv in args.shapes.split(","):
+            k, v = kv.split("=")
+            dcode.set_shape(k, int(v))
+        shapes = {s: dcode.shape(s) for s in scheds}
+    elif not args.no_tune:
         eb, d = dev_points[len(dev_points) // 2]
         for s in scheds:
             shapes[s] = gfbp.tune(dcode, d, schedule=s, trial_iters=3, workspace=ws[s], outputs=outs[s])
@@ -140,6 +150,10 @@ def main():
     wall = time.perf_counter() - t0
     gfbp.profile_enable(False)
     prof = gfbp.profile_read()
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
 
     EQ = code.E * code.q
     total_eq = sum(float(r["iters"].sum()) * EQ for r in rec)
@@ -165,10 +179,18 @@ def main():
     if dom:
         d = prof[dom]
         ach = d["algo_bytes"] / (d["total_ms"] / 1e3)
+        algo = d["algo_bytes"] / d["launches"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": None,
                 "avg_launch_ms": d["total_ms"] / d["launches"], "launches": d["launches"],
-                "algo_bytes_per_launch": d["algo_bytes"] / d["launches"]}
+                "algo_bytes_per_launch": algo}
+        from paper_cs_0605069_amd.profiling import read_traffic
+
+        tr = read_traffic(args.traffic)
+        if tr and dom in tr["kernels"] and all(int(tr["shapes"].get(s, -1)) == shapes[s] for s in scheds):
+            roof["traffic"] = tr["kernels"][dom]["bytes_per_dispatch"]
+            roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+            roof["traffic_over_algorithmic"] = roof["traffic"] / algo
     kernels = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
                    "share_of_gpu_time": v["total_ms"] / max(1e-9, sum(x["total_ms"] for x in prof.values())),
                    "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0}
