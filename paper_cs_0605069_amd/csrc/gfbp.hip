@@ -208,9 +208,10 @@ Bytes bytes_per_frame(const gfbp_code *code, int needQ, int has_z) {
 
 // Kernel shape for a code and schedule.  Degree class "small" (rows <= 6,
 // columns <= 4) keeps up to 6 siblings' transforms in registers and allows
-// EL = 2, 4 or 8 entries per lane; the general class (rows <= 16, columns <= 8)
-// allows EL = 2 or 4.  The default is the largest allowed EL (at most q);
-// gfbp_code_set_shape / gfbp_tune choose another.
+// EL = 2, 4 or 8 entries per lane (and 16 for the sequential schedule, whose
+// column step keeps one transform at a time); the general class (rows <= 16,
+// columns <= 8) allows EL = 2 or 4.  EL never exceeds q.  The default is the
+// largest allowed EL; gfbp_code_set_shape / gfbp_tune choose another.
 struct Shape {
     bool small;
     int lel;  // log2 of entries per lane
@@ -220,11 +221,14 @@ inline bool small_class(const gfbp_code *code) {
     return code->info.max_row_degree <= 6 && code->info.max_col_degree <= 4;
 }
 
-inline int max_lel(const gfbp_code *code) { return std::min(code->info.p, small_class(code) ? 3 : 2); }
+inline int max_lel(const gfbp_code *code, int schedule) {
+    const int cap = small_class(code) ? (schedule == GFBP_SUS ? 4 : 3) : 2;
+    return std::min(code->info.p, cap);
+}
 
-inline bool allowed_el(const gfbp_code *code, int el) {
+inline bool allowed_el(const gfbp_code *code, int schedule, int el) {
     if (el == 0) return true;
-    for (int l = 1; l <= max_lel(code); ++l)
+    for (int l = 1; l <= max_lel(code, schedule); ++l)
         if (el == (1 << l)) return true;
     return false;
 }
@@ -233,9 +237,9 @@ inline Shape shape_of(const gfbp_code *code, int schedule) {
     Shape sh;
     sh.small = small_class(code);
     const int el = code->el[schedule == GFBP_SUS ? 1 : 0];
-    int lel = max_lel(code);
+    int lel = max_lel(code, schedule);
     if (el > 0)
-        for (int l = 1; l <= max_lel(code); ++l)
+        for (int l = 1; l <= max_lel(code, schedule); ++l)
             if (el == (1 << l)) lel = l;
     sh.lel = lel;
     return sh;
@@ -267,12 +271,13 @@ struct TiledLaunch {
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                           Snap sn, const int32_t *cols, int nc) {
         hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
-                           dim3(DVM * kWave), 0, st, c, s, z, markov, wantQ, sn, cols, nc);
+                           dim3(unsigned(std::min(c.max_dv, DVM)) * kWave), 0, st, c, s, z, markov, wantQ, sn, cols,
+                           nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))), dim3(DVM * kWave), 0, st, c,
-                           s, z, markov, wantQ, sn);
+        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
+                           dim3(unsigned(std::min(c.max_dv, DVM)) * kWave), 0, st, c, s, z, markov, wantQ, sn);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
         hipLaunchKernelGGL((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
@@ -287,7 +292,7 @@ struct TiledLaunch {
     }
     static void vectors(hipStream_t st, const float *src, int n, const DevState &s, float *out) {
         const size_t tot = size_t(n) * s.F * (1 << P);
-        hipLaunchKernelGGL((tiled::k_out_vectors<P, LG>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, src, n,
+        hipLaunchKernelGGL((tiled::k_out_vectors<P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, src, n,
                            s.F, s.Fp, out);
     }
 };
@@ -384,7 +389,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
 template <int P, int LEL>
 gfbp_status run_lel(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
                     int needQ, bool small) {
-    if constexpr (LEL <= 3 && LEL <= P) {
+    if constexpr (LEL <= 4 && LEL <= P) {
         if (small) return run_batch<P, TiledLaunch<P, P - LEL, 6, 4>>(code, b, out, s, st, needQ);
     }
     if constexpr (LEL <= 2 && LEL <= P) {
@@ -401,6 +406,7 @@ gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out
         case 1: return run_lel<P, 1>(code, b, out, s, st, needQ, sh.small);
         case 2: return run_lel<P, 2>(code, b, out, s, st, needQ, sh.small);
         case 3: return run_lel<P, 3>(code, b, out, s, st, needQ, sh.small);
+        case 4: return run_lel<P, 4>(code, b, out, s, st, needQ, sh.small);
         default: return fail(GFBP_EUNSUPPORTED, "bad shape");
     }
 }
@@ -589,7 +595,7 @@ struct SessionRun {
 
 template <int P, int LEL>
 bool session_bind_lel(gfbp_session *ss, bool small) {
-    if constexpr (LEL <= 3 && LEL <= P) {
+    if constexpr (LEL <= 4 && LEL <= P) {
         if (small) {
             using K = TiledLaunch<P, P - LEL, 6, 4>;
             ss->init_fn = &SessionRun<P, K>::init;
@@ -617,6 +623,7 @@ bool session_bind(gfbp_session *ss) {
         case 1: return session_bind_lel<P, 1>(ss, sh.small);
         case 2: return session_bind_lel<P, 2>(ss, sh.small);
         case 3: return session_bind_lel<P, 3>(ss, sh.small);
+        case 4: return session_bind_lel<P, 4>(ss, sh.small);
         default: return false;
     }
 }
@@ -851,7 +858,7 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     c->level_sibs = std::move(level_sibs);
     c->level_edges = std::move(level_edges);
     c->level_cols = reinterpret_cast<const int32_t *>(base + o_lc);
-    c->dev = DevCode{n, m, E, q, p, d->n_info,
+    c->dev = DevCode{n, m, E, q, p, d->n_info, max_dv,
                      reinterpret_cast<const int32_t *>(base + o_rp), reinterpret_cast<const int32_t *>(base + o_col),
                      reinterpret_cast<const uint8_t *>(base + o_coef), reinterpret_cast<const int32_t *>(base + o_cp),
                      reinterpret_cast<const int32_t *>(base + o_ce), reinterpret_cast<const int32_t *>(base + o_er),
@@ -942,7 +949,8 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
 gfbp_status gfbp_code_set_shape(gfbp_code *c, int32_t schedule, int32_t entries_per_lane) {
     if (!c) return fail(GFBP_EINVAL, "null code");
     if (schedule != GFBP_PUS && schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
-    if (!allowed_el(c, entries_per_lane)) return fail(GFBP_EUNSUPPORTED, "entries per lane not available for this code");
+    if (!allowed_el(c, schedule, entries_per_lane))
+        return fail(GFBP_EUNSUPPORTED, "entries per lane not available for this code and schedule");
     c->el[schedule == GFBP_SUS ? 1 : 0] = entries_per_lane;
     return GFBP_OK;
 }
@@ -967,7 +975,7 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     to.snap_q = to.snap_r = to.snap_Q = nullptr;
     double best_t = 1e300;
     int best = 0;
-    for (int l = 1; l <= max_lel(c); ++l) {
+    for (int l = 1; l <= max_lel(c, b->schedule); ++l) {
         c->el[slot] = 1 << l;
         double t = 0;
         for (int rep = 0; rep < 2; ++rep) {  // the first run warms up, the second is timed

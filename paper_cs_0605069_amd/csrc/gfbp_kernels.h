@@ -1,24 +1,16 @@
-// Device-side building blocks of the GF(2^p) belief-propagation decoder.
+// Device-side building blocks of the GF(2^p) belief-propagation decoder:
+// the graph and state views passed to every kernel, multiplication by a
+// fixed field element, and lane exchanges inside a 64-lane wavefront.
 //
-// Thread mapping: one "group" of Q = 2^P consecutive lanes holds one q-vector
-// of one frame, lane k holding entry k; a 64-lane wavefront holds 64/Q frames
-// that all work on the same graph node, so every index into the graph is
-// wavefront-uniform and every message access stays inside one contiguous
-// 256-byte run.
-//
-// Message layout (frame-interleaved, edge-major): message[e][f][a] with f the
-// frame and a the field element, messages kept as probabilities in float32
-// (which holds small probabilities to full relative precision).
-//
-// Check-node arithmetic (Eq. (3)): with y = h x the weighted symbol of an
-// edge, the check constraint is an XOR-sum of the y's, so the sum over
-// configurations is an XOR-convolution of the siblings' distributions of y,
-// q~(y) = q(h^-1 y).  The Walsh-Hadamard transform (WHT) turns XOR-convolution
-// into a pointwise product.  The permutation by h^-1 is folded into the load
-// address (lane y reads entry h^-1 y), the transforms and products run in
-// float64 registers (a float32 transform loses every probability below ~1e-7
-// of the largest one to cancellation), and the result S(y) goes back to
-// r(a) = S(z + h a) by the store address a = h^-1 (y + z).
+// Every per-frame vector array (messages, likelihoods, posteriors) is stored
+// as array[node][frame][a]: the q entries of one frame's vector are
+// contiguous and consecutive frames follow each other, frames padded to a
+// whole number of 64-frame tiles.  Messages are float32 probabilities (which
+// keep small probabilities to full relative precision).  The variable-to-
+// check messages of edge e are stored in the weighted domain,
+// q~_e(y) = q_e(h_e^-1 y) (entry y holds the probability that h_e x = y),
+// which is what the check update consumes; every other array is indexed by
+// the field element a itself.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,6 +24,7 @@ constexpr int kDvMax = 8;   // GFBP_MAX_COL_DEGREE
 
 struct DevCode {
     int n, m, E, q, p, n_info;
+    int max_dv;               // largest column degree
     const int32_t *row_ptr;   // [m+1]
     const int32_t *col;       // [E]
     const uint8_t *coef;      // [E]
@@ -43,7 +36,7 @@ struct DevCode {
 };
 
 struct DevState {
-    float *Qm;        // [E][F][Q] variable-to-check messages q
+    float *Qm;        // [E][F][Q] variable-to-check messages, weighted domain q~(y) = q(h^-1 y)
     float *R;         // [E][F][Q] check-to-variable messages r (PUS only)
     float *L;         // [n][F][Q] normalised channel likelihoods
     float *Pr;        // [K][F][Q] normalised likelihood x Markov prior (Markov only)
@@ -82,10 +75,11 @@ __device__ __forceinline__ int gf_apply(uint64_t packed, int y) {
 }
 
 // ---------------------------------------------------------------- group ops
-// Exchange with lane (lane ^ MASK) without the LDS crossbar: DPP quad
-// permutes for masks 1 and 2, half-row mirror followed by a quad reversal for
-// 4, a 16-lane row rotation by 8 for 8, and the gfx950 row swaps
-// v_permlane16_swap / v_permlane32_swap for 16 and 32.
+// Exchange with lane (lane ^ MASK), each in one step that reads the partner
+// lane directly (the lanes of one frame may be the only active ones): DPP
+// quad permutes for masks 1 and 2, an xor swizzle for 4, a 16-lane row
+// rotation by 8 for 8, and the gfx950 row swaps v_permlane16_swap /
+// v_permlane32_swap for 16 and 32.
 template <int MASK>
 __device__ __forceinline__ uint32_t xchg_u32(uint32_t v) {
     const int x = int(v);
@@ -94,8 +88,9 @@ __device__ __forceinline__ uint32_t xchg_u32(uint32_t v) {
     } else if constexpr (MASK == 2) {
         return uint32_t(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
     } else if constexpr (MASK == 4) {
-        const int t = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);      // row_half_mirror: i -> 7-i
-        return uint32_t(__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false));   // quad_perm [3,2,1,0]
+        // swizzle in bit-mask mode: and 0x1F, or 0, xor 4 (one step: the value
+        // comes straight from the partner lane, whatever the other lanes do)
+        return uint32_t(__builtin_amdgcn_ds_swizzle(x, 0x101F));
     } else if constexpr (MASK == 8) {
         return uint32_t(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));  // row_ror:8
     } else if constexpr (MASK == 16) {
@@ -125,58 +120,34 @@ __device__ __forceinline__ double xchg(double v) {
     return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
 }
 
-template <int P, typename T>
-__device__ __forceinline__ T grp_gather(T v, int src_in_group) {
-    return __shfl(v, src_in_group, 1 << P);
-}
-
-// Unnormalised Walsh-Hadamard transform across the Q lanes of a group:
-// out(k) = sum_y v(y) (-1)^popcount(k & y).  Stage S pairs lanes that differ
-// in bit S.
-template <int P, int S = 0, typename T>
-__device__ __forceinline__ T wht(T v, int k) {
-    if constexpr (S < P) {
-        const T o = xchg<(1 << S)>(v);
-        v = (k & (1 << S)) ? (o - v) : (v + o);
-        return wht<P, S + 1>(v, k);
+// Row swap of two registers (gfx950 v_permlane16_swap / v_permlane32_swap):
+// for MASK = 32 the upper half-wave (lanes 32..63) of `a` trades places with
+// the lower half-wave of `b`; for MASK = 16 the odd 16-lane rows of `a` with
+// the even rows of `b`.  Afterwards a lane whose MASK bit is 0 holds its own
+// a and its partner's a (in b); a lane whose bit is 1 holds its partner's b
+// (in a) and its own b.
+template <int MASK>
+__device__ __forceinline__ void row_swap(uint32_t &a, uint32_t &b) {
+    if constexpr (MASK == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
     } else {
-        return v;
+        static_assert(MASK == 32, "row swap mask");
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
     }
 }
 
-// Sum over the group, bitwise identical on every lane.
-template <int P, int S = 0, typename T>
-__device__ __forceinline__ T grp_sum(T v) {
-    if constexpr (S < P) {
-        return grp_sum<P, S + 1>(v + xchg<(1 << S)>(v));
-    } else {
-        return v;
-    }
-}
-
-// Index of the largest entry, the smallest index among equal maxima.
-template <int P, int S = 0>
-__device__ __forceinline__ int grp_argmax(float v, int k) {
-    if constexpr (S < P) {
-        const float ov = xchg<(1 << S)>(v);
-        const int oi = xchg<(1 << S)>(k);
-        const bool take = ov > v || (ov == v && oi < k);
-        return grp_argmax<P, S + 1>(take ? ov : v, take ? oi : k);
-    } else {
-        return k;
-    }
-}
-
-// v / sum over the group; uniform 1/Q (and a guard event) when the sum is
-// zero or not finite.
-template <int P>
-__device__ __forceinline__ double grp_normalise(double v, int32_t *guards, int f, int k) {
-    const double s = grp_sum<P>(v);
-    if (!(s > 0.0) || !isfinite(s)) {
-        if (k == 0) atomicAdd(&guards[f], 1);
-        return 1.0 / double(1 << P);
-    }
-    return v / s;
+template <int MASK>
+__device__ __forceinline__ void row_swap(double &a, double &b) {
+    const uint64_t ua = uint64_t(__double_as_longlong(a)), ub = uint64_t(__double_as_longlong(b));
+    uint32_t al = uint32_t(ua), ah = uint32_t(ua >> 32), bl = uint32_t(ub), bh = uint32_t(ub >> 32);
+    row_swap<MASK>(al, bl);
+    row_swap<MASK>(ah, bh);
+    a = __longlong_as_double((long long)((uint64_t(ah) << 32) | al));
+    b = __longlong_as_double((long long)((uint64_t(bh) << 32) | bl));
 }
 
 }  // namespace gfbp

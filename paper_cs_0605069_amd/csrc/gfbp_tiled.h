@@ -1,33 +1,41 @@
 // Decoder kernels for gfx950: one kernel family, tiled by (frames x lanes).
 //
 // Thread mapping.  A q-vector (q = 2^P) of one frame is spread over
-// G = 2^LG consecutive lanes, each holding EL = q/G entries in registers:
+// G = 2^LG lanes, each holding EL = q/G consecutive entries in registers:
 // lane g of the frame holds entries y = g*EL + r, r = 0..EL-1.  A 64-lane
-// wavefront therefore holds TF = 64/G frames, all working on the same graph
-// node, so every index into the graph (and each edge coefficient h) is
-// wavefront-uniform.  Walsh-Hadamard butterflies over the EL register bits
-// are plain register arithmetic; only the LG lane bits need lane exchanges
-// (DPP), and normalisation sums / decisions need LG exchange steps.
-// G = 1 puts a whole vector in one lane (no exchanges at all); the kernels
-// pick EL = 8 (4 for rows longer than 8) so that the register budget is the
-// same for every q.
+// wavefront holds TF = 64/G frames, all working on the same graph node, so
+// every index into the graph (and each edge coefficient h) is
+// wavefront-uniform.  Lane = g*TF + fw: the frame index fills the low lane
+// bits and g the high ones, so the lanes of one frame differ in the top LG
+// lane bits (exchange masks TF, 2TF, ..., 32).
 //
-// Layout.  Every per-frame vector array is stored as
-//   array[node][tile][a][fw]   (frame f = tile*TF + fw, frames padded to Fp)
-// so that, for a fixed entry a, the TF frames of a wavefront are adjacent.
-// Loads and stores of entry a for a wavefront touch G runs of TF*4 bytes.
+// Memory.  Arrays are [node][frame][a] (frames padded to whole 64-frame
+// tiles), so a lane's EL entries are contiguous and the wavefront's TF
+// frames form one contiguous run of TF*q floats: every load and store of a
+// vector is a 16-byte-per-lane (or 8-byte) access covering whole cache lines.
+// Where the field element multiplies the index (the weighted domain of the
+// check side versus the symbol domain of the variable side), values pass
+// through a per-wavefront LDS row buffer instead of scattered global accesses.
 //
 // Check node (Eq. (3)).  With y = h x the weighted symbol of an edge, a
 // check constrains the XOR-sum of the y's, so the sum over configurations is
-// the XOR-convolution of the siblings' distributions q~(y) = q(h^-1 y).  The
-// Walsh-Hadamard transform (WHT) turns that into a pointwise product.  The
-// permutation by h^-1 is folded into the load address (entry h^-1 y is read
-// for position y); the syndrome z is folded into the transform as the sign
-// pattern (-1)^popcount(z & k), which shifts the result by z; the inverse
-// transform gives T(y) = S(y + z) and r(a) = T(h a) is stored by writing
-// position y to entry h^-1 y.  Transforms, products and normalisations run in
-// float64 (a float32 transform loses every probability below ~1e-7 of the
-// largest to cancellation); messages are stored as float32 probabilities.
+// the XOR-convolution of the siblings' distributions q~(y) = q(h^-1 y), which
+// the q-messages store directly.  The Walsh-Hadamard transform (WHT) turns
+// that into a pointwise product; the syndrome z is folded into the product as
+// the sign pattern (-1)^popcount(z & k), which shifts the result by z; the
+// inverse transform gives T(y) = S(y + z) and r(a) = T(h a).  Transforms,
+// products and normalisations run in float64 (a float32 transform loses every
+// probability below ~1e-7 of the largest to cancellation).
+//
+// Transform layout.  The WHT is a butterfly over each of the P index bits.
+// Register bits are local.  The lane bits with masks 32 and 16 use the row
+// swaps: one swap per pair of registers hands each lane the two operands of a
+// butterfly, and afterwards that lane bit and the paired register bit have
+// traded places.  So the forward transform leaves the entries in a
+// transposed order (tindex gives the transform index of each register), the
+// products are pointwise in that order, and the inverse transform, the same
+// routine again, restores the natural order.  Lane bits with smaller masks
+// (G > 4) exchange with DPP and combine in place.
 #pragma once
 #include "gfbp_kernels.h"
 
@@ -40,13 +48,30 @@ struct Geo {
     static constexpr int G = 1 << LG;        // lanes per frame
     static constexpr int LEL = P - LG;       // log2 entries per lane
     static constexpr int EL = 1 << LEL;      // entries per lane
-    static constexpr int TF = kWave >> LG;   // frames per wavefront
+    static constexpr int LTF = 6 - LG;       // log2 frames per wavefront
+    static constexpr int TF = 1 << LTF;      // frames per wavefront
+    static constexpr int QS = Q + 4;         // LDS row stride (floats): 16-byte aligned rows, banks staggered
+    static constexpr int PERM = TF * QS;     // LDS floats per wavefront
+    // lane bit of mask 32 (g bit LG-1) pairs with register bit LEL-1; mask 16
+    // (g bit LG-2) with register bit LEL-2
+    static constexpr bool S32 = LG >= 1 && LEL >= 1;
+    static constexpr bool S16 = LG >= 2 && LEL >= 2;
+    static constexpr int NSWAP = int(S32) + int(S16);
 };
 
 struct Item {
     int node, tile, fw, g, f;
     bool ok;
 };
+
+template <int P, int LG>
+__device__ __forceinline__ void lane_of(Item &it) {
+    using Gm = Geo<P, LG>;
+    const int lane = int(threadIdx.x) % kWave;
+    it.fw = lane & (Gm::TF - 1);
+    it.g = lane >> Gm::LTF;
+    it.f = it.tile * Gm::TF + it.fw;
+}
 
 // Wavefront w works on node w / nb and on entry w % nb of the list of tiles
 // that still hold a running frame (entries past the list's current length,
@@ -55,7 +80,6 @@ template <int P, int LG>
 __device__ __forceinline__ Item item(int nodes, const DevState &s) {
     using Gm = Geo<P, LG>;
     const int w = int(blockIdx.x) * (kBlock / kWave) + int(threadIdx.x) / kWave;
-    const int lane = int(threadIdx.x) % kWave;
     Item it;
     it.node = w / s.nb;
     const int ti = w % s.nb;
@@ -65,18 +89,66 @@ __device__ __forceinline__ Item item(int nodes, const DevState &s) {
         it.ok = false;
         it.tile = 0;
     }
-    it.fw = lane >> LG;
-    it.g = lane & (Gm::G - 1);
-    it.f = it.tile * Gm::TF + it.fw;
+    lane_of<P, LG>(it);
     return it;
 }
 
-// Base of vector `node` for tile `tile`: entry a of frame fw is at
-// base[a * TF + fw].
-template <int P, int LG, typename T>
-__device__ __forceinline__ T *vec_base(T *arr, size_t node, int tile, int ntiles) {
+// Workgroup item: (node, tile) for the whole workgroup; each lane's frame.
+template <int P, int LG>
+__device__ __forceinline__ Item block_item(int nodes, const DevState &s) {
     using Gm = Geo<P, LG>;
-    return arr + (node * size_t(ntiles) + size_t(tile)) * (Gm::Q * Gm::TF);
+    const int b = int(blockIdx.x);
+    Item it;
+    it.node = b / s.nb;
+    const int ti = b % s.nb;
+    it.ok = it.node < nodes && ti < int(*s.nact);
+    it.tile = it.ok ? s.act[ti] : 0;
+    if (it.tile < 0 || it.tile >= s.Fp / Gm::TF) {
+        it.ok = false;
+        it.tile = 0;
+    }
+    lane_of<P, LG>(it);
+    return it;
+}
+
+// This lane's EL entries of vector `node` of frame f.
+template <int P, int LG, typename T>
+__device__ __forceinline__ T *chunk(T *arr, size_t node, int Fp, const Item &it) {
+    using Gm = Geo<P, LG>;
+    return arr + (node * size_t(Fp) + size_t(it.f)) * Gm::Q + size_t(it.g * Gm::EL);
+}
+
+template <int EL>
+__device__ __forceinline__ void ld(const float *p, float *v) {
+    if constexpr (EL == 1) {
+        v[0] = p[0];
+    } else if constexpr (EL == 2) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < EL / 4; ++k) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[k];
+            v[4 * k] = t.x;
+            v[4 * k + 1] = t.y;
+            v[4 * k + 2] = t.z;
+            v[4 * k + 3] = t.w;
+        }
+    }
+}
+
+template <int EL>
+__device__ __forceinline__ void st(float *p, const float *v) {
+    if constexpr (EL == 1) {
+        p[0] = v[0];
+    } else if constexpr (EL == 2) {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < EL / 4; ++k)
+            reinterpret_cast<float4 *>(p)[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    }
 }
 
 // Images under multiplication by h (basis images packed in `packed`) of the
@@ -90,55 +162,132 @@ __device__ __forceinline__ void gf_positions(uint64_t packed, int g, int *out) {
     for (int r = 0; r < Gm::EL; ++r) out[r] = hg ^ gf_apply<P>(packed, r);
 }
 
-// Index of entry a of vector `node` for frame (tile, fw).
+// Permute one vector per frame through the wavefront's LDS rows: the value
+// this lane holds for position g*EL + r goes to position pos[r]; afterwards
+// the lane holds positions g*EL + r of the permuted vector.  Lanes of one
+// frame only touch that frame's row.
 template <int P, int LG>
-__device__ __forceinline__ size_t at(size_t node, int tile, int a, int fw, int ntiles) {
+__device__ __forceinline__ void lds_permute(float *buf, const Item &it, const int *pos, const float *in,
+                                            float *out) {
     using Gm = Geo<P, LG>;
-    return ((node * size_t(ntiles) + size_t(tile)) * Gm::Q + size_t(a)) * Gm::TF + size_t(fw);
+    float *row = buf + it.fw * Gm::QS;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int r = 0; r < Gm::EL; ++r) row[pos[r]] = in[r];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    ld<Gm::EL>(row + it.g * Gm::EL, out);
 }
 
-// Unnormalised WHT of the distributed vector (positions y = g*EL + r).
-template <int P, int LG, int S = 0>
-__device__ __forceinline__ void wht(double *v, int g) {
-    using Gm = Geo<P, LG>;
-    if constexpr (S < P) {
-        if constexpr (S < Gm::LEL) {
-            constexpr int m = 1 << S;
+// ------------------------------------------------------------- transforms
+template <int EL, int S = 0>
+__device__ __forceinline__ void wht_regs(double *v) {
+    if constexpr ((1 << S) < EL) {
+        constexpr int m = 1 << S;
 #pragma unroll
-            for (int r = 0; r < Gm::EL; ++r) {
-                if (!(r & m)) {
-                    const double a = v[r], b = v[r | m];
-                    v[r] = a + b;
-                    v[r | m] = a - b;
-                }
+        for (int r = 0; r < EL; ++r) {
+            if (!(r & m)) {
+                const double a = v[r], b = v[r | m];
+                v[r] = a + b;
+                v[r | m] = a - b;
             }
-        } else {
-            constexpr int mask = 1 << (S - Gm::LEL);
-            const double sg = (g & mask) ? -1.0 : 1.0;
-#pragma unroll
-            for (int r = 0; r < Gm::EL; ++r) v[r] = fma(sg, v[r], xchg<mask>(v[r]));
         }
-        wht<P, LG, S + 1>(v, g);
+        wht_regs<EL, S + 1>(v);
     }
 }
 
+// Butterflies over g bits B..LG-NSWAP-1 (lane masks below 16): exchange and
+// combine in place.
+template <int P, int LG, int B = 0>
+__device__ __forceinline__ void wht_lanes(double *v, int g) {
+    using Gm = Geo<P, LG>;
+    if constexpr (B < LG - Gm::NSWAP) {
+        constexpr int mask = Gm::TF << B;
+        const double sg = ((g >> B) & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int r = 0; r < Gm::EL; ++r) v[r] = fma(sg, v[r], xchg<mask>(v[r]));
+        wht_lanes<P, LG, B + 1>(v, g);
+    }
+}
+
+// Butterfly over the lane bit MASK (16 or 32) paired with register bit S:
+// after the swap each lane holds both operands of a butterfly in registers
+// r and r | 2^S; the sum goes to r and the difference to r | 2^S.
+template <int MASK, int S, int EL>
+__device__ __forceinline__ void wht_swap(double *v) {
+    constexpr int m = 1 << S;
+#pragma unroll
+    for (int r = 0; r < EL; ++r) {
+        if (!(r & m)) {
+            double a = v[r], b = v[r | m];
+            row_swap<MASK>(a, b);
+            v[r] = a + b;
+            v[r | m] = a - b;
+        }
+    }
+}
+
+// Unnormalised WHT: natural order in, transposed order out, and back.
+template <int P, int LG>
+__device__ __forceinline__ void wht(double *v, int g) {
+    using Gm = Geo<P, LG>;
+    wht_regs<Gm::EL>(v);
+    wht_lanes<P, LG>(v, g);
+    if constexpr (Gm::S32) wht_swap<32, Gm::LEL - 1, Gm::EL>(v);
+    if constexpr (Gm::S16) wht_swap<16, Gm::LEL - 2, Gm::EL>(v);
+}
+
+__device__ __forceinline__ int swap_bits(int k, int i, int j) {
+    const int d = ((k >> i) ^ (k >> j)) & 1;
+    return k ^ ((d << i) | (d << j));
+}
+
+// Transform index held by register r of lane g in the transposed order.
+template <int P, int LG>
+__device__ __forceinline__ int tindex(int g, int r) {
+    using Gm = Geo<P, LG>;
+    int k = (g << Gm::LEL) | r;
+    if constexpr (Gm::S32) k = swap_bits(k, Gm::LEL - 1, P - 1);
+    if constexpr (Gm::S16) k = swap_bits(k, Gm::LEL - 2, P - 2);
+    return k;
+}
+
+// Syndrome sign pattern (-1)^popcount(z & k) in the transposed order.
+template <int P, int LG>
+__device__ __forceinline__ void syndrome_signs(int z, int g, double *v) {
+    using Gm = Geo<P, LG>;
+#pragma unroll
+    for (int r = 0; r < Gm::EL; ++r) v[r] = (__popc(z & tindex<P, LG>(g, r)) & 1) ? -1.0 : 1.0;
+}
+
+template <int P, int LG>
+__device__ __forceinline__ void transform(const float *raw, double *v, int g) {
+    using Gm = Geo<P, LG>;
+#pragma unroll
+    for (int r = 0; r < Gm::EL; ++r) v[r] = double(raw[r]);
+    wht<P, LG>(v, g);
+}
+
+// ------------------------------------------------------------ reductions
 // Sum over the G lanes of a frame (bitwise identical on each of them).
-template <int LG, int S = 0>
+template <int P, int LG, int B = 0>
 __device__ __forceinline__ double lanes_sum(double v) {
-    if constexpr (S < LG) {
-        return lanes_sum<LG, S + 1>(v + xchg<(1 << S)>(v));
+    using Gm = Geo<P, LG>;
+    if constexpr (B < LG) {
+        return lanes_sum<P, LG, B + 1>(v + xchg<(Gm::TF << B)>(v));
     } else {
         return v;
     }
 }
 
-template <int LG, int S = 0>
+template <int P, int LG, int B = 0>
 __device__ __forceinline__ int lanes_argmax(float v, int k) {
-    if constexpr (S < LG) {
-        const float ov = xchg<(1 << S)>(v);
-        const int ok = xchg<(1 << S)>(k);
+    using Gm = Geo<P, LG>;
+    if constexpr (B < LG) {
+        constexpr int mask = Gm::TF << B;
+        const float ov = xchg<mask>(v);
+        const int ok = xchg<mask>(k);
         const bool take = ov > v || (ov == v && ok < k);
-        return lanes_argmax<LG, S + 1>(take ? ov : v, take ? ok : k);
+        return lanes_argmax<P, LG, B + 1>(take ? ov : v, take ? ok : k);
     } else {
         return k;
     }
@@ -152,7 +301,7 @@ __device__ __forceinline__ void normalise(double *v, int32_t *guards, int f, int
     double s = 0.0;
 #pragma unroll
     for (int r = 0; r < Gm::EL; ++r) s += v[r];
-    s = lanes_sum<LG>(s);
+    s = lanes_sum<P, LG>(s);
     if (!(s > 0.0) || !isfinite(s)) {
         if (g == 0) atomicAdd(&guards[f], 1);
 #pragma unroll
@@ -164,33 +313,32 @@ __device__ __forceinline__ void normalise(double *v, int32_t *guards, int f, int
     for (int r = 0; r < Gm::EL; ++r) v[r] *= inv;
 }
 
+// q-message of edge e from its natural-order values q(a): stored in the
+// weighted domain, the value for a going to position h_e a.
 template <int P, int LG>
-__device__ __forceinline__ void syndrome_signs(int z, int g, double *v) {
+__device__ __forceinline__ void store_q(const DevCode &c, const DevState &s, size_t e, const Item &it,
+                                        const float *qa, float *perm) {
     using Gm = Geo<P, LG>;
-#pragma unroll
-    for (int r = 0; r < Gm::EL; ++r) v[r] = (__popc(z & (g * Gm::EL + r)) & 1) ? -1.0 : 1.0;
-}
-
-// Edge e's weighted-symbol distribution q~(y) = q(h^-1 y) at this lane's
-// positions (loads only; all the loads of a check are issued before any
-// transform so that their latencies overlap).
-template <int P, int LG>
-__device__ __forceinline__ void load_permuted(const float *Qm, size_t e, const Item &it, int ntiles, uint64_t hinv,
-                                              float *v) {
-    using Gm = Geo<P, LG>;
-    const float *base = vec_base<P, LG>(Qm, e, it.tile, ntiles);
     int pos[Gm::EL];
-    gf_positions<P, LG>(hinv, it.g, pos);
-#pragma unroll
-    for (int r = 0; r < Gm::EL; ++r) v[r] = base[pos[r] * Gm::TF + it.fw];
+    gf_positions<P, LG>(c.emap[2 * e + 1], it.g, pos);
+    float out[Gm::EL];
+    lds_permute<P, LG>(perm, it, pos, qa, out);
+    st<Gm::EL>(chunk<P, LG>(s.Qm, e, s.Fp, it), out);
 }
 
+// r-message of edge e from the inverse transform T (natural order, position
+// y): r(a) = T(h_e a), so the value for y goes to entry h_e^-1 y.  Returns
+// r in natural order in rv.
 template <int P, int LG>
-__device__ __forceinline__ void transform(const float *raw, double *v, int g) {
+__device__ __forceinline__ void r_from_transform(const DevCode &c, size_t e, const Item &it, const double *T,
+                                                 float *perm, float *rv) {
     using Gm = Geo<P, LG>;
+    int pos[Gm::EL];
+    gf_positions<P, LG>(c.emap[2 * e], it.g, pos);
+    float tv[Gm::EL];
 #pragma unroll
-    for (int r = 0; r < Gm::EL; ++r) v[r] = double(raw[r]);
-    wht<P, LG>(v, g);
+    for (int r = 0; r < Gm::EL; ++r) tv[r] = float(fmax(T[r] * (1.0 / double(Gm::Q)), 0.0));
+    lds_permute<P, LG>(perm, it, pos, tv, rv);
 }
 
 struct Chan {
@@ -206,7 +354,8 @@ struct Chan {
 template <int P, int LG>
 __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch) {
     using Gm = Geo<P, LG>;
-    const int ntiles = s.Fp / Gm::TF;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
     const Item it = item<P, LG>(c.n, s);
     if (!it.ok || it.f >= s.F) return;
     if (s.fresh && !s.fresh[it.f]) return;
@@ -256,26 +405,18 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
     normalise<P, LG>(L, s.guards, f, it.g);
     float pf[Gm::EL];
 #pragma unroll
-    for (int r = 0; r < Gm::EL; ++r) {
-        pf[r] = float(L[r]);
-        s.L[at<P, LG>(j, it.tile, it.g * Gm::EL + r, it.fw, ntiles)] = pf[r];
-    }
+    for (int r = 0; r < Gm::EL; ++r) pf[r] = float(L[r]);
+    st<Gm::EL>(chunk<P, LG>(s.L, j, s.Fp, it), pf);
     if (markov && j < c.n_info) {
         double pr[Gm::EL];
 #pragma unroll
         for (int r = 0; r < Gm::EL; ++r) pr[r] = double(pf[r]) * double(ch.pi[it.g * Gm::EL + r]);
         normalise<P, LG>(pr, s.guards, f, it.g);
 #pragma unroll
-        for (int r = 0; r < Gm::EL; ++r) {
-            pf[r] = float(pr[r]);
-            s.Pr[at<P, LG>(j, it.tile, it.g * Gm::EL + r, it.fw, ntiles)] = pf[r];
-        }
+        for (int r = 0; r < Gm::EL; ++r) pf[r] = float(pr[r]);
+        st<Gm::EL>(chunk<P, LG>(s.Pr, j, s.Fp, it), pf);
     }
-    for (int t = c.col_ptr[j]; t < c.col_ptr[j + 1]; ++t) {
-        const size_t e = size_t(c.col_edge[t]);
-#pragma unroll
-        for (int r = 0; r < Gm::EL; ++r) s.Qm[at<P, LG>(e, it.tile, it.g * Gm::EL + r, it.fw, ntiles)] = pf[r];
-    }
+    for (int t = c.col_ptr[j]; t < c.col_ptr[j + 1]; ++t) store_q<P, LG>(c, s, size_t(c.col_edge[t]), it, pf, perm);
 }
 
 // A3, parallel schedule: all r of check i from the previous iteration's q.
@@ -283,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
 template <int P, int LG, int DCM>
 __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const uint8_t *z, Snap snap) {
     using Gm = Geo<P, LG>;
-    const int ntiles = s.Fp / Gm::TF;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
     const Item it = item<P, LG>(c.m, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
     const int i = it.node, f = it.f;
@@ -292,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
     float raw[DCM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DCM; ++d)
-        if (d < dc) load_permuted<P, LG>(s.Qm, size_t(rs + d), it, ntiles, c.emap[2 * (rs + d)], raw[d]);
+        if (d < dc) ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + d), s.Fp, it), raw[d]);
     double W[DCM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DCM; ++d)
@@ -310,34 +452,33 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
                 }
             wht<P, LG>(T, it.g);
             const size_t e = size_t(rs + d);
-            float *base = vec_base<P, LG>(s.R, e, it.tile, ntiles);
-            int pos[Gm::EL];
-            gf_positions<P, LG>(c.emap[2 * e], it.g, pos);
+            float rv[Gm::EL];
+            r_from_transform<P, LG>(c, e, it, T, perm, rv);
+            st<Gm::EL>(chunk<P, LG>(s.R, e, s.Fp, it), rv);
+            if (snap.r)
 #pragma unroll
-            for (int r = 0; r < Gm::EL; ++r) {
-                const float rv = float(fmax(T[r] * (1.0 / double(Gm::Q)), 0.0));
-                base[pos[r] * Gm::TF + it.fw] = rv;
-                if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + pos[r]] = rv;
-            }
+                for (int r = 0; r < Gm::EL; ++r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + r] = rv[r];
         }
     }
 }
 
-// A4 variable-node update of column j from its r-messages r[d][.]: the
-// pseudo-posterior Q_j (Eq. (5)) and its decision, then each edge's q
-// (Eq. (4)), normalised.
+// A4 variable-node update of column j from its r-messages r[d][.] (natural
+// order): the pseudo-posterior Q_j (Eq. (5)) and its decision, then each
+// edge's q (Eq. (4)), normalised.
 template <int P, int LG, int DVM>
-__device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, const Item &it, int ntiles,
-                                                int j, const float (*r)[Geo<P, LG>::EL], int cs, int dv, int markov,
-                                                int wantQ, const Snap &snap) {
+__device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, const Item &it, int j,
+                                                const float (*r)[Geo<P, LG>::EL], int cs, int dv, int markov,
+                                                int wantQ, const Snap &snap, float *perm) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
     const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
     const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
+    float pf[Gm::EL];
+    ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
     double pv[Gm::EL], acc[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
-        pv[q] = pj[at<P, LG>(j, it.tile, it.g * Gm::EL + q, it.fw, ntiles)];
+        pv[q] = pf[q];
         acc[q] = pv[q];
     }
 #pragma unroll
@@ -349,13 +490,14 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
     normalise<P, LG>(acc, s.guards, f, it.g);
     int best = it.g * Gm::EL;
     float bv = float(acc[0]);
+    float Qf[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
-        const float v = float(acc[q]);
-        if (wantQ) s.Qp[at<P, LG>(j, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = v;
-        if (v > bv) { bv = v; best = it.g * Gm::EL + q; }
+        Qf[q] = float(acc[q]);
+        if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
     }
-    best = lanes_argmax<LG>(bv, best);
+    if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
+    best = lanes_argmax<P, LG>(bv, best);
     if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
 #pragma unroll
     for (int d = 0; d < DVM; ++d) {
@@ -371,12 +513,13 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
                 }
             normalise<P, LG>(qv, s.guards, f, it.g);
             const size_t e = size_t(c.col_edge[cs + d]);
+            float qn[Gm::EL];
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) {
-                const float qn = float(qv[q]);
-                s.Qm[at<P, LG>(e, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = qn;
-                if (snap.q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn;
-            }
+            for (int q = 0; q < Gm::EL; ++q) qn[q] = float(qv[q]);
+            if (snap.q)
+#pragma unroll
+                for (int q = 0; q < Gm::EL; ++q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn[q];
+            store_q<P, LG>(c, s, e, it, qn, perm);
         }
     }
 }
@@ -385,7 +528,8 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
 template <int P, int LG, int DVM>
 __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int markov, int wantQ, Snap snap) {
     using Gm = Geo<P, LG>;
-    const int ntiles = s.Fp / Gm::TF;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
     const Item it = item<P, LG>(c.n, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
     const int j = it.node;
@@ -393,12 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
     float r[DVM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DVM; ++d)
-        if (d < dv) {
-            const float *base = vec_base<P, LG>(s.R, size_t(c.col_edge[cs + d]), it.tile, ntiles);
-#pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) r[d][q] = base[(it.g * Gm::EL + q) * Gm::TF + it.fw];
-        }
-    variable_update<P, LG, DVM>(c, s, it, ntiles, j, r, cs, dv, markov, wantQ, snap);
+        if (d < dv) ld<Gm::EL>(chunk<P, LG>(s.R, size_t(c.col_edge[cs + d]), s.Fp, it), r[d]);
+    variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, markov, wantQ, snap, perm);
 }
 
 // A6 sequential schedule, the step of column j for one tile of frames, done
@@ -407,13 +547,11 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
 // after a workgroup barrier, wavefront d combines the column's r into its
 // edge's q and wavefront 0 into the pseudo-posterior and decision (partial
 // vertical pass).  `live`: this lane's frame is still iterating.  perm is the
-// wavefront's Q x TF buffer that applies r(a) = T(h a) (position y written to
-// entry h^-1 y, entries read back in order); rsh holds the column's r as
-// [d][register][lane].
+// wavefront's LDS rows; rsh holds the column's r as [d][register][lane].
 template <int P, int LG, int DCM, int DVM>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
-                                           bool live, int ntiles, int j, int markov, int wantQ, const Snap &snap,
-                                           float *perm, float *rsh) {
+                                           bool live, int j, int markov, int wantQ, const Snap &snap, float *perm,
+                                           float *rsh) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
     const int d = int(threadIdx.x) / kWave, lane = int(threadIdx.x) % kWave;
@@ -428,8 +566,7 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
         float raw[DCM][Gm::EL];
 #pragma unroll
         for (int t = 0; t < DCM; ++t)
-            if (t < dc && t != self)
-                load_permuted<P, LG>(s.Qm, size_t(rs + t), it, ntiles, c.emap[2 * (rs + t)], raw[t]);
+            if (t < dc && t != self) ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + t), s.Fp, it), raw[t]);
         double acc[Gm::EL];
         syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + i] : 0, it.g, acc);
 #pragma unroll
@@ -442,26 +579,23 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
             }
         }
         wht<P, LG>(acc, it.g);
-        int pos[Gm::EL];
-        gf_positions<P, LG>(c.emap[2 * e], it.g, pos);
-#pragma unroll
-        for (int q = 0; q < Gm::EL; ++q) perm[pos[q] * Gm::TF + it.fw] = float(fmax(acc[q] * (1.0 / double(Gm::Q)), 0.0));
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        float rv[Gm::EL];
+        r_from_transform<P, LG>(c, e, it, acc, perm, rv);
 #pragma unroll
         for (int q = 0; q < Gm::EL; ++q) {
-            const float rv = perm[(it.g * Gm::EL + q) * Gm::TF + it.fw];
-            rsh[(d * Gm::EL + q) * kWave + lane] = rv;
-            if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = rv;
+            rsh[(d * Gm::EL + q) * kWave + lane] = rv[q];
+            if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = rv[q];
         }
     }
     __syncthreads();
     if (mine) {
         const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
         const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
-        const float *pb = vec_base<P, LG>(pj, size_t(j), it.tile, ntiles);
+        float pf[Gm::EL];
+        ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
         double pv[Gm::EL];
 #pragma unroll
-        for (int q = 0; q < Gm::EL; ++q) pv[q] = pb[(it.g * Gm::EL + q) * Gm::TF + it.fw];
+        for (int q = 0; q < Gm::EL; ++q) pv[q] = pf[q];
         if (d == 0) {
             // A4/A5: pseudo-posterior (Eq. (5)) and decision
             double acc[Gm::EL];
@@ -476,13 +610,14 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
             normalise<P, LG>(acc, s.guards, f, it.g);
             int best = it.g * Gm::EL;
             float bv = float(acc[0]);
+            float Qf[Gm::EL];
 #pragma unroll
             for (int q = 0; q < Gm::EL; ++q) {
-                const float v = float(acc[q]);
-                if (wantQ) s.Qp[at<P, LG>(j, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = v;
-                if (v > bv) { bv = v; best = it.g * Gm::EL + q; }
+                Qf[q] = float(acc[q]);
+                if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
             }
-            best = lanes_argmax<LG>(bv, best);
+            if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
+            best = lanes_argmax<P, LG>(bv, best);
             if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
         }
         // Eq. (4) for this wavefront's edge
@@ -496,53 +631,32 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
                 for (int q = 0; q < Gm::EL; ++q) qv[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
             }
         normalise<P, LG>(qv, s.guards, f, it.g);
-        float *qb = vec_base<P, LG>(s.Qm, e, it.tile, ntiles);
+        float qn[Gm::EL];
 #pragma unroll
-        for (int q = 0; q < Gm::EL; ++q) {
-            const float qn = float(qv[q]);
-            qb[(it.g * Gm::EL + q) * Gm::TF + it.fw] = qn;
-            if (snap.q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn;
-        }
+        for (int q = 0; q < Gm::EL; ++q) qn[q] = float(qv[q]);
+        if (snap.q)
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn[q];
+        store_q<P, LG>(c, s, e, it, qn, perm);
     }
     __syncthreads();
 }
 
-// Workgroup item: (node, tile) for the whole workgroup; each lane's frame.
-template <int P, int LG>
-__device__ __forceinline__ Item block_item(int nodes, const DevState &s) {
-    using Gm = Geo<P, LG>;
-    const int b = int(blockIdx.x);
-    const int lane = int(threadIdx.x) % kWave;
-    Item it;
-    it.node = b / s.nb;
-    const int ti = b % s.nb;
-    it.ok = it.node < nodes && ti < int(*s.nact);
-    it.tile = it.ok ? s.act[ti] : 0;
-    if (it.tile < 0 || it.tile >= s.Fp / Gm::TF) {
-        it.ok = false;
-        it.tile = 0;
-    }
-    it.fw = lane >> LG;
-    it.g = lane & (Gm::G - 1);
-    it.f = it.tile * Gm::TF + it.fw;
-    return it;
-}
-
 // A6, one dependency level: the columns cols[0..ncols) share no check, so
 // their steps commute; each runs exactly as in the strict order.  One
-// workgroup of DVM wavefronts per (column, tile).
+// workgroup per (column, tile), one wavefront per edge of the column
+// (blockDim = 64 x the largest column degree, at most DVM wavefronts).
 template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
                                                           int wantQ, Snap snap, const int32_t *cols, int ncols) {
     using Gm = Geo<P, LG>;
-    __shared__ float perm[DVM * Gm::Q * Gm::TF];
+    __shared__ __align__(16) float perm[DVM * Gm::PERM];
     __shared__ float rsh[DVM * Gm::EL * kWave];
-    const int ntiles = s.Fp / Gm::TF;
     const Item it = block_item<P, LG>(ncols, s);
     if (!it.ok) return;  // uniform over the workgroup
     const bool live = it.f < s.F && s.active[it.f];
-    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, ntiles, cols[it.node], markov, wantQ, snap,
-                                perm + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF, rsh);
+    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, cols[it.node], markov, wantQ, snap,
+                                perm + (int(threadIdx.x) / kWave) * Gm::PERM, rsh);
 }
 
 // A6, strict order: columns 0..n-1 one after the other for each tile.
@@ -550,14 +664,13 @@ template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
                                                            int wantQ, Snap snap) {
     using Gm = Geo<P, LG>;
-    __shared__ float perm[DVM * Gm::Q * Gm::TF];
+    __shared__ __align__(16) float perm[DVM * Gm::PERM];
     __shared__ float rsh[DVM * Gm::EL * kWave];
-    const int ntiles = s.Fp / Gm::TF;
     const Item it = block_item<P, LG>(1, s);
     if (!it.ok) return;  // uniform over the workgroup
     const bool live = it.f < s.F && s.active[it.f];
-    float *mine = perm + (int(threadIdx.x) / kWave) * Gm::Q * Gm::TF;
-    for (int j = 0; j < c.n; ++j) sus_column<P, LG, DCM, DVM>(c, s, z, it, live, ntiles, j, markov, wantQ, snap, mine, rsh);
+    float *mine = perm + (int(threadIdx.x) / kWave) * Gm::PERM;
+    for (int j = 0; j < c.n; ++j) sus_column<P, LG, DCM, DVM>(c, s, z, it, live, j, markov, wantQ, snap, mine, rsh);
 }
 
 // A7 dynamical block prior (Eq. (7)) for source symbol k: from this
@@ -566,7 +679,6 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
 template <int P, int LG>
 __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi) {
     using Gm = Geo<P, LG>;
-    const int ntiles = s.Fp / Gm::TF;
     const Item it = item<P, LG>(c.n_info, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
     if (s.mark && !s.mark[it.f]) return;
@@ -578,26 +690,36 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
         u[q] = k == 0 ? double(pi[b]) : 0.0;
         v[q] = k == K - 1 ? 1.0 : 0.0;
     }
-    if (k > 0)
+    // the whole neighbour vectors (every lane of the frame reads all q entries)
+    const size_t fo = size_t(it.f) * Gm::Q;
+    if (k > 0) {
+        const float *qp = s.Qp + size_t(k - 1) * s.Fp * Gm::Q + fo;
         for (int a = 0; a < Gm::Q; ++a) {
-            const double qa = s.Qp[at<P, LG>(k - 1, it.tile, a, it.fw, ntiles)];
+            const double qa = qp[a];
 #pragma unroll
             for (int q = 0; q < Gm::EL; ++q) u[q] += qa * double(M[a * Gm::Q + it.g * Gm::EL + q]);
         }
-    if (k < K - 1)
+    }
+    if (k < K - 1) {
+        const float *qp = s.Qp + size_t(k + 1) * s.Fp * Gm::Q + fo;
         for (int cc = 0; cc < Gm::Q; ++cc) {
-            const double qc = s.Qp[at<P, LG>(k + 1, it.tile, cc, it.fw, ntiles)];
+            const double qc = qp[cc];
 #pragma unroll
             for (int q = 0; q < Gm::EL; ++q) v[q] += double(M[(it.g * Gm::EL + q) * Gm::Q + cc]) * qc;
         }
+    }
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) u[q] *= v[q];
     normalise<P, LG>(u, s.guards, it.f, it.g);
+    float lf[Gm::EL];
+    ld<Gm::EL>(chunk<P, LG>(s.L, size_t(k), s.Fp, it), lf);
 #pragma unroll
-    for (int q = 0; q < Gm::EL; ++q) u[q] *= double(s.L[at<P, LG>(k, it.tile, it.g * Gm::EL + q, it.fw, ntiles)]);
+    for (int q = 0; q < Gm::EL; ++q) u[q] *= double(lf[q]);
     normalise<P, LG>(u, s.guards, it.f, it.g);
+    float pf[Gm::EL];
 #pragma unroll
-    for (int q = 0; q < Gm::EL; ++q) s.Pr[at<P, LG>(k, it.tile, it.g * Gm::EL + q, it.fw, ntiles)] = float(u[q]);
+    for (int q = 0; q < Gm::EL; ++q) pf[q] = float(u[q]);
+    st<Gm::EL>(chunk<P, LG>(s.Pr, size_t(k), s.Fp, it), pf);
 }
 
 // Ordered list of the tiles (of TF frames) holding a frame whose mask byte is
@@ -637,16 +759,16 @@ __global__ __launch_bounds__(1024) void k_tiles(const uint8_t *mask, int F, int 
     if (threadIdx.x == 0) *count = base;
 }
 
-// [n][tile][Q][TF] -> [F][n][Q]
-template <int P, int LG>
+// [n][Fp][Q] -> [F][n][Q]
+template <int P>
 __global__ void k_out_vectors(const float *src, int n, int F, int Fp, float *out) {
-    using Gm = Geo<P, LG>;
+    constexpr int Q = 1 << P;
     const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= size_t(n) * F * Gm::Q) return;
-    const int a = int(t % Gm::Q);
-    const size_t fj = t / Gm::Q;
+    if (t >= size_t(n) * F * Q) return;
+    const int a = int(t % Q);
+    const size_t fj = t / Q;
     const int f = int(fj / n), j = int(fj % n);
-    out[t] = src[at<P, LG>(j, f / Gm::TF, a, f % Gm::TF, Fp / Gm::TF)];
+    out[t] = src[(size_t(j) * Fp + f) * Q + a];
 }
 
 }  // namespace tiled

@@ -347,10 +347,12 @@ def test_levelled_sus_is_bitwise_the_strict_sweep(gfbp, q, channel, param, prior
 
 
 # --------------------------------------------------------------- kernel shapes and the tuner
-@pytest.mark.parametrize("q", [2, 4, 16, 64])
+@pytest.mark.parametrize("q", [2, 4, 8, 16, 32, 64])
 def test_every_kernel_shape_matches_the_reference(gfbp, q):
-    """Each allowed entries-per-lane choice (EL = 2, 4, 8) is a different
-    register/lane split of the same arithmetic; all must match the oracle."""
+    """Each allowed entries-per-lane choice (EL = 2, 4, 8; 16 for SUS) is a
+    different register/lane split of the same arithmetic (a different mix of
+    register butterflies, row-swap butterflies and DPP exchanges); all must
+    match the oracle."""
     import torch
 
     code, enc = _small_code(q, 72, seed=300 + q)
@@ -359,8 +361,8 @@ def test_every_kernel_shape_matches_the_reference(gfbp, q):
     dfr = gfbp.frames_to_device(fr)
     for sch in ("pus", "sus"):
         r = _ref(code, fr, sch, max_iter=2, early_stop=False, snap_iter=2)
-        for el in (2, 4, 8):
-            if el > q:
+        for el in (2, 4, 8, 16):
+            if el > q or (el == 16 and sch == "pus"):
                 with pytest.raises(gfbp.GfbpError):
                     dcode.set_shape(sch, el)
                 continue
@@ -380,7 +382,7 @@ def test_tuner_keeps_an_allowed_shape_and_decodes_correctly(gfbp):
     dfr = gfbp.frames_to_device(fr)
     for sch in ("pus", "sus"):
         el = gfbp.tune(dcode, dfr, schedule=sch, trial_iters=2)
-        assert el in (2, 4, 8) and dcode.shape(sch) == el
+        assert el in ((2, 4, 8) if sch == "pus" else (2, 4, 8, 16)) and dcode.shape(sch) == el
         out = gfbp.decode_batch(dcode, dfr, schedule=sch, max_iter=50)
         g = {k: v.cpu().numpy() for k, v in out.items()}
         r = _ref(code, fr, sch, max_iter=50)
