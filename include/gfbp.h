@@ -243,8 +243,8 @@ gfbp_status gfbp_graph_destroy(gfbp_graph *graph);
  * Walsh-Hadamard butterflies register arithmetic, a smaller EL uses fewer
  * registers (more wavefronts per compute unit).  EL in {2, 4, 8} (at most q;
  * at most 4 for codes with rows longer than 6 or columns longer than 4).
- * gfbp_code_set_shape fixes EL for one schedule (0 = default, the largest
- * allowed); gfbp_code_get_shape returns the EL in use.  gfbp_tune times
+ * gfbp_code_set_shape fixes EL for one schedule (0 = default: 4, or 2 when
+ * q = 2); gfbp_code_get_shape returns the EL in use.  gfbp_tune times
  * trial_iters fixed iterations of `batch` (same buffers and workspace as a
  * decode; outputs are overwritten) with every allowed EL and keeps the
  * fastest for batch->schedule, returned in *chosen.  These calls change the
@@ -258,8 +258,8 @@ gfbp_status gfbp_tune(gfbp_code *code, const gfbp_batch *batch, gfbp_result *out
  * Off by default.  When on, every kernel launch of gfbp_decode_batch is
  * bracketed by two HIP events on the caller's stream; after the decode's final
  * synchronisation the elapsed times are added to process-wide totals per
- * kernel kind ("init", "check", "variable", "sequential", "syndrome",
- * "markov", "output"), together with the launch's algorithmic HBM bytes
+ * kernel kind ("init", "check", "variable", "sequential", "sus_level",
+ * "syndrome", "retire", "markov", "output"), together with the launch's algorithmic HBM bytes
  * (float32 messages read and written once, as the method defines them; frames
  * that have stopped iterating are not counted) and its edge-q updates (E*q per
  * running frame for one iteration). */

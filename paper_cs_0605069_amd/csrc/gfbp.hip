@@ -51,6 +51,7 @@ struct gfbp_code {
     std::vector<double> level_sibs;   // per level: sibling vectors read (sum over its edges of d_c - 1)
     std::vector<double> level_edges;  // per level: edges
     const int32_t *level_cols = nullptr;  // device [n]
+    const SusRec *sus_recs = nullptr;     // device [n][max column degree], columns in level order
     int el[2] = {0, 0};   // entries per lane chosen for PUS / SUS (0 = default)
     void *mem = nullptr;  // one device allocation holding every array of dev
 };
@@ -208,10 +209,10 @@ Bytes bytes_per_frame(const gfbp_code *code, int needQ, int has_z) {
 
 // Kernel shape for a code and schedule.  Degree class "small" (rows <= 6,
 // columns <= 4) keeps up to 6 siblings' transforms in registers and allows
-// EL = 2, 4 or 8 entries per lane (and 16 for the sequential schedule, whose
-// column step keeps one transform at a time); the general class (rows <= 16,
-// columns <= 8) allows EL = 2 or 4.  EL never exceeds q.  The default is the
-// largest allowed EL; gfbp_code_set_shape / gfbp_tune choose another.
+// EL = 2, 4 or 8 entries per lane; the general class (rows <= 16, columns <=
+// 8) allows EL = 2 or 4.  EL never exceeds q.  The default is EL = 4 (2 for
+// q = 2), the fastest on every field measured; gfbp_code_set_shape /
+// gfbp_tune choose another.
 struct Shape {
     bool small;
     int lel;  // log2 of entries per lane
@@ -221,14 +222,11 @@ inline bool small_class(const gfbp_code *code) {
     return code->info.max_row_degree <= 6 && code->info.max_col_degree <= 4;
 }
 
-inline int max_lel(const gfbp_code *code, int schedule) {
-    const int cap = small_class(code) ? (schedule == GFBP_SUS ? 4 : 3) : 2;
-    return std::min(code->info.p, cap);
-}
+inline int max_lel(const gfbp_code *code) { return std::min(code->info.p, small_class(code) ? 3 : 2); }
 
-inline bool allowed_el(const gfbp_code *code, int schedule, int el) {
+inline bool allowed_el(const gfbp_code *code, int el) {
     if (el == 0) return true;
-    for (int l = 1; l <= max_lel(code, schedule); ++l)
+    for (int l = 1; l <= max_lel(code); ++l)
         if (el == (1 << l)) return true;
     return false;
 }
@@ -237,9 +235,9 @@ inline Shape shape_of(const gfbp_code *code, int schedule) {
     Shape sh;
     sh.small = small_class(code);
     const int el = code->el[schedule == GFBP_SUS ? 1 : 0];
-    int lel = max_lel(code, schedule);
+    int lel = std::min(2, max_lel(code));
     if (el > 0)
-        for (int l = 1; l <= max_lel(code, schedule); ++l)
+        for (int l = 1; l <= max_lel(code); ++l)
             if (el == (1 << l)) lel = l;
     sh.lel = lel;
     return sh;
@@ -269,15 +267,15 @@ struct TiledLaunch {
                            s, markov, wantQ, sn);
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
-                          Snap sn, const int32_t *cols, int nc) {
+                          Snap sn, const SusRec *recs, int nc) {
         hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
-                           dim3(unsigned(std::min(c.max_dv, DVM)) * kWave), 0, st, c, s, z, markov, wantQ, sn, cols,
-                           nc);
+                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, recs,
+                           std::max(1, c.max_dv), nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn) {
         hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
-                           dim3(unsigned(std::min(c.max_dv, DVM)) * kWave), 0, st, c, s, z, markov, wantQ, sn);
+                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
         hipLaunchKernelGGL((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
@@ -342,7 +340,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             for (int l = 0; l < nlev; ++l) {
                 const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
                 tr.begin();
-                K::sus_level(st, c, s, b->syndrome, markov, wantQ, sn, code->level_cols + c0, nc);
+                K::sus_level(st, c, s, b->syndrome, markov, wantQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
                 tr.end(K_SUS_LEVEL,
                        Fa * (4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1)),
                        Fa * code->level_edges[l] * Q);
@@ -389,7 +387,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
 template <int P, int LEL>
 gfbp_status run_lel(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
                     int needQ, bool small) {
-    if constexpr (LEL <= 4 && LEL <= P) {
+    if constexpr (LEL <= 3 && LEL <= P) {
         if (small) return run_batch<P, TiledLaunch<P, P - LEL, 6, 4>>(code, b, out, s, st, needQ);
     }
     if constexpr (LEL <= 2 && LEL <= P) {
@@ -406,7 +404,6 @@ gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out
         case 1: return run_lel<P, 1>(code, b, out, s, st, needQ, sh.small);
         case 2: return run_lel<P, 2>(code, b, out, s, st, needQ, sh.small);
         case 3: return run_lel<P, 3>(code, b, out, s, st, needQ, sh.small);
-        case 4: return run_lel<P, 4>(code, b, out, s, st, needQ, sh.small);
         default: return fail(GFBP_EUNSUPPORTED, "bad shape");
     }
 }
@@ -575,7 +572,7 @@ struct SessionRun {
                 const int nlev = int(code->level_ptr.size()) - 1;
                 for (int l = 0; l < nlev; ++l) {
                     const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
-                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, code->level_cols + c0, nc);
+                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
                 }
             }
             hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
@@ -595,7 +592,7 @@ struct SessionRun {
 
 template <int P, int LEL>
 bool session_bind_lel(gfbp_session *ss, bool small) {
-    if constexpr (LEL <= 4 && LEL <= P) {
+    if constexpr (LEL <= 3 && LEL <= P) {
         if (small) {
             using K = TiledLaunch<P, P - LEL, 6, 4>;
             ss->init_fn = &SessionRun<P, K>::init;
@@ -623,7 +620,6 @@ bool session_bind(gfbp_session *ss) {
         case 1: return session_bind_lel<P, 1>(ss, sh.small);
         case 2: return session_bind_lel<P, 2>(ss, sh.small);
         case 3: return session_bind_lel<P, 3>(ss, sh.small);
-        case 4: return session_bind_lel<P, 4>(ss, sh.small);
         default: return false;
     }
 }
@@ -822,13 +818,37 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
         emap[2 * size_t(e) + 1] = wm;
     }
 
+    // sequential-schedule records, columns in level order, RS slots each
+    const int RS = std::max(1, max_dv);
+    std::vector<SusRec> recs(size_t(n) * RS);
+    for (int p = 0; p < n; ++p) {
+        const int j = level_cols[p], dv = col_ptr[j + 1] - col_ptr[j];
+        for (int t = 0; t < RS; ++t) {
+            SusRec r{};
+            r.j = j;
+            r.dv = dv;
+            if (t < dv) {
+                const int e = col_edge[col_ptr[j] + t], i = edge_row[e];
+                r.e = e;
+                r.i = i;
+                r.rs = d->row_ptr[i];
+                r.dc = d->row_ptr[i + 1] - d->row_ptr[i];
+                r.self = e - r.rs;
+                r.hinv = emap[2 * size_t(e)];
+                r.h = emap[2 * size_t(e) + 1];
+            }
+            recs[size_t(p) * RS + t] = r;
+        }
+    }
+
     gfbp_code *c = new (std::nothrow) gfbp_code();
     if (!c) return fail(GFBP_ENOMEM, "host allocation");
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes ? bytes : 1); return o; };
     const size_t o_rp = take(4 * size_t(m + 1)), o_col = take(4 * size_t(E)), o_coef = take(size_t(E)),
                  o_cp = take(4 * size_t(n + 1)), o_ce = take(4 * size_t(E)), o_er = take(4 * size_t(E)),
-                 o_mul = take(size_t(q) * q), o_em = take(16 * size_t(E)), o_lc = take(4 * size_t(n));
+                 o_mul = take(size_t(q) * q), o_em = take(16 * size_t(E)), o_lc = take(4 * size_t(n)),
+                 o_sr = take(sizeof(SusRec) * recs.size());
     if (hipMalloc(&c->mem, off) != hipSuccess) {
         delete c;
         return fail(GFBP_ENOMEM, "device allocation for the code");
@@ -847,6 +867,7 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (err == hipSuccess) err = up(o_mul, mul.data(), mul.size());
     if (err == hipSuccess) err = up(o_em, emap.data(), 16 * size_t(E));
     if (err == hipSuccess) err = up(o_lc, level_cols.data(), 4 * size_t(n));
+    if (err == hipSuccess) err = up(o_sr, recs.data(), sizeof(SusRec) * recs.size());
     if (err != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
@@ -858,6 +879,7 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     c->level_sibs = std::move(level_sibs);
     c->level_edges = std::move(level_edges);
     c->level_cols = reinterpret_cast<const int32_t *>(base + o_lc);
+    c->sus_recs = reinterpret_cast<const SusRec *>(base + o_sr);
     c->dev = DevCode{n, m, E, q, p, d->n_info, max_dv,
                      reinterpret_cast<const int32_t *>(base + o_rp), reinterpret_cast<const int32_t *>(base + o_col),
                      reinterpret_cast<const uint8_t *>(base + o_coef), reinterpret_cast<const int32_t *>(base + o_cp),
@@ -949,8 +971,7 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
 gfbp_status gfbp_code_set_shape(gfbp_code *c, int32_t schedule, int32_t entries_per_lane) {
     if (!c) return fail(GFBP_EINVAL, "null code");
     if (schedule != GFBP_PUS && schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
-    if (!allowed_el(c, schedule, entries_per_lane))
-        return fail(GFBP_EUNSUPPORTED, "entries per lane not available for this code and schedule");
+    if (!allowed_el(c, entries_per_lane)) return fail(GFBP_EUNSUPPORTED, "entries per lane not available for this code");
     c->el[schedule == GFBP_SUS ? 1 : 0] = entries_per_lane;
     return GFBP_OK;
 }
@@ -975,7 +996,7 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     to.snap_q = to.snap_r = to.snap_Q = nullptr;
     double best_t = 1e300;
     int best = 0;
-    for (int l = 1; l <= max_lel(c, b->schedule); ++l) {
+    for (int l = 1; l <= max_lel(c); ++l) {
         c->el[slot] = 1 << l;
         double t = 0;
         for (int rep = 0; rep < 2; ++rep) {  // the first run warms up, the second is timed

@@ -35,6 +35,16 @@ struct DevCode {
     const uint64_t *emap;     // [E][2] images of x^b under h^-1 (word 0) and h (word 1), 6 bits each
 };
 
+// One edge slot of a column in the sequential schedule, precomputed so that
+// a column step starts from a single wave-uniform load: the column j and its
+// degree dv, and for slots below dv the edge e, its row i, the row's first
+// edge rs, the row degree dc, e's place in its row (self) and the packed
+// images of the basis under h_e^-1 and h_e.
+struct SusRec {
+    int32_t j, dv, e, i, rs, dc, self, pad;
+    uint64_t hinv, h;
+};
+
 struct DevState {
     float *Qm;        // [E][F][Q] variable-to-check messages, weighted domain q~(y) = q(h^-1 y)
     float *R;         // [E][F][Q] check-to-variable messages r (PUS only)

@@ -79,7 +79,7 @@ __device__ __forceinline__ void lane_of(Item &it) {
 template <int P, int LG>
 __device__ __forceinline__ Item item(int nodes, const DevState &s) {
     using Gm = Geo<P, LG>;
-    const int w = int(blockIdx.x) * (kBlock / kWave) + int(threadIdx.x) / kWave;
+    const int w = int(blockIdx.x) * (kBlock / kWave) + __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     Item it;
     it.node = w / s.nb;
     const int ti = w % s.nb;
@@ -541,34 +541,40 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
     variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, markov, wantQ, snap, perm);
 }
 
-// A6 sequential schedule, the step of column j for one tile of frames, done
-// by a workgroup: wavefront d (< column degree) computes the r of the
-// column's d-th edge from the siblings' current q (partial horizontal pass);
-// after a workgroup barrier, wavefront d combines the column's r into its
-// edge's q and wavefront 0 into the pseudo-posterior and decision (partial
-// vertical pass).  `live`: this lane's frame is still iterating.  perm is the
-// wavefront's LDS rows; rsh holds the column's r as [d][register][lane].
+// A6 sequential schedule, the step of one column for one tile of frames,
+// done by a workgroup: wavefront d (< column degree) computes the r of the
+// column's d-th edge (record rec) from the siblings' current q (partial
+// horizontal pass); after a workgroup barrier, wavefront d combines the
+// column's r into its edge's q and wavefront 0 into the pseudo-posterior and
+// decision (partial vertical pass).  `live`: this lane's frame is still
+// iterating.  perm is the wavefront's LDS rows; rsh holds the column's r as
+// [d][register][lane].  The column's prior is loaded first so that its
+// latency overlaps the check-side work.
 template <int P, int LG, int DCM, int DVM>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
-                                           bool live, int j, int markov, int wantQ, const Snap &snap, float *perm,
-                                           float *rsh) {
+                                           bool live, const SusRec &rec, int markov, int wantQ, const Snap &snap,
+                                           float *perm, float *rsh) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
-    const int d = int(threadIdx.x) / kWave, lane = int(threadIdx.x) % kWave;
-    const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
+    const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave), lane = int(threadIdx.x) % kWave;
+    const int j = rec.j, dv = rec.dv;
     const bool mine = live && d < dv;
-    size_t e = 0;
-    if (d < dv) e = size_t(c.col_edge[cs + d]);
+    const bool post = live && d == 0;  // pseudo-posterior and decision (also for a column without edges)
+    const size_t e = size_t(rec.e);
+    float pf[Gm::EL];
+    if (mine || post) {
+        const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
+        const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
+        ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
+    }
     if (mine) {
-        const int i = c.edge_row[e];
-        const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
-        const int self = int(e) - rs;
+        const int rs = rec.rs, dc = rec.dc, self = rec.self;
         float raw[DCM][Gm::EL];
 #pragma unroll
         for (int t = 0; t < DCM; ++t)
             if (t < dc && t != self) ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + t), s.Fp, it), raw[t]);
         double acc[Gm::EL];
-        syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + i] : 0, it.g, acc);
+        syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + rec.i] : 0, it.g, acc);
 #pragma unroll
         for (int t = 0; t < DCM; ++t) {
             if (t < dc && t != self) {
@@ -579,8 +585,12 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
             }
         }
         wht<P, LG>(acc, it.g);
-        float rv[Gm::EL];
-        r_from_transform<P, LG>(c, e, it, acc, perm, rv);
+        int pos[Gm::EL];
+        gf_positions<P, LG>(rec.hinv, it.g, pos);
+        float tv[Gm::EL], rv[Gm::EL];
+#pragma unroll
+        for (int q = 0; q < Gm::EL; ++q) tv[q] = float(fmax(acc[q] * (1.0 / double(Gm::Q)), 0.0));
+        lds_permute<P, LG>(perm, it, pos, tv, rv);
 #pragma unroll
         for (int q = 0; q < Gm::EL; ++q) {
             rsh[(d * Gm::EL + q) * kWave + lane] = rv[q];
@@ -588,38 +598,34 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
         }
     }
     __syncthreads();
-    if (mine) {
-        const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
-        const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
-        float pf[Gm::EL];
-        ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
-        double pv[Gm::EL];
+    double pv[Gm::EL];
 #pragma unroll
-        for (int q = 0; q < Gm::EL; ++q) pv[q] = pf[q];
-        if (d == 0) {
-            // A4/A5: pseudo-posterior (Eq. (5)) and decision
-            double acc[Gm::EL];
+    for (int q = 0; q < Gm::EL; ++q) pv[q] = pf[q];
+    if (post) {
+        // A4/A5: pseudo-posterior (Eq. (5)) and decision
+        double acc[Gm::EL];
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) acc[q] = pv[q];
+        for (int q = 0; q < Gm::EL; ++q) acc[q] = pv[q];
 #pragma unroll
-            for (int d2 = 0; d2 < DVM; ++d2)
-                if (d2 < dv) {
+        for (int d2 = 0; d2 < DVM; ++d2)
+            if (d2 < dv) {
 #pragma unroll
-                    for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
-                }
-            normalise<P, LG>(acc, s.guards, f, it.g);
-            int best = it.g * Gm::EL;
-            float bv = float(acc[0]);
-            float Qf[Gm::EL];
-#pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) {
-                Qf[q] = float(acc[q]);
-                if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
+                for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
             }
-            if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
-            best = lanes_argmax<P, LG>(bv, best);
-            if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
+        normalise<P, LG>(acc, s.guards, f, it.g);
+        int best = it.g * Gm::EL;
+        float bv = float(acc[0]);
+        float Qf[Gm::EL];
+#pragma unroll
+        for (int q = 0; q < Gm::EL; ++q) {
+            Qf[q] = float(acc[q]);
+            if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
         }
+        if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
+        best = lanes_argmax<P, LG>(bv, best);
+        if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
+    }
+    if (mine) {
         // Eq. (4) for this wavefront's edge
         double qv[Gm::EL];
 #pragma unroll
@@ -637,26 +643,32 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
         if (snap.q)
 #pragma unroll
             for (int q = 0; q < Gm::EL; ++q) snap.q[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = qn[q];
-        store_q<P, LG>(c, s, e, it, qn, perm);
+        int pos[Gm::EL];
+        gf_positions<P, LG>(rec.h, it.g, pos);
+        float out[Gm::EL];
+        lds_permute<P, LG>(perm, it, pos, qn, out);
+        st<Gm::EL>(chunk<P, LG>(s.Qm, e, s.Fp, it), out);
     }
-    __syncthreads();
 }
 
-// A6, one dependency level: the columns cols[0..ncols) share no check, so
+// A6, one dependency level: the columns of recs[0..ncols) share no check, so
 // their steps commute; each runs exactly as in the strict order.  One
 // workgroup per (column, tile), one wavefront per edge of the column
-// (blockDim = 64 x the largest column degree, at most DVM wavefronts).
+// (blockDim = 64 x the largest column degree, at most DVM wavefronts; recs
+// holds rstride >= that many slots per column).
 template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
-                                                          int wantQ, Snap snap, const int32_t *cols, int ncols) {
+                                                          int wantQ, Snap snap, const SusRec *recs, int rstride,
+                                                          int ncols) {
     using Gm = Geo<P, LG>;
     __shared__ __align__(16) float perm[DVM * Gm::PERM];
     __shared__ float rsh[DVM * Gm::EL * kWave];
     const Item it = block_item<P, LG>(ncols, s);
     if (!it.ok) return;  // uniform over the workgroup
+    const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const SusRec rec = recs[size_t(it.node) * rstride + d];
     const bool live = it.f < s.F && s.active[it.f];
-    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, cols[it.node], markov, wantQ, snap,
-                                perm + (int(threadIdx.x) / kWave) * Gm::PERM, rsh);
+    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, perm + d * Gm::PERM, rsh);
 }
 
 // A6, strict order: columns 0..n-1 one after the other for each tile.
@@ -669,8 +681,25 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
     const Item it = block_item<P, LG>(1, s);
     if (!it.ok) return;  // uniform over the workgroup
     const bool live = it.f < s.F && s.active[it.f];
-    float *mine = perm + (int(threadIdx.x) / kWave) * Gm::PERM;
-    for (int j = 0; j < c.n; ++j) sus_column<P, LG, DCM, DVM>(c, s, z, it, live, j, markov, wantQ, snap, mine, rsh);
+    const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    float *mine = perm + d * Gm::PERM;
+    for (int j = 0; j < c.n; ++j) {
+        SusRec rec{};
+        rec.j = j;
+        const int cs = c.col_ptr[j];
+        rec.dv = c.col_ptr[j + 1] - cs;
+        if (d < rec.dv) {
+            rec.e = c.col_edge[cs + d];
+            rec.i = c.edge_row[rec.e];
+            rec.rs = c.row_ptr[rec.i];
+            rec.dc = c.row_ptr[rec.i + 1] - rec.rs;
+            rec.self = rec.e - rec.rs;
+            rec.hinv = c.emap[2 * size_t(rec.e)];
+            rec.h = c.emap[2 * size_t(rec.e) + 1];
+        }
+        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, mine, rsh);
+        __syncthreads();  // rsh and the LDS rows are reused by the next column
+    }
 }
 
 // A7 dynamical block prior (Eq. (7)) for source symbol k: from this
