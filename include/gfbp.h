@@ -134,6 +134,16 @@ typedef struct {
  * other within each frame). */
 #define GFBP_OPT_SUS_STRICT 1
 
+/* Frames are processed in tiles of up to 64 frames that share every kernel
+ * launch, and a tile keeps running while any of its frames does.  When, after
+ * an iteration, the running frames fill less than 3/4 of the running tiles,
+ * the decoder by default moves running frames (their messages, likelihoods,
+ * priors and counters) into the slots of finished frames so that the running
+ * frames form whole tiles again; each frame's arithmetic, and so every output,
+ * is unchanged (results are written per frame when it finishes).  Not done
+ * when posteriors or snapshots are requested.  This option turns it off. */
+#define GFBP_OPT_NO_COMPACT 2
+
 /* Outputs, device memory owned by the caller. */
 typedef struct {
     uint8_t *xhat;           /* [F][n] decision after the frame's last iteration      */

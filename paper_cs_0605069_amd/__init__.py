@@ -24,6 +24,7 @@ PUS, SUS = 0, 1
 CH_BSC, CH_BEC, CH_BIAWGN, CH_LIKELIHOOD = 0, 1, 2, 3
 PRIOR_UNIFORM, PRIOR_MARKOV = 0, 1
 OPT_SUS_STRICT = 1
+OPT_NO_COMPACT = 2
 CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
@@ -268,7 +269,7 @@ def frames_to_device(frames, device="cuda"):
 def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
-                 sus_strict: bool = False, tune_iters: int = 0) -> dict:
+                 sus_strict: bool = False, tune_iters: int = 0, compact: bool = True) -> dict:
     """``gfbp_decode_batch`` on device tensors; returns device tensors.
 
     dframes: dict from :func:`frames_to_device` (or with the same keys).
@@ -305,7 +306,7 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     b = Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes["channel"]], _dptr(dframes.get("param")),
               _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")), _dptr(dframes.get("y")),
               _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")), pk, _dptr(Mt), _dptr(pt),
-              OPT_SUS_STRICT if sus_strict else 0)
+              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT))
     r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), _dptr(out.get("posterior")),
                _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
                _dptr(out.get("snap_Q")))

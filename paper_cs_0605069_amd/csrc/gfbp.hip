@@ -3,6 +3,7 @@
 // Paper: Yacov, Efraim, Kfir, Kanter, Shental, "Parallel vs. Sequential Belief
 // Propagation Decoding of LDPC Codes over GF(q) and Markov Sources", Section 2.
 // The public contract is include/gfbp.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -62,9 +63,11 @@ struct gfbp_code {
 // launch attached.  Read back after the decode's final synchronisation.
 namespace {
 
-enum Kind { K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COUNT };
-const char *kKindName[K_COUNT] = {"init",     "check",   "variable", "sequential", "sus_level",
-                                  "syndrome", "retire",  "markov",   "output"};
+enum Kind {
+    K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COMPACT, K_COUNT
+};
+const char *kKindName[K_COUNT] = {"init",     "check",  "variable", "sequential", "sus_level",
+                                  "syndrome", "retire", "markov",   "output",     "compact"};
 
 struct Totals {
     int64_t launches = 0;
@@ -75,6 +78,10 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 Totals g_prof[K_COUNT];
 
+// Events handed to the next kernel launch (see launch()): the kernel's own
+// start and end timestamps, so a traced duration is the kernel's alone.
+thread_local hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
+
 struct Tracer {
     struct Rec {
         int kind;
@@ -84,7 +91,6 @@ struct Tracer {
     bool on;
     hipStream_t st;
     std::vector<Rec> recs;
-    hipEvent_t pending = nullptr;
     static thread_local std::vector<hipEvent_t> pool;
 
     explicit Tracer(hipStream_t s) : st(s) {
@@ -101,19 +107,30 @@ struct Tracer {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
+    // the next launch() on this thread carries a pair of events
     void begin() {
         if (!on) return;
-        pending = get();
-        if (pending) (void)hipEventRecord(pending, st);
+        hipEvent_t a = get(), b = get();
+        if (!a || !b) {
+            if (a) pool.push_back(a);
+            if (b) pool.push_back(b);
+            return;
+        }
+        g_launch_ev[0] = a;
+        g_launch_ev[1] = b;
     }
+    // the launch since begin() took the events (else nothing is recorded)
     void end(int kind, double bytes, double edgeq) {
-        if (!on || !pending) return;
-        hipEvent_t b = get();
-        if (!b) return;
-        (void)hipEventRecord(b, st);
-        recs.push_back(Rec{kind, pending, b, bytes, edgeq});
-        pending = nullptr;
+        if (!on) return;
+        if (g_launch_ev[0]) {  // no launch happened
+            pool.push_back(g_launch_ev[0]);
+            pool.push_back(g_launch_ev[1]);
+            g_launch_ev[0] = g_launch_ev[1] = nullptr;
+            return;
+        }
+        recs.push_back(Rec{kind, last_[0], last_[1], bytes, edgeq});
     }
+    static thread_local hipEvent_t last_[2];
     // call after the stream has been synchronised
     void flush() {
         if (!on) return;
@@ -133,22 +150,52 @@ struct Tracer {
         recs.clear();
     }
 };
+thread_local hipEvent_t Tracer::last_[2] = {nullptr, nullptr};
 thread_local std::vector<hipEvent_t> Tracer::pool;
+
+// Kernel launch; when a tracer has handed out events, they are attached to
+// this launch (hipExtLaunchKernelGGL) and then belong to the tracer.
+template <typename F, typename... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, Args... args) {
+    if (g_launch_ev[0]) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, g_launch_ev[0], g_launch_ev[1], 0, args...);
+        Tracer::last_[0] = g_launch_ev[0];
+        Tracer::last_[1] = g_launch_ev[1];
+        g_launch_ev[0] = g_launch_ev[1] = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+    }
+}
 
 }  // namespace
 
 // ======================================================================= kernels
 namespace {
 
-__global__ void k_state_init(DevState s, int32_t *iters, uint8_t *conv) {
+// Per-slot state of a batch decode that is not in DevState.  A slot holds
+// frame orig[slot]; running frames may move to other slots (compaction), so
+// every per-frame result is written through orig when the frame finishes.
+struct BatchAux {
+    int32_t *orig;    // [Fp] frame held by each slot
+    int32_t *iters;   // [Fp] first converged iteration (or max_iter)
+    uint8_t *conv;    // [Fp] converged at some iteration
+    uint8_t *z;       // [Fp][m] syndromes by slot (null when z = 0)
+    int32_t *holes;   // [Fp] compaction: finished slots below the running count
+    int32_t *movers;  // [Fp] compaction: running slots at or above it
+    uint8_t *pending; // [Fp] finished frame whose decision is not yet written out
+};
+
+__global__ void k_state_init(DevState s, BatchAux a) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < 4 && blockIdx.x == 0) s.count[f] = 0;
+    if (f < 16 && blockIdx.x == 0) s.count[f] = 0;
     if (f >= s.F) return;
     s.active[f] = 1;
     s.unsat[f] = 0;
-    iters[f] = 0;
-    conv[f] = 0;
     s.guards[f] = 0;
+    a.iters[f] = 0;
+    a.conv[f] = 0;
+    a.orig[f] = f;
+    a.pending[f] = 0;
 }
 
 // A5 convergence test: check i of frame f against z_i.
@@ -164,17 +211,31 @@ __global__ __launch_bounds__(kBlock) void k_syndrome(DevCode c, DevState s, cons
     if (acc != (z ? z[size_t(f) * c.m + i] : 0)) s.unsat[f] = 1;
 }
 
-// A5 retirement after iteration t.
-__global__ void k_retire(DevState s, int t, int max_iter, int early_stop, int32_t *iters, uint8_t *conv) {
+// A5 retirement after iteration t: a frame whose decision satisfies H x = z
+// (with early stopping) or that has run max_iter iterations stops; its
+// iteration count, convergence flag and guard count are written to the
+// outputs of frame orig[f], its decision later (k_emit) from the slot.
+// Running frames are counted for this iteration's parity; the other parity's
+// counter is cleared for the next.
+__global__ void k_retire(DevState s, BatchAux a, int t, int max_iter, int early_stop, int32_t *out_iters,
+                         uint8_t *out_conv, int32_t *out_guards) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f == 0) s.count[2 * ((t + 1) & 1)] = 0;
     if (f >= s.F) return;
     if (s.active[f]) {
         const bool ok = s.unsat[f] == 0;
-        if (ok && !conv[f]) { conv[f] = 1; iters[f] = t; }
+        if (ok && !a.conv[f]) {
+            a.conv[f] = 1;
+            a.iters[f] = t;
+        }
         if ((ok && early_stop) || t >= max_iter) {
             s.active[f] = 0;
-            if (!conv[f]) iters[f] = max_iter;
+            if (!a.conv[f]) a.iters[f] = max_iter;
+            const size_t o = size_t(a.orig[f]);
+            out_iters[o] = a.iters[f];
+            out_conv[o] = a.conv[f];
+            if (out_guards) out_guards[o] = s.guards[f];
+            a.pending[f] = 1;
         } else {
             atomicAdd(&s.count[2 * (t & 1)], 1u);
         }
@@ -182,11 +243,101 @@ __global__ void k_retire(DevState s, int t, int max_iter, int early_stop, int32_
     s.unsat[f] = 0;
 }
 
-__global__ void k_out_xhat(const uint8_t *xh, int n, int F, int Fp, uint8_t *out) {
+// Decisions of finished frames to their rows of out: the frames in slots
+// list[0..k) (before those slots are reused), or with list null every slot
+// r < k still flagged pending.
+__global__ void k_emit(DevState s, BatchAux a, const int32_t *list, int k, int n, uint8_t *out) {
     const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= size_t(n) * F) return;
-    const int f = int(t / n), j = int(t % n);
-    out[t] = xh[size_t(j) * Fp + f];
+    if (t >= size_t(k) * n) return;
+    const int r = int(t / n), j = int(t % n);
+    const int f = list ? list[r] : r;
+    if (!list && !a.pending[f]) return;
+    out[size_t(a.orig[f]) * n + j] = s.xh[size_t(j) * s.Fp + f];
+}
+
+// Compaction plan with R frames running: the finished slots below R (holes)
+// and the running slots at or above R (movers), both in increasing order;
+// there are as many of each, written to *count.  One workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_plan_moves(const uint8_t *active, int F, int R, int32_t *holes,
+                                                     int32_t *movers, uint32_t *count) {
+    __shared__ uint32_t hs[1024 / kWave], ms[1024 / kWave];
+    __shared__ uint32_t hb, mb;
+    const int lane = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
+    if (threadIdx.x == 0) hb = mb = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < F; c0 += 1024) {
+        const int f = c0 + int(threadIdx.x);
+        const bool act = f < F && active[f];
+        const bool hole = f < F && f < R && !act, mover = f >= R && act;
+        const uint64_t bh = __ballot(hole), bm = __ballot(mover);
+        if (lane == 0) {
+            hs[wv] = uint32_t(__popcll(bh));
+            ms[wv] = uint32_t(__popcll(bm));
+        }
+        __syncthreads();
+        uint32_t oh = hb, om = mb;
+        for (int w = 0; w < wv; ++w) {
+            oh += hs[w];
+            om += ms[w];
+        }
+        const uint64_t below = (uint64_t(1) << lane) - 1;
+        if (hole) holes[oh + uint32_t(__popcll(bh & below))] = f;
+        if (mover) movers[om + uint32_t(__popcll(bm & below))] = f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < 1024 / kWave; ++w) {
+                hb += hs[w];
+                mb += ms[w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = mb;
+}
+
+// Move running frame movers[k] into finished slot holes[k] (k = blockIdx.x):
+// its q-messages, likelihoods and Markov-weighted likelihoods (the vectors
+// that carry over between iterations), W floats per thread over
+// blockIdx.y; block y = 0 also moves the per-slot scalars and the syndrome.
+// Holes and movers are disjoint, so the copies never overlap.
+__global__ __launch_bounds__(256) void k_move_frames(DevState s, BatchAux a, int E, int n, int K, int Q, int W,
+                                                     int m) {
+    const int k = blockIdx.x;
+    const int src = a.movers[k], dst = a.holes[k];
+    const size_t o = (size_t(blockIdx.y) * blockDim.x + threadIdx.x) * W;
+    const size_t per = size_t(E + n + K) * Q;
+    if (o < per) {
+        const size_t v = o / Q, e = o % Q;
+        float *arr;
+        size_t node;
+        if (v < size_t(E)) {
+            arr = s.Qm;
+            node = v;
+        } else if (v < size_t(E + n)) {
+            arr = s.L;
+            node = v - E;
+        } else {
+            arr = s.Pr;
+            node = v - E - n;
+        }
+        const float *from = arr + (node * s.Fp + src) * Q + e;
+        float *to = arr + (node * s.Fp + dst) * Q + e;
+        if (W == 4) *reinterpret_cast<float4 *>(to) = *reinterpret_cast<const float4 *>(from);
+        else *reinterpret_cast<float2 *>(to) = *reinterpret_cast<const float2 *>(from);
+    }
+    if (blockIdx.y == 0) {
+        if (a.z)
+            for (int i = threadIdx.x; i < m; i += blockDim.x) a.z[size_t(dst) * m + i] = a.z[size_t(src) * m + i];
+        if (threadIdx.x == 0) {
+            a.orig[dst] = a.orig[src];
+            a.iters[dst] = a.iters[src];
+            a.conv[dst] = a.conv[src];
+            a.pending[dst] = 0;
+            s.guards[dst] = s.guards[src];
+            s.active[dst] = 1;
+            s.active[src] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -256,47 +407,47 @@ struct TiledLaunch {
     static void init(hipStream_t st, const DevCode &c, const DevState &s, const gfbp_batch *b) {
         tiled::Chan ch{b->channel, b->prior == GFBP_PRIOR_MARKOV, b->rx, b->erasure, b->y, b->likelihood, b->param,
                        b->markov_pi};
-        hipLaunchKernelGGL((tiled::k_init<P, LG>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
+        launch((tiled::k_init<P, LG>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
     }
     static void check(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_check<P, LG, DCM>), dim3(tiled_blocks(c.m, s)), dim3(kBlock), 0, st, c, s,
+        launch((tiled::k_check<P, LG, DCM>), dim3(tiled_blocks(c.m, s)), dim3(kBlock), 0, st, c, s,
                            z, sn);
     }
     static void variable(hipStream_t st, const DevCode &c, const DevState &s, int markov, int wantQ, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_variable<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c,
+        launch((tiled::k_variable<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c,
                            s, markov, wantQ, sn);
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                           Snap sn, const SusRec *recs, int nc) {
-        hipLaunchKernelGGL((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
+        launch((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
                            dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, recs,
                            std::max(1, c.max_dv), nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn) {
-        hipLaunchKernelGGL((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
+        launch((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
                            dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
-        hipLaunchKernelGGL((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
+        launch((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
                            M, pi);
     }
     static constexpr int TF = kWave >> LG;
     static void tiles(hipStream_t st, const uint8_t *mask, int F, int Fp, int32_t *out, uint32_t *count) {
-        hipLaunchKernelGGL(tiled::k_tiles, dim3(1), dim3(1024), 0, st, mask, F, Fp, TF, out, count);
+        launch(tiled::k_tiles, dim3(1), dim3(1024), 0, st, mask, F, Fp, TF, out, count);
     }
     static void markov_any(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
         markov(st, c, s, M, pi);
     }
     static void vectors(hipStream_t st, const float *src, int n, const DevState &s, float *out) {
         const size_t tot = size_t(n) * s.F * (1 << P);
-        hipLaunchKernelGGL((tiled::k_out_vectors<P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, src, n,
+        launch((tiled::k_out_vectors<P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, src, n,
                            s.F, s.Fp, out);
     }
 };
 
 template <int P, class K>
-gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s,
+gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
                       hipStream_t st, int needQ) {
     constexpr int Q = 1 << P;
     const DevCode &c = code->dev;
@@ -304,8 +455,16 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const unsigned fb = unsigned((F + kBlock - 1) / kBlock);
     const Bytes bpf = bytes_per_frame(code, needQ, b->syndrome != nullptr);
     const double eq_frame = double(c.E) * Q;
+    const uint8_t *z = b->syndrome ? a.z : nullptr;  // syndromes by slot
+    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
+    // moving frames keeps running frames in whole tiles; posteriors and
+    // snapshots are read by slot at the end, so they keep frames in place
+    const bool compact = !(b->options & GFBP_OPT_NO_COMPACT) && !out->posterior && out->snap_iter <= 0 &&
+                         F > K::TF;
+    const int Kp = markov ? c.n_info : 0;  // Markov-weighted likelihoods move with the frame
     Tracer tr(st);
-    hipLaunchKernelGGL(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, out->iters, out->converged);
+    launch(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, a);
+    if (b->syndrome) HIP_TRY(hipMemcpyAsync(a.z, b->syndrome, size_t(F) * c.m, hipMemcpyDeviceToDevice, st));
     const int ntiles = s.Fp / K::TF;
     K::tiles(st, s.active, F, s.Fp, s.tiles, s.count + 1);
     // the first list holds exactly the tiles holding a frame: ceil(F / TF) of
@@ -317,7 +476,6 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     K::init(st, c, s, b);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
     HIP_TRY(hipGetLastError());
-    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
     uint32_t running = uint32_t(F);
     for (int t = 1; t <= b->max_iter; ++t) {
         const bool snap_now = (t == out->snap_iter);
@@ -326,21 +484,21 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         const double Fa = running;
         if (b->schedule == GFBP_PUS) {
             tr.begin();
-            K::check(st, c, s, b->syndrome, sn);
+            K::check(st, c, s, z, sn);
             tr.end(K_CHECK, Fa * bpf.check, Fa * eq_frame);
             tr.begin();
             K::variable(st, c, s, markov, wantQ, sn);
             tr.end(K_VARIABLE, Fa * bpf.variable, Fa * eq_frame);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
             tr.begin();
-            K::sequential(st, c, s, b->syndrome, markov, wantQ, sn);
+            K::sequential(st, c, s, z, markov, wantQ, sn);
             tr.end(K_SEQUENTIAL, Fa * bpf.sequential, Fa * eq_frame);
         } else {
             const int nlev = int(code->level_ptr.size()) - 1;
             for (int l = 0; l < nlev; ++l) {
                 const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
                 tr.begin();
-                K::sus_level(st, c, s, b->syndrome, markov, wantQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
+                K::sus_level(st, c, s, z, markov, wantQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
                 tr.end(K_SUS_LEVEL,
                        Fa * (4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1)),
                        Fa * code->level_edges[l] * Q);
@@ -348,10 +506,12 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
         tr.begin();
-        hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, b->syndrome);
+        launch(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
         tr.end(K_SYNDROME, Fa * bpf.syndrome, 0);
-        hipLaunchKernelGGL(k_retire, dim3(fb), dim3(kBlock), 0, st, s, t, b->max_iter, b->early_stop, out->iters,
-                           out->converged);
+        tr.begin();
+        launch(k_retire, dim3(fb), dim3(kBlock), 0, st, s, a, t, b->max_iter, b->early_stop,
+                           out->iters, out->converged, out->guards);
+        tr.end(K_RETIRE, Fa * 8.0, 0);
         HIP_TRY(hipGetLastError());
         if (t == b->max_iter) break;
         K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, s.count + 2 * (t & 1) + 1);
@@ -369,15 +529,42 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             K::markov(st, c, s, b->markov_M, b->markov_pi);
             tr.end(K_MARKOV, double(left) * bpf.markov, 0);
         }
+        if (compact && uint64_t(left) * 4 < uint64_t(cnt[1]) * K::TF * 3) {
+            // running frames fill less than 3/4 of their tiles: move them into
+            // the finished slots below `left`, then list the (now whole) tiles
+            launch(k_plan_moves, dim3(1), dim3(1024), 0, st, s.active, F, int(left), a.holes, a.movers,
+                               s.count + 8);
+            uint32_t nm = 0;
+            HIP_TRY(hipMemcpyAsync(&nm, s.count + 8, sizeof nm, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (nm > 0) {
+                const size_t ne = size_t(nm) * c.n;
+                launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm),
+                                   c.n, out->xhat);
+                const int W = Q >= 4 ? 4 : 2;
+                const size_t per = size_t(c.E + c.n + Kp) * Q;
+                const unsigned chunks = unsigned((per / W + 255) / 256);
+                tr.begin();
+                launch(k_move_frames, dim3(nm, chunks), dim3(256), 0, st, s, a, c.E, c.n, Kp, Q, W, c.m);
+                tr.end(K_COMPACT, double(nm) * (8.0 * per + 2.0 * c.m), 0);
+                K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, s.count + 2 * (t & 1) + 1);
+                s.nb = int((left + K::TF - 1) / K::TF);
+                HIP_TRY(hipGetLastError());
+            }
+        }
     }
     tr.begin();
     {
-        const size_t tot = size_t(c.n) * F;
-        hipLaunchKernelGGL(k_out_xhat, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, s.xh, c.n, F, s.Fp,
+        const size_t ne = size_t(F) * c.n;
+        launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, nullptr, F, c.n,
                            out->xhat);
     }
-    if (out->posterior) K::vectors(st, s.Qp, c.n, s, out->posterior);
-    tr.end(K_OUTPUT, double(F) * c.n * (2.0 + (out->posterior ? 8.0 * Q : 0.0)), 0);
+    tr.end(K_OUTPUT, double(F) * c.n * 2.0, 0);
+    if (out->posterior) {
+        tr.begin();
+        K::vectors(st, s.Qp, c.n, s, out->posterior);
+        tr.end(K_OUTPUT, double(F) * c.n * 8.0 * Q, 0);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     tr.flush();
@@ -385,25 +572,25 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
 }
 
 template <int P, int LEL>
-gfbp_status run_lel(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
-                    int needQ, bool small) {
+gfbp_status run_lel(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
+                    hipStream_t st, int needQ, bool small) {
     if constexpr (LEL <= 3 && LEL <= P) {
-        if (small) return run_batch<P, TiledLaunch<P, P - LEL, 6, 4>>(code, b, out, s, st, needQ);
+        if (small) return run_batch<P, TiledLaunch<P, P - LEL, 6, 4>>(code, b, out, s, a, st, needQ);
     }
     if constexpr (LEL <= 2 && LEL <= P) {
-        if (!small) return run_batch<P, TiledLaunch<P, P - LEL, 16, 8>>(code, b, out, s, st, needQ);
+        if (!small) return run_batch<P, TiledLaunch<P, P - LEL, 16, 8>>(code, b, out, s, a, st, needQ);
     }
     return fail(GFBP_EUNSUPPORTED, "no kernel for this shape");
 }
 
 template <int P>
-gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, hipStream_t st,
-                    int needQ) {
+gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
+                    hipStream_t st, int needQ) {
     const Shape sh = shape_of(code, b->schedule);
     switch (sh.lel) {
-        case 1: return run_lel<P, 1>(code, b, out, s, st, needQ, sh.small);
-        case 2: return run_lel<P, 2>(code, b, out, s, st, needQ, sh.small);
-        case 3: return run_lel<P, 3>(code, b, out, s, st, needQ, sh.small);
+        case 1: return run_lel<P, 1>(code, b, out, s, a, st, needQ, sh.small);
+        case 2: return run_lel<P, 2>(code, b, out, s, a, st, needQ, sh.small);
+        case 3: return run_lel<P, 3>(code, b, out, s, a, st, needQ, sh.small);
         default: return fail(GFBP_EUNSUPPORTED, "bad shape");
     }
 }
@@ -626,7 +813,8 @@ bool session_bind(gfbp_session *ss) {
 
 // Workspace carving, shared by size query and decode.
 struct Carve {
-    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, total;
+    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, orig, iters, conv, z, holes, movers, pending,
+        total;
 };
 
 Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
@@ -643,9 +831,16 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     c.xh = take(n * F);
     c.unsat = take(size_t(F_) * 4);
     c.active = take(size_t(F_));
-    c.count = take(16);
+    c.count = take(64);
     c.tiles = take(2 * F * 4);
-    c.guards = take(size_t(F_) * 4);
+    c.guards = take(F * 4);
+    c.orig = take(F * 4);
+    c.iters = take(F * 4);
+    c.conv = take(F);
+    c.z = take(F * size_t(code->info.m));
+    c.holes = take(F * 4);
+    c.movers = take(F * 4);
+    c.pending = take(F);
     c.total = off;
     return c;
 }
@@ -952,18 +1147,26 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
     s.active = reinterpret_cast<uint8_t *>(w + cv.active);
     s.count = reinterpret_cast<uint32_t *>(w + cv.count);
     s.tiles = reinterpret_cast<int32_t *>(w + cv.tiles);
-    s.guards = out->guards ? out->guards : reinterpret_cast<int32_t *>(w + cv.guards);
+    s.guards = reinterpret_cast<int32_t *>(w + cv.guards);
+    BatchAux a{};
+    a.orig = reinterpret_cast<int32_t *>(w + cv.orig);
+    a.iters = reinterpret_cast<int32_t *>(w + cv.iters);
+    a.conv = reinterpret_cast<uint8_t *>(w + cv.conv);
+    a.z = reinterpret_cast<uint8_t *>(w + cv.z);
+    a.holes = reinterpret_cast<int32_t *>(w + cv.holes);
+    a.movers = reinterpret_cast<int32_t *>(w + cv.movers);
+    a.pending = reinterpret_cast<uint8_t *>(w + cv.pending);
     s.F = F;
     s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (code->info.p) {
-        case 1: return run_any<1>(code, b, out, s, st, needQ);
-        case 2: return run_any<2>(code, b, out, s, st, needQ);
-        case 3: return run_any<3>(code, b, out, s, st, needQ);
-        case 4: return run_any<4>(code, b, out, s, st, needQ);
-        case 5: return run_any<5>(code, b, out, s, st, needQ);
-        case 6: return run_any<6>(code, b, out, s, st, needQ);
+        case 1: return run_any<1>(code, b, out, s, a, st, needQ);
+        case 2: return run_any<2>(code, b, out, s, a, st, needQ);
+        case 3: return run_any<3>(code, b, out, s, a, st, needQ);
+        case 4: return run_any<4>(code, b, out, s, a, st, needQ);
+        case 5: return run_any<5>(code, b, out, s, a, st, needQ);
+        case 6: return run_any<6>(code, b, out, s, a, st, needQ);
         default: return fail(GFBP_EUNSUPPORTED, "bad field");
     }
 }

@@ -276,6 +276,36 @@ def test_frame_alone_equals_frame_in_batch_and_runs_repeat(gfbp, schedule):
         assert one["iters"][0] == a["iters"][f]
 
 
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_frame_compaction_changes_nothing(gfbp, schedule):
+    """Moving running frames into finished slots (on by default) gives bitwise
+    the outputs of decoding with every frame in place, with a Markov prior and
+    a syndrome; the batch mixes fast and slow frames so that compaction runs
+    several times."""
+    import torch
+
+    q = 8
+    code, enc = wl.regular_code(240, 3, 6, q, seed=37)
+    M = wl.self_transition_matrix(q, 0.7)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 700, 38, "bsc", np.linspace(0.02, 0.14, 700), source="markov", markov=M)
+    z = np.random.default_rng(39).integers(0, q, size=(fr.F, code.m)).astype(np.uint8)
+    z[::3] = 0
+    fr.syndrome = z
+    dcode = gfbp.DeviceCode(code)
+    dfr = gfbp.frames_to_device(fr)
+    outs = []
+    for compact in (False, True):
+        o = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=60, prior="markov", markov_M=M, markov_pi=pi,
+                              compact=compact)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    it = outs[0]["iters"]
+    assert it.min() < 10 and (it == 60).sum() > 20  # fast and slow frames
+    for k in ("xhat", "iters", "converged", "guards"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
 def test_edge_cases(gfbp):
     import torch
 
