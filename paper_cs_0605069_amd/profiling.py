@@ -73,7 +73,7 @@ def stats(path: str) -> list[dict]:
     return out
 
 
-def stats_markdown(path: str, command: str, bench_line: str | None = None) -> str:
+def stats_markdown(path: str, command: str, bench_line: str | None = None, plain_line: str | None = None) -> str:
     rows = stats(path)
     lines = ["# Kernel time: rocprofv3 --kernel-trace --stats", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | avg µs | total ms | % of GPU time |", "|---|---:|---:|---:|---:|"]
@@ -90,6 +90,13 @@ def stats_markdown(path: str, command: str, bench_line: str | None = None) -> st
                       f"average over {roof['launches']} launches; this trace gives {tot / max(calls, 1) * 1e3:.2f} µs "
                       f"over {calls} dispatches.  Algorithmic bytes per launch {roof['algo_bytes_per_launch'] / 1e6:.3f} MB, "
                       f"achieved {roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of {roof['peak']:.0f} GB/s)."]
+    if plain_line:
+        # the same bench without the profiler attached
+        last = [ln for ln in open(plain_line).read().splitlines() if ln.startswith("{")][-1]
+        roof = json.loads(last)["roofline"]
+        lines += ["", f"The same bench without the profiler (its default steps): `{roof['kernel']}` "
+                      f"{roof['avg_launch_ms'] * 1e3:.2f} µs average over {roof['launches']} launches, "
+                      f"{roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of {roof['peak']:.0f} GB/s)."]
     return "\n".join(lines) + "\n"
 
 
@@ -170,6 +177,7 @@ def main():
     a.add_argument("--command", required=True)
     a.add_argument("--out", required=True)
     a.add_argument("--bench-line", help="the program's own output (its last JSON line) to compare against")
+    a.add_argument("--plain-line", help="output of the same program run without the profiler")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -179,7 +187,7 @@ def main():
     b.add_argument("--out", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
-        text = stats_markdown(args.csv, args.command, args.bench_line)
+        text = stats_markdown(args.csv, args.command, args.bench_line, args.plain_line)
     else:
         text = traffic_markdown(args.fetch_csv, args.write_csv, args.copy_bytes, args.shapes, args.command)
     with open(args.out, "w") as f:
