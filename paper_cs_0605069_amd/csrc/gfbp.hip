@@ -1426,14 +1426,45 @@ gfbp_status gfbp_graph_capture(gfbp_session *const *sessions, int32_t n, int32_t
     if (!st) return fail(GFBP_EINVAL, "graph capture needs a created stream, not the default stream");
     for (int k = 0; k < n; ++k)
         if (!sessions[k]) return fail(GFBP_EINVAL, "null session");
-    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    // each session's iterations on a stream of its own, forked from and joined
+    // back into the capturing stream, so the graph's session branches are
+    // independent and may run concurrently
+    std::vector<hipStream_t> ws(size_t(n), nullptr);
+    std::vector<hipEvent_t> ev(size_t(n) + 1, nullptr);
+    auto release = [&]() {
+        for (auto &x : ws)
+            if (x) (void)hipStreamDestroy(x);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (int k = 0; k < n; ++k)
+        if (hipStreamCreateWithFlags(&ws[k], hipStreamNonBlocking) != hipSuccess) {
+            release();
+            return fail(GFBP_EHIP, "creating capture streams");
+        }
+    for (auto &e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            release();
+            return fail(GFBP_EHIP, "creating capture events");
+        }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        release();
+        return fail(GFBP_EHIP, "hipStreamBeginCapture");
+    }
     gfbp_status rs = GFBP_OK;
-    for (int k = 0; k < n && rs == GFBP_OK; ++k) rs = sessions[k]->step_fn(sessions[k], iters, st, true);
+    hipError_t he = hipEventRecord(ev[n], st);
+    for (int k = 0; k < n && rs == GFBP_OK && he == hipSuccess; ++k) {
+        he = hipStreamWaitEvent(ws[k], ev[n], 0);
+        if (he == hipSuccess) rs = sessions[k]->step_fn(sessions[k], iters, ws[k], true);
+        if (rs == GFBP_OK && he == hipSuccess) he = hipEventRecord(ev[k], ws[k]);
+        if (rs == GFBP_OK && he == hipSuccess) he = hipStreamWaitEvent(st, ev[k], 0);
+    }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &graph);
-    if (rs != GFBP_OK) {
+    release();
+    if (rs != GFBP_OK || he != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        return rs;
+        return rs != GFBP_OK ? rs : fail(GFBP_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
     }
     if (ec != hipSuccess) return fail(GFBP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
     hipGraphExec_t exec = nullptr;

@@ -23,21 +23,24 @@ def gfbp():
     return g
 
 
+@pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_served_frames_equal_alone_decoding(gfbp, schedule):
+def test_served_frames_equal_alone_decoding(gfbp, schedule, graph):
     import torch
     from paper_cs_0605069_amd import serving
 
     pool = wl.mixed_pool(4, seed=71, n_range=(256, 900))
     queues, markov = serving.make_requests(pool, 500, rate=20000.0, seed=72)
-    srv = serving.Server(queues, slots=64, schedule=schedule, max_iter=40, budget_bytes=8 << 30, step_iters=3,
-                         markov=markov, keep_results=True)
+    srv = serving.Server(queues, slots=64, schedule=schedule, max_iter=40, budget_bytes=8 << 30,
+                         step_iters=2 if graph else 3, markov=markov, keep_results=True, graph=graph)
     st = srv.run()
-    assert st.done == 500 and len(st.results) == 500
+    assert srv.opened == len(queues)
+    assert st.done == 500 and st.offered == 500 and len(st.results) == 500
     assert len(st.latency) == 500 and min(st.latency) >= 0
     for cq in queues:
         M, pi = markov[cq.code.q]
-        for g, m, gids in cq.groups:
+        for g, m, pos in cq.groups:
+            gids = cq.ids[pos]  # one request per pool frame here
             kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
             out = gfbp.decode_batch(cq.dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40, **kw)
             torch.cuda.synchronize()
@@ -62,6 +65,24 @@ def test_memory_budget_defers_sessions(gfbp):
     # room for the largest session only: sessions run one after another
     srv = serving.Server(queues, slots=64, schedule="pus", max_iter=30, budget_bytes=max(need), markov=markov,
                          autotune=False)
-    st = srv.run()
+    st = srv.run(prewarm=False)
     assert st.done == 150
     assert srv.refused > 0
+
+
+def test_pool_frames_are_reused_cyclically(gfbp):
+    """With a pool of P frames per code, request k of a code decodes frame
+    k mod P: requests k and k + P give identical results."""
+    from paper_cs_0605069_amd import serving
+
+    pool = wl.mixed_pool(2, seed=75, n_range=(256, 500))
+    queues, markov = serving.make_requests(pool, 200, rate=50000.0, seed=76, pool_max=16)
+    srv = serving.Server(queues, slots=64, schedule="sus", max_iter=30, budget_bytes=4 << 30, markov=markov,
+                         keep_results=True, autotune=False)
+    st = srv.run()
+    assert st.done == 200
+    for cq in queues:
+        assert cq.P == 16 and len(cq.ids) > 32
+        for k in range(len(cq.ids) - 16):
+            a, b = st.results[int(cq.ids[k])], st.results[int(cq.ids[k + 16])]
+            assert a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2])
