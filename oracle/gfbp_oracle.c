@@ -235,6 +235,13 @@ typedef struct {
     const double *markov_pi;  /* [q] */
     int snap_iter;            /* 1-based iteration after which messages are copied out; 0 = none */
     int n_threads;            /* 0 = OpenMP default */
+    int precision_model;      /* test instrument, 0 (normal): full double precision.
+                                 1: every stored vector (q, r, Q, p) rounded to float32 after it
+                                 is computed (a decoder keeping its messages in float32);
+                                 2: as 1, and entries of each r-vector below 4e-16 of its largest
+                                 entry set to 0 (the resolution of an Eq. (3) evaluated through a
+                                 double-precision transform, whose small outputs are differences
+                                 of order-one terms) */
 } ref_batch;
 
 typedef struct {
@@ -278,6 +285,22 @@ static int graph_build(const ref_code *C, ref_graph *G)
 static void graph_free(ref_graph *G)
 {
     free(G->col_ptr); free(G->col_edge); free(G->edge_row);
+}
+
+/* v[0..q) rounded to float32 when asked (see precision_model) */
+static void round32(double *v, int q, int on)
+{
+    if (on)
+        for (int a = 0; a < q; ++a) v[a] = (double)(float)v[a];
+}
+
+/* entries of v[0..q) below 4e-16 of the largest set to 0 when asked (see precision_model) */
+static void floor_rel(double *v, int q, int on)
+{
+    if (!on) return;
+    double mx = 0;
+    for (int a = 0; a < q; ++a) mx = v[a] > mx ? v[a] : mx;
+    for (int a = 0; a < q; ++a) if (v[a] < mx * 4.0e-16) v[a] = 0.0;
 }
 
 /* r-message of edge e from the current q-messages of its siblings */
@@ -377,26 +400,40 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
         for (int a = 0; a < q; ++a)
             pj[(size_t)j * q + a] = L[(size_t)j * q + a] * ((markov && j < K) ? Pk[(size_t)j * q + a] : 1.0);
         guards += normalise(pj + (size_t)j * q, q);
+        round32(pj + (size_t)j * q, q, B->precision_model >= 1);
     }
     for (int e = 0; e < E; ++e) memcpy(qm + (size_t)e * q, pj + (size_t)C->col[e] * q, sizeof(double) * (size_t)q);
 
     int first_ok = 0, last_ok = 0;
     for (int t = 1; t <= B->max_iter; ++t) {
+        const int r32 = B->precision_model >= 1, floor_r = B->precision_model == 2;
         if (B->schedule == 0) {
-            for (int e = 0; e < E; ++e) update_r(F, C, G, z, qm, rm, e, sq, sh);
+            for (int e = 0; e < E; ++e) {
+                update_r(F, C, G, z, qm, rm, e, sq, sh);
+                floor_rel(rm + (size_t)e * q, q, floor_r);
+                round32(rm + (size_t)e * q, q, r32);
+            }
             for (int j = 0; j < n; ++j)
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
                     guards += update_q(q, G, j, G->col_edge[s], pj, rm, qm);
+                    round32(qm + (size_t)G->col_edge[s] * q, q, r32);
+                }
         } else {
             for (int j = 0; j < n; ++j) {
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
                     update_r(F, C, G, z, qm, rm, G->col_edge[s], sq, sh);
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
+                    floor_rel(rm + (size_t)G->col_edge[s] * q, q, floor_r);
+                    round32(rm + (size_t)G->col_edge[s] * q, q, r32);
+                }
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
                     guards += update_q(q, G, j, G->col_edge[s], pj, rm, qm);
+                    round32(qm + (size_t)G->col_edge[s] * q, q, r32);
+                }
             }
         }
         for (int j = 0; j < n; ++j) {
             guards += posterior(q, G, j, pj, rm, Q);
+            round32(Q + (size_t)j * q, q, r32);
             x[j] = (uint8_t)clip(Q + (size_t)j * q, q);
         }
         if (R->xhat_trace) memcpy(R->xhat_trace + ((size_t)f * B->max_iter + (t - 1)) * n, x, (size_t)n);
@@ -414,6 +451,7 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
             for (int k = 0; k < K; ++k) {
                 for (int a = 0; a < q; ++a) pj[(size_t)k * q + a] = L[(size_t)k * q + a] * Pk[(size_t)k * q + a];
                 guards += normalise(pj + (size_t)k * q, q);
+                round32(pj + (size_t)k * q, q, B->precision_model >= 1);
             }
         }
     }

@@ -489,3 +489,24 @@ def test_sequential_schedule_needs_fewer_iterations():
     both = (pus["converged"] == 1) & (sus["converged"] == 1)
     assert both.sum() > 30
     assert sus["iters"][both].mean() < 0.85 * pus["iters"][both].mean()
+
+
+def test_precision_instrument_is_off_by_default_and_models_what_it_says():
+    """The reference's precision model (a test instrument for classifying
+    GPU/reference differences) leaves the default decoder untouched; model 1
+    keeps every stored vector in float32, model 2 also zeroes r entries below
+    4e-16 of each r-vector's largest."""
+    code, enc = wl.regular_code(96, 3, 6, 8, seed=41)
+    fr = wl.make_frames(code, enc, 6, 42, "bsc", 0.12)
+    base = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3)
+    m0 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=0)
+    for k in ("snap_q", "snap_r", "snap_Q", "xhat"):
+        assert np.array_equal(base[k], m0[k])
+    m1 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=1)
+    for k in ("snap_q", "snap_r", "snap_Q"):
+        assert np.array_equal(m1[k], m1[k].astype(np.float32).astype(np.float64))  # float32 values
+        assert np.abs(m1[k] - base[k]).max() < 1e-5
+    m2 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=2)
+    r = m2["snap_r"]
+    mx = r.max(axis=2, keepdims=True)
+    assert ((r == 0) | (r >= mx * 4e-16 * (1 - 1e-7))).all()
