@@ -262,7 +262,7 @@ def frames_to_device(frames, device="cuda"):
         "erasure": dev(frames.erasure, torch.uint8),
         "y": dev(frames.y, torch.float32),
         "syndrome": dev(frames.syndrome, torch.uint8),
-        "likelihood": None,
+        "likelihood": dev(getattr(frames, "lik", None), torch.float32),
     }
 
 

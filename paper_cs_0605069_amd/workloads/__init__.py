@@ -392,6 +392,7 @@ class Frames:
     erasure: np.ndarray | None = None  # uint8 [F][n]
     y: np.ndarray | None = None  # float32 [F][n][p]
     syndrome: np.ndarray | None = None  # uint8 [F][m] (None means z = 0)
+    lik: np.ndarray | None = None  # float32 [F][n][q] per-symbol likelihoods (channel "likelihood")
 
     @property
     def F(self) -> int:
@@ -400,7 +401,7 @@ class Frames:
     def subset(self, idx) -> "Frames":
         g = lambda a: None if a is None else np.ascontiguousarray(a[idx])
         return Frames(self.channel, self.param[idx].copy(), g(self.codeword), g(self.rx), g(self.erasure),
-                      g(self.y), g(self.syndrome))
+                      g(self.y), g(self.syndrome), g(self.lik))
 
 
 def make_frames(code: Code, enc: Encoder, F: int, seed: int, channel: str, param,
@@ -450,12 +451,14 @@ def gf_mul_table(p: int, poly: int | None = None) -> np.ndarray:
 def syndromes(code: Code, x: np.ndarray) -> np.ndarray:
     """z = H x for every row of x [F][n]."""
     T = gf_mul_table(code.p, code.poly)
-    prod = T[code.coef[None, :], x[:, code.col]]  # [F][E]
     z = np.zeros((x.shape[0], code.m), dtype=np.uint8)
-    rows = code.row_of_edge()
-    for i0 in range(0, code.E, 1 << 16):
-        sl = slice(i0, min(code.E, i0 + (1 << 16)))
-        np.bitwise_xor.at(z.T, rows[sl], prod[:, sl].T)
+    deg = np.diff(code.row_ptr)
+    rows = np.nonzero(deg > 0)[0]
+    if len(rows) == 0:
+        return z
+    for f0 in range(0, x.shape[0], 256):
+        prod = T[code.coef[None, :], x[f0:f0 + 256][:, code.col]]  # [F][E], edges grouped by row
+        z[f0:f0 + 256, rows] = np.bitwise_xor.reduceat(prod, code.row_ptr[rows], axis=1)
     return z
 
 
@@ -512,3 +515,135 @@ def mixed_pool(n_codes: int, seed: int, qs=(4, 16, 64), n_range=(256, 8000), q_w
         c.meta.update(rate=R, d_v=dv)
         out.append(c)
     return out
+
+
+# --------------------------------------------------------------------------
+# MacKay-Neal syndrome form (Section 2): H = [A | B], x = (source, noise)
+# --------------------------------------------------------------------------
+def mn_code(N: int, M: int, q: int, seed: int, d_a: int = 3, extra: float = 0.5) -> Code:
+    """H = [A | B] over GF(q): A (M x N) with column weight d_a (rows balanced,
+    no repeated edge, no 4-cycle inside A), B (M x M) lower triangular with a
+    nonzero diagonal, hence invertible: row i holds columns i and i-1 and,
+    with probability `extra`, one random earlier column that has no such
+    extra entry yet (so a column of B has at most 3 entries).  Columns
+    0..N-1 of H are the source symbols (n_info = N), columns N..N+M-1 the
+    noise symbols.  Nonzero coefficients are uniform on GF(q) minus {0}.
+    This is a stand-in for the paper's Kanter-Saad construction, which it
+    does not specify."""
+    A = make_code(N, M, d_a, q, seed)
+    rng = np.random.default_rng([seed, 0xB])
+    br, bc = [], []
+    avail = []  # columns < i-1 without an extra entry
+    for i in range(M):
+        if i >= 2:
+            avail.append(i - 2)
+        br.append(i)
+        bc.append(N + i)
+        if i >= 1:
+            br.append(i)
+            bc.append(N + i - 1)
+        if avail and rng.random() < extra:
+            k = int(rng.integers(0, len(avail)))
+            avail[k], avail[-1] = avail[-1], avail[k]
+            br.append(i)
+            bc.append(N + avail.pop())
+    r = np.concatenate([A.row_of_edge(), np.array(br, dtype=np.int64)])
+    c = np.concatenate([A.col.astype(np.int64), np.array(bc, dtype=np.int64)])
+    h = np.concatenate([A.coef, rng.integers(1, q, size=len(br)).astype(np.uint8)])
+    order = np.lexsort((c, r))
+    row_ptr = np.zeros(M + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(np.bincount(r, minlength=M))
+    return Code(q=q, n=N + M, m=M, row_ptr=row_ptr, col=c[order].astype(np.int32), coef=h[order], n_info=N,
+                seed=seed, meta={"mn": True, "N": N, "M": M, "d_a": d_a, "extra": extra})
+
+
+def mn_encode(code: Code, s: np.ndarray) -> np.ndarray:
+    """t = B^-1 A s for sources s [F][N] (Eq. (1)), by forward substitution
+    (B is lower triangular with a nonzero diagonal)."""
+    N, M, q = code.meta["N"], code.meta["M"], code.q
+    T = gf_mul_table(code.p, code.poly)
+    inv = np.zeros(q, dtype=np.uint8)
+    for a in range(1, q):
+        inv[a] = int(np.nonzero(T[a] == 1)[0][0])
+    F = s.shape[0]
+    t = np.zeros((F, M), dtype=np.uint8)
+    for i in range(M):
+        acc = np.zeros(F, dtype=np.uint8)
+        diag = 0
+        for e in range(code.row_ptr[i], code.row_ptr[i + 1]):
+            j, h = int(code.col[e]), int(code.coef[e])
+            if j < N:
+                acc ^= T[h, s[:, j]]
+            elif j - N < i:
+                acc ^= T[h, t[:, j - N]]
+            else:
+                diag = h
+        t[:, i] = T[inv[diag], acc]
+    return t
+
+
+def lift_binary_chain(M2: np.ndarray, p: int) -> tuple[np.ndarray, np.ndarray]:
+    """Symbol-level chain (q x q transition matrix, start distribution) of a
+    2-state chain over bits grouped into p-bit symbols, bit b of a symbol
+    being the b-th bit sent: P(b | a) = M2[a_{p-1}, b_0] prod_k M2[b_{k-1}, b_k]."""
+    q = 1 << p
+    pi2 = stationary(M2)
+    Mq = np.zeros((q, q))
+    start = np.zeros(q)
+    for b in range(q):
+        inner = 1.0
+        for k in range(1, p):
+            inner *= M2[(b >> (k - 1)) & 1, (b >> k) & 1]
+        start[b] = pi2[b & 1] * inner
+        for a in range(q):
+            Mq[a, b] = M2[(a >> (p - 1)) & 1, b & 1] * inner
+    return Mq, start
+
+
+def make_mn_frames(code: Code, F: int, seed: int, channel: str, param, source: str = "iid",
+                   markov: np.ndarray | None = None, start: np.ndarray | None = None) -> Frames:
+    """Frames of the MN syndrome form: sources s [F][N] (i.i.d. uniform or a
+    Markov chain with transition matrix `markov` from `start`), t = B^-1 A s
+    sent over the channel, r the received word (hard decisions for BI-AWGN,
+    erased bits set to 0 for the BEC), z = B r = A s + B n (Eq. (2)) with
+    n = r - t.  The decoder sees z and per-symbol likelihoods: uniform for the
+    source columns (their prior is the source model) and, for noise column
+    j, the probability of each noise symbol given the channel output (for the
+    BSC the paper's f^L (1-f)^(p-L)).  `codeword` holds the true x = (s, n)."""
+    N, M, q, p = code.meta["N"], code.meta["M"], code.q, code.p
+    if source == "iid":
+        s = iid_source(F, N, q, seed)
+    else:
+        s = markov_source(F, N, markov, stationary(markov) if start is None else start, seed)
+    t = mn_encode(code, s)
+    prm = np.broadcast_to(np.asarray(param, dtype=np.float64), (F,)).copy()
+    a_bits = ((np.arange(q)[:, None] >> np.arange(p)[None, :]) & 1).astype(np.float64)  # [q][p]
+    if channel == "bsc":
+        r = bsc(t, p, prm, seed)
+        f = prm[:, None, None, None]
+        pbit = np.where(a_bits[None, None] == 1, f, 1.0 - f)  # [F][1][q][p]
+        lik = np.broadcast_to(pbit.prod(axis=3), (F, M, q))
+    elif channel == "bec":
+        r, er = bec(t, p, prm, seed)
+        erb = symbol_bits(er, p).astype(bool)[:, :, None, :]  # [F][M][1][p]
+        pbit = np.where(erb, 0.5, np.where(a_bits[None, None] == 1, 0.0, 1.0))
+        lik = pbit.prod(axis=3)
+    elif channel == "biawgn":
+        y = biawgn(t, p, prm, seed).astype(np.float64)
+        r = pack_bits(y < 0)
+        sg = prm[:, None, None]
+        p0 = 1.0 / (1.0 + np.exp(-2.0 * np.abs(y) / sg ** 2))  # [F][M][p]: noise bit 0
+        pbit = np.where(a_bits[None, None] == 1, (1.0 - p0)[:, :, None, :], p0[:, :, None, :])
+        lik = pbit.prod(axis=3)
+    else:
+        raise ValueError(channel)
+    r = r.astype(np.uint8)
+    n = (r ^ t).astype(np.uint8)
+    x = np.concatenate([s, n], axis=1)
+    L = np.empty((F, N + M, q), dtype=np.float32)
+    L[:, :N] = 1.0 / q
+    L[:, N:] = lik / lik.sum(axis=2, keepdims=True)
+    z = syndromes(code, np.concatenate([np.zeros_like(s), r], axis=1))
+    fr = Frames("likelihood", prm, x, lik=L)
+    fr.syndrome = z
+    return fr

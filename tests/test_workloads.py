@@ -1,0 +1,103 @@
+"""The seeded input generators (CPU): codes, encoders, syndrome-form frames,
+the mixed pool and the MacKay-Neal (MN) syndrome form of Section 2."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0605069_amd import workloads as wl
+
+
+def _dense(code):
+    H = np.zeros((code.m, code.n), dtype=np.int64)
+    H[code.row_of_edge(), code.col] = code.coef
+    return H
+
+
+def test_regular_code_shape_and_no_four_cycles():
+    code = wl.make_code(120, 60, 3, 8, seed=1)
+    assert (code.col_degrees() == 3).all() and set(code.row_degrees().tolist()) == {6}
+    B = (_dense(code) != 0).astype(np.int64)
+    overlap = B @ B.T
+    np.fill_diagonal(overlap, 0)
+    assert overlap.max() <= 1  # two rows share at most one column
+
+
+def test_systematic_codewords_satisfy_h():
+    code, enc = wl.regular_code(96, 3, 6, 16, seed=2)
+    fr = wl.make_frames(code, enc, 20, 3, "bsc", 0.0)
+    assert (wl.syndromes(code, fr.codeword) == 0).all()
+
+
+def test_coset_frames_carry_their_syndrome():
+    code, _ = wl.regular_code(96, 3, 6, 4, seed=4)
+    fr = wl.make_coset_frames(code, 10, 5, "bec", 0.3)
+    assert np.array_equal(wl.syndromes(code, fr.codeword), fr.syndrome)
+
+
+def test_mixed_pool_shapes():
+    pool = wl.mixed_pool(12, seed=6, n_range=(256, 1000), q_weights=[0.35, 0.35, 0.3])
+    for c in pool:
+        assert c.q in (4, 16, 64) and 256 <= c.n <= 1000
+        assert set(np.unique(c.col_degrees()).tolist()) <= {2, 3}
+        assert c.meta["rate"] in (1 / 3, 1 / 2) and c.m == round((1 - c.meta["rate"]) * c.n)
+
+
+@pytest.mark.parametrize("q", [2, 4, 8])
+def test_mn_code_is_a_then_invertible_b(q):
+    N, M = 30, 90
+    code = wl.mn_code(N, M, q, seed=7)
+    H = _dense(code)
+    A, B = H[:, :N], H[:, N:]
+    assert code.n_info == N and (np.count_nonzero(A, axis=0) == 3).all()
+    assert (np.triu(B, 1) == 0).all() and (np.diag(B) != 0).all()  # lower triangular, nonzero diagonal
+    s = wl.iid_source(5, N, q, seed=8)
+    t = wl.mn_encode(code, s)
+    # B t = A s, i.e. H (s, t) = 0 ... checked through the syndrome map
+    assert (wl.syndromes(code, np.concatenate([s, t], axis=1)) == 0).all()
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.1), ("bec", 0.3), ("biawgn", 0.8)])
+def test_mn_frames_syndrome_and_noise_likelihoods(channel, param):
+    q, p = 8, 3
+    code = wl.mn_code(20, 60, q, seed=9)
+    fr = wl.make_mn_frames(code, 6, 10, channel, param)
+    N = 20
+    assert np.array_equal(wl.syndromes(code, fr.codeword), fr.syndrome)  # z = H (s, n)
+    assert np.allclose(fr.lik[:, :N], 1.0 / q) and np.allclose(fr.lik.sum(axis=2), 1.0, atol=1e-6)
+    noise = fr.codeword[:, N:]
+    # the true noise symbol is never excluded by its likelihood
+    assert (np.take_along_axis(fr.lik[:, N:], noise[:, :, None], axis=2) > 0).all()
+    if channel == "bsc":  # the paper's noise prior f^L (1-f)^(p-L), L = ones in a
+        L = np.array([bin(a).count("1") for a in range(q)])
+        assert np.allclose(fr.lik[0, N], param ** L * (1 - param) ** (p - L), rtol=1e-6)
+
+
+def test_lifted_binary_chain():
+    Mq, start = wl.lift_binary_chain(wl.PAPER_MARKOV_2S, 3)
+    assert np.allclose(Mq.sum(axis=1), 1.0) and np.isclose(start.sum(), 1.0)
+    assert np.allclose(start @ Mq, start)  # the start distribution is stationary
+    # symbols of a long 2-state bit chain, grouped 3 bits at a time (bit b sent b-th)
+    rng = np.random.default_rng(11)
+    T = 3 * 60000
+    bits = np.zeros(T, dtype=np.int64)
+    u = rng.random(T)
+    for k in range(1, T):
+        bits[k] = bits[k - 1] ^ int(u[k] < wl.PAPER_MARKOV_2S[bits[k - 1], 1 - bits[k - 1]])
+    sym = bits[0::3] | (bits[1::3] << 1) | (bits[2::3] << 2)
+    emp = np.zeros((8, 8))
+    np.add.at(emp, (sym[:-1], sym[1:]), 1.0)
+    nrow = emp.sum(axis=1, keepdims=True)
+    emp /= nrow
+    tol = 5.0 * np.sqrt(Mq * (1 - Mq) / nrow) + 1e-3  # five binomial standard deviations
+    assert (np.abs(emp - Mq) <= tol).all()
+
+
+def test_mn_frames_decode_at_low_noise():
+    q = 4
+    code = wl.mn_code(40, 120, q, seed=12)
+    M = wl.PAPER_MARKOV_4S
+    fr = wl.make_mn_frames(code, 8, 13, "bsc", 0.02, source="markov", markov=M)
+    for sch in (oracle.PUS, oracle.SUS):
+        out = oracle.decode(code, None, schedule=sch, max_iter=50, prior="markov", markov_M=M,
+                            markov_pi=wl.stationary(M), likelihoods=fr.lik, syndrome=fr.syndrome)
+        assert out["converged"].all() and (out["xhat"] == fr.codeword).all()
