@@ -122,6 +122,7 @@ typedef struct {
     const float *markov_M;   /* [q][q] M[a][b] = P(next = b | current = a) (MARKOV)   */
     const float *markov_pi;  /* [q] distribution of the first source symbol (MARKOV)  */
     int32_t options;         /* bit set of GFBP_OPT_*                                 */
+    const uint8_t *truth;    /* [F][n] true symbols, for gfbp_result.trace, or NULL   */
 } gfbp_batch;
 
 /* SUS runs, by default, in dependency levels: two columns that share no check
@@ -141,7 +142,8 @@ typedef struct {
  * priors and counters) into the slots of finished frames so that the running
  * frames form whole tiles again; each frame's arithmetic, and so every output,
  * is unchanged (results are written per frame when it finishes).  Not done
- * when posteriors or snapshots are requested.  This option turns it off. */
+ * when posteriors, snapshots or a trace are requested.  This option turns it
+ * off. */
 #define GFBP_OPT_NO_COMPACT 2
 
 /* Outputs, device memory owned by the caller. */
@@ -155,6 +157,11 @@ typedef struct {
     float *snap_q;           /* [F][E][q] q-messages (probability domain), or NULL   */
     float *snap_r;           /* [F][E][q] r-messages, or NULL                         */
     float *snap_Q;           /* [F][n][q] pseudo-posteriors, or NULL                  */
+    int32_t *trace;          /* [F][max_iter] or NULL (needs batch->truth): after each
+                                iteration t the frame ran, entry t-1 counts the bits of
+                                its source symbols (columns 0..n_info-1; all columns when
+                                n_info = 0) whose decision equals the truth; entries after
+                                its last iteration are 0 (the Fig. 1 diagnostic)        */
 } gfbp_result;
 
 /* Bytes of device workspace gfbp_decode_batch needs for F frames. */
@@ -165,8 +172,8 @@ size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t sche
  * aligned, owned by the caller, clobbered.  stream: a hipStream_t (NULL =
  * default stream).  All work is enqueued on the stream; the call returns after
  * the frames have finished (it reads the number of frames still iterating
- * back to the host every `poll` iterations to stop early).  Results are then
- * complete in the output buffers. */
+ * back to the host after every iteration to stop early and to size the next
+ * launches).  Results are then complete in the output buffers. */
 gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 

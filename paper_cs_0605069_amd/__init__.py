@@ -53,13 +53,15 @@ class Batch(ctypes.Structure):
                 ("early_stop", ctypes.c_int32), ("channel", ctypes.c_int32), ("param", ctypes.c_void_p),
                 ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p), ("prior", ctypes.c_int32),
-                ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("options", ctypes.c_int32)]
+                ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("options", ctypes.c_int32),
+                ("truth", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("xhat", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("converged", ctypes.c_void_p),
                 ("posterior", ctypes.c_void_p), ("guards", ctypes.c_void_p), ("snap_iter", ctypes.c_int32),
-                ("snap_q", ctypes.c_void_p), ("snap_r", ctypes.c_void_p), ("snap_Q", ctypes.c_void_p)]
+                ("snap_q", ctypes.c_void_p), ("snap_r", ctypes.c_void_p), ("snap_Q", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p)]
 
 
 class KernelStats(ctypes.Structure):
@@ -269,13 +271,15 @@ def frames_to_device(frames, device="cuda"):
 def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
-                 sus_strict: bool = False, tune_iters: int = 0, compact: bool = True) -> dict:
+                 sus_strict: bool = False, tune_iters: int = 0, compact: bool = True, truth=None) -> dict:
     """``gfbp_decode_batch`` on device tensors; returns device tensors.
 
     dframes: dict from :func:`frames_to_device` (or with the same keys).
     workspace: optional preallocated uint8 device tensor of at least
     ``dcode.workspace_size(F, schedule, prior)`` bytes, 256-byte aligned.
     outputs: optional preallocated output tensors (xhat, iters, converged).
+    truth: optional device uint8 [F][n] true symbols; then out["trace"] [F][max_iter]
+    counts the correct source bits after each iteration (the Fig. 1 diagnostic).
     """
     import torch
 
@@ -292,6 +296,8 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
         out.setdefault("posterior", torch.empty((F, n, q), dtype=torch.float32, device=dev))
     if guards:
         out.setdefault("guards", torch.empty((F,), dtype=torch.int32, device=dev))
+    if truth is not None:
+        out.setdefault("trace", torch.empty((F, int(max_iter)), dtype=torch.int32, device=dev))
     if snap_iter:
         out["snap_q"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
         out["snap_r"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
@@ -306,10 +312,10 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     b = Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes["channel"]], _dptr(dframes.get("param")),
               _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")), _dptr(dframes.get("y")),
               _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")), pk, _dptr(Mt), _dptr(pt),
-              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT))
+              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT), _dptr(truth))
     r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), _dptr(out.get("posterior")),
                _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
-               _dptr(out.get("snap_Q")))
+               _dptr(out.get("snap_Q")), _dptr(out.get("trace")))
     st = torch.cuda.current_stream() if stream is None else stream
     if tune_iters:
         chosen = ctypes.c_int32(0)

@@ -243,6 +243,25 @@ __global__ void k_retire(DevState s, BatchAux a, int t, int max_iter, int early_
     s.unsat[f] = 0;
 }
 
+// Fig. 1 diagnostic: correct bits of the first K symbols of running frame f
+// after iteration t, added to trace[f][t-1] (slot = frame: frames do not move
+// when a trace is asked for).  Threads over frames, blockIdx.y over chunks of
+// 128 columns.
+__global__ void k_trace(DevState s, const uint8_t *truth, int n, int K, int p, int t, int max_iter,
+                        int32_t *trace) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j0 = int(blockIdx.y) * 128, j1 = min(K, j0 + 128);
+    if (f >= s.F || !s.active[f]) return;
+    int c = 0;
+    for (int j = j0; j < j1; ++j) c += p - __popc(unsigned(s.xh[size_t(j) * s.Fp + f] ^ truth[size_t(f) * n + j]));
+    if (c) atomicAdd(&trace[size_t(f) * max_iter + (t - 1)], c);
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t count, int32_t v) {
+    const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = v;
+}
+
 // Decisions of finished frames to their rows of out: the frames in slots
 // list[0..k) (before those slots are reused), or with list null every slot
 // r < k still flagged pending.
@@ -459,11 +478,16 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
     // moving frames keeps running frames in whole tiles; posteriors and
     // snapshots are read by slot at the end, so they keep frames in place
+    const bool tracing = out->trace && b->truth;
     const bool compact = !(b->options & GFBP_OPT_NO_COMPACT) && !out->posterior && out->snap_iter <= 0 &&
-                         F > K::TF;
+                         !tracing && F > K::TF;
     const int Kp = markov ? c.n_info : 0;  // Markov-weighted likelihoods move with the frame
     Tracer tr(st);
     launch(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, a);
+    if (tracing) {
+        const size_t cnt = size_t(F) * b->max_iter;
+        launch(k_fill_i32, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st, out->trace, cnt, 0);
+    }
     if (b->syndrome) HIP_TRY(hipMemcpyAsync(a.z, b->syndrome, size_t(F) * c.m, hipMemcpyDeviceToDevice, st));
     const int ntiles = s.Fp / K::TF;
     K::tiles(st, s.active, F, s.Fp, s.tiles, s.count + 1);
@@ -505,6 +529,11 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             }
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
+        if (tracing) {
+            const int Kt = c.n_info > 0 ? c.n_info : c.n;
+            launch(k_trace, dim3(fb, unsigned((Kt + 127) / 128)), dim3(kBlock), 0, st, s, b->truth, c.n, Kt, P, t,
+                   b->max_iter, out->trace);
+        }
         tr.begin();
         launch(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
         tr.end(K_SYNDROME, Fa * bpf.syndrome, 0);
@@ -1197,6 +1226,7 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     to.posterior = nullptr;
     to.snap_iter = 0;
     to.snap_q = to.snap_r = to.snap_Q = nullptr;
+    to.trace = nullptr;
     double best_t = 1e300;
     int best = 0;
     for (int l = 1; l <= max_lel(c); ++l) {

@@ -423,6 +423,40 @@ def test_mn_syndrome_form(gfbp, q, source, channel, param, schedule):
     assert np.array_equal(wl.syndromes(code, g["xhat"][ok]), fr.syndrome[ok])
 
 
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_trace_of_correct_source_bits(gfbp, schedule):
+    """The per-iteration count of correct source bits (Fig. 1 diagnostic)
+    equals the count from the reference's decisions after each iteration
+    (frames whose decisions match the reference's at every iteration: a
+    near-tie at some iteration may flip a bit there and be corrected later;
+    the test needs such frames to be rare and their final counts equal)."""
+    import torch
+
+    q, p = 4, 2
+    code = wl.mn_code(60, 180, q, seed=420)
+    M, start = _MN_SOURCES["4s"]
+    fr = wl.make_mn_frames(code, 120, 421, "biawgn", 1.2, source="markov", markov=M, start=start)
+    kw = dict(prior="markov", markov_M=M, markov_pi=start)
+    dcode = gfbp.DeviceCode(code)
+    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, max_iter=60,
+                            truth=torch.from_numpy(fr.codeword).cuda(), **kw)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    r = oracle.decode(code, likelihoods=fr.lik.astype(np.float64), syndrome=fr.syndrome,
+                      schedule=gfbp_sched(schedule), max_iter=60, trace=True, **kw)
+    K = code.n_info
+    same = (g["xhat"] == r["xhat"]).all(axis=1) & (g["iters"] == r["iters"]) & (r["converged"] == 1)
+    assert same.mean() > 0.9
+    exact = 0
+    for f in np.nonzero(same)[0]:
+        t = int(r["iters"][f])
+        wrong = np.unpackbits((r["trace"][f, :t, :K] ^ fr.codeword[f, None, :K])[..., None], axis=-1).sum(axis=(1, 2))
+        exact += int(np.array_equal(g["trace"][f, :t], p * K - wrong))
+        assert g["trace"][f, t - 1] == p * K - wrong[-1], f"frame {f}"  # the final decision is the same
+        assert (g["trace"][f, t:] == 0).all()
+    assert exact >= 0.95 * same.sum(), f"{exact} of {int(same.sum())} traces identical"
+
+
 # --------------------------------------------------------------- SUS by dependency levels
 def _sus_levels(code):
     rows = code.row_of_edge()
