@@ -75,6 +75,44 @@ def cpu_baseline(code, points, n_frames: int):
             "frames_per_s": 2 * fr.F / dt, "mean_iters": iters}
 
 
+def gf64_leg(gfbp, torch, steps: int) -> dict:
+    """GF(64) (3,6) rate-1/2 N=2000, BI-AWGN at 1.6 dB, 2048 frames, max 100
+    iterations, autotuned: per schedule edge-q/s and the roofline of its
+    dominant kernel (not part of `value`)."""
+    from paper_cs_0605069_amd import workloads as wl
+
+    code, enc = wl.systematic(wl.make_code(2000, 1000, 3, 64, seed=0xC0DE0040))
+    fr = wl.make_frames(code, enc, 2048, 0xDA7A0040, "biawgn", wl.sigma_from_ebn0(1.6, code.n_info / code.n))
+    dcode = gfbp.DeviceCode(code)
+    d = gfbp.frames_to_device(fr)
+    res = {"workload": "GF(64) regular (3,6) rate-1/2 LDPC, N=2000 symbols, BI-AWGN 1.6 dB, 2048 frames, "
+                       "max 100 iterations", "edges": code.E, "q": 64}
+    for s in ("pus", "sus"):
+        res[f"{s}_entries_per_lane"] = gfbp.tune(dcode, d, schedule=s, trial_iters=3)
+        gfbp.decode_batch(dcode, d, schedule=s, max_iter=100)
+        torch.cuda.synchronize()
+        gfbp.profile_reset()
+        gfbp.profile_enable(True)
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(steps):
+            o = gfbp.decode_batch(dcode, d, schedule=s, max_iter=100)
+            its.append(o["iters"].cpu().numpy())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gfbp.profile_enable(False)
+        prof = gfbp.profile_read()
+        it = np.concatenate(its)
+        res[f"{s}_edge_q_per_s"] = float(it.sum()) * code.E * code.q / wall
+        res[f"{s}_mean_iters"] = float(it.mean())
+        ks = {k: v for k, v in prof.items() if k in ("check", "variable", "sus_level")}
+        dom = max(ks, key=lambda k: ks[k]["total_ms"])
+        ach = ks[dom]["algo_bytes"] / (ks[dom]["total_ms"] / 1e3)
+        res[f"{s}_roofline"] = {"kernel": dom, "achieved_GBps": ach / 1e9, "frac": ach / HBM_PEAK,
+                                "avg_launch_ms": ks[dom]["total_ms"] / ks[dom]["launches"]}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +125,7 @@ def main():
     ap.add_argument("--shapes", default="", help="fix entries per lane instead of autotuning, e.g. pus=8,sus=4")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--no-gf64", action="store_true", help="skip the GF(64) leg")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_gf16_n2000_bi-awgn.txt"),
                     help="measured HBM traffic summary to report beside the roofline")
     args = ap.parse_args()
@@ -196,6 +235,7 @@ def main():
                    "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0}
                for k, v in prof.items()}
 
+    gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, points, args.cpu_frames)
@@ -223,6 +263,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "gf64": gf64,
     }
     print(json.dumps(line), flush=True)
 
