@@ -86,7 +86,8 @@ struct Tracer {
     struct Rec {
         int kind;
         hipEvent_t a, b;
-        double bytes, edgeq;
+        double bytes, edgeq;  // absolute, or per running frame when iter > 0
+        int iter;
     };
     bool on;
     hipStream_t st;
@@ -128,21 +129,29 @@ struct Tracer {
             g_launch_ev[0] = g_launch_ev[1] = nullptr;
             return;
         }
-        recs.push_back(Rec{kind, last_[0], last_[1], bytes, edgeq});
+        recs.push_back(Rec{kind, last_[0], last_[1], bytes, edgeq, 0});
+    }
+    // as end(), with bytes and updates per running frame of iteration `iter`
+    // (multiplied at flush by the number of frames that iteration ran)
+    void end_iter(int kind, double bytes_per_frame, double edgeq_per_frame, int iter) {
+        end(kind, bytes_per_frame, edgeq_per_frame);
+        if (on && !recs.empty() && recs.back().a == last_[0]) recs.back().iter = iter;
     }
     static thread_local hipEvent_t last_[2];
-    // call after the stream has been synchronised
-    void flush() {
+    // call after the stream has been synchronised; running[t] = frames that
+    // iteration t ran
+    void flush(const std::vector<double> &running = {}) {
         if (!on) return;
         std::lock_guard<std::mutex> g(g_prof_mu);
         for (auto &r : recs) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                const double mult = r.iter > 0 && size_t(r.iter) < running.size() ? running[size_t(r.iter)] : 1.0;
                 Totals &t = g_prof[r.kind];
                 t.launches++;
                 t.ms += ms;
-                t.bytes += r.bytes;
-                t.edgeq += r.edgeq;
+                t.bytes += r.bytes * mult;
+                t.edgeq += r.edgeq * mult;
             }
             pool.push_back(r.a);
             pool.push_back(r.b);
@@ -274,11 +283,12 @@ __global__ void k_emit(DevState s, BatchAux a, const int32_t *list, int k, int n
     out[size_t(a.orig[f]) * n + j] = s.xh[size_t(j) * s.Fp + f];
 }
 
-// Compaction plan with R frames running: the finished slots below R (holes)
+// Compaction plan with R = *running frames running: the finished slots below R (holes)
 // and the running slots at or above R (movers), both in increasing order;
 // there are as many of each, written to *count.  One workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_plan_moves(const uint8_t *active, int F, int R, int32_t *holes,
-                                                     int32_t *movers, uint32_t *count) {
+__global__ __launch_bounds__(1024) void k_plan_moves(const uint8_t *active, int F, const uint32_t *running,
+                                                     int32_t *holes, int32_t *movers, uint32_t *count) {
+    const int R = int(*running);
     __shared__ uint32_t hs[1024 / kWave], ms[1024 / kWave];
     __shared__ uint32_t hb, mb;
     const int lane = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
@@ -465,6 +475,26 @@ struct TiledLaunch {
     }
 };
 
+// Per-thread pinned host slots for the iteration counts (4 iterations x 2,
+// plus one for compaction) and their events; allocated once, kept for the
+// life of the thread.
+uint32_t *pinned_counts() {
+    static thread_local uint32_t *p = nullptr;
+    if (!p) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, 16 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) return nullptr;
+        p = static_cast<uint32_t *>(q);
+    }
+    return p;
+}
+
+hipEvent_t *count_events() {
+    static thread_local hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (auto &x : e)
+        if (!x && hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
 template <int P, class K>
 gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
                       hipStream_t st, int needQ) {
@@ -500,32 +530,52 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     K::init(st, c, s, b);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
     HIP_TRY(hipGetLastError());
-    uint32_t running = uint32_t(F);
+    // The host stays one iteration ahead of the device: iteration t+1 is
+    // launched with a grid bound taken from the counts of iteration t-1 (tile
+    // lists only shrink, so that bound covers the list the kernels read on the
+    // device), while the counts of iteration t come back asynchronously.
+    std::vector<double> ran(size_t(b->max_iter) + 2, 0.0);  // frames iteration t ran
+    ran[1] = F;
+    uint32_t *pin = pinned_counts();
+    if (!pin) return fail(GFBP_ENOMEM, "pinned host memory for the iteration counts");
+    hipEvent_t *ev = count_events();
+    if (!ev) return fail(GFBP_EHIP, "events for the iteration counts");
+    int last_read = 0;  // the latest iteration whose counts the host has read
+    uint32_t known_running = uint32_t(F), known_tiles = uint32_t(s.nb);
+    auto read_counts = [&](int t) -> gfbp_status {  // counts after iteration t
+        HIP_TRY(hipEventSynchronize(ev[t & 3]));
+        known_running = pin[2 * (t & 3)];
+        known_tiles = pin[2 * (t & 3) + 1];
+        ran[size_t(t) + 1 < ran.size() ? size_t(t) + 1 : ran.size() - 1] = known_running;
+        last_read = t;
+        return GFBP_OK;
+    };
+    int t_end = 0;
     for (int t = 1; t <= b->max_iter; ++t) {
+        t_end = t;
         const bool snap_now = (t == out->snap_iter);
         Snap sn{snap_now ? out->snap_q : nullptr, snap_now ? out->snap_r : nullptr};
         const int wantQ = needQ || (snap_now && out->snap_Q);
-        const double Fa = running;
         if (b->schedule == GFBP_PUS) {
             tr.begin();
             K::check(st, c, s, z, sn);
-            tr.end(K_CHECK, Fa * bpf.check, Fa * eq_frame);
+            tr.end_iter(K_CHECK, bpf.check, eq_frame, t);
             tr.begin();
             K::variable(st, c, s, markov, wantQ, sn);
-            tr.end(K_VARIABLE, Fa * bpf.variable, Fa * eq_frame);
+            tr.end_iter(K_VARIABLE, bpf.variable, eq_frame, t);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
             tr.begin();
             K::sequential(st, c, s, z, markov, wantQ, sn);
-            tr.end(K_SEQUENTIAL, Fa * bpf.sequential, Fa * eq_frame);
+            tr.end_iter(K_SEQUENTIAL, bpf.sequential, eq_frame, t);
         } else {
             const int nlev = int(code->level_ptr.size()) - 1;
             for (int l = 0; l < nlev; ++l) {
                 const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
                 tr.begin();
                 K::sus_level(st, c, s, z, markov, wantQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
-                tr.end(K_SUS_LEVEL,
-                       Fa * (4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1)),
-                       Fa * code->level_edges[l] * Q);
+                tr.end_iter(K_SUS_LEVEL,
+                            4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1),
+                            code->level_edges[l] * Q, t);
             }
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
@@ -536,52 +586,64 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         }
         tr.begin();
         launch(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
-        tr.end(K_SYNDROME, Fa * bpf.syndrome, 0);
+        tr.end_iter(K_SYNDROME, bpf.syndrome, 0, t);
         tr.begin();
         launch(k_retire, dim3(fb), dim3(kBlock), 0, st, s, a, t, b->max_iter, b->early_stop,
-                           out->iters, out->converged, out->guards);
-        tr.end(K_RETIRE, Fa * 8.0, 0);
+               out->iters, out->converged, out->guards);
+        tr.end_iter(K_RETIRE, 8.0, 0, t);
         HIP_TRY(hipGetLastError());
         if (t == b->max_iter) break;
-        K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, s.count + 2 * (t & 1) + 1);
-        uint32_t cnt[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(cnt, s.count + 2 * (t & 1), sizeof cnt, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const uint32_t left = cnt[0];
-        running = left;
-        if (left == 0) break;
+        uint32_t *cnt_dev = s.count + 2 * (t & 1);  // [running after t, tiles listed]
+        K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, cnt_dev + 1);
+        HIP_TRY(hipMemcpyAsync(pin + 2 * (t & 3), cnt_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipEventRecord(ev[t & 3], st));
+        if (t >= 2) {
+            const gfbp_status rs = read_counts(t - 1);
+            if (rs != GFBP_OK) return rs;
+            if (known_running == 0) break;  // every frame finished by iteration t-1
+        }
         s.act = s.tiles + size_t(t & 1) * ntiles;
-        s.nact = s.count + 2 * (t & 1) + 1;
-        s.nb = int(cnt[1]);
+        s.nact = cnt_dev + 1;
+        s.nb = int(known_tiles);  // counts of iteration t-1 (or the first list): a bound on the list of t
         if (markov) {
             tr.begin();
             K::markov(st, c, s, b->markov_M, b->markov_pi);
-            tr.end(K_MARKOV, double(left) * bpf.markov, 0);
+            tr.end_iter(K_MARKOV, bpf.markov, 0, t + 1);
         }
-        if (compact && uint64_t(left) * 4 < uint64_t(cnt[1]) * K::TF * 3) {
-            // running frames fill less than 3/4 of their tiles: move them into
-            // the finished slots below `left`, then list the (now whole) tiles
-            launch(k_plan_moves, dim3(1), dim3(1024), 0, st, s.active, F, int(left), a.holes, a.movers,
-                               s.count + 8);
-            uint32_t nm = 0;
-            HIP_TRY(hipMemcpyAsync(&nm, s.count + 8, sizeof nm, hipMemcpyDeviceToHost, st));
+        if (compact && t >= 2 && uint64_t(known_running) * 4 < uint64_t(known_tiles) * K::TF * 3) {
+            // running frames filled less than 3/4 of their tiles: move the
+            // frames still running after iteration t into the finished slots
+            // below their count, then list the (now whole) tiles
+            launch(k_plan_moves, dim3(1), dim3(1024), 0, st, s.active, F, cnt_dev, a.holes, a.movers, s.count + 8);
+            HIP_TRY(hipMemcpyAsync(pin + 8, s.count + 8, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(pin + 2 * (t & 3), cnt_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            const uint32_t nm = pin[8];
+            known_running = pin[2 * (t & 3)];
+            known_tiles = pin[2 * (t & 3) + 1];
+            ran[size_t(t) + 1] = known_running;
+            last_read = t;
+            if (known_running == 0) break;
             if (nm > 0) {
                 const size_t ne = size_t(nm) * c.n;
-                launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm),
-                                   c.n, out->xhat);
+                launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm), c.n,
+                       out->xhat);
                 const int W = Q >= 4 ? 4 : 2;
                 const size_t per = size_t(c.E + c.n + Kp) * Q;
                 const unsigned chunks = unsigned((per / W + 255) / 256);
                 tr.begin();
                 launch(k_move_frames, dim3(nm, chunks), dim3(256), 0, st, s, a, c.E, c.n, Kp, Q, W, c.m);
                 tr.end(K_COMPACT, double(nm) * (8.0 * per + 2.0 * c.m), 0);
-                K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, s.count + 2 * (t & 1) + 1);
-                s.nb = int((left + K::TF - 1) / K::TF);
+                K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, cnt_dev + 1);
+                known_tiles = (known_running + K::TF - 1) / K::TF;
+                s.nb = int(known_tiles);
                 HIP_TRY(hipGetLastError());
+            } else {
+                s.nb = int(known_tiles);
             }
         }
     }
+    (void)t_end;
     tr.begin();
     {
         const size_t ne = size_t(F) * c.n;
@@ -596,7 +658,11 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
-    tr.flush();
+    if (tr.on) {
+        // iterations whose counts were not read: the frames they ran
+        for (int t = last_read + 1; t < t_end; ++t) ran[size_t(t) + 1] = pin[2 * (t & 3)];
+    }
+    tr.flush(ran);
     return GFBP_OK;
 }
 
