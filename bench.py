@@ -76,16 +76,16 @@ def cpu_baseline(code, points, n_frames: int):
 
 
 def gf64_leg(gfbp, torch, steps: int) -> dict:
-    """GF(64) (3,6) rate-1/2 N=2000, BI-AWGN at 1.6 dB, 2048 frames, max 100
+    """GF(64) (3,6) rate-1/2 N=2000, BI-AWGN at 1.6 dB, 4096 frames, max 100
     iterations, autotuned: per schedule edge-q/s and the roofline of its
     dominant kernel (not part of `value`)."""
     from paper_cs_0605069_amd import workloads as wl
 
     code, enc = wl.systematic(wl.make_code(2000, 1000, 3, 64, seed=0xC0DE0040))
-    fr = wl.make_frames(code, enc, 2048, 0xDA7A0040, "biawgn", wl.sigma_from_ebn0(1.6, code.n_info / code.n))
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0040, "biawgn", wl.sigma_from_ebn0(1.6, code.n_info / code.n))
     dcode = gfbp.DeviceCode(code)
     d = gfbp.frames_to_device(fr)
-    res = {"workload": "GF(64) regular (3,6) rate-1/2 LDPC, N=2000 symbols, BI-AWGN 1.6 dB, 2048 frames, "
+    res = {"workload": "GF(64) regular (3,6) rate-1/2 LDPC, N=2000 symbols, BI-AWGN 1.6 dB, 4096 frames, "
                        "max 100 iterations", "edges": code.E, "q": 64}
     for s in ("pus", "sus"):
         res[f"{s}_entries_per_lane"] = gfbp.tune(dcode, d, schedule=s, trial_iters=3)

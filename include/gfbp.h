@@ -146,6 +146,15 @@ typedef struct {
  * off. */
 #define GFBP_OPT_NO_COMPACT 2
 
+/* Sessions: gfbp_session_step with an even number of iterations on a created
+ * (non-default) stream replays a HIP graph of those iterations, captured on
+ * first use and kept by the session for each (iterations, launch bound)
+ * pair, the launch bound being the smallest power of two of tiles covering
+ * the running frames.  The work and the results are those of the eager step;
+ * only the host's launch cost changes.  The graphs are freed with the
+ * session. */
+#define GFBP_OPT_STEP_GRAPHS 4
+
 /* Outputs, device memory owned by the caller. */
 typedef struct {
     uint8_t *xhat;           /* [F][n] decision after the frame's last iteration      */

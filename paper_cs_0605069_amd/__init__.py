@@ -25,6 +25,7 @@ CH_BSC, CH_BEC, CH_BIAWGN, CH_LIKELIHOOD = 0, 1, 2, 3
 PRIOR_UNIFORM, PRIOR_MARKOV = 0, 1
 OPT_SUS_STRICT = 1
 OPT_NO_COMPACT = 2
+OPT_STEP_GRAPHS = 4
 CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
@@ -350,14 +351,17 @@ class Session:
     """
 
     def __init__(self, dcode: DeviceCode, n_slots: int, schedule="pus", max_iter: int = 100,
-                 has_syndrome: bool = False, markov_M=None, markov_pi=None, sus_strict: bool = False):
+                 has_syndrome: bool = False, markov_M=None, markov_pi=None, sus_strict: bool = False,
+                 step_graphs: bool = False):
+        """step_graphs: replay a captured HIP graph for each even-iteration
+        :meth:`step` on a created stream (the same work; fewer host launches)."""
         self.dcode = dcode
         self._M = None if markov_M is None else np.ascontiguousarray(markov_M, dtype=np.float32)
         self._pi = None if markov_pi is None else np.ascontiguousarray(markov_pi, dtype=np.float32)
         self.desc = SessionDesc(int(n_slots), SCHEDULES[schedule], int(max_iter), int(bool(has_syndrome)),
                                 None if self._M is None else self._M.ctypes.data,
                                 None if self._pi is None else self._pi.ctypes.data,
-                                OPT_SUS_STRICT if sus_strict else 0)
+                                (OPT_SUS_STRICT if sus_strict else 0) | (OPT_STEP_GRAPHS if step_graphs else 0))
         h = ctypes.c_void_p()
         _check(lib().gfbp_session_create(dcode.handle, ctypes.byref(self.desc), ctypes.byref(h)), "gfbp_session_create")
         self.handle = h

@@ -731,7 +731,14 @@ struct gfbp_session {
     void *pin = nullptr;              // pinned host staging
     size_t pin_bytes = 0;
     gfbp_status (*init_fn)(gfbp_session *, int, hipStream_t) = nullptr;
-    gfbp_status (*step_fn)(gfbp_session *, int, hipStream_t, bool) = nullptr;
+    gfbp_status (*step_fn)(gfbp_session *, int, hipStream_t, int) = nullptr;
+    // GFBP_OPT_STEP_GRAPHS: captured steps by (iterations, launch bound, parity)
+    struct StepGraph {
+        int iters, nb, parity;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs;
 };
 
 namespace {
@@ -830,13 +837,13 @@ struct SessionRun {
         return GFBP_OK;
     }
     // `iters` iterations of every running slot, no host synchronisation.
-    // full: launch grids for every slot (for graph capture), not just for the
-    // slots running now.
-    static gfbp_status step(gfbp_session *ss, int iters, hipStream_t st, bool full) {
+    // nb: the launch bound in tiles (at least the tiles holding a running
+    // frame; every slot's tile for a graph that must outlive admissions).
+    static gfbp_status step(gfbp_session *ss, int iters, hipStream_t st, int nb) {
         const gfbp_code *code = ss->code;
         const DevCode &c = code->dev;
         DevState s = ss->dv.st;
-        s.nb = full ? ss->ntiles : std::min(ss->ntiles, ss->running);
+        s.nb = std::min(ss->ntiles, nb);
         if (s.nb == 0) return GFBP_OK;
         const Snap sn{nullptr, nullptr};
         const int needQ = ss->markov;
@@ -1430,6 +1437,10 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
 
 gfbp_status gfbp_session_destroy(gfbp_session *ss) {
     if (!ss) return GFBP_OK;
+    for (auto &g : ss->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
     hipError_t e1 = hipFree(ss->mem), e2 = hipHostFree(ss->pin);
     delete ss;
     if (e1 != hipSuccess || e2 != hipSuccess) return fail(GFBP_EHIP, "freeing the session");
@@ -1475,7 +1486,38 @@ gfbp_status gfbp_session_admit(gfbp_session *ss, int32_t n, const int64_t *ids, 
 gfbp_status gfbp_session_step(gfbp_session *ss, int32_t iters, void *stream) {
     if (!ss) return fail(GFBP_EINVAL, "null session");
     if (iters < 1) return fail(GFBP_EINVAL, "iters < 1");
-    return ss->step_fn(ss, iters, static_cast<hipStream_t>(stream), false);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int need = std::min(ss->ntiles, ss->running);  // tiles holding a running frame, at most
+    if (need == 0) return GFBP_OK;
+    if (!(ss->options & GFBP_OPT_STEP_GRAPHS) || iters % 2 || !st) return ss->step_fn(ss, iters, st, need);
+    int nb = 1;
+    while (nb < need) nb <<= 1;
+    nb = std::min(nb, ss->ntiles);
+    for (const auto &g : ss->graphs)
+        if (g.iters == iters && g.nb == nb && g.parity == ss->parity) {
+            HIP_TRY(hipGraphLaunch(g.exec, st));
+            return GFBP_OK;
+        }
+    // capture: an even number of iterations leaves the parity as it was
+    const int parity = ss->parity;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const gfbp_status rs = ss->step_fn(ss, iters, st, nb);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rs != GFBP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rs;
+    }
+    if (ec != hipSuccess) return fail(GFBP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(GFBP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    ss->graphs.push_back(gfbp_session::StepGraph{iters, nb, parity, graph, exec});
+    HIP_TRY(hipGraphLaunch(exec, st));
+    return GFBP_OK;
 }
 
 gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat, int32_t cap, int32_t *n_out,
@@ -1551,7 +1593,7 @@ gfbp_status gfbp_graph_capture(gfbp_session *const *sessions, int32_t n, int32_t
     hipError_t he = hipEventRecord(ev[n], st);
     for (int k = 0; k < n && rs == GFBP_OK && he == hipSuccess; ++k) {
         he = hipStreamWaitEvent(ws[k], ev[n], 0);
-        if (he == hipSuccess) rs = sessions[k]->step_fn(sessions[k], iters, ws[k], true);
+        if (he == hipSuccess) rs = sessions[k]->step_fn(sessions[k], iters, ws[k], sessions[k]->ntiles);
         if (rs == GFBP_OK && he == hipSuccess) he = hipEventRecord(ev[k], ws[k]);
         if (rs == GFBP_OK && he == hipSuccess) he = hipStreamWaitEvent(st, ev[k], 0);
     }

@@ -65,7 +65,7 @@ class Stats:
 class Server:
     def __init__(self, queues: list[CodeQueue], slots: int, schedule: str, max_iter: int, budget_bytes: int,
                  step_iters: int = 2, markov: dict | None = None, keep_results: bool = False, autotune: bool = True,
-                 graph: bool = False):
+                 graph: bool = False, step_graphs: bool = False):
         self.queues = queues
         self.slots = slots
         self.schedule = schedule
@@ -83,6 +83,11 @@ class Server:
         # end); its grids cover every slot, which costs more than it saves
         # while few frames are in flight
         self.use_graph = graph
+        # optionally each session replays its own captured step (one per
+        # power-of-two bound on the tiles in flight): half the host's launch
+        # cost of a SUS step, but no gain in latency, which the device's time
+        # per launch bounds
+        self.step_graphs = step_graphs
         self.graph = None
         self.gstream = None
 
@@ -124,7 +129,7 @@ class Server:
             self.refused += 1
             return False
         cq.session = Session(cq.dcode, self.slots, self.schedule, self.max_iter, has_syndrome=True,
-                             markov_M=M, markov_pi=pi)
+                             markov_M=M, markov_pi=pi, step_graphs=self.step_graphs)
         cq.stream = torch.cuda.Stream()
         cq.need = need
         self.used += need
@@ -276,6 +281,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--step-iters", type=int, default=2)
     ap.add_argument("--graph", action="store_true", help="step all sessions as one HIP graph")
+    ap.add_argument("--step-graphs", action="store_true", help="replay a captured graph per session step")
     args = ap.parse_args()
     import torch
 
@@ -286,7 +292,8 @@ def main():
             n = int(rate * args.seconds)
             queues, markov = make_requests(pool, n, rate, seed=0xDA7A0005, pool_max=args.pool)
             srv = Server(queues, args.slots, schedule, args.max_iter, int(args.budget_gb * 2 ** 30),
-                         step_iters=args.step_iters, markov=markov, graph=args.graph)
+                         step_iters=args.step_iters, markov=markov, graph=args.graph,
+                         step_graphs=args.step_graphs)
             st = srv.run(deadline=args.seconds + args.drain)
             lat = np.array(st.latency) * 1e3
             print(json.dumps({
@@ -297,7 +304,7 @@ def main():
                 "mean_iters": float(np.mean(st.iters)) if st.iters else None,
                 "fer": 1 - st.converged / max(1, st.done), "sessions_opened": srv.opened,
                 "codes": args.codes, "slots": args.slots, "step_iters": args.step_iters,
-                "graph": args.graph}), flush=True)
+                "graph": args.graph, "step_graphs": args.step_graphs}), flush=True)
             del queues, srv
             torch.cuda.empty_cache()
 

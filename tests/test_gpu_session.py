@@ -28,17 +28,17 @@ def _slice(d, lo, hi):
     return {k: (v[lo:hi] if hasattr(v, "shape") and v is not None else v) for k, v in d.items()}
 
 
-def _drain(sess, dfr, F, step_iters=3, max_rounds=10000):
+def _drain(sess, dfr, F, step_iters=3, max_rounds=10000, stream=None):
     """Offer frames in order as slots free up; step; collect.  Returns
     {id: (iters, converged, xhat)}."""
     done = {}
     nxt = 0
     for _ in range(max_rounds):
         if nxt < F:
-            k = sess.admit(np.arange(nxt, F), _slice(dfr, nxt, F))
+            k = sess.admit(np.arange(nxt, F), _slice(dfr, nxt, F), stream=stream)
             nxt += k
-        sess.step(step_iters)
-        ids, it, cv, xh = sess.poll()
+        sess.step(step_iters, stream=stream)
+        ids, it, cv, xh = sess.poll(stream=stream)
         for r in range(len(ids)):
             done[int(ids[r])] = (int(it[r]), int(cv[r]), xh[r].copy())
         if len(done) == F:
@@ -67,6 +67,34 @@ def test_session_equals_batch_with_staggered_admission(gfbp, schedule):
         it, cv, xh = got[f]
         assert it == ref["iters"][f] and cv == ref["converged"][f], f"frame {f}"
         assert np.array_equal(xh, ref["xhat"][f]), f"frame {f}"
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_session_step_graphs_equal_batch(gfbp, schedule):
+    """Replayed step graphs (one per launch bound, captured as the number of
+    frames in flight rises and falls) give the eager results."""
+    import torch
+
+    q = 16
+    code, enc = wl.regular_code(200, 3, 6, q, seed=61)
+    M = wl.self_transition_matrix(q, 0.8)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 700, 62, "bsc", 0.06, source="markov", markov=M)
+    dcode = gfbp.DeviceCode(code)
+    ref = _batch(gfbp, dcode, fr, schedule, 40, prior="markov", markov_M=M, markov_pi=pi)
+    dfr = gfbp.frames_for_session([fr])
+    dfr["markov"] = torch.ones(fr.F, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    sess = gfbp.Session(dcode, n_slots=256, schedule=schedule, max_iter=40, markov_M=M, markov_pi=pi,
+                        step_graphs=True)
+    with torch.cuda.stream(stream):
+        got = _drain(sess, dfr, fr.F, step_iters=2, stream=stream)
+    assert sess.running == 0
+    for f in range(fr.F):
+        it, cv, xh = got[f]
+        assert it == ref["iters"][f] and cv == ref["converged"][f] and np.array_equal(xh, ref["xhat"][f]), f"frame {f}"
+    sess.close()
 
 
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
