@@ -192,6 +192,7 @@ struct BatchAux {
     int32_t *holes;   // [Fp] compaction: finished slots below the running count
     int32_t *movers;  // [Fp] compaction: running slots at or above it
     uint8_t *pending; // [Fp] finished frame whose decision is not yet written out
+    float *mshape;    // [4] shape of the Markov matrix (k_markov_shape)
 };
 
 __global__ void k_state_init(DevState s, BatchAux a) {
@@ -457,16 +458,14 @@ struct TiledLaunch {
         launch((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
                            dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn);
     }
-    static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
+    static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi,
+                       const float *mshape) {
         launch((tiled::k_markov<P, LG>), dim3(tiled_blocks(c.n_info, s)), dim3(kBlock), 0, st, c, s,
-                           M, pi);
+                           M, pi, mshape);
     }
     static constexpr int TF = kWave >> LG;
     static void tiles(hipStream_t st, const uint8_t *mask, int F, int Fp, int32_t *out, uint32_t *count) {
         launch(tiled::k_tiles, dim3(1), dim3(1024), 0, st, mask, F, Fp, TF, out, count);
-    }
-    static void markov_any(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi) {
-        markov(st, c, s, M, pi);
     }
     static void vectors(hipStream_t st, const float *src, int n, const DevState &s, float *out) {
         const size_t tot = size_t(n) * s.F * (1 << P);
@@ -526,6 +525,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     s.act = s.tiles;
     s.nact = s.count + 1;
     s.nb = (F + K::TF - 1) / K::TF;
+    if (markov) hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, st, b->markov_M, Q, a.mshape);
     tr.begin();
     K::init(st, c, s, b);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
@@ -607,7 +607,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         s.nb = int(known_tiles);  // counts of iteration t-1 (or the first list): a bound on the list of t
         if (markov) {
             tr.begin();
-            K::markov(st, c, s, b->markov_M, b->markov_pi);
+            K::markov(st, c, s, b->markov_M, b->markov_pi, a.mshape);
             tr.end_iter(K_MARKOV, bpf.markov, 0, t + 1);
         }
         if (compact && t >= 2 && uint64_t(known_running) * 4 < uint64_t(known_tiles) * K::TF * 3) {
@@ -720,7 +720,7 @@ struct gfbp_session {
     void *mem = nullptr;
     size_t bytes = 0;
     SessDev dv{};
-    float *M = nullptr, *pi = nullptr;
+    float *M = nullptr, *pi = nullptr, *mshape = nullptr;
     int32_t *ftiles = nullptr;
     uint32_t *aux = nullptr;  // [0] fresh tiles, [1] finished slots, [2..3] running tiles by parity
     int parity = 0;
@@ -871,7 +871,7 @@ struct SessionRun {
             if (ss->markov) {
                 s.act = ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles;
                 s.nact = ss->aux + 2 + ss->parity;
-                K::markov(st, c, s, ss->M, ss->pi);
+                K::markov(st, c, s, ss->M, ss->pi, ss->mshape);
             }
         }
         HIP_TRY(hipGetLastError());
@@ -916,7 +916,7 @@ bool session_bind(gfbp_session *ss) {
 // Workspace carving, shared by size query and decode.
 struct Carve {
     size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, orig, iters, conv, z, holes, movers, pending,
-        total;
+        mshape, total;
 };
 
 Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
@@ -943,6 +943,7 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     c.holes = take(F * 4);
     c.movers = take(F * 4);
     c.pending = take(F);
+    c.mshape = take(16);
     c.total = off;
     return c;
 }
@@ -950,7 +951,7 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
 // Device memory of a session, carved from one allocation.
 struct SessCarve {
     size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards;
-    size_t rx, er, y, param, z, chan, mark, iters, conv, fresh, done, xout, pairs, list, res, ftiles, aux, M, pi;
+    size_t rx, er, y, param, z, chan, mark, iters, conv, fresh, done, xout, pairs, list, res, ftiles, aux, M, pi, mshape;
     size_t total;
 };
 
@@ -990,6 +991,7 @@ SessCarve session_carve(const gfbp_code *code, int S, int schedule, int markov, 
     c.aux = take(64);
     c.M = take(Q * Q * 4);
     c.pi = take(Q * 4);
+    c.mshape = take(16);
     c.total = off;
     return c;
 }
@@ -1258,6 +1260,7 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
     a.holes = reinterpret_cast<int32_t *>(w + cv.holes);
     a.movers = reinterpret_cast<int32_t *>(w + cv.movers);
     a.pending = reinterpret_cast<uint8_t *>(w + cv.pending);
+    a.mshape = reinterpret_cast<float *>(w + cv.mshape);
     s.F = F;
     s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
@@ -1418,10 +1421,16 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
     ss->aux = reinterpret_cast<uint32_t *>(w + cv.aux);
     ss->M = reinterpret_cast<float *>(w + cv.M);
     ss->pi = reinterpret_cast<float *>(w + cv.pi);
+    ss->mshape = reinterpret_cast<float *>(w + cv.mshape);
     if (ss->markov) {
         const int q = code->info.q;
-        if (hipMemcpy(ss->M, d->markov_M, sizeof(float) * q * q, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(ss->pi, d->markov_pi, sizeof(float) * q, hipMemcpyHostToDevice) != hipSuccess) {
+        bool ok = hipMemcpy(ss->M, d->markov_M, sizeof(float) * q * q, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(ss->pi, d->markov_pi, sizeof(float) * q, hipMemcpyHostToDevice) == hipSuccess;
+        if (ok) {
+            hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, nullptr, ss->M, q, ss->mshape);
+            ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+        }
+        if (!ok) {
             (void)hipFree(ss->mem);
             (void)hipHostFree(ss->pin);
             delete ss;

@@ -705,8 +705,16 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
 // A7 dynamical block prior (Eq. (7)) for source symbol k: from this
 // iteration's pseudo-posteriors of its chain neighbours, multiplied into the
 // channel likelihood for the next iteration.
+//
+// mshape (from k_markov_shape): when M = s I + o (J - I) (every diagonal entry
+// s, every other entry o, as for a source that keeps its symbol or moves to
+// any other one uniformly), the neighbour sums of Eq. (7) take O(q):
+// sum_a Q(a) M(a, b) = sum_c M(b, c) Q(c) = s Q(b) + o (S - Q(b)), S = sum Q,
+// and each lane needs only its own entries of the neighbours; any other M
+// takes the O(q^2) sums.
 template <int P, int LG>
-__global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi) {
+__global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi,
+                                                   const float *mshape) {
     using Gm = Geo<P, LG>;
     const Item it = item<P, LG>(c.n_info, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
@@ -719,9 +727,32 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
         u[q] = k == 0 ? double(pi[b]) : 0.0;
         v[q] = k == K - 1 ? 1.0 : 0.0;
     }
-    // the whole neighbour vectors (every lane of the frame reads all q entries)
     const size_t fo = size_t(it.f) * Gm::Q;
-    if (k > 0) {
+    if (mshape[0] != 0.0f) {
+        const double sd = mshape[1], od = mshape[2];
+        // the two neighbours' sums, in the same order for both (lanes_sum
+        // over the frame's lanes)
+        float nb[2][Gm::EL];
+        double S[2] = {0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kk = h == 0 ? k - 1 : k + 1;
+            if (kk >= 0 && kk < K) ld<Gm::EL>(chunk<P, LG>(s.Qp, size_t(kk), s.Fp, it), nb[h]);
+            else
+#pragma unroll
+                for (int q = 0; q < Gm::EL; ++q) nb[h][q] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) S[h] += double(nb[h][q]);
+            S[h] = lanes_sum<P, LG>(S[h]);
+        }
+        if (k > 0)
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) u[q] = sd * double(nb[0][q]) + od * (S[0] - double(nb[0][q]));
+        if (k < K - 1)
+#pragma unroll
+            for (int q = 0; q < Gm::EL; ++q) v[q] = sd * double(nb[1][q]) + od * (S[1] - double(nb[1][q]));
+    } else if (k > 0) {
+        // the whole neighbour vectors (every lane of the frame reads all q entries)
         const float *qp = s.Qp + size_t(k - 1) * s.Fp * Gm::Q + fo;
         for (int a = 0; a < Gm::Q; ++a) {
             const double qa = qp[a];
@@ -729,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
             for (int q = 0; q < Gm::EL; ++q) u[q] += qa * double(M[a * Gm::Q + it.g * Gm::EL + q]);
         }
     }
-    if (k < K - 1) {
+    if (mshape[0] == 0.0f && k < K - 1) {
         const float *qp = s.Qp + size_t(k + 1) * s.Fp * Gm::Q + fo;
         for (int cc = 0; cc < Gm::Q; ++cc) {
             const double qc = qp[cc];
@@ -749,6 +780,22 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) pf[q] = float(u[q]);
     st<Gm::EL>(chunk<P, LG>(s.Pr, size_t(k), s.Fp, it), pf);
+}
+
+// Shape of the Markov matrix for k_markov: out = {1, s, o} when every
+// diagonal entry of M (q x q) equals s and every other entry o, else {0, 0, 0}.
+// One wavefront.
+__global__ __launch_bounds__(kWave) void k_markov_shape(const float *M, int q, float *out) {
+    const float sd = M[0], od = q > 1 ? M[1] : 0.0f;
+    bool ok = true;
+    for (int t = int(threadIdx.x); t < q * q; t += kWave) ok &= M[t] == ((t / q == t % q) ? sd : od);
+    const bool all = __ballot(!ok) == 0;
+    if (threadIdx.x == 0) {
+        out[0] = all ? 1.0f : 0.0f;
+        out[1] = all ? sd : 0.0f;
+        out[2] = all ? od : 0.0f;
+        out[3] = 0.0f;
+    }
 }
 
 // Ordered list of the tiles (of TF frames) holding a frame whose mask byte is

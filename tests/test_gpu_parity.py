@@ -211,11 +211,16 @@ def test_other_channels(gfbp, channel, param, schedule):
         assert np.abs(g["snap_q"] - r["snap_q"]).max() <= MSG_TOL
 
 
+@pytest.mark.parametrize("q,kind", [(8, "self"), (8, "general"), (64, "self")])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_markov_prior(gfbp, schedule):
-    q = 8
+def test_markov_prior(gfbp, schedule, q, kind):
+    """Eq. (7) priors: a self-transition source (the device takes the O(q)
+    neighbour sums) and a general transition matrix (O(q^2) sums)."""
     code, enc = wl.regular_code(300, 3, 6, q, seed=11)
     M = wl.self_transition_matrix(q, 0.7)
+    if kind == "general":
+        D = np.random.default_rng(0x3A7).dirichlet(np.ones(q), size=q)
+        M = 0.5 * M + 0.5 * D
     pi = wl.stationary(M)
     fr = wl.make_frames(code, enc, 120, 12, "bsc", 0.1, source="markov", markov=M)
     kw = dict(prior="markov", markov_M=M, markov_pi=pi)
@@ -227,7 +232,7 @@ def test_markov_prior(gfbp, schedule):
             assert err <= MSG_TOL, f"{schedule} iter {it} {key}: {err:.3g}"
     g = _gpu(gfbp, code, fr, schedule, max_iter=100, **kw)
     r = _ref(code, fr, schedule, max_iter=100, **kw)
-    _compare_decisions(g, r, f"markov {schedule}",
+    _compare_decisions(g, r, f"markov {kind} q={q} {schedule}",
                        recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=100, **kw))
 
 

@@ -69,15 +69,19 @@ def test_session_equals_batch_with_staggered_admission(gfbp, schedule):
         assert np.array_equal(xh, ref["xhat"][f]), f"frame {f}"
 
 
+@pytest.mark.parametrize("kind", ["self", "general"])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_session_step_graphs_equal_batch(gfbp, schedule):
+def test_session_step_graphs_equal_batch(gfbp, schedule, kind):
     """Replayed step graphs (one per launch bound, captured as the number of
-    frames in flight rises and falls) give the eager results."""
+    frames in flight rises and falls) give the eager results; with a
+    self-transition and with a general Markov matrix."""
     import torch
 
     q = 16
     code, enc = wl.regular_code(200, 3, 6, q, seed=61)
     M = wl.self_transition_matrix(q, 0.8)
+    if kind == "general":
+        M = 0.5 * M + 0.5 * np.random.default_rng(0x3A8).dirichlet(np.ones(q), size=q)
     pi = wl.stationary(M)
     fr = wl.make_frames(code, enc, 700, 62, "bsc", 0.06, source="markov", markov=M)
     dcode = gfbp.DeviceCode(code)
