@@ -44,7 +44,7 @@ class _Batch(ctypes.Structure):
                 ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p), ("prior", ctypes.c_int),
                 ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("snap_iter", ctypes.c_int),
-                ("n_threads", ctypes.c_int), ("precision_model", ctypes.c_int)]
+                ("n_threads", ctypes.c_int), ("precision_model", ctypes.c_int), ("prior_in_sweep", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
@@ -135,10 +135,13 @@ def max_threads() -> int:
 def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_stop: bool = True,
            prior: str = "uniform", markov_M=None, markov_pi=None, snap_iter: int = 0, posterior: bool = False,
            trace: bool = False, n_threads: int = 0, likelihoods=None, syndrome=None,
-           precision_model: int = 0) -> dict:
+           precision_model: int = 0, prior_in_sweep: bool = False) -> dict:
     """Decode every frame of ``frames`` (a ``workloads.Frames``) on ``code``.
 
     ``likelihoods`` [F][n][q] replaces the channel when given.
+    ``prior_in_sweep`` (SUS with the Markov prior): each source symbol's
+    prior is assigned when its column is visited, from the newest
+    pseudo-posteriors of its neighbours, instead of after each iteration.
     ``precision_model`` is a test instrument (0, the default, is the plain
     double-precision decoder): 1 rounds every stored vector to float32; 2
     also drops each r-vector's entries below 4e-16 of its largest (the
@@ -189,7 +192,7 @@ def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_st
     c = _Code(code.p, code.poly, n, m, code.n_info, rp.ctypes.data, cl.ctypes.data, cf.ctypes.data)
     b = _Batch(F, schedule, max_iter, int(early_stop), ch, param.ctypes.data, _ptr(rx), _ptr(er), _ptr(y),
                _ptr(lk), _ptr(syn), 1 if prior == "markov" else 0, _ptr(Mk), _ptr(pk), snap_iter, n_threads,
-               int(precision_model))
+               int(precision_model), int(bool(prior_in_sweep)))
     r = _Result(out["xhat"].ctypes.data, out["iters"].ctypes.data, out["converged"].ctypes.data,
                 _ptr(out.get("posterior")), _ptr(out.get("snap_q")), _ptr(out.get("snap_r")),
                 _ptr(out.get("snap_Q")), _ptr(out.get("trace")), out["guards"].ctypes.data)

@@ -46,7 +46,12 @@
  *     the left and a vector of ones on the right; the prior is normalised and
  *     multiplied into the channel likelihood;
  *   - in SUS the pseudo-posterior is computed after the sweep from the
- *     r-messages of that sweep.
+ *     r-messages of that sweep;
+ *   - SUS variant with the prior assigned during the vertical pass (Section
+ *     2, priors paragraph): from iteration 2 on, source symbol j takes, when
+ *     its column is visited, the Eq. (7) prior from Q_{j-1} of the current
+ *     sweep and Q_{j+1} of the previous one (iteration 1 uses pi, as above),
+ *     and no refresh follows the iteration.
  */
 #include <math.h>
 #include <stdint.h>
@@ -186,24 +191,28 @@ static int normalise(double *v, int q)
     return 0;
 }
 
-/* Eq. (7) over a chain of K source symbols: P_k(b) is proportional to
+/* Eq. (7) for source symbol k of a chain of K: P_k(b) is proportional to
  * [sum_a Q_{k-1}(a) M(a,b)] [sum_c M(b,c) Q_{k+1}(c)], with pi in place of the
- * left factor at k = 0 and 1 in place of the right factor at k = K-1. */
+ * left factor at k = 0 and 1 in place of the right factor at k = K-1.  Q holds
+ * the pseudo-posteriors of the chain, [K][q]. */
+static int markov_prior_at(int q, int K, int k, const double *Q, const double *M, const double *pi, double *Pk)
+{
+    for (int b = 0; b < q; ++b) {
+        double u = 0.0, v = 0.0;
+        if (k == 0) u = pi[b];
+        else for (int a = 0; a < q; ++a) u += Q[(size_t)(k - 1) * q + a] * M[a * q + b];
+        if (k == K - 1) v = 1.0;
+        else for (int c = 0; c < q; ++c) v += M[b * q + c] * Q[(size_t)(k + 1) * q + c];
+        Pk[b] = u * v;
+    }
+    return normalise(Pk, q);
+}
+
+/* Eq. (7) for every source symbol, all from the same Q */
 int ref_markov_prior(int q, int K, const double *Q, const double *M, const double *pi, double *P)
 {
     int guards = 0;
-    for (int k = 0; k < K; ++k) {
-        double *Pk = P + (size_t)k * q;
-        for (int b = 0; b < q; ++b) {
-            double u = 0.0, v = 0.0;
-            if (k == 0) u = pi[b];
-            else for (int a = 0; a < q; ++a) u += Q[(size_t)(k - 1) * q + a] * M[a * q + b];
-            if (k == K - 1) v = 1.0;
-            else for (int c = 0; c < q; ++c) v += M[b * q + c] * Q[(size_t)(k + 1) * q + c];
-            Pk[b] = u * v;
-        }
-        guards += normalise(Pk, q);
-    }
+    for (int k = 0; k < K; ++k) guards += markov_prior_at(q, K, k, Q, M, pi, P + (size_t)k * q);
     return guards;
 }
 
@@ -242,6 +251,8 @@ typedef struct {
                                  entry set to 0 (the resolution of an Eq. (3) evaluated through a
                                  double-precision transform, whose small outputs are differences
                                  of order-one terms) */
+    int prior_in_sweep;       /* SUS with the Markov prior: 0, priors refreshed after each
+                                 iteration; 1, refreshed during the sweep (see decode_frame) */
 } ref_batch;
 
 typedef struct {
@@ -370,6 +381,7 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
 {
     const int q = F->q, p = F->p, n = C->n, E = C->row_ptr[C->m], K = C->n_info;
     const int markov = (B->prior == 1) && K > 0;
+    const int in_sweep = markov && B->schedule == 1 && B->prior_in_sweep;
     double *L = (double *)malloc(sizeof(double) * (size_t)n * q);
     double *pj = (double *)malloc(sizeof(double) * (size_t)n * q);
     double *Pk = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1) * q);
@@ -425,9 +437,26 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
                     floor_rel(rm + (size_t)G->col_edge[s] * q, q, floor_r);
                     round32(rm + (size_t)G->col_edge[s] * q, q, r32);
                 }
+                if (in_sweep && j < K && t >= 2) {
+                    /* the prior of source symbol j, assigned at its vertical
+                     * pass from the newest pseudo-posteriors of its chain
+                     * neighbours: Q_{j-1} of this sweep, Q_{j+1} of the last */
+                    double *Pj = Pk + (size_t)j * q;
+                    guards += markov_prior_at(q, K, j, Q, B->markov_M, B->markov_pi, Pj);
+                    for (int a = 0; a < q; ++a) pj[(size_t)j * q + a] = L[(size_t)j * q + a] * Pj[a];
+                    guards += normalise(pj + (size_t)j * q, q);
+                    round32(pj + (size_t)j * q, q, B->precision_model >= 1);
+                }
                 for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
                     guards += update_q(q, G, j, G->col_edge[s], pj, rm, qm);
                     round32(qm + (size_t)G->col_edge[s] * q, q, r32);
+                }
+                if (in_sweep && j < K) {
+                    /* Q_j now, for the next symbol's prior (the same value the
+                     * pass after the sweep computes: neither p_j nor the r of
+                     * column j change later in the sweep) */
+                    (void)posterior(q, G, j, pj, rm, Q);
+                    round32(Q + (size_t)j * q, q, r32);
                 }
             }
         }
@@ -446,7 +475,7 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
         if (last_ok && !first_ok) first_ok = t;
         if (last_ok && B->early_stop) break;
         if (t == B->max_iter) break;
-        if (markov) {
+        if (markov && !in_sweep) {
             guards += ref_markov_prior(q, K, Q, B->markov_M, B->markov_pi, Pk);
             for (int k = 0; k < K; ++k) {
                 for (int a = 0; a < q; ++a) pj[(size_t)k * q + a] = L[(size_t)k * q + a] * Pk[(size_t)k * q + a];

@@ -433,14 +433,16 @@ def _lik(code, fr):
     return out
 
 
-@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
-def test_markov_prior_with_memoryless_matrix_is_a_static_prior(c1_small, schedule):
+@pytest.mark.parametrize("schedule,in_sweep", [(oracle.PUS, False), (oracle.SUS, False), (oracle.SUS, True)])
+def test_markov_prior_with_memoryless_matrix_is_a_static_prior(c1_small, schedule, in_sweep):
+    """With identical rows (M(a, b) = pi(b)), Eq. (7) gives P_k = pi whatever
+    the posteriors, so either refresh timing is the static prior pi."""
     code, enc = c1_small
     q = code.q
     fr = wl.make_frames(code, enc, 4, 36, "bsc", 0.14)
     pi = np.array([0.4, 0.3, 0.2, 0.1])
     a = oracle.decode(code, fr, schedule=schedule, max_iter=20, prior="markov", markov_M=np.tile(pi, (q, 1)),
-                      markov_pi=pi, posterior=True, early_stop=False)
+                      markov_pi=pi, posterior=True, early_stop=False, prior_in_sweep=in_sweep)
     L = _lik(code, fr)
     L[:, :code.n_info] *= pi
     b = oracle.decode(code, likelihoods=L, schedule=schedule, max_iter=20, posterior=True, early_stop=False)
@@ -476,6 +478,77 @@ def test_markov_prior_refresh_timing_pus(c1_small):
             Q2[code.col[e]] *= r2[e]
         Q2 /= Q2.sum(1, keepdims=True)
         np.testing.assert_allclose(two["snap_Q"][f], Q2, atol=1e-12)
+
+
+def _tree_sus_by_hand(L, M, pi, iters, in_sweep):
+    """SUS on the binary tree 0 - A - 2 - B - 1 (checks x0 + x2 = 0 and
+    x1 + x2 = 0, source symbols 0 and 1), worked out by hand: a degree-2
+    binary check passes its other q-message through unchanged (r = q), a
+    column with one edge sends its prior, and Eq. (7) on a two-symbol chain
+    is P0 = norm(pi * (M Q1)), P1 = norm(Q0 M).  Returns per iteration the
+    q-messages [e0 (0,A), e1 (2,A), e2 (1,B), e3 (2,B)], the r-messages and
+    the posteriors Q0, Q1, Q2."""
+    nz = lambda v: v / v.sum()
+    P0, P1 = pi.copy(), pi.copy()
+    p0, p1, p2 = nz(L[0] * P0), nz(L[1] * P1), nz(L[2])
+    q0A, q1B, q2A, q2B = p0, p1, p2, p2
+    Q0 = Q1 = None
+    out = []
+    for t in range(1, iters + 1):
+        rA0 = q2A                                   # column 0
+        if in_sweep and t >= 2:
+            p0 = nz(L[0] * nz(pi * (M @ Q1)))       # Q1 of the previous sweep
+        q0A = p0
+        Q0 = nz(p0 * rA0)
+        rB1 = q2B                                   # column 1
+        if in_sweep and t >= 2:
+            p1 = nz(L[1] * nz(Q0 @ M))              # Q0 of this sweep
+        q1B = p1
+        Q1 = nz(p1 * rB1)
+        rA2, rB2 = q0A, q1B                         # column 2
+        q2A, q2B = nz(p2 * rB2), nz(p2 * rA2)
+        Q2 = nz(p2 * rA2 * rB2)
+        out.append((np.array([q0A, q2A, q1B, q2B]), np.array([rA0, rA2, rB1, rB2]), np.array([Q0, Q1, Q2])))
+        if not in_sweep:
+            p0, p1 = nz(L[0] * nz(pi * (M @ Q1))), nz(L[1] * nz(Q0 @ M))
+    return out
+
+
+@pytest.mark.parametrize("in_sweep", [False, True])
+def test_markov_prior_timing_worked_example(in_sweep):
+    """Both refresh timings of the Markov prior on a three-column tree,
+    against the messages worked out by hand; the two timings differ from
+    iteration 2 on (the second source symbol sees Q0 of the current sweep
+    rather than of the previous one)."""
+    code = _code(2, 3, [[0, 2], [1, 2]])
+    code.n_info = 2
+    L = np.array([[[0.7, 0.3], [0.35, 0.65], [0.55, 0.45]]])
+    M = np.array([[0.9, 0.1], [0.25, 0.75]])
+    pi = np.array([0.6, 0.4])
+    hand = _tree_sus_by_hand(L[0], M, pi, 3, in_sweep)
+    other = _tree_sus_by_hand(L[0], M, pi, 3, not in_sweep)
+    for t in (1, 2, 3):
+        o = oracle.decode(code, likelihoods=L, schedule=oracle.SUS, max_iter=t, early_stop=False, prior="markov",
+                          markov_M=M, markov_pi=pi, snap_iter=t, prior_in_sweep=in_sweep)
+        qh, rh, Qh = hand[t - 1]
+        np.testing.assert_allclose(o["snap_q"][0], qh, atol=1e-14)
+        np.testing.assert_allclose(o["snap_r"][0], rh, atol=1e-14)
+        np.testing.assert_allclose(o["snap_Q"][0], Qh, atol=1e-14)
+        if t >= 2:
+            assert np.abs(Qh - other[t - 1][2]).max() > 1e-3
+
+
+def test_in_sweep_prior_leaves_pus_and_uniform_priors_alone(c1_small):
+    """The in-sweep timing only concerns SUS with the Markov prior."""
+    code, enc = c1_small
+    M = wl.self_transition_matrix(code.q, 0.7)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 4, 39, "bsc", 0.12, source="markov", markov=M)
+    kw = dict(max_iter=15, early_stop=False, posterior=True)
+    for sch, prior in ((oracle.PUS, "markov"), (oracle.SUS, "uniform")):
+        a = oracle.decode(code, fr, schedule=sch, prior=prior, markov_M=M, markov_pi=pi, **kw)
+        b = oracle.decode(code, fr, schedule=sch, prior=prior, markov_M=M, markov_pi=pi, prior_in_sweep=True, **kw)
+        assert (a["xhat"] == b["xhat"]).all() and np.array_equal(a["posterior"], b["posterior"])
 
 
 # ------------------------------------------------------------------ schedules' headline behaviour
