@@ -92,6 +92,8 @@ typedef struct {
     int32_t max_row_degree, max_col_degree;
     int32_t poly;
     int32_t sus_levels;      /* dependency levels of one SUS sweep (see GFBP_OPT_SUS_STRICT) */
+    int32_t sus_levels_in_sweep; /* the same when source symbol k also waits for k-1
+                                    (GFBP_OPT_PRIOR_IN_SWEEP): at least n_info */
 } gfbp_code_info;
 
 /* Build the device-resident graph of a code on the current HIP device.
@@ -154,6 +156,17 @@ typedef struct {
  * only the host's launch cost changes.  The graphs are freed with the
  * session. */
 #define GFBP_OPT_STEP_GRAPHS 4
+
+/* Batch decode, SUS with the Markov prior: the prior of each source symbol is
+ * assigned during the sweep, at its column's vertical pass (Section 2, the
+ * paragraph on priors), instead of after each iteration.  From iteration 2 on,
+ * source symbol k takes the Eq. (7) prior from the pseudo-posterior of symbol
+ * k-1 computed earlier in the same sweep and that of symbol k+1 from the
+ * previous sweep; iteration 1 uses pi as usual.  Symbol k then depends on
+ * symbol k-1 within a sweep, so the sweep has at least n_info dependency
+ * levels (gfbp_code_info.sus_levels_in_sweep).  GFBP_EINVAL with PUS; no
+ * effect with the uniform prior; sessions return GFBP_EUNSUPPORTED. */
+#define GFBP_OPT_PRIOR_IN_SWEEP 8
 
 /* Outputs, device memory owned by the caller. */
 typedef struct {

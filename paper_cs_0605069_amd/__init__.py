@@ -26,6 +26,7 @@ PRIOR_UNIFORM, PRIOR_MARKOV = 0, 1
 OPT_SUS_STRICT = 1
 OPT_NO_COMPACT = 2
 OPT_STEP_GRAPHS = 4
+OPT_PRIOR_IN_SWEEP = 8
 CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
@@ -46,7 +47,8 @@ class CodeDesc(ctypes.Structure):
 class CodeInfo(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("p", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_info", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("max_row_degree", ctypes.c_int32),
-                ("max_col_degree", ctypes.c_int32), ("poly", ctypes.c_int32), ("sus_levels", ctypes.c_int32)]
+                ("max_col_degree", ctypes.c_int32), ("poly", ctypes.c_int32), ("sus_levels", ctypes.c_int32),
+                ("sus_levels_in_sweep", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -272,7 +274,8 @@ def frames_to_device(frames, device="cuda"):
 def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
-                 sus_strict: bool = False, tune_iters: int = 0, compact: bool = True, truth=None) -> dict:
+                 sus_strict: bool = False, tune_iters: int = 0, compact: bool = True, truth=None,
+                 prior_in_sweep: bool = False) -> dict:
     """``gfbp_decode_batch`` on device tensors; returns device tensors.
 
     dframes: dict from :func:`frames_to_device` (or with the same keys).
@@ -281,6 +284,8 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     outputs: optional preallocated output tensors (xhat, iters, converged).
     truth: optional device uint8 [F][n] true symbols; then out["trace"] [F][max_iter]
     counts the correct source bits after each iteration (the Fig. 1 diagnostic).
+    prior_in_sweep: SUS with the Markov prior assigns each source symbol's
+    prior at its column's vertical pass (``GFBP_OPT_PRIOR_IN_SWEEP``).
     """
     import torch
 
@@ -313,7 +318,8 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     b = Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes["channel"]], _dptr(dframes.get("param")),
               _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")), _dptr(dframes.get("y")),
               _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")), pk, _dptr(Mt), _dptr(pt),
-              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT), _dptr(truth))
+              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT) |
+              (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0), _dptr(truth))
     r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), _dptr(out.get("posterior")),
                _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
                _dptr(out.get("snap_Q")), _dptr(out.get("trace")))

@@ -47,12 +47,15 @@ struct gfbp_code {
     gfbp_code_info info;
     DevCode dev;
     double sum_dc2;       // sum over checks of d_c (d_c - 1): sibling vectors read by one SUS sweep
-    // SUS dependency levels: columns level_ptr[l]..level_ptr[l+1]-1 of level_cols
-    std::vector<int32_t> level_ptr;
-    std::vector<double> level_sibs;   // per level: sibling vectors read (sum over its edges of d_c - 1)
-    std::vector<double> level_edges;  // per level: edges
-    const int32_t *level_cols = nullptr;  // device [n]
-    const SusRec *sus_recs = nullptr;     // device [n][max column degree], columns in level order
+    // SUS dependency levels, [0]: from shared checks; [1]: also source
+    // symbol k after k-1 (priors assigned during the sweep)
+    struct Levels {
+        std::vector<int32_t> ptr;   // level l: the columns at positions ptr[l]..ptr[l+1]-1 of recs
+        std::vector<double> sibs;   // per level: sibling vectors read (sum over its edges of d_c - 1)
+        std::vector<double> edges;  // per level: edges
+        std::vector<double> src;    // per level: source columns
+        const SusRec *recs = nullptr;  // device [n][max column degree], columns in level order
+    } lv[2];
     int el[2] = {0, 0};   // entries per lane chosen for PUS / SUS (0 = default)
     void *mem = nullptr;  // one device allocation holding every array of dev
 };
@@ -330,12 +333,12 @@ __global__ __launch_bounds__(1024) void k_plan_moves(const uint8_t *active, int 
 // that carry over between iterations), W floats per thread over
 // blockIdx.y; block y = 0 also moves the per-slot scalars and the syndrome.
 // Holes and movers are disjoint, so the copies never overlap.
-__global__ __launch_bounds__(256) void k_move_frames(DevState s, BatchAux a, int E, int n, int K, int Q, int W,
-                                                     int m) {
+__global__ __launch_bounds__(256) void k_move_frames(DevState s, BatchAux a, int E, int n, int K, int Kq, int Q,
+                                                     int W, int m) {
     const int k = blockIdx.x;
     const int src = a.movers[k], dst = a.holes[k];
     const size_t o = (size_t(blockIdx.y) * blockDim.x + threadIdx.x) * W;
-    const size_t per = size_t(E + n + K) * Q;
+    const size_t per = size_t(E + n + K + Kq) * Q;
     if (o < per) {
         const size_t v = o / Q, e = o % Q;
         float *arr;
@@ -346,9 +349,12 @@ __global__ __launch_bounds__(256) void k_move_frames(DevState s, BatchAux a, int
         } else if (v < size_t(E + n)) {
             arr = s.L;
             node = v - E;
-        } else {
+        } else if (v < size_t(E + n + K)) {
             arr = s.Pr;
             node = v - E - n;
+        } else {
+            arr = s.Qp;
+            node = v - E - n - K;
         }
         const float *from = arr + (node * s.Fp + src) * Q + e;
         float *to = arr + (node * s.Fp + dst) * Q + e;
@@ -448,15 +454,16 @@ struct TiledLaunch {
                            s, markov, wantQ, sn);
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
-                          Snap sn, const SusRec *recs, int nc) {
+                          Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
         launch((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
-                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, recs,
-                           std::max(1, c.max_dv), nc);
+                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, sp,
+                           recs, std::max(1, c.max_dv), nc);
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
-                           int wantQ, Snap sn) {
+                           int wantQ, Snap sn, const SweepPrior &sp) {
         launch((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
-                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn);
+                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn,
+                           sp);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi,
                        const float *mshape) {
@@ -505,6 +512,8 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const double eq_frame = double(c.E) * Q;
     const uint8_t *z = b->syndrome ? a.z : nullptr;  // syndromes by slot
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
+    // SUS priors assigned during the sweep (from iteration 2)
+    const int insweep = markov && b->schedule == GFBP_SUS && (b->options & GFBP_OPT_PRIOR_IN_SWEEP);
     // moving frames keeps running frames in whole tiles; posteriors and
     // snapshots are read by slot at the end, so they keep frames in place
     const bool tracing = out->trace && b->truth;
@@ -564,18 +573,23 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             K::variable(st, c, s, markov, wantQ, sn);
             tr.end_iter(K_VARIABLE, bpf.variable, eq_frame, t);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
+            const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
             tr.begin();
-            K::sequential(st, c, s, z, markov, wantQ, sn);
-            tr.end_iter(K_SEQUENTIAL, bpf.sequential, eq_frame, t);
+            K::sequential(st, c, s, z, markov, wantQ, sn, sp);
+            tr.end_iter(K_SEQUENTIAL, bpf.sequential + (sp.on ? 8.0 * Q * c.n_info : 0.0), eq_frame, t);
         } else {
-            const int nlev = int(code->level_ptr.size()) - 1;
+            const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
+            const gfbp_code::Levels &lv = code->lv[insweep ? 1 : 0];
+            const int nlev = int(lv.ptr.size()) - 1;
             for (int l = 0; l < nlev; ++l) {
-                const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
+                const int c0 = lv.ptr[l], nc = lv.ptr[l + 1] - c0;
                 tr.begin();
-                K::sus_level(st, c, s, z, markov, wantQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
+                K::sus_level(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(c0) * std::max(1, c.max_dv), nc);
+                // an assigned prior reads two neighbours' Q and L in place of Pr
                 tr.end_iter(K_SUS_LEVEL,
-                            4.0 * Q * (code->level_sibs[l] + code->level_edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1),
-                            code->level_edges[l] * Q, t);
+                            4.0 * Q * (lv.sibs[l] + lv.edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1) +
+                                (sp.on ? 8.0 * Q * lv.src[l] : 0.0),
+                            lv.edges[l] * Q, t);
             }
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
@@ -605,7 +619,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         s.act = s.tiles + size_t(t & 1) * ntiles;
         s.nact = cnt_dev + 1;
         s.nb = int(known_tiles);  // counts of iteration t-1 (or the first list): a bound on the list of t
-        if (markov) {
+        if (markov && !insweep) {
             tr.begin();
             K::markov(st, c, s, b->markov_M, b->markov_pi, a.mshape);
             tr.end_iter(K_MARKOV, bpf.markov, 0, t + 1);
@@ -629,10 +643,11 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                 launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm), c.n,
                        out->xhat);
                 const int W = Q >= 4 ? 4 : 2;
-                const size_t per = size_t(c.E + c.n + Kp) * Q;
+                const int Kq = insweep ? c.n_info : 0;  // the next sweep's priors read these Q
+                const size_t per = size_t(c.E + c.n + Kp + Kq) * Q;
                 const unsigned chunks = unsigned((per / W + 255) / 256);
                 tr.begin();
-                launch(k_move_frames, dim3(nm, chunks), dim3(256), 0, st, s, a, c.E, c.n, Kp, Q, W, c.m);
+                launch(k_move_frames, dim3(nm, chunks), dim3(256), 0, st, s, a, c.E, c.n, Kp, Kq, Q, W, c.m);
                 tr.end(K_COMPACT, double(nm) * (8.0 * per + 2.0 * c.m), 0);
                 K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, cnt_dev + 1);
                 known_tiles = (known_running + K::TF - 1) / K::TF;
@@ -846,6 +861,7 @@ struct SessionRun {
         s.nb = std::min(ss->ntiles, nb);
         if (s.nb == 0) return GFBP_OK;
         const Snap sn{nullptr, nullptr};
+        const SweepPrior sp{ss->M, ss->pi, ss->mshape, 0};  // sessions refresh priors after each iteration
         const int needQ = ss->markov;
         const uint8_t *z = ss->has_z ? ss->dv.z : nullptr;
         const unsigned fb = unsigned((s.F + kBlock - 1) / kBlock);
@@ -856,12 +872,13 @@ struct SessionRun {
                 K::check(st, c, s, z, sn);
                 K::variable(st, c, s, ss->markov, needQ, sn);
             } else if (ss->options & GFBP_OPT_SUS_STRICT) {
-                K::sequential(st, c, s, z, ss->markov, needQ, sn);
+                K::sequential(st, c, s, z, ss->markov, needQ, sn, sp);
             } else {
-                const int nlev = int(code->level_ptr.size()) - 1;
+                const gfbp_code::Levels &lv = code->lv[0];
+                const int nlev = int(lv.ptr.size()) - 1;
                 for (int l = 0; l < nlev; ++l) {
-                    const int c0 = code->level_ptr[l], nc = code->level_ptr[l + 1] - c0;
-                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, code->sus_recs + size_t(c0) * std::max(1, c.max_dv), nc);
+                    const int c0 = lv.ptr[l], nc = lv.ptr[l + 1] - c0;
+                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, sp, lv.recs + size_t(c0) * std::max(1, c.max_dv), nc);
                 }
             }
             hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
@@ -1077,33 +1094,6 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
             const int j = d->col[e];
             col_edge[col_ptr[j] + fill[j]++] = e;
         }
-    // SUS dependency levels: level(j) = 1 + the highest level among earlier
-    // columns sharing a check with j (0 if none).
-    std::vector<int32_t> level(n, 0), row_top(m, -1);
-    int nlev = 0;
-    for (int j = 0; j < n; ++j) {
-        int lv = 0;
-        for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) lv = std::max(lv, row_top[edge_row[col_edge[t]]] + 1);
-        for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) row_top[edge_row[col_edge[t]]] = lv;
-        level[j] = lv;
-        nlev = std::max(nlev, lv + 1);
-    }
-    std::vector<int32_t> level_ptr(nlev + 1, 0), level_cols(n);
-    std::vector<double> level_sibs(nlev, 0.0), level_edges(nlev, 0.0);
-    for (int j = 0; j < n; ++j) level_ptr[level[j] + 1]++;
-    for (int l = 0; l < nlev; ++l) level_ptr[l + 1] += level_ptr[l];
-    {
-        std::vector<int32_t> fillp(level_ptr.begin(), level_ptr.end() - 1);
-        for (int j = 0; j < n; ++j) {
-            const int l = level[j];
-            level_cols[fillp[l]++] = j;
-            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) {
-                const int i = edge_row[col_edge[t]];
-                level_sibs[l] += d->row_ptr[i + 1] - d->row_ptr[i] - 1;
-                level_edges[l] += 1;
-            }
-        }
-    }
     // per-edge images of the basis x^b under multiplication by h^-1 and h
     std::vector<uint64_t> emap(2 * size_t(E));
     for (int e = 0; e < E; ++e) {
@@ -1117,26 +1107,62 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
         emap[2 * size_t(e) + 1] = wm;
     }
 
-    // sequential-schedule records, columns in level order, RS slots each
+    // SUS dependency levels: level(j) = 1 + the highest level among earlier
+    // columns sharing a check with j (0 if none); with chain = 1 source
+    // column k also comes after source column k-1.  Then the sequential-
+    // schedule records, columns in level order, RS slots each.
     const int RS = std::max(1, max_dv);
-    std::vector<SusRec> recs(size_t(n) * RS);
-    for (int p = 0; p < n; ++p) {
-        const int j = level_cols[p], dv = col_ptr[j + 1] - col_ptr[j];
-        for (int t = 0; t < RS; ++t) {
-            SusRec r{};
-            r.j = j;
-            r.dv = dv;
-            if (t < dv) {
-                const int e = col_edge[col_ptr[j] + t], i = edge_row[e];
-                r.e = e;
-                r.i = i;
-                r.rs = d->row_ptr[i];
-                r.dc = d->row_ptr[i + 1] - d->row_ptr[i];
-                r.self = e - r.rs;
-                r.hinv = emap[2 * size_t(e)];
-                r.h = emap[2 * size_t(e) + 1];
+    gfbp_code::Levels lvs[2];
+    std::vector<SusRec> recs[2];
+    for (int chain = 0; chain < 2; ++chain) {
+        std::vector<int32_t> level(n, 0), row_top(m, -1);
+        int nlev = 0;
+        for (int j = 0; j < n; ++j) {
+            int lv = 0;
+            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) lv = std::max(lv, row_top[edge_row[col_edge[t]]] + 1);
+            if (chain && j > 0 && j < d->n_info) lv = std::max(lv, level[j - 1] + 1);
+            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) row_top[edge_row[col_edge[t]]] = lv;
+            level[j] = lv;
+            nlev = std::max(nlev, lv + 1);
+        }
+        gfbp_code::Levels &L = lvs[chain];
+        L.ptr.assign(nlev + 1, 0);
+        L.sibs.assign(nlev, 0.0);
+        L.edges.assign(nlev, 0.0);
+        L.src.assign(nlev, 0.0);
+        std::vector<int32_t> cols(n);
+        for (int j = 0; j < n; ++j) L.ptr[level[j] + 1]++;
+        for (int l = 0; l < nlev; ++l) L.ptr[l + 1] += L.ptr[l];
+        std::vector<int32_t> fillp(L.ptr.begin(), L.ptr.end() - 1);
+        for (int j = 0; j < n; ++j) {
+            const int l = level[j];
+            cols[fillp[l]++] = j;
+            L.src[l] += j < d->n_info ? 1.0 : 0.0;
+            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) {
+                const int i = edge_row[col_edge[t]];
+                L.sibs[l] += d->row_ptr[i + 1] - d->row_ptr[i] - 1;
+                L.edges[l] += 1;
             }
-            recs[size_t(p) * RS + t] = r;
+        }
+        recs[chain].resize(size_t(n) * RS);
+        for (int p = 0; p < n; ++p) {
+            const int j = cols[p], dv = col_ptr[j + 1] - col_ptr[j];
+            for (int t = 0; t < RS; ++t) {
+                SusRec r{};
+                r.j = j;
+                r.dv = dv;
+                if (t < dv) {
+                    const int e = col_edge[col_ptr[j] + t], i = edge_row[e];
+                    r.e = e;
+                    r.i = i;
+                    r.rs = d->row_ptr[i];
+                    r.dc = d->row_ptr[i + 1] - d->row_ptr[i];
+                    r.self = e - r.rs;
+                    r.hinv = emap[2 * size_t(e)];
+                    r.h = emap[2 * size_t(e) + 1];
+                }
+                recs[chain][size_t(p) * RS + t] = r;
+            }
         }
     }
 
@@ -1146,8 +1172,8 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes ? bytes : 1); return o; };
     const size_t o_rp = take(4 * size_t(m + 1)), o_col = take(4 * size_t(E)), o_coef = take(size_t(E)),
                  o_cp = take(4 * size_t(n + 1)), o_ce = take(4 * size_t(E)), o_er = take(4 * size_t(E)),
-                 o_mul = take(size_t(q) * q), o_em = take(16 * size_t(E)), o_lc = take(4 * size_t(n)),
-                 o_sr = take(sizeof(SusRec) * recs.size());
+                 o_mul = take(size_t(q) * q), o_em = take(16 * size_t(E)),
+                 o_sr0 = take(sizeof(SusRec) * recs[0].size()), o_sr1 = take(sizeof(SusRec) * recs[1].size());
     if (hipMalloc(&c->mem, off) != hipSuccess) {
         delete c;
         return fail(GFBP_ENOMEM, "device allocation for the code");
@@ -1165,20 +1191,20 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (err == hipSuccess) err = up(o_er, edge_row.data(), 4 * size_t(E));
     if (err == hipSuccess) err = up(o_mul, mul.data(), mul.size());
     if (err == hipSuccess) err = up(o_em, emap.data(), 16 * size_t(E));
-    if (err == hipSuccess) err = up(o_lc, level_cols.data(), 4 * size_t(n));
-    if (err == hipSuccess) err = up(o_sr, recs.data(), sizeof(SusRec) * recs.size());
+    if (err == hipSuccess) err = up(o_sr0, recs[0].data(), sizeof(SusRec) * recs[0].size());
+    if (err == hipSuccess) err = up(o_sr1, recs[1].data(), sizeof(SusRec) * recs[1].size());
     if (err != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
         return fail(GFBP_EHIP, std::string("copying the code to the device: ") + hipGetErrorString(err));
     }
-    c->info = gfbp_code_info{q, p, n, m, d->n_info, E, max_dc, max_dv, int32_t(poly), nlev};
+    c->info = gfbp_code_info{q, p, n, m, d->n_info, E, max_dc, max_dv, int32_t(poly),
+                             int32_t(lvs[0].ptr.size()) - 1, int32_t(lvs[1].ptr.size()) - 1};
     c->sum_dc2 = sum_dc2;
-    c->level_ptr = std::move(level_ptr);
-    c->level_sibs = std::move(level_sibs);
-    c->level_edges = std::move(level_edges);
-    c->level_cols = reinterpret_cast<const int32_t *>(base + o_lc);
-    c->sus_recs = reinterpret_cast<const SusRec *>(base + o_sr);
+    c->lv[0] = std::move(lvs[0]);
+    c->lv[1] = std::move(lvs[1]);
+    c->lv[0].recs = reinterpret_cast<const SusRec *>(base + o_sr0);
+    c->lv[1].recs = reinterpret_cast<const SusRec *>(base + o_sr1);
     c->dev = DevCode{n, m, E, q, p, d->n_info, max_dv,
                      reinterpret_cast<const int32_t *>(base + o_rp), reinterpret_cast<const int32_t *>(base + o_col),
                      reinterpret_cast<const uint8_t *>(base + o_coef), reinterpret_cast<const int32_t *>(base + o_cp),
@@ -1234,6 +1260,8 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
     }
     if (b->prior == GFBP_PRIOR_MARKOV && (!b->markov_M || !b->markov_pi))
         return fail(GFBP_EINVAL, "Markov prior needs markov_M and markov_pi");
+    if ((b->options & GFBP_OPT_PRIOR_IN_SWEEP) && b->schedule != GFBP_SUS)
+        return fail(GFBP_EINVAL, "priors assigned during the sweep need the sequential schedule");
     if (!out->xhat || !out->iters || !out->converged) return fail(GFBP_EINVAL, "null output buffer");
     if (!workspace) return fail(GFBP_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(GFBP_EINVAL, "workspace not 256-byte aligned");
@@ -1340,6 +1368,8 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
     if (d->schedule != GFBP_PUS && d->schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
     if (d->max_iter < 1) return fail(GFBP_EINVAL, "max_iter < 1");
     if ((d->markov_M == nullptr) != (d->markov_pi == nullptr)) return fail(GFBP_EINVAL, "markov_M and markov_pi go together");
+    if (d->options & GFBP_OPT_PRIOR_IN_SWEEP)
+        return fail(GFBP_EUNSUPPORTED, "sessions refresh priors after each iteration");
     gfbp_session *ss = new (std::nothrow) gfbp_session();
     if (!ss) return fail(GFBP_ENOMEM, "host allocation");
     ss->code = code;

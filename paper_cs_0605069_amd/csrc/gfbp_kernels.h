@@ -68,6 +68,17 @@ struct DevState {
     const uint8_t *mark;     // 1 if the frame's source symbols take the Markov prior
 };
 
+// Markov source for priors assigned during a SUS sweep: the transition
+// matrix M [q][q], the first symbol's distribution pi [q], the matrix shape
+// from k_markov_shape, and whether this sweep assigns them (0: the priors in
+// Pr are used as they are).
+struct SweepPrior {
+    const float *M;
+    const float *pi;
+    const float *mshape;
+    int on;
+};
+
 struct Snap {
     float *q;  // [F][E][Q] or null
     float *r;  // [F][E][Q] or null

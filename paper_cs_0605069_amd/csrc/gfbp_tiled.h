@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
 template <int P, int LG, int DCM, int DVM>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
                                            bool live, const SusRec &rec, int markov, int wantQ, const Snap &snap,
-                                           float *perm, float *rsh) {
+                                           const SweepPrior &sp, float *perm, float *rsh) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
     const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave), lane = int(threadIdx.x) % kWave;
@@ -564,8 +564,15 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
     float pf[Gm::EL];
     if (mine || post) {
         const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
-        const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
-        ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
+        if (sp.on && mk && j < c.n_info) {
+            // the prior assigned at this column's vertical pass, from Q_{j-1}
+            // of this sweep (an earlier level) and Q_{j+1} of the last (a
+            // later level): source columns lie on increasing levels
+            markov_prior<P, LG>(c, s, it, j, sp.M, sp.pi, sp.mshape, pf);
+        } else {
+            const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
+            ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
+        }
     }
     if (mine) {
         const int rs = rec.rs, dc = rec.dc, self = rec.self;
@@ -658,8 +665,8 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
 // holds rstride >= that many slots per column).
 template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
-                                                          int wantQ, Snap snap, const SusRec *recs, int rstride,
-                                                          int ncols) {
+                                                          int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
+                                                          int rstride, int ncols) {
     using Gm = Geo<P, LG>;
     __shared__ __align__(16) float perm[DVM * Gm::PERM];
     __shared__ float rsh[DVM * Gm::EL * kWave];
@@ -668,13 +675,13 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
     const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const SusRec rec = recs[size_t(it.node) * rstride + d];
     const bool live = it.f < s.F && s.active[it.f];
-    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, perm + d * Gm::PERM, rsh);
+    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, perm + d * Gm::PERM, rsh);
 }
 
 // A6, strict order: columns 0..n-1 one after the other for each tile.
 template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
-                                                           int wantQ, Snap snap) {
+                                                           int wantQ, Snap snap, SweepPrior sp) {
     using Gm = Geo<P, LG>;
     __shared__ __align__(16) float perm[DVM * Gm::PERM];
     __shared__ float rsh[DVM * Gm::EL * kWave];
@@ -697,29 +704,27 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
             rec.hinv = c.emap[2 * size_t(rec.e)];
             rec.h = c.emap[2 * size_t(rec.e) + 1];
         }
-        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, mine, rsh);
+        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
         __syncthreads();  // rsh and the LDS rows are reused by the next column
     }
 }
 
-// A7 dynamical block prior (Eq. (7)) for source symbol k: from this
-// iteration's pseudo-posteriors of its chain neighbours, multiplied into the
-// channel likelihood for the next iteration.
+// A7 dynamical block prior (Eq. (7)) for source symbol k of frame it.f,
+// from the current pseudo-posteriors of its chain neighbours in Qp, times the
+// channel likelihood, into pf (both normalised).
 //
 // mshape (from k_markov_shape): when M = s I + o (J - I) (every diagonal entry
 // s, every other entry o, as for a source that keeps its symbol or moves to
 // any other one uniformly), the neighbour sums of Eq. (7) take O(q):
 // sum_a Q(a) M(a, b) = sum_c M(b, c) Q(c) = s Q(b) + o (S - Q(b)), S = sum Q,
 // and each lane needs only its own entries of the neighbours; any other M
-// takes the O(q^2) sums.
+// takes the O(q^2) sums.  Every lane of the frame takes part.
 template <int P, int LG>
-__global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi,
-                                                   const float *mshape) {
+__device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s, const Item &it, int k,
+                                             const float *M, const float *pi, const float *mshape,
+                                             float (&pf)[Geo<P, LG>::EL]) {
     using Gm = Geo<P, LG>;
-    const Item it = item<P, LG>(c.n_info, s);
-    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
-    if (s.mark && !s.mark[it.f]) return;
-    const int k = it.node, K = c.n_info;
+    const int K = c.n_info;
     double u[Gm::EL], v[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
@@ -751,21 +756,23 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
         if (k < K - 1)
 #pragma unroll
             for (int q = 0; q < Gm::EL; ++q) v[q] = sd * double(nb[1][q]) + od * (S[1] - double(nb[1][q]));
-    } else if (k > 0) {
+    } else {
         // the whole neighbour vectors (every lane of the frame reads all q entries)
-        const float *qp = s.Qp + size_t(k - 1) * s.Fp * Gm::Q + fo;
-        for (int a = 0; a < Gm::Q; ++a) {
-            const double qa = qp[a];
+        if (k > 0) {
+            const float *qp = s.Qp + size_t(k - 1) * s.Fp * Gm::Q + fo;
+            for (int a = 0; a < Gm::Q; ++a) {
+                const double qa = qp[a];
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) u[q] += qa * double(M[a * Gm::Q + it.g * Gm::EL + q]);
+                for (int q = 0; q < Gm::EL; ++q) u[q] += qa * double(M[a * Gm::Q + it.g * Gm::EL + q]);
+            }
         }
-    }
-    if (mshape[0] == 0.0f && k < K - 1) {
-        const float *qp = s.Qp + size_t(k + 1) * s.Fp * Gm::Q + fo;
-        for (int cc = 0; cc < Gm::Q; ++cc) {
-            const double qc = qp[cc];
+        if (k < K - 1) {
+            const float *qp = s.Qp + size_t(k + 1) * s.Fp * Gm::Q + fo;
+            for (int cc = 0; cc < Gm::Q; ++cc) {
+                const double qc = qp[cc];
 #pragma unroll
-            for (int q = 0; q < Gm::EL; ++q) v[q] += double(M[(it.g * Gm::EL + q) * Gm::Q + cc]) * qc;
+                for (int q = 0; q < Gm::EL; ++q) v[q] += double(M[(it.g * Gm::EL + q) * Gm::Q + cc]) * qc;
+            }
         }
     }
 #pragma unroll
@@ -776,10 +783,21 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) u[q] *= double(lf[q]);
     normalise<P, LG>(u, s.guards, it.f, it.g);
-    float pf[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) pf[q] = float(u[q]);
-    st<Gm::EL>(chunk<P, LG>(s.Pr, size_t(k), s.Fp, it), pf);
+}
+
+// A7 after an iteration: every source symbol's prior for the next one.
+template <int P, int LG>
+__global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const float *M, const float *pi,
+                                                   const float *mshape) {
+    using Gm = Geo<P, LG>;
+    const Item it = item<P, LG>(c.n_info, s);
+    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    if (s.mark && !s.mark[it.f]) return;
+    float pf[Gm::EL];
+    markov_prior<P, LG>(c, s, it, it.node, M, pi, mshape, pf);
+    st<Gm::EL>(chunk<P, LG>(s.Pr, size_t(it.node), s.Fp, it), pf);
 }
 
 // Shape of the Markov matrix for k_markov: out = {1, s, o} when every

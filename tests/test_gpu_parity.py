@@ -236,6 +236,60 @@ def test_markov_prior(gfbp, schedule, q, kind):
                        recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=100, **kw))
 
 
+@pytest.mark.parametrize("kind", ["self", "general"])
+@pytest.mark.parametrize("strict", [False, True])
+def test_prior_in_sweep(gfbp, strict, kind):
+    """SUS with each source symbol's prior assigned at its column's vertical
+    pass (Section 2, priors paragraph), against the reference's in-sweep
+    timing: messages after iterations 1, 2 and 4, then the decisions; in the
+    levelled sweep (source symbols on increasing levels) and the strict one."""
+    q = 8
+    code, enc = wl.regular_code(300, 3, 6, q, seed=11)
+    M = wl.self_transition_matrix(q, 0.7)
+    if kind == "general":
+        M = 0.5 * M + 0.5 * np.random.default_rng(0x3A9).dirichlet(np.ones(q), size=q)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 120, 13, "bsc", 0.11 if kind == "self" else 0.07, source="markov", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=pi, prior_in_sweep=True)
+    dcode = gfbp.DeviceCode(code)
+    assert dcode.info.sus_levels_in_sweep >= code.n_info > dcode.info.sus_levels
+    for it in (1, 2, 4):
+        g = _gpu(gfbp, code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, sus_strict=strict, **kw)
+        r = _ref(code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, **kw)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            err = np.abs(g[key] - r[key]).max()
+            assert err <= MSG_TOL, f"iter {it} {key}: {err:.3g}"
+        if it == 2:  # the timing matters from iteration 2 on
+            d = _gpu(gfbp, code, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, prior="markov",
+                     markov_M=M, markov_pi=pi)
+            assert np.abs(d["snap_Q"] - g["snap_Q"]).max() > 1e-3
+    g = _gpu(gfbp, code, fr, "sus", max_iter=100, sus_strict=strict, **kw)
+    r = _ref(code, fr, "sus", max_iter=100, **kw)
+    _compare_decisions(g, r, f"in-sweep {kind} strict={strict}",
+                       recheck=lambda idx: _precision_sensitive(code, fr, "sus", idx, max_iter=100, **kw))
+
+
+def test_prior_in_sweep_levelled_is_bitwise_strict_and_errors(gfbp):
+    import ctypes
+
+    q = 16
+    code, enc = wl.regular_code(256, 3, 6, q, seed=14)
+    M = wl.self_transition_matrix(q, 0.8)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 70, 15, "biawgn", 0.75, source="markov", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=pi, prior_in_sweep=True, max_iter=50, posterior=True)
+    a = _gpu(gfbp, code, fr, "sus", **kw)
+    b = _gpu(gfbp, code, fr, "sus", sus_strict=True, **kw)
+    for k in ("xhat", "iters", "converged", "posterior"):
+        assert np.array_equal(a[k], b[k]), k
+    with pytest.raises(gfbp.GfbpError):
+        _gpu(gfbp, code, fr, "pus", **kw)
+    dcode = gfbp.DeviceCode(code)
+    d = gfbp.SessionDesc(64, gfbp.SCHEDULES["sus"], 10, 0, None, None, gfbp.OPT_PRIOR_IN_SWEEP)
+    h = ctypes.c_void_p()
+    assert gfbp.lib().gfbp_session_create(dcode.handle, ctypes.byref(d), ctypes.byref(h)) != 0 and not h.value
+
+
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_nonzero_syndrome_and_given_likelihoods(gfbp, schedule):
     """Coset decoding (H x = z with z != 0) from raw likelihood vectors."""
@@ -318,12 +372,13 @@ def test_frame_alone_equals_frame_in_batch_and_runs_repeat(gfbp, schedule):
         assert one["iters"][0] == a["iters"][f]
 
 
-@pytest.mark.parametrize("schedule", ["pus", "sus"])
+@pytest.mark.parametrize("schedule", ["pus", "sus", "sus-in-sweep"])
 def test_frame_compaction_changes_nothing(gfbp, schedule):
     """Moving running frames into finished slots (on by default) gives bitwise
     the outputs of decoding with every frame in place, with a Markov prior and
-    a syndrome; the batch mixes fast and slow frames so that compaction runs
-    several times."""
+    a syndrome (and, for priors assigned during the sweep, the source symbols'
+    pseudo-posteriors the next sweep reads); the batch mixes fast and slow
+    frames so that compaction runs several times."""
     import torch
 
     q = 8
@@ -338,8 +393,8 @@ def test_frame_compaction_changes_nothing(gfbp, schedule):
     dfr = gfbp.frames_to_device(fr)
     outs = []
     for compact in (False, True):
-        o = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=60, prior="markov", markov_M=M, markov_pi=pi,
-                              compact=compact)
+        o = gfbp.decode_batch(dcode, dfr, schedule=schedule[:3], max_iter=60, prior="markov", markov_M=M,
+                              markov_pi=pi, compact=compact, prior_in_sweep=schedule.endswith("in-sweep"))
         torch.cuda.synchronize()
         outs.append({k: v.cpu().numpy() for k, v in o.items()})
     it = outs[0]["iters"]
