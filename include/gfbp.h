@@ -298,7 +298,8 @@ gfbp_status gfbp_tune(gfbp_code *code, const gfbp_batch *batch, gfbp_result *out
  * bracketed by two HIP events on the caller's stream; after the decode's final
  * synchronisation the elapsed times are added to process-wide totals per
  * kernel kind ("init", "check", "variable", "sequential", "sus_level",
- * "syndrome", "retire", "markov", "output"), together with the launch's algorithmic HBM bytes
+ * "sus_run" (runs of thin SUS levels), "syndrome", "retire", "markov", "output",
+ * "compact"), together with the launch's algorithmic HBM bytes
  * (float32 messages read and written once, as the method defines them; frames
  * that have stopped iterating are not counted) and its edge-q updates (E*q per
  * running frame for one iteration). */

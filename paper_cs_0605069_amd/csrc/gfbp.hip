@@ -41,6 +41,10 @@ gfbp_status fail(gfbp_status s, const std::string &msg) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// SUS levels with at most this many columns are walked in runs (k_sus_run):
+// one launch then costs more than walking a couple of columns in a row
+constexpr int kThinLevel = 2;
+
 }  // namespace
 
 struct gfbp_code {
@@ -55,6 +59,13 @@ struct gfbp_code {
         std::vector<double> edges;  // per level: edges
         std::vector<double> src;    // per level: source columns
         const SusRec *recs = nullptr;  // device [n][max column degree], columns in level order
+        // launches of one sweep: a wide level alone (one workgroup per column
+        // and tile), or a run of consecutive thin levels (one per tile)
+        struct Seg {
+            int c0, nc, run;
+            double sibs, edges, src;
+        };
+        std::vector<Seg> segs;
     } lv[2];
     int el[2] = {0, 0};   // entries per lane chosen for PUS / SUS (0 = default)
     void *mem = nullptr;  // one device allocation holding every array of dev
@@ -67,10 +78,11 @@ struct gfbp_code {
 namespace {
 
 enum Kind {
-    K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COMPACT, K_COUNT
+    K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COMPACT,
+    K_SUS_RUN, K_COUNT
 };
-const char *kKindName[K_COUNT] = {"init",     "check",  "variable", "sequential", "sus_level",
-                                  "syndrome", "retire", "markov",   "output",     "compact"};
+const char *kKindName[K_COUNT] = {"init",     "check",  "variable", "sequential", "sus_level", "syndrome",
+                                  "retire",   "markov", "output",   "compact",    "sus_run"};
 
 struct Totals {
     int64_t launches = 0;
@@ -459,6 +471,28 @@ struct TiledLaunch {
                            dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, sp,
                            recs, std::max(1, c.max_dv), nc);
     }
+    static void sus_run(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+                        Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
+        launch((tiled::k_sus_run<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
+                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, sp,
+                           recs, std::max(1, c.max_dv), nc);
+    }
+    // one sweep of levels (lv.segs)
+    static void sweep(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+                      Snap sn, const SweepPrior &sp, const gfbp_code::Levels &lv, Tracer *tr, int needQ, int t) {
+        const int RS = std::max(1, c.max_dv);
+        for (const auto &g : lv.segs) {
+            if (tr) tr->begin();
+            if (g.run) sus_run(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
+            else sus_level(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
+            // an assigned prior reads two neighbours' Q and L in place of Pr
+            if (tr)
+                tr->end_iter(g.run ? K_SUS_RUN : K_SUS_LEVEL,
+                             4.0 * (1 << P) * (g.sibs + g.edges) + g.nc * (4.0 * (1 << P) * (1 + needQ) + 1) +
+                                 (sp.on ? 8.0 * (1 << P) * g.src : 0.0),
+                             g.edges * (1 << P), t);
+        }
+    }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn, const SweepPrior &sp) {
         launch((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
@@ -579,18 +613,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             tr.end_iter(K_SEQUENTIAL, bpf.sequential + (sp.on ? 8.0 * Q * c.n_info : 0.0), eq_frame, t);
         } else {
             const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
-            const gfbp_code::Levels &lv = code->lv[insweep ? 1 : 0];
-            const int nlev = int(lv.ptr.size()) - 1;
-            for (int l = 0; l < nlev; ++l) {
-                const int c0 = lv.ptr[l], nc = lv.ptr[l + 1] - c0;
-                tr.begin();
-                K::sus_level(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(c0) * std::max(1, c.max_dv), nc);
-                // an assigned prior reads two neighbours' Q and L in place of Pr
-                tr.end_iter(K_SUS_LEVEL,
-                            4.0 * Q * (lv.sibs[l] + lv.edges[l]) + nc * (4.0 * Q * (1 + needQ) + 1) +
-                                (sp.on ? 8.0 * Q * lv.src[l] : 0.0),
-                            lv.edges[l] * Q, t);
-            }
+            K::sweep(st, c, s, z, markov, wantQ, sn, sp, code->lv[insweep ? 1 : 0], &tr, needQ, t);
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
         if (tracing) {
@@ -874,12 +897,7 @@ struct SessionRun {
             } else if (ss->options & GFBP_OPT_SUS_STRICT) {
                 K::sequential(st, c, s, z, ss->markov, needQ, sn, sp);
             } else {
-                const gfbp_code::Levels &lv = code->lv[0];
-                const int nlev = int(lv.ptr.size()) - 1;
-                for (int l = 0; l < nlev; ++l) {
-                    const int c0 = lv.ptr[l], nc = lv.ptr[l + 1] - c0;
-                    K::sus_level(st, c, s, z, ss->markov, needQ, sn, sp, lv.recs + size_t(c0) * std::max(1, c.max_dv), nc);
-                }
+                K::sweep(st, c, s, z, ss->markov, needQ, sn, sp, code->lv[0], nullptr, needQ, 0);
             }
             hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
             hipLaunchKernelGGL(k_session_retire, dim3(fb), dim3(kBlock), 0, st, ss->dv);
@@ -1142,6 +1160,20 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
                 const int i = edge_row[col_edge[t]];
                 L.sibs[l] += d->row_ptr[i + 1] - d->row_ptr[i] - 1;
                 L.edges[l] += 1;
+            }
+        }
+        // levels of at most kThinLevel columns are walked in runs
+        for (int l = 0; l < nlev; ++l) {
+            const int c0 = L.ptr[l], nc = L.ptr[l + 1] - c0;
+            const bool thin = nc <= kThinLevel;
+            if (thin && !L.segs.empty() && L.segs.back().run) {
+                gfbp_code::Levels::Seg &g = L.segs.back();
+                g.nc += nc;
+                g.sibs += L.sibs[l];
+                g.edges += L.edges[l];
+                g.src += L.src[l];
+            } else {
+                L.segs.push_back({c0, nc, thin ? 1 : 0, L.sibs[l], L.edges[l], L.src[l]});
             }
         }
         recs[chain].resize(size_t(n) * RS);

@@ -678,6 +678,30 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
     sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, perm + d * Gm::PERM, rsh);
 }
 
+// A6, a run of thin dependency levels (a few columns each) in one launch:
+// one workgroup per tile takes the columns of recs[0..ncols), in level order,
+// one after the other as the strict sweep does; every column of the run
+// depends only on columns of this frame at lower levels, which come earlier
+// in the run or in an earlier launch.
+template <int P, int LG, int DCM, int DVM>
+__global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, const uint8_t *z, int markov,
+                                                        int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
+                                                        int rstride, int ncols) {
+    using Gm = Geo<P, LG>;
+    __shared__ __align__(16) float perm[DVM * Gm::PERM];
+    __shared__ float rsh[DVM * Gm::EL * kWave];
+    const Item it = block_item<P, LG>(1, s);
+    if (!it.ok) return;  // uniform over the workgroup
+    const bool live = it.f < s.F && s.active[it.f];
+    const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    float *mine = perm + d * Gm::PERM;
+    for (int p = 0; p < ncols; ++p) {
+        const SusRec rec = recs[size_t(p) * rstride + d];
+        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
+        __syncthreads();  // rsh and the LDS rows are reused by the next column
+    }
+}
+
 // A6, strict order: columns 0..n-1 one after the other for each tile.
 template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,

@@ -12,7 +12,9 @@ so the iteration counts and error rates are not the paper's: the comparison
 is the schedules' ratio.
 
 ``python -m paper_cs_0605069_amd.table1`` decodes every setting with both
-schedules on the same samples and prints one JSON line per setting.
+schedules on the same samples and prints one JSON line per setting;
+``--schedules pus,sus,sus-in-sweep`` adds SUS with the Markov priors assigned
+during the sweep (the same as SUS for the i.i.d. rows).
 """
 from __future__ import annotations
 
@@ -58,10 +60,10 @@ def run_setting(channel: str, q: int, source: str, param: float, samples: int, b
     M, start = source_model(source, q)
     kw = {} if M is None else dict(prior="markov", markov_M=M, markov_pi=start)
     dcode = DeviceCode(code)
-    it = {"pus": [], "sus": []}
-    conv = {"pus": [], "sus": []}
-    berr = {"pus": 0, "sus": 0}
-    gpu_s = {"pus": 0.0, "sus": 0.0}
+    it = {s: [] for s in schedules}
+    conv = {s: [] for s in schedules}
+    berr = {s: 0 for s in schedules}
+    gpu_s = {s: 0.0 for s in schedules}
     prm = param * scale
     for b0 in range(0, samples, batch):
         F = min(batch, samples - b0)
@@ -71,9 +73,12 @@ def run_setting(channel: str, q: int, source: str, param: float, samples: int, b
         torch.cuda.synchronize()
         for s in schedules:
             t0 = time.perf_counter()
-            out = decode_batch(dcode, d, schedule=s, max_iter=max_iter, **kw)
+            out = decode_batch(dcode, d, schedule=s[:3], max_iter=max_iter,
+                               prior_in_sweep=s.endswith("in-sweep") and M is not None, **kw)
             torch.cuda.synchronize()
             gpu_s[s] += time.perf_counter() - t0
+            print(f"# {channel} q={q} {source} {s}: frames {b0}..{b0 + F} in {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
             xh = out["xhat"].cpu().numpy()
             it[s].append(out["iters"].cpu().numpy())
             conv[s].append(out["converged"].cpu().numpy().astype(bool))
@@ -90,15 +95,17 @@ def run_setting(channel: str, q: int, source: str, param: float, samples: int, b
         res[f"fer_{s}"] = float(1.0 - cv[s].mean())
         res[f"ber_{s}"] = berr[s] / float(samples * N * p)
         res[f"edge_q_per_s_{s}"] = float(ti[s].sum() * code.E * q / gpu_s[s])
-    if len(schedules) < 2:
-        return res
-    both = cv["pus"] & cv["sus"]
-    res["ratio_of_means"] = res["t_sus"] / res["t_pus"]
-    if both.any():
-        r = ti["sus"][both] / ti["pus"][both]
-        res["mean_of_ratios"] = float(r.mean())
-        res["stdev_of_ratios"] = float(r.std())
-        res["both_converged"] = int(both.sum())
+    for s in schedules:
+        if s == "pus" or "pus" not in schedules:
+            continue
+        tag = "" if s == "sus" else f"_{s.replace('-', '_')}"
+        both = cv["pus"] & cv[s]
+        res[f"ratio_of_means{tag}"] = res[f"t_{s}"] / res["t_pus"]
+        if both.any():
+            r = ti[s][both] / ti["pus"][both]
+            res[f"mean_of_ratios{tag}"] = float(r.mean())
+            res[f"stdev_of_ratios{tag}"] = float(r.std())
+            res[f"both_converged{tag}"] = int(both.sum())
     return res
 
 

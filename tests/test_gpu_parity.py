@@ -553,6 +553,24 @@ def test_levelled_sus_is_bitwise_the_strict_sweep(gfbp, q, channel, param, prior
             assert np.array_equal(a[k], b[k]), f"levelled and strict SUS differ in {k}"
 
 
+@pytest.mark.parametrize("q,source", [(4, "4s"), (8, "2s")])
+def test_thin_level_runs_are_bitwise_the_strict_sweep(gfbp, q, source):
+    """An MN syndrome-form code (B's chain: most levels hold one or two
+    columns, walked in runs of levels per tile): levelled SUS, also with the
+    priors assigned during the sweep, equals the strict column order."""
+    M, start = (wl.PAPER_MARKOV_4S, wl.stationary(wl.PAPER_MARKOV_4S)) if source == "4s" else \
+        wl.lift_binary_chain(wl.PAPER_MARKOV_2S, 3)
+    code = wl.mn_code(60, 180, q, seed=41 + q)
+    fr = wl.make_mn_frames(code, 40, 42 + q, "bsc", 0.12, source="markov", markov=M, start=start)
+    for in_sweep in (False, True):
+        kw = dict(prior="markov", markov_M=M, markov_pi=start, prior_in_sweep=in_sweep)
+        for extra in (dict(max_iter=60, posterior=True), dict(max_iter=3, early_stop=False, snap_iter=3)):
+            a = _gpu(gfbp, code, fr, "sus", **extra, **kw)
+            b = _gpu(gfbp, code, fr, "sus", sus_strict=True, **extra, **kw)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), f"in_sweep={in_sweep}: levelled and strict SUS differ in {k}"
+
+
 # --------------------------------------------------------------- kernel shapes and the tuner
 @pytest.mark.parametrize("q", [2, 4, 8, 16, 32, 64])
 def test_every_kernel_shape_matches_the_reference(gfbp, q):
