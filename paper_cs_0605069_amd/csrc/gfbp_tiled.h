@@ -165,11 +165,17 @@ __device__ __forceinline__ void gf_positions(uint64_t packed, int g, int *out) {
 // Permute one vector per frame through the wavefront's LDS rows: the value
 // this lane holds for position g*EL + r goes to position pos[r]; afterwards
 // the lane holds positions g*EL + r of the permuted vector.  Lanes of one
-// frame only touch that frame's row.
+// frame only touch that frame's row.  Over GF(2) the only multiplier is 1:
+// the permutation is the identity.
 template <int P, int LG>
 __device__ __forceinline__ void lds_permute(float *buf, const Item &it, const int *pos, const float *in,
                                             float *out) {
     using Gm = Geo<P, LG>;
+    if constexpr (P == 1) {
+#pragma unroll
+        for (int r = 0; r < Gm::EL; ++r) out[r] = in[r];
+        return;
+    }
     float *row = buf + it.fw * Gm::QS;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll

@@ -172,9 +172,11 @@ def test_messages_after_first_iterations(gfbp, q, schedule):
             assert err <= MSG_TOL, f"q={q} {schedule} iter {it} {key}: max abs error {err:.3g}"
 
 
+@pytest.mark.parametrize("q", [2, 8])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_bec_messages_bit_identical(gfbp, schedule):
-    code, enc = _small_code(8, 96, seed=7)
+def test_bec_messages_bit_identical(gfbp, schedule, q):
+    """Every BEC message value is dyadic, so it is exact in float32."""
+    code, enc = _small_code(q, 96, seed=7)
     fr = wl.make_frames(code, enc, 10, 8, "bec", 0.3)
     for it in (1, 2, 4):
         g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
@@ -372,8 +374,8 @@ def test_frame_alone_equals_frame_in_batch_and_runs_repeat(gfbp, schedule):
         assert one["iters"][0] == a["iters"][f]
 
 
-@pytest.mark.parametrize("schedule", ["pus", "sus", "sus-in-sweep"])
-def test_frame_compaction_changes_nothing(gfbp, schedule):
+@pytest.mark.parametrize("schedule,q", [("pus", 8), ("sus", 8), ("sus-in-sweep", 8), ("pus", 2), ("sus", 2)])
+def test_frame_compaction_changes_nothing(gfbp, schedule, q):
     """Moving running frames into finished slots (on by default) gives bitwise
     the outputs of decoding with every frame in place, with a Markov prior and
     a syndrome (and, for priors assigned during the sweep, the source symbols'
@@ -381,7 +383,6 @@ def test_frame_compaction_changes_nothing(gfbp, schedule):
     frames so that compaction runs several times."""
     import torch
 
-    q = 8
     code, enc = wl.regular_code(240, 3, 6, q, seed=37)
     M = wl.self_transition_matrix(q, 0.7)
     pi = wl.stationary(M)
