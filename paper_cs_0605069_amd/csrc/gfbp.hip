@@ -467,15 +467,25 @@ struct TiledLaunch {
     }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                           Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
-        launch((tiled::k_sus_level<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(nc) * unsigned(s.nb))),
-                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, sp,
-                           recs, std::max(1, c.max_dv), nc);
+        const dim3 g(std::max(1u, unsigned(nc) * unsigned(s.nb)));
+        const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
+        if (sp.on)
+            launch((tiled::k_sus_level<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+                   std::max(1, c.max_dv), nc);
+        else
+            launch((tiled::k_sus_level<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+                   std::max(1, c.max_dv), nc);
     }
     static void sus_run(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
                         Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
-        launch((tiled::k_sus_run<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
-                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn, sp,
-                           recs, std::max(1, c.max_dv), nc);
+        const dim3 g(std::max(1u, unsigned(s.nb)));
+        const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
+        if (sp.on)
+            launch((tiled::k_sus_run<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+                   std::max(1, c.max_dv), nc);
+        else
+            launch((tiled::k_sus_run<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+                   std::max(1, c.max_dv), nc);
     }
     // one sweep of levels (lv.segs)
     static void sweep(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
@@ -495,9 +505,12 @@ struct TiledLaunch {
     }
     static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
                            int wantQ, Snap sn, const SweepPrior &sp) {
-        launch((tiled::k_sequential<P, LG, DCM, DVM>), dim3(std::max(1u, unsigned(s.nb))),
-                           dim3(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave), 0, st, c, s, z, markov, wantQ, sn,
-                           sp);
+        const dim3 g(std::max(1u, unsigned(s.nb)));
+        const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
+        if (sp.on)
+            launch((tiled::k_sequential<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp);
+        else
+            launch((tiled::k_sequential<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi,
                        const float *mshape) {

@@ -555,8 +555,10 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
 // decision (partial vertical pass).  `live`: this lane's frame is still
 // iterating.  perm is the wavefront's LDS rows; rsh holds the column's r as
 // [d][register][lane].  The column's prior is loaded first so that its
-// latency overlaps the check-side work.
-template <int P, int LG, int DCM, int DVM>
+// latency overlaps the check-side work.  SWEEP_PRIOR: the variant whose
+// source-symbol priors are assigned during the sweep (a separate
+// instantiation, so the default one carries none of its code or registers).
+template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
                                            bool live, const SusRec &rec, int markov, int wantQ, const Snap &snap,
                                            const SweepPrior &sp, float *perm, float *rsh) {
@@ -570,7 +572,7 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
     float pf[Gm::EL];
     if (mine || post) {
         const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
-        if (sp.on && mk && j < c.n_info) {
+        if (SWEEP_PRIOR && sp.on && mk && j < c.n_info) {
             // the prior assigned at this column's vertical pass, from Q_{j-1}
             // of this sweep (an earlier level) and Q_{j+1} of the last (a
             // later level): source columns lie on increasing levels
@@ -669,7 +671,7 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
 // workgroup per (column, tile), one wavefront per edge of the column
 // (blockDim = 64 x the largest column degree, at most DVM wavefronts; recs
 // holds rstride >= that many slots per column).
-template <int P, int LG, int DCM, int DVM>
+template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
 __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
                                                           int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
                                                           int rstride, int ncols) {
@@ -681,7 +683,8 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
     const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const SusRec rec = recs[size_t(it.node) * rstride + d];
     const bool live = it.f < s.F && s.active[it.f];
-    sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, perm + d * Gm::PERM, rsh);
+    sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, perm + d * Gm::PERM,
+                                             rsh);
 }
 
 // A6, a run of thin dependency levels (a few columns each) in one launch:
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
 // one after the other as the strict sweep does; every column of the run
 // depends only on columns of this frame at lower levels, which come earlier
 // in the run or in an earlier launch.
-template <int P, int LG, int DCM, int DVM>
+template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
 __global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, const uint8_t *z, int markov,
                                                         int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
                                                         int rstride, int ncols) {
@@ -703,13 +706,13 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, c
     float *mine = perm + d * Gm::PERM;
     for (int p = 0; p < ncols; ++p) {
         const SusRec rec = recs[size_t(p) * rstride + d];
-        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
+        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
         __syncthreads();  // rsh and the LDS rows are reused by the next column
     }
 }
 
 // A6, strict order: columns 0..n-1 one after the other for each tile.
-template <int P, int LG, int DCM, int DVM>
+template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
 __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
                                                            int wantQ, Snap snap, SweepPrior sp) {
     using Gm = Geo<P, LG>;
@@ -734,7 +737,7 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
             rec.hinv = c.emap[2 * size_t(rec.e)];
             rec.h = c.emap[2 * size_t(rec.e) + 1];
         }
-        sus_column<P, LG, DCM, DVM>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
+        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
         __syncthreads();  // rsh and the LDS rows are reused by the next column
     }
 }
