@@ -285,8 +285,9 @@ gfbp_status gfbp_graph_destroy(gfbp_graph *graph);
  * gfbp_code_set_shape fixes EL for one schedule (0 = default: 4, or 2 when
  * q = 2); gfbp_code_get_shape returns the EL in use.  gfbp_tune times
  * trial_iters fixed iterations of `batch` (same buffers and workspace as a
- * decode; outputs are overwritten) with every allowed EL and keeps the
- * fastest for batch->schedule, returned in *chosen.  These calls change the
+ * decode; outputs are overwritten) with every allowed EL (one warm-up run
+ * each, then three rounds over them, each keeping its fastest run) and keeps
+ * the fastest for batch->schedule, returned in *chosen.  These calls change the
  * code handle: do not run them concurrently with decodes on the same code. */
 gfbp_status gfbp_code_set_shape(gfbp_code *code, int32_t schedule, int32_t entries_per_lane);
 int32_t gfbp_code_get_shape(const gfbp_code *code, int32_t schedule);

@@ -1376,25 +1376,30 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     to.snap_iter = 0;
     to.snap_q = to.snap_r = to.snap_Q = nullptr;
     to.trace = nullptr;
-    double best_t = 1e300;
-    int best = 0;
-    for (int l = 1; l <= max_lel(c); ++l) {
-        c->el[slot] = 1 << l;
-        double t = 0;
-        for (int rep = 0; rep < 2; ++rep) {  // the first run warms up, the second is timed
+    // one warm-up run per candidate, then kRounds rounds over the candidates
+    // in turn (so that drift hits all alike); each keeps its fastest run
+    constexpr int kRounds = 3;
+    const int nl = max_lel(c);
+    std::vector<double> best_of(size_t(nl) + 1, 1e300);
+    for (int round = -1; round < kRounds; ++round)
+        for (int l = 1; l <= nl; ++l) {
+            c->el[slot] = 1 << l;
             const auto t0 = std::chrono::steady_clock::now();
             const gfbp_status st = gfbp_decode_batch(c, &tb, &to, workspace, ws_bytes, stream);
             if (st != GFBP_OK) {
                 c->el[slot] = keep;
                 return st;
             }
-            t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (round >= 0) best_of[size_t(l)] = std::min(best_of[size_t(l)], t);
         }
-        if (t < best_t) {
-            best_t = t;
+    double best_t = 1e300;
+    int best = 0;
+    for (int l = 1; l <= nl; ++l)
+        if (best_of[size_t(l)] < best_t) {
+            best_t = best_of[size_t(l)];
             best = 1 << l;
         }
-    }
     c->el[slot] = best;
     if (chosen) *chosen = best;
     return GFBP_OK;

@@ -64,3 +64,46 @@ def test_null_arguments():
     assert L.gfbp_decode_batch(None, None, None, None, 0, None) == -1
     assert L.gfbp_workspace_size(None, 10, 0, 0) == 0
     assert L.gfbp_code_free(None) == 0
+
+
+def _header_defines():
+    txt = open(os.path.join(ROOT, "include", "gfbp.h")).read()
+    return {k: int(v) for k, v in re.findall(r"#define (GFBP_[A-Z0-9_]+) \(?(-?\d+)\)?", txt)}
+
+
+def _header_struct(name):
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "gfbp.h")).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", txt).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        first, *rest = decl.split(",")
+        names.append(re.findall(r"(\w+)\s*(?:\[[^\]]*\])?$", first.strip())[0])
+        names += [r.strip().lstrip("*").strip() for r in rest]
+    return names
+
+
+def test_binding_constants_match_the_header():
+    import paper_cs_0605069_amd as gfbp
+
+    d = _header_defines()
+    for name, val in d.items():
+        short = name[len("GFBP_"):]
+        if hasattr(gfbp, short):
+            assert getattr(gfbp, short) == val, name
+    for short in ("OPT_SUS_STRICT", "OPT_NO_COMPACT", "OPT_STEP_GRAPHS", "OPT_PRIOR_IN_SWEEP", "PUS", "SUS",
+                  "CH_BSC", "CH_BEC", "CH_BIAWGN", "CH_LIKELIHOOD", "PRIOR_UNIFORM", "PRIOR_MARKOV"):
+        assert "GFBP_" + short in d and getattr(gfbp, short) == d["GFBP_" + short], short
+
+
+@pytest.mark.parametrize("cname,pyname", [("gfbp_code_desc", "CodeDesc"), ("gfbp_code_info", "CodeInfo"),
+                                          ("gfbp_batch", "Batch"), ("gfbp_result", "Result"),
+                                          ("gfbp_session_desc", "SessionDesc"), ("gfbp_frames", "FramesIn"),
+                                          ("gfbp_retired", "Retired"), ("gfbp_kernel_stats", "KernelStats")])
+def test_binding_structs_match_the_header(cname, pyname):
+    """The ctypes mirrors list the header's fields in the header's order."""
+    import paper_cs_0605069_amd as gfbp
+
+    assert [f[0] for f in getattr(gfbp, pyname)._fields_] == _header_struct(cname)
