@@ -226,7 +226,8 @@ def main():
         from paper_cs_0605069_amd.profiling import read_traffic
 
         tr = read_traffic(args.traffic)
-        if tr and dom in tr["kernels"] and all(int(tr["shapes"].get(s, -1)) == shapes[s] for s in scheds):
+        dsch = "pus" if dom in ("check", "variable") else "sus"  # the schedule whose kernel shape it is
+        if tr and dom in tr["kernels"] and dsch in shapes and int(tr["shapes"].get(dsch, -1)) == shapes[dsch]:
             roof["traffic"] = tr["kernels"][dom]["bytes_per_dispatch"]
             roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
             roof["traffic_over_algorithmic"] = roof["traffic"] / algo
