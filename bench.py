@@ -110,6 +110,17 @@ def gf64_leg(gfbp, torch, steps: int) -> dict:
         ach = ks[dom]["algo_bytes"] / (ks[dom]["total_ms"] / 1e3)
         res[f"{s}_roofline"] = {"kernel": dom, "achieved_GBps": ach / 1e9, "frac": ach / HBM_PEAK,
                                 "avg_launch_ms": ks[dom]["total_ms"] / ks[dom]["launches"]}
+        # the same kernel with every frame running (fixed iterations, no early stop): its
+        # bandwidth at full occupancy, without the convergence tail's small launches
+        gfbp.profile_reset()
+        gfbp.profile_enable(True)
+        gfbp.decode_batch(dcode, d, schedule=s, max_iter=4, early_stop=False)
+        torch.cuda.synchronize()
+        gfbp.profile_enable(False)
+        full = gfbp.profile_read()[dom]
+        fa = full["algo_bytes"] / (full["total_ms"] / 1e3)
+        res[f"{s}_roofline"]["all_frames_active"] = {"iterations": 4, "achieved_GBps": fa / 1e9, "frac": fa / HBM_PEAK,
+                                                     "avg_launch_ms": full["total_ms"] / full["launches"]}
     return res
 
 

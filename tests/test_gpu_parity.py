@@ -484,6 +484,30 @@ def test_mn_syndrome_form(gfbp, q, source, channel, param, schedule):
     assert np.array_equal(wl.syndromes(code, g["xhat"][ok]), fr.syndrome[ok])
 
 
+@pytest.mark.parametrize("q,source,channel,param", [(4, "4s", "bsc", 0.17), (8, "2s", "biawgn", 1.1)])
+def test_mn_syndrome_form_prior_in_sweep(gfbp, q, source, channel, param):
+    """The MN syndrome form with the source priors assigned during the SUS
+    sweep (R7(ii) timing): messages after iterations 2 and 3, then decisions."""
+    code = wl.mn_code(60, 180, q, seed=410 + q)
+    M, start = _MN_SOURCES[source]
+    fr = wl.make_mn_frames(code, 300, 411 + q, channel, param, source="markov", markov=M, start=start)
+    kw = dict(prior="markov", markov_M=M, markov_pi=start, prior_in_sweep=True)
+    L = fr.lik.astype(np.float64)
+    for it in (2, 3):
+        g = _gpu(gfbp, code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, **kw)
+        r = oracle.decode(code, likelihoods=L, syndrome=fr.syndrome, schedule=oracle.SUS, max_iter=it,
+                          early_stop=False, snap_iter=it, **kw)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            err = np.abs(g[key] - r[key]).max()
+            assert err <= MSG_TOL, f"iter {it} {key}: {err:.3g}"
+    g = _gpu(gfbp, code, fr, "sus", max_iter=80, **kw)
+    r = oracle.decode(code, likelihoods=L, syndrome=fr.syndrome, schedule=oracle.SUS, max_iter=80, **kw)
+    _compare_decisions(g, r, f"MN in-sweep q={q} {source} {channel}",
+                       recheck=lambda idx: _precision_sensitive(code, fr, "sus", idx, max_iter=80, **kw),
+                       near_tie=lambda idx, upto: _near_tie(code, fr, "sus", idx, upto, **kw))
+    assert r["converged"].mean() > 0.5
+
+
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_trace_of_correct_source_bits(gfbp, schedule):
     """The per-iteration count of correct source bits (Fig. 1 diagnostic)
