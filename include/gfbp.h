@@ -139,7 +139,7 @@ typedef struct {
 
 /* Frames are processed in tiles of up to 64 frames that share every kernel
  * launch, and a tile keeps running while any of its frames does.  When, after
- * an iteration, the running frames fill less than 3/4 of the running tiles,
+ * an iteration, the running frames fill less than 31/32 of the running tiles,
  * the decoder by default moves running frames (their messages, likelihoods,
  * priors and counters) into the slots of finished frames so that the running
  * frames form whole tiles again; each frame's arithmetic, and so every output,

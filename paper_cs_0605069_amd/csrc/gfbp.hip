@@ -660,8 +660,8 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             K::markov(st, c, s, b->markov_M, b->markov_pi, a.mshape);
             tr.end_iter(K_MARKOV, bpf.markov, 0, t + 1);
         }
-        if (compact && t >= 2 && uint64_t(known_running) * 4 < uint64_t(known_tiles) * K::TF * 3) {
-            // running frames filled less than 3/4 of their tiles: move the
+        if (compact && t >= 2 && uint64_t(known_running) * 32 < uint64_t(known_tiles) * K::TF * 31) {
+            // running frames filled less than 31/32 of their tiles: move the
             // frames still running after iteration t into the finished slots
             // below their count, then list the (now whole) tiles
             launch(k_plan_moves, dim3(1), dim3(1024), 0, st, s.active, F, cnt_dev, a.holes, a.movers, s.count + 8);
