@@ -425,6 +425,35 @@ def test_edge_cases(gfbp):
     assert ei.value.status == -5
 
 
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_largest_shape_gf64_n8000_sampled(gfbp, schedule):
+    """The largest shape the workloads use: GF(64), N = 8000, (3,6) (E =
+    24000, so q-message offsets pass 2^32 at 4096 frames), syndrome-form
+    BI-AWGN frames, in the bench's batch size; pseudo-posteriors and
+    decisions after 3 iterations of the first, a middle and the last frame
+    against the reference."""
+    import torch
+
+    code = wl.make_code(8000, 4000, 3, 64, seed=0xC0DE8000)
+    fr = wl.make_coset_frames(code, 4096, 0xDA7A8000, "biawgn", 0.75)
+    assert code.E * 64 * 4096 > 2 ** 32
+    dcode = gfbp.DeviceCode(code)
+    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, max_iter=3, early_stop=False,
+                            posterior=True)
+    torch.cuda.synchronize()
+    idx = [0, 2047, 4095]
+    post = out["posterior"][idx].cpu().numpy()
+    xh = out["xhat"][idx].cpu().numpy()
+    it = out["iters"][idx].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    r = oracle.decode(code, fr.subset(idx), schedule=gfbp_sched(schedule), max_iter=3, early_stop=False,
+                      posterior=True)
+    assert np.abs(post - r["posterior"]).max() <= MSG_TOL
+    assert (xh == r["xhat"]).mean() > 0.999  # decisions off only where two entries nearly tie
+    assert np.array_equal(it, r["iters"])
+
+
 def test_column_without_edges(gfbp):
     """A column in no check: its pseudo-posterior is its channel likelihood
     alone, under every schedule (the sequential step still decides it)."""
