@@ -244,7 +244,8 @@ def main():
             roof["traffic_over_algorithmic"] = roof["traffic"] / algo
     kernels = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
                    "share_of_gpu_time": v["total_ms"] / max(1e-9, sum(x["total_ms"] for x in prof.values())),
-                   "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0}
+                   "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0,
+                   "frac_of_hbm_peak": (v["algo_bytes"] / (v["total_ms"] / 1e3) / HBM_PEAK) if v["total_ms"] else 0.0}
                for k, v in prof.items()}
 
     gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps))

@@ -149,6 +149,21 @@ def _compare_decisions(g, r, label, min_frac=0.999, recheck=None, near_tie=None)
     return same
 
 
+def _wilson(k, n, z=1.96):
+    """95% Wilson score interval of a binomial proportion k/n."""
+    p = k / n
+    c = (p + z * z / (2 * n)) / (1 + z * z / n)
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / (1 + z * z / n)
+    return c - h, c + h
+
+
+def _fer_ci_overlap(conv_a, conv_b):
+    """The frame error rates' 95% Wilson intervals overlap."""
+    a = _wilson(int((conv_a == 0).sum()), len(conv_a))
+    b = _wilson(int((conv_b == 0).sum()), len(conv_b))
+    return a[0] <= b[1] and b[0] <= a[1]
+
+
 def _ci_overlap(a, b):
     """95% CIs of two means (normal approximation) overlap."""
     ma, mb = a.mean(), b.mean()
@@ -196,6 +211,7 @@ def test_config1_all_frames(gfbp, schedule):
     _compare_decisions(g, r, f"C1 {schedule}",
                        recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=200))
     assert _ci_overlap(g["iters"].astype(float), r["iters"].astype(float))
+    assert _fer_ci_overlap(g["converged"], r["converged"])
 
 
 @pytest.mark.parametrize("channel,param", [("bec", 0.42), ("biawgn", 0.85)])
