@@ -264,7 +264,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 messages, f64 transforms",
+        "dtype": "f64",
+        "message_storage": "f32",
         "data": "synthetic",
         "config": {"workload": f"GF({Q}) regular ({DV},{DC}) rate-1/2 LDPC, N={N_SYM} symbols, BI-AWGN "
                                f"Eb/N0 {EBN0[0]}-{EBN0[-1]} dB step 0.2, {FRAMES} frames per point, max {MAX_ITER} "
