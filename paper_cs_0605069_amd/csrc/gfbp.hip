@@ -223,17 +223,43 @@ __global__ void k_state_init(DevState s, BatchAux a) {
     a.pending[f] = 0;
 }
 
-// A5 convergence test: check i of frame f against z_i.
+// A5 convergence test: check i of frames 8k..8k+7 against z_i (one 8-byte
+// load of each column's decisions for the eight frames; the frame stride is a
+// multiple of 64 and every per-frame byte array is padded to 256 bytes, so the
+// loads are aligned and stay inside their arrays).
+constexpr int kSynFrames = 8;
+
 __global__ __launch_bounds__(kBlock) void k_syndrome(DevCode c, DevState s, const uint8_t *z) {
+    __shared__ uint8_t mul[64 * 64];  // the field's multiplication table
+    for (int t = int(threadIdx.x); t < c.q * c.q; t += kBlock) mul[t] = c.mul[t];
+    __syncthreads();
     const int F = s.F;
-    const int nchunk = (F + kBlock - 1) / kBlock;
+    const int groups = (F + kSynFrames - 1) / kSynFrames;
+    const int nchunk = (groups + kBlock - 1) / kBlock;
     const int i = blockIdx.x / nchunk;
-    const int f = (blockIdx.x % nchunk) * kBlock + threadIdx.x;
-    if (f >= F || !s.active[f]) return;
-    int acc = 0;
-    for (int e = c.row_ptr[i]; e < c.row_ptr[i + 1]; ++e)
-        acc ^= c.mul[c.coef[e] * c.q + s.xh[size_t(c.col[e]) * s.Fp + f]];
-    if (acc != (z ? z[size_t(f) * c.m + i] : 0)) s.unsat[f] = 1;
+    const int k = (blockIdx.x % nchunk) * kBlock + threadIdx.x;
+    if (k >= groups) return;
+    const int f0 = k * kSynFrames;
+    uint64_t act = *reinterpret_cast<const uint64_t *>(s.active + f0);
+    if (F - f0 < kSynFrames) act &= (uint64_t(1) << (8 * (F - f0))) - 1;  // frames past F
+    if (!act) return;
+    int acc[kSynFrames];
+#pragma unroll
+    for (int u = 0; u < kSynFrames; ++u) acc[u] = 0;
+    for (int e = c.row_ptr[i]; e < c.row_ptr[i + 1]; ++e) {
+        const uint8_t *m = mul + c.coef[e] * c.q;
+        const uint64_t x = *reinterpret_cast<const uint64_t *>(s.xh + size_t(c.col[e]) * s.Fp + f0);
+#pragma unroll
+        for (int u = 0; u < kSynFrames; ++u) acc[u] ^= m[(x >> (8 * u)) & 0xffu];
+    }
+#pragma unroll
+    for (int u = 0; u < kSynFrames; ++u)
+        if (((act >> (8 * u)) & 0xffu) && acc[u] != (z ? z[size_t(f0 + u) * c.m + i] : 0)) s.unsat[f0 + u] = 1;
+}
+
+inline unsigned syndrome_blocks(int m, int F) {
+    const int groups = (F + kSynFrames - 1) / kSynFrames;
+    return unsigned(m) * unsigned((groups + kBlock - 1) / kBlock);
 }
 
 // A5 retirement after iteration t: a frame whose decision satisfies H x = z
@@ -635,7 +661,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                    b->max_iter, out->trace);
         }
         tr.begin();
-        launch(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
+        launch(k_syndrome, dim3(syndrome_blocks(c.m, F)), dim3(kBlock), 0, st, c, s, z);
         tr.end_iter(K_SYNDROME, bpf.syndrome, 0, t);
         tr.begin();
         launch(k_retire, dim3(fb), dim3(kBlock), 0, st, s, a, t, b->max_iter, b->early_stop,
@@ -912,7 +938,7 @@ struct SessionRun {
             } else {
                 K::sweep(st, c, s, z, ss->markov, needQ, sn, sp, code->lv[0], nullptr, needQ, 0);
             }
-            hipLaunchKernelGGL(k_syndrome, dim3(unsigned(c.m) * fb), dim3(kBlock), 0, st, c, s, z);
+            hipLaunchKernelGGL(k_syndrome, dim3(syndrome_blocks(c.m, s.F)), dim3(kBlock), 0, st, c, s, z);
             hipLaunchKernelGGL(k_session_retire, dim3(fb), dim3(kBlock), 0, st, ss->dv);
             ss->parity ^= 1;
             K::tiles(st, s.active, s.F, s.Fp, ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles, ss->aux + 2 + ss->parity);
