@@ -14,7 +14,8 @@
  *     r of column j's edges from the current q, then column j's q.
  * After each iteration the decision is tested against H x = z.  With a Markov
  * source, the priors of the information symbols are re-estimated after every
- * iteration by the dynamical block prior of Eq. (7).
+ * iteration by the dynamical block prior of Eq. (7) (or, for SUS on request,
+ * during the sweep: GFBP_OPT_PRIOR_IN_SWEEP).
  *
  * Conventions shared by every call:
  *   - GF(2^p) in the polynomial basis of a primitive polynomial (bit b of a
@@ -29,9 +30,11 @@
  * errors, and gfbp_last_error() returns a message for the calling thread's
  * last failure.  No C++ exception crosses this interface.
  *
- * Threads and streams: code handles are immutable after gfbp_code_build and
- * may be shared by concurrent decode calls on different streams, each with
- * its own workspace.
+ * Threads and streams: decodes only read a code handle, so one handle may be
+ * shared by concurrent decode calls on different streams, each with its own
+ * workspace; gfbp_code_set_shape and gfbp_tune change the handle and must not
+ * run concurrently with decodes on it.  A session is used by one thread at a
+ * time.
  */
 #ifndef GFBP_H
 #define GFBP_H
@@ -220,7 +223,8 @@ typedef struct {
     int32_t has_syndrome;    /* 1: frames may carry z (else z = 0)                        */
     const float *markov_M;   /* host [q][q], or NULL: no frame uses a Markov prior        */
     const float *markov_pi;  /* host [q] (with markov_M)                                  */
-    int32_t options;         /* GFBP_OPT_*                                                */
+    int32_t options;         /* GFBP_OPT_SUS_STRICT, GFBP_OPT_STEP_GRAPHS (PRIOR_IN_SWEEP:
+                                GFBP_EUNSUPPORTED)                                        */
 } gfbp_session_desc;
 
 /* n frames to admit: device pointers, frame-major, read during the call. */
@@ -249,7 +253,9 @@ gfbp_status gfbp_session_destroy(gfbp_session *session);
  * slots; the caller offers the rest later) and initialises them on stream. */
 gfbp_status gfbp_session_admit(gfbp_session *session, int32_t n, const int64_t *ids, const gfbp_frames *frames,
                                int32_t *n_admitted, void *stream);
-/* Enqueues `iters` iterations of every running slot; no host synchronisation. */
+/* Enqueues `iters` iterations of every running slot; no host synchronisation
+ * (with GFBP_OPT_STEP_GRAPHS, an even `iters` on a non-null stream replays a
+ * captured graph; the first use of a key captures and instantiates it). */
 gfbp_status gfbp_session_step(gfbp_session *session, int32_t iters, void *stream);
 /* Collects up to cap finished frames: out[0..*n_out) and, if xhat (host) is
  * not NULL, their decisions xhat[r][code n]; frees their slots.  Synchronises
