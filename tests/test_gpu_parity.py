@@ -470,6 +470,54 @@ def test_largest_shape_gf64_n8000_sampled(gfbp, schedule):
     assert np.array_equal(it, r["iters"])
 
 
+def _random_irregular_code(rng, q, n, m):
+    """Column degrees 1..5, rows of 2..16 entries, random nonzero coefficients."""
+    while True:
+        cols_of_row = [set() for _ in range(m)]
+        for j in range(n):
+            for i in rng.choice(m, size=int(rng.integers(1, 6)), replace=False):
+                cols_of_row[i].add(j)
+        sizes = [len(r) for r in cols_of_row]
+        if min(sizes) >= 2 and max(sizes) <= 16:
+            break
+    row_ptr = np.zeros(m + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(sizes)
+    col = np.array([c for r in cols_of_row for c in sorted(r)], dtype=np.int32)
+    coef = rng.integers(1, q, size=len(col)).astype(np.uint8)
+    code = wl.Code(q=q, n=n, m=m, row_ptr=row_ptr, col=col, coef=coef)
+    code.n_info = n // 2
+    return code
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_irregular_codes(gfbp, seed):
+    """Seeded random irregular codes (every field, column degrees 1-5, rows up
+    to 16, syndromes z != 0, a random channel, Markov prior or not): messages
+    after 2 iterations and decisions after up to 40, both schedules."""
+    rng = np.random.default_rng([0x12E6, seed])
+    q = int(2 ** (1 + seed % 6))
+    n = int(rng.integers(40, 160))
+    code = _random_irregular_code(rng, q, n, int(n * rng.uniform(0.4, 0.7)))
+    channel, param = [("bsc", 0.04), ("bec", 0.3), ("biawgn", 0.7)][seed % 3]
+    markov = seed % 2 == 1
+    M = wl.self_transition_matrix(q, 0.75) if markov else None
+    if markov and seed % 4 == 3:
+        M = 0.5 * M + 0.5 * rng.dirichlet(np.ones(q), size=q)
+    fr = wl.make_coset_frames(code, 70, 500 + seed, channel, param, source="markov" if markov else "iid", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M)) if markov else {}
+    for sch in ("pus", "sus"):
+        g = _gpu(gfbp, code, fr, sch, max_iter=2, early_stop=False, snap_iter=2, **kw)
+        r = _ref(code, fr, sch, max_iter=2, early_stop=False, snap_iter=2, **kw)
+        for key in ("snap_q", "snap_r", "snap_Q"):
+            err = np.abs(g[key] - r[key]).max()
+            assert err <= MSG_TOL, f"seed {seed} q={q} {sch} {key}: {err:.3g}"
+        g = _gpu(gfbp, code, fr, sch, max_iter=40, **kw)
+        r = _ref(code, fr, sch, max_iter=40, **kw)
+        _compare_decisions(g, r, f"random seed {seed} q={q} n={n} {channel} markov={markov} {sch}",
+                           recheck=lambda idx: _precision_sensitive(code, fr, sch, idx, max_iter=40, **kw),
+                           near_tie=lambda idx, upto: _near_tie(code, fr, sch, idx, upto, **kw))
+
+
 def test_column_without_edges(gfbp):
     """A column in no check: its pseudo-posterior is its channel likelihood
     alone, under every schedule (the sequential step still decides it)."""
