@@ -2,7 +2,8 @@
 
 Every served frame must equal, bitwise, its gfbp_decode_batch result (decoded
 alone with its own channel group and prior), whatever it was batched with;
-converged frames must satisfy their syndrome; every request is answered once.
+converged frames must satisfy their syndrome; every request is answered once;
+a sample of served frames also matches the float64 reference decoder.
 """
 import numpy as np
 import pytest
@@ -86,3 +87,34 @@ def test_pool_frames_are_reused_cyclically(gfbp):
         for k in range(len(cq.ids) - 16):
             a, b = st.results[int(cq.ids[k])], st.results[int(cq.ids[k + 16])]
             assert a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_served_frames_match_the_reference(gfbp, schedule):
+    """Served frames (mixed codes, channels and priors through the Poisson
+    loop) against the float64 reference decoder directly: the same decisions
+    and iteration counts, up to the reference's own logged exception classes."""
+    import oracle
+    from paper_cs_0605069_amd import serving
+    from tests.test_gpu_parity import _compare_decisions, _near_tie, _precision_sensitive
+
+    pool = wl.mixed_pool(3, seed=75, n_range=(256, 600))
+    queues, markov = serving.make_requests(pool, 240, rate=20000.0, seed=76)
+    srv = serving.Server(queues, slots=64, schedule=schedule, max_iter=40, budget_bytes=8 << 30, step_iters=2,
+                         markov=markov, keep_results=True)
+    st = srv.run()
+    assert st.done == 240
+    sch = {"pus": oracle.PUS, "sus": oracle.SUS}[schedule]
+    for cq in queues:
+        M, pi = markov[cq.code.q]
+        for g, m, pos in cq.groups:
+            take = np.arange(min(6, g.F))
+            sub = g.subset(take)
+            kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
+            r = oracle.decode(cq.code, sub, schedule=sch, max_iter=40, **kw)
+            got = [st.results[int(cq.ids[pos[f]])] for f in take]
+            gd = {"xhat": np.stack([x for _, _, x in got]), "iters": np.array([i for i, _, _ in got]),
+                  "converged": np.array([c for _, c, _ in got])}
+            _compare_decisions(gd, r, f"served q={cq.code.q} n={cq.code.n} {g.channel} markov={m} {schedule}",
+                               recheck=lambda idx: _precision_sensitive(cq.code, sub, schedule, idx, max_iter=40, **kw),
+                               near_tie=lambda idx, upto: _near_tie(cq.code, sub, schedule, idx, upto, **kw))
