@@ -101,3 +101,30 @@ def test_mn_frames_decode_at_low_noise():
         out = oracle.decode(code, None, schedule=sch, max_iter=50, prior="markov", markov_M=M,
                             markov_pi=wl.stationary(M), likelihoods=fr.lik, syndrome=fr.syndrome)
         assert out["converged"].all() and (out["xhat"] == fr.codeword).all()
+
+
+def test_sigma_from_ebn0_closed_form():
+    """sigma^2 = 1 / (2 R 10^(Eb/N0 / 10)): the benchmark's five points at R = 1/2."""
+    got = [round(wl.sigma_from_ebn0(e, 0.5), 3) for e in (0.8, 1.0, 1.2, 1.4, 1.6)]
+    assert got == [0.912, 0.891, 0.871, 0.851, 0.832]
+    assert wl.sigma_from_ebn0(0.0, 0.5) == 1.0
+
+
+@pytest.mark.parametrize("rate,limit_db", [(1 / 2, 0.187), (1 / 3, -0.495)])
+def test_biawgn_capacity_at_the_bpsk_shannon_limits(rate, limit_db):
+    """The BPSK-input AWGN channel's capacity equals the code rate at the
+    textbook Shannon limits (Eb/N0 = 0.187 dB for R = 1/2, -0.495 dB for
+    R = 1/3), and tends to 1 and 0 at the extremes."""
+    assert abs(wl.biawgn_capacity(wl.sigma_from_ebn0(limit_db, rate)) - rate) < 2e-3
+    assert wl.biawgn_capacity(0.2) > 0.9999 and wl.biawgn_capacity(20.0) < 0.01
+
+
+def test_capacity_matched_channel_parameters():
+    """R20: BSC and BEC parameters with the BI-AWGN capacity at the frame's sigma."""
+    for e in (1.0, 1.5, 2.0):
+        for R in (1 / 3, 1 / 2):
+            C = wl.biawgn_capacity(wl.sigma_from_ebn0(e, R))
+            f = wl.channel_for("bsc", e, R)
+            assert 0 < f < 0.5 and abs(1 - wl.h2(f) - C) < 1e-9
+            assert abs(wl.channel_for("bec", e, R) - (1 - C)) < 1e-12
+            assert wl.channel_for("biawgn", e, R) == wl.sigma_from_ebn0(e, R)
