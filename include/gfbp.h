@@ -198,7 +198,10 @@ size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t sche
  * default stream).  All work is enqueued on the stream; the call returns after
  * the frames have finished (it reads the number of frames still iterating
  * back to the host after every iteration to stop early and to size the next
- * launches).  Results are then complete in the output buffers. */
+ * launches).  Results are then complete in the output buffers.  No device
+ * memory is allocated; a calling thread's first decode allocates 64 bytes of
+ * pinned host memory and four events for the iteration counts, kept for the
+ * life of the thread. */
 gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 
