@@ -35,22 +35,24 @@ def build(verbose: bool = False) -> str:
 class _Code(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("poly", ctypes.c_uint), ("n", ctypes.c_int), ("m", ctypes.c_int),
                 ("n_info", ctypes.c_int), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("coef", ctypes.c_void_p)]
+                ("coef", ctypes.c_void_p), ("visit", ctypes.c_void_p), ("source", ctypes.c_void_p)]
 
 
 class _Batch(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int), ("schedule", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("early_stop", ctypes.c_int), ("channel", ctypes.c_int), ("param", ctypes.c_void_p),
-                ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
-                ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p), ("prior", ctypes.c_int),
-                ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("snap_iter", ctypes.c_int),
-                ("n_threads", ctypes.c_int), ("precision_model", ctypes.c_int), ("prior_in_sweep", ctypes.c_int)]
+                ("early_stop", ctypes.c_int), ("channel", ctypes.c_int), ("evidence", ctypes.c_int),
+                ("param", ctypes.c_void_p), ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p),
+                ("prior", ctypes.c_int), ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p),
+                ("static_P", ctypes.c_void_p), ("static_per_symbol", ctypes.c_int), ("snap_iter", ctypes.c_int),
+                ("n_threads", ctypes.c_int), ("prior_in_sweep", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
     _fields_ = [("xhat", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("converged", ctypes.c_void_p),
                 ("posterior", ctypes.c_void_p), ("snap_q", ctypes.c_void_p), ("snap_r", ctypes.c_void_p),
-                ("snap_Q", ctypes.c_void_p), ("xhat_trace", ctypes.c_void_p), ("guards", ctypes.c_void_p)]
+                ("snap_Q", ctypes.c_void_p), ("xhat_trace", ctypes.c_void_p), ("gap_trace", ctypes.c_void_p),
+                ("guards", ctypes.c_void_p)]
 
 
 def _load():
@@ -68,6 +70,8 @@ def _load():
         lib.ref_markov_prior.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.ref_markov_prior.restype = ctypes.c_int
+        lib.ref_noise_evidence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p]
         lib.ref_frame_likelihoods.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.ref_decode.argtypes = [ctypes.POINTER(_Code), ctypes.POINTER(_Batch), ctypes.POINTER(_Result)]
@@ -93,6 +97,15 @@ def likelihood(p: int, channel: str, param: float, rx: int = 0, er: int = 0, y=N
     out = np.zeros(1 << p, dtype=np.float64)
     yy = None if y is None else np.ascontiguousarray(y, dtype=np.float32)
     _load().ref_likelihood(p, CHANNELS[channel], float(param), int(rx), int(er), _ptr(yy), out.ctypes.data)
+    return out
+
+
+def noise_evidence(p: int, channel: str, param: float, er: int = 0, y=None) -> np.ndarray:
+    """P(noise symbol = a | channel output) of one noise symbol of the
+    MacKay-Neal syndrome form (Section 2)."""
+    out = np.zeros(1 << p, dtype=np.float64)
+    yy = None if y is None else np.ascontiguousarray(y, dtype=np.float32)
+    _load().ref_noise_evidence(p, CHANNELS[channel], float(param), int(er), _ptr(yy), out.ctypes.data)
     return out
 
 
@@ -133,26 +146,31 @@ def max_threads() -> int:
 
 
 def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_stop: bool = True,
-           prior: str = "uniform", markov_M=None, markov_pi=None, snap_iter: int = 0, posterior: bool = False,
-           trace: bool = False, n_threads: int = 0, likelihoods=None, syndrome=None,
-           precision_model: int = 0, prior_in_sweep: bool = False) -> dict:
+           prior: str = "uniform", markov_M=None, markov_pi=None, static_prior=None, snap_iter: int = 0,
+           posterior: bool = False, trace: bool = False, gap_trace: bool = False, n_threads: int = 0,
+           likelihoods=None, syndrome=None, prior_in_sweep: bool = False) -> dict:
     """Decode every frame of ``frames`` (a ``workloads.Frames``) on ``code``.
 
-    ``likelihoods`` [F][n][q] replaces the channel when given.
-    ``prior_in_sweep`` (SUS with the Markov prior): each source symbol's
-    prior is assigned when its column is visited, from the newest
-    pseudo-posteriors of its neighbours, instead of after each iteration.
-    ``precision_model`` is a test instrument (0, the default, is the plain
-    double-precision decoder): 1 rounds every stored vector to float32; 2
-    also drops each r-vector's entries below 4e-16 of its largest (the
-    resolution of a check update computed through a double-precision
-    transform).  Returns a dict
-    of numpy arrays: xhat, iters, converged, guards and, when asked, posterior,
-    snap_q / snap_r / snap_Q (messages after iteration ``snap_iter``) and
-    trace (decisions after each iteration).
+    ``likelihoods`` [F][n][q] replaces the channel when given.  Frames whose
+    ``evidence`` attribute is "mn" are in the MacKay-Neal syndrome form: the
+    source columns carry no channel evidence and every other column is a
+    noise symbol whose evidence comes from the channel output at that column.
+    ``prior``: "uniform", "markov" (``markov_M``, ``markov_pi``) or "static"
+    (``static_prior`` [q], or [n_info][q] in chain order).  The code's
+    optional ``visit_order`` [n] and ``source_cols`` [n_info] attributes set
+    the SUS visiting order and the source chain.  ``prior_in_sweep`` (SUS
+    with the Markov prior): each source symbol's prior is assigned when its
+    column is visited, from the newest pseudo-posteriors of its chain
+    neighbours, instead of after each iteration.  Returns a dict of numpy
+    arrays: xhat, iters, converged, guards and, when asked, posterior,
+    snap_q / snap_r / snap_Q (messages after iteration ``snap_iter``), trace
+    (decisions after each iteration) and gap_trace (after each iteration,
+    the smallest gap over the columns between the two largest
+    pseudo-posterior entries).
     """
     lib = _load()
     q, n, m, E = code.q, code.n, code.m, code.E
+    evidence = 0
     if likelihoods is not None:
         lk = np.ascontiguousarray(likelihoods, dtype=np.float64)
         F = lk.shape[0]
@@ -161,6 +179,7 @@ def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_st
     else:
         F = frames.F
         ch = CHANNELS[frames.channel]
+        evidence = 1 if getattr(frames, "evidence", "symbol") == "mn" else 0
         lk = None
         param = np.ascontiguousarray(frames.param, dtype=np.float64)
         rx = None if frames.rx is None else np.ascontiguousarray(frames.rx, dtype=np.uint8)
@@ -171,10 +190,19 @@ def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_st
     rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
     cl = np.ascontiguousarray(code.col, dtype=np.int32)
     cf = np.ascontiguousarray(code.coef, dtype=np.uint8)
-    Mk = pk = None
+    vo = getattr(code, "visit_order", None)
+    sc = getattr(code, "source_cols", None)
+    vo = None if vo is None else np.ascontiguousarray(vo, dtype=np.int32)
+    sc = None if sc is None else np.ascontiguousarray(sc, dtype=np.int32)
+    Mk = pk = sp = None
+    prior_kind = {"uniform": 0, "markov": 1, "static": 2}[prior]
+    per_symbol = 0
     if prior == "markov":
         Mk = np.ascontiguousarray(markov_M, dtype=np.float64)
         pk = np.ascontiguousarray(markov_pi, dtype=np.float64)
+    elif prior == "static":
+        sp = np.ascontiguousarray(static_prior, dtype=np.float64)
+        per_symbol = int(sp.ndim == 2)
     out = {
         "xhat": np.zeros((F, n), dtype=np.uint8),
         "iters": np.zeros(F, dtype=np.int32),
@@ -189,13 +217,16 @@ def decode(code, frames=None, schedule: int = PUS, max_iter: int = 100, early_st
         out["snap_Q"] = np.zeros((F, n, q))
     if trace:
         out["trace"] = np.zeros((F, max_iter, n), dtype=np.uint8)
-    c = _Code(code.p, code.poly, n, m, code.n_info, rp.ctypes.data, cl.ctypes.data, cf.ctypes.data)
-    b = _Batch(F, schedule, max_iter, int(early_stop), ch, param.ctypes.data, _ptr(rx), _ptr(er), _ptr(y),
-               _ptr(lk), _ptr(syn), 1 if prior == "markov" else 0, _ptr(Mk), _ptr(pk), snap_iter, n_threads,
-               int(precision_model), int(bool(prior_in_sweep)))
+    if gap_trace:
+        out["gap_trace"] = np.full((F, max_iter), np.nan)
+    c = _Code(code.p, code.poly, n, m, code.n_info, rp.ctypes.data, cl.ctypes.data, cf.ctypes.data, _ptr(vo),
+              _ptr(sc))
+    b = _Batch(F, schedule, max_iter, int(early_stop), ch, evidence, param.ctypes.data, _ptr(rx), _ptr(er), _ptr(y),
+               _ptr(lk), _ptr(syn), prior_kind, _ptr(Mk), _ptr(pk), _ptr(sp), per_symbol, snap_iter, n_threads,
+               int(bool(prior_in_sweep)))
     r = _Result(out["xhat"].ctypes.data, out["iters"].ctypes.data, out["converged"].ctypes.data,
                 _ptr(out.get("posterior")), _ptr(out.get("snap_q")), _ptr(out.get("snap_r")),
-                _ptr(out.get("snap_Q")), _ptr(out.get("trace")), out["guards"].ctypes.data)
+                _ptr(out.get("snap_Q")), _ptr(out.get("trace")), _ptr(out.get("gap_trace")), out["guards"].ctypes.data)
     rc = lib.ref_decode(ctypes.byref(c), ctypes.byref(b), ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"ref_decode failed ({rc})")

@@ -17,6 +17,15 @@
  *   ref_likelihood .......... BSC noise prior f^L (1-f)^(p-L) of Section 2,
  *                             taken about the received symbol; BEC and BI-AWGN
  *                             as bit-wise products (Section 3 channels)
+ *   ref_noise_evidence ...... MacKay-Neal syndrome form (Section 2, Eqs. (1),
+ *                             (2)): the decoder sees z = B r and, for each
+ *                             noise symbol, the probability of each noise
+ *                             value given the channel output; for the BSC
+ *                             the paper's noise prior f^L (1-f)^(p-L), for
+ *                             the BEC and BI-AWGN the bit-wise analogues
+ *   static prior ............ Section 2: source symbols carry a prior that is
+ *                             multiplied into their evidence (fixed here; the
+ *                             Markov prior below re-estimates it)
  *   check update ............ Eq. (3): sum, over sibling configurations
  *                             that satisfy check i with x_j = a, of the
  *                             product of sibling q-messages, accumulated one
@@ -36,22 +45,26 @@
  *   - r is left unnormalised, as Eq. (3) states it;
  *   - a zero or non-finite normaliser makes the vector uniform and counts a
  *     guard event;
- *   - the clipping decision is taken on the posterior rounded to float32
- *     (the GPU decoder's precision), ties going to the smallest symbol;
+ *   - the clipping decision is the argmax of the double-precision
+ *     pseudo-posterior, exact ties going to the smallest symbol;
  *   - the iteration count is the first iteration whose decision satisfies
  *     H x = z (max_iter if none);
  *   - Markov priors: iteration 1 uses the stationary marginal pi; after every
- *     iteration that does not end decoding, all information symbols are
- *     refreshed from that iteration's pseudo-posteriors; chain ends use pi on
- *     the left and a vector of ones on the right; the prior is normalised and
- *     multiplied into the channel likelihood;
+ *     iteration that does not end decoding, all source symbols are refreshed
+ *     from that iteration's pseudo-posteriors; chain ends use pi on the left
+ *     and a vector of ones on the right; the prior is normalised and
+ *     multiplied into the channel evidence;
+ *   - the source symbols form a chain in a given order of columns (by
+ *     default columns 0..n_info-1), and SUS visits the columns in a given
+ *     order (by default 0..n-1);
  *   - in SUS the pseudo-posterior is computed after the sweep from the
  *     r-messages of that sweep;
  *   - SUS variant with the prior assigned during the vertical pass (Section
- *     2, priors paragraph): from iteration 2 on, source symbol j takes, when
- *     its column is visited, the Eq. (7) prior from Q_{j-1} of the current
- *     sweep and Q_{j+1} of the previous one (iteration 1 uses pi, as above),
- *     and no refresh follows the iteration.
+ *     2, priors paragraph): from iteration 2 on, source symbol k takes, when
+ *     its column is visited, the Eq. (7) prior from the newest pseudo-
+ *     posteriors of its chain neighbours k-1 and k+1 (of the current sweep
+ *     for a neighbour visited earlier in it, else of the previous sweep;
+ *     iteration 1 uses pi, as above), and no refresh follows the iteration.
  */
 #include <math.h>
 #include <stdint.h>
@@ -147,6 +160,45 @@ void ref_frame_likelihoods(int p, int channel, int F, int n, const double *param
         }
 }
 
+/* MacKay-Neal syndrome form (Section 2): the decoder is given z = B r, r
+ * the received word, so the unknowns are the source symbols and the noise
+ * symbols n = r - t.  N[a] = P(noise symbol = a | channel output) for one
+ * noise symbol.  BSC (param f): the paper's noise prior f^L (1-f)^(p-L), L the
+ * number of ones of a (the BSC flips bits independently of what was sent).
+ * BEC (er: erased-bit mask): an unerased bit was received as sent, so its
+ * noise bit is 0; an erased bit was read as 0, so its noise bit equals the
+ * unknown sent bit, 0 or 1 alike.  BI-AWGN (y[p], sigma): r takes the sign
+ * of y, and the noise bit is 0 when the sent bit has that sign, which has
+ * probability exp(|y|/s2) / (exp(|y|/s2) + exp(-|y|/s2)) for BPSK +-1 in
+ * Gaussian noise of variance s2. */
+void ref_noise_evidence(int p, int channel, double param, int er, const float *y, double *N)
+{
+    const int q = 1 << p;
+    for (int a = 0; a < q; ++a) {
+        if (channel == 0) {
+            int L = 0;
+            for (int b = 0; b < p; ++b) L += (a >> b) & 1;
+            N[a] = pow(param, L) * pow(1.0 - param, p - L);
+        } else if (channel == 1) {
+            double v = 1.0;
+            for (int b = 0; b < p; ++b) {
+                if ((er >> b) & 1) v *= 0.5;
+                else if ((a >> b) & 1) v = 0.0;
+            }
+            N[a] = v;
+        } else {
+            const double s2 = param * param;
+            double v = 1.0;
+            for (int b = 0; b < p; ++b) {
+                const double u = fabs((double)y[b]) / s2;
+                const double same = 1.0 / (1.0 + exp(-2.0 * u));  /* noise bit 0 */
+                v *= ((a >> b) & 1) ? 1.0 - same : same;
+            }
+            N[a] = v;
+        }
+    }
+}
+
 /* Eq. (3) for edge d of a check with dc edges (coefficients h, syndrome z),
  * from the q-messages qin[dc][q]: sum over configurations of the other dc-1
  * symbols such that  h_d a + sum_{d' != d} h_d' x_d' = z.  The sum is taken
@@ -193,26 +245,29 @@ static int normalise(double *v, int q)
 
 /* Eq. (7) for source symbol k of a chain of K: P_k(b) is proportional to
  * [sum_a Q_{k-1}(a) M(a,b)] [sum_c M(b,c) Q_{k+1}(c)], with pi in place of the
- * left factor at k = 0 and 1 in place of the right factor at k = K-1.  Q holds
- * the pseudo-posteriors of the chain, [K][q]. */
-static int markov_prior_at(int q, int K, int k, const double *Q, const double *M, const double *pi, double *Pk)
+ * left factor at k = 0 (Qprev NULL) and 1 in place of the right factor at
+ * k = K-1 (Qnext NULL). */
+static int markov_prior_at(int q, const double *Qprev, const double *Qnext, const double *M, const double *pi,
+                           double *Pk)
 {
     for (int b = 0; b < q; ++b) {
         double u = 0.0, v = 0.0;
-        if (k == 0) u = pi[b];
-        else for (int a = 0; a < q; ++a) u += Q[(size_t)(k - 1) * q + a] * M[a * q + b];
-        if (k == K - 1) v = 1.0;
-        else for (int c = 0; c < q; ++c) v += M[b * q + c] * Q[(size_t)(k + 1) * q + c];
+        if (!Qprev) u = pi[b];
+        else for (int a = 0; a < q; ++a) u += Qprev[a] * M[a * q + b];
+        if (!Qnext) v = 1.0;
+        else for (int c = 0; c < q; ++c) v += M[b * q + c] * Qnext[c];
         Pk[b] = u * v;
     }
     return normalise(Pk, q);
 }
 
-/* Eq. (7) for every source symbol, all from the same Q */
+/* Eq. (7) for every source symbol of a chain, all from the same Q [K][q] */
 int ref_markov_prior(int q, int K, const double *Q, const double *M, const double *pi, double *P)
 {
     int guards = 0;
-    for (int k = 0; k < K; ++k) guards += markov_prior_at(q, K, k, Q, M, pi, P + (size_t)k * q);
+    for (int k = 0; k < K; ++k)
+        guards += markov_prior_at(q, k > 0 ? Q + (size_t)(k - 1) * q : NULL, k < K - 1 ? Q + (size_t)(k + 1) * q : NULL,
+                                  M, pi, P + (size_t)k * q);
     return guards;
 }
 
@@ -225,6 +280,8 @@ typedef struct {
     const int32_t *row_ptr;   /* [m+1] */
     const int32_t *col;       /* [E] column of each edge; edges numbered row by row */
     const uint8_t *coef;      /* [E] nonzero coefficient of each edge */
+    const int32_t *visit;     /* [n] order in which SUS visits the columns, or NULL for 0..n-1 */
+    const int32_t *source;    /* [n_info] columns of the source symbols in chain order, or NULL for 0..n_info-1 */
 } ref_code;
 
 typedef struct {
@@ -233,26 +290,24 @@ typedef struct {
     int max_iter;
     int early_stop;           /* 0: always run max_iter iterations */
     int channel;              /* 0 BSC, 1 BEC, 2 BI-AWGN, 3 given likelihoods */
+    int evidence;             /* 0: the channel output of every column is about that column's symbol;
+                                 1: MacKay-Neal syndrome form, source columns carry no channel
+                                 evidence and every other column is a noise symbol (ref_noise_evidence) */
     const double *param;      /* [F] f, eps or sigma */
     const uint8_t *rx;        /* [F][n] */
     const uint8_t *erasure;   /* [F][n] */
     const float *y;           /* [F][n][p] */
     const double *likelihood; /* [F][n][q] */
     const uint8_t *syndrome;  /* [F][m] or NULL for z = 0 */
-    int prior;                /* 0 uniform, 1 Markov over columns 0..n_info-1 */
+    int prior;                /* 0 uniform, 1 Markov, 2 static, over the source symbols */
     const double *markov_M;   /* [q][q] row-stochastic, M[a][b] = P(next b | a) */
     const double *markov_pi;  /* [q] */
+    const double *static_P;   /* [q], or [n_info][q] in chain order when static_per_symbol */
+    int static_per_symbol;
     int snap_iter;            /* 1-based iteration after which messages are copied out; 0 = none */
     int n_threads;            /* 0 = OpenMP default */
-    int precision_model;      /* test instrument, 0 (normal): full double precision.
-                                 1: every stored vector (q, r, Q, p) rounded to float32 after it
-                                 is computed (a decoder keeping its messages in float32);
-                                 2: as 1, and entries of each r-vector below 4e-16 of its largest
-                                 entry set to 0 (the resolution of an Eq. (3) evaluated through a
-                                 double-precision transform, whose small outputs are differences
-                                 of order-one terms) */
     int prior_in_sweep;       /* SUS with the Markov prior: 0, priors refreshed after each
-                                 iteration; 1, refreshed during the sweep (see decode_frame) */
+                                 iteration; 1, assigned during the sweep (see decode_frame) */
 } ref_batch;
 
 typedef struct {
@@ -264,6 +319,8 @@ typedef struct {
     double *snap_r;           /* [F][E][q] or NULL */
     double *snap_Q;           /* [F][n][q] or NULL */
     uint8_t *xhat_trace;      /* [F][max_iter][n] or NULL: decision after each iteration */
+    double *gap_trace;        /* [F][max_iter] or NULL: after each iteration, the smallest gap over
+                                 the columns between the two largest pseudo-posterior entries */
     int32_t *guards;          /* [F] or NULL */
 } ref_result;
 
@@ -271,16 +328,31 @@ typedef struct {
     int *col_ptr;             /* [n+1] */
     int *col_edge;            /* [E] edges of each column, increasing edge id */
     int *edge_row;            /* [E] */
+    int *visit;               /* [n] SUS visiting order */
+    int *source;              /* [K] source columns in chain order */
+    int *chain;               /* [n] chain position of a source column, -1 for the others */
 } ref_graph;
+
+static void graph_free(ref_graph *G)
+{
+    free(G->col_ptr); free(G->col_edge); free(G->edge_row); free(G->visit); free(G->source); free(G->chain);
+}
 
 static int graph_build(const ref_code *C, ref_graph *G)
 {
-    const int n = C->n, m = C->m, E = C->row_ptr[m];
+    const int n = C->n, m = C->m, E = C->row_ptr[m], K = C->n_info;
+    memset(G, 0, sizeof *G);
     G->col_ptr = (int *)calloc((size_t)n + 1, sizeof(int));
     G->col_edge = (int *)malloc(sizeof(int) * (size_t)(E > 0 ? E : 1));
     G->edge_row = (int *)malloc(sizeof(int) * (size_t)(E > 0 ? E : 1));
+    G->visit = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    G->source = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    G->chain = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
     int *fill = (int *)calloc((size_t)n + 1, sizeof(int));
-    if (!G->col_ptr || !G->col_edge || !G->edge_row || !fill) { free(fill); return -1; }
+    if (!G->col_ptr || !G->col_edge || !G->edge_row || !G->visit || !G->source || !G->chain || !fill) {
+        free(fill);
+        return -1;
+    }
     for (int e = 0; e < E; ++e) G->col_ptr[C->col[e] + 1]++;
     for (int j = 0; j < n; ++j) G->col_ptr[j + 1] += G->col_ptr[j];
     for (int i = 0; i < m; ++i)
@@ -289,29 +361,23 @@ static int graph_build(const ref_code *C, ref_graph *G)
             const int j = C->col[e];
             G->col_edge[G->col_ptr[j] + fill[j]++] = e;
         }
+    /* the visiting order and the chain must be permutations / distinct columns */
+    memset(fill, 0, sizeof(int) * ((size_t)n + 1));
+    for (int t = 0; t < n; ++t) {
+        const int j = C->visit ? C->visit[t] : t;
+        if (j < 0 || j >= n || fill[j]) { free(fill); return -3; }
+        fill[j] = 1;
+        G->visit[t] = j;
+    }
+    for (int j = 0; j < n; ++j) G->chain[j] = -1;
+    for (int k = 0; k < K; ++k) {
+        const int j = C->source ? C->source[k] : k;
+        if (j < 0 || j >= n || G->chain[j] >= 0) { free(fill); return -3; }
+        G->source[k] = j;
+        G->chain[j] = k;
+    }
     free(fill);
     return 0;
-}
-
-static void graph_free(ref_graph *G)
-{
-    free(G->col_ptr); free(G->col_edge); free(G->edge_row);
-}
-
-/* v[0..q) rounded to float32 when asked (see precision_model) */
-static void round32(double *v, int q, int on)
-{
-    if (on)
-        for (int a = 0; a < q; ++a) v[a] = (double)(float)v[a];
-}
-
-/* entries of v[0..q) below 4e-16 of the largest set to 0 when asked (see precision_model) */
-static void floor_rel(double *v, int q, int on)
-{
-    if (!on) return;
-    double mx = 0;
-    for (int a = 0; a < q; ++a) mx = v[a] > mx ? v[a] : mx;
-    for (int a = 0; a < q; ++a) if (v[a] < mx * 4.0e-16) v[a] = 0.0;
 }
 
 /* r-message of edge e from the current q-messages of its siblings */
@@ -355,15 +421,25 @@ static int posterior(int q, const ref_graph *G, int j, const double *pj, const d
     return normalise(out, q);
 }
 
+/* the decision for one column: the symbol of largest pseudo-posterior, the
+ * smallest such symbol when several share the maximum exactly */
 static int clip(const double *Qj, int q)
 {
     int best = 0;
-    float bv = (float)Qj[0];
-    for (int a = 1; a < q; ++a) {
-        const float v = (float)Qj[a];
-        if (v > bv) { bv = v; best = a; }
-    }
+    for (int a = 1; a < q; ++a)
+        if (Qj[a] > Qj[best]) best = a;
     return best;
+}
+
+/* gap between the two largest entries of Qj */
+static double top_gap(const double *Qj, int q)
+{
+    double m1 = -1.0, m2 = -1.0;
+    for (int a = 0; a < q; ++a) {
+        if (Qj[a] > m1) { m2 = m1; m1 = Qj[a]; }
+        else if (Qj[a] > m2) m2 = Qj[a];
+    }
+    return m1 - m2;
 }
 
 static int satisfied(const ref_field *F, const ref_code *C, const uint8_t *z, const uint8_t *x)
@@ -376,11 +452,29 @@ static int satisfied(const ref_field *F, const ref_code *C, const uint8_t *z, co
     return 1;
 }
 
+/* Eq. (7) prior of chain symbol k from the current pseudo-posteriors of its
+ * chain neighbours (columns G->source[k-1], G->source[k+1]) */
+static int markov_prior_of(int q, int K, const ref_graph *G, int k, const double *Q, const double *M,
+                           const double *pi, double *Pk)
+{
+    const double *prev = k > 0 ? Q + (size_t)G->source[k - 1] * q : NULL;
+    const double *next = k < K - 1 ? Q + (size_t)G->source[k + 1] * q : NULL;
+    return markov_prior_at(q, prev, next, M, pi, Pk);
+}
+
+/* p_j = norm(L_j * P_k) for the source symbol k at column j */
+static int source_prior(int q, const double *Lj, const double *Pk, double *pj)
+{
+    for (int a = 0; a < q; ++a) pj[a] = Lj[a] * Pk[a];
+    return normalise(pj, q);
+}
+
 static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph *G, const ref_batch *B,
                          int f, ref_result *R)
 {
     const int q = F->q, p = F->p, n = C->n, E = C->row_ptr[C->m], K = C->n_info;
     const int markov = (B->prior == 1) && K > 0;
+    const int prior_on = (B->prior == 1 || B->prior == 2) && K > 0;
     const int in_sweep = markov && B->schedule == 1 && B->prior_in_sweep;
     double *L = (double *)malloc(sizeof(double) * (size_t)n * q);
     double *pj = (double *)malloc(sizeof(double) * (size_t)n * q);
@@ -394,78 +488,84 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
     const uint8_t *z = B->syndrome ? B->syndrome + (size_t)f * C->m : NULL;
     int guards = 0;
 
-    /* channel likelihoods and priors for iteration 1 */
+    /* evidence of every column */
     for (int j = 0; j < n; ++j) {
         double *Lj = L + (size_t)j * q;
+        const size_t fj = (size_t)f * n + j;
         if (B->channel == 3) {
-            for (int a = 0; a < q; ++a) Lj[a] = B->likelihood[((size_t)f * n + j) * q + a];
+            for (int a = 0; a < q; ++a) Lj[a] = B->likelihood[fj * q + a];
+        } else if (B->evidence == 1) {
+            if (G->chain[j] >= 0) {
+                for (int a = 0; a < q; ++a) Lj[a] = 1.0;  /* a source symbol: no channel evidence */
+            } else {
+                ref_noise_evidence(p, B->channel, B->param[f], B->erasure ? B->erasure[fj] : 0,
+                                   B->y ? B->y + fj * p : NULL, Lj);
+            }
         } else {
-            const int rx = B->rx ? B->rx[(size_t)f * n + j] : 0;
-            const int er = B->erasure ? B->erasure[(size_t)f * n + j] : 0;
-            const float *yj = B->y ? B->y + ((size_t)f * n + j) * p : NULL;
-            ref_likelihood(p, B->channel, B->param[f], rx, er, yj, Lj);
+            ref_likelihood(p, B->channel, B->param[f], B->rx ? B->rx[fj] : 0, B->erasure ? B->erasure[fj] : 0,
+                           B->y ? B->y + fj * p : NULL, Lj);
         }
     }
-    if (markov)
-        for (int k = 0; k < K; ++k) memcpy(Pk + (size_t)k * q, B->markov_pi, sizeof(double) * (size_t)q);
+    /* the source symbols' priors for iteration 1: pi (Markov) or the static prior */
+    if (prior_on)
+        for (int k = 0; k < K; ++k) {
+            const double *src = B->prior == 1 ? B->markov_pi
+                                              : B->static_P + (B->static_per_symbol ? (size_t)k * q : 0);
+            memcpy(Pk + (size_t)k * q, src, sizeof(double) * (size_t)q);
+        }
     for (int j = 0; j < n; ++j) {
-        for (int a = 0; a < q; ++a)
-            pj[(size_t)j * q + a] = L[(size_t)j * q + a] * ((markov && j < K) ? Pk[(size_t)j * q + a] : 1.0);
-        guards += normalise(pj + (size_t)j * q, q);
-        round32(pj + (size_t)j * q, q, B->precision_model >= 1);
+        const int k = G->chain[j];
+        if (prior_on && k >= 0) {
+            guards += source_prior(q, L + (size_t)j * q, Pk + (size_t)k * q, pj + (size_t)j * q);
+        } else {
+            memcpy(pj + (size_t)j * q, L + (size_t)j * q, sizeof(double) * (size_t)q);
+            guards += normalise(pj + (size_t)j * q, q);
+        }
     }
     for (int e = 0; e < E; ++e) memcpy(qm + (size_t)e * q, pj + (size_t)C->col[e] * q, sizeof(double) * (size_t)q);
 
     int first_ok = 0, last_ok = 0;
     for (int t = 1; t <= B->max_iter; ++t) {
-        const int r32 = B->precision_model >= 1, floor_r = B->precision_model == 2;
         if (B->schedule == 0) {
-            for (int e = 0; e < E; ++e) {
-                update_r(F, C, G, z, qm, rm, e, sq, sh);
-                floor_rel(rm + (size_t)e * q, q, floor_r);
-                round32(rm + (size_t)e * q, q, r32);
-            }
+            for (int e = 0; e < E; ++e) update_r(F, C, G, z, qm, rm, e, sq, sh);
             for (int j = 0; j < n; ++j)
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
                     guards += update_q(q, G, j, G->col_edge[s], pj, rm, qm);
-                    round32(qm + (size_t)G->col_edge[s] * q, q, r32);
-                }
         } else {
-            for (int j = 0; j < n; ++j) {
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
+            for (int v = 0; v < n; ++v) {
+                const int j = G->visit[v];
+                const int k = G->chain[j];
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
                     update_r(F, C, G, z, qm, rm, G->col_edge[s], sq, sh);
-                    floor_rel(rm + (size_t)G->col_edge[s] * q, q, floor_r);
-                    round32(rm + (size_t)G->col_edge[s] * q, q, r32);
-                }
-                if (in_sweep && j < K && t >= 2) {
-                    /* the prior of source symbol j, assigned at its vertical
+                if (in_sweep && k >= 0 && t >= 2) {
+                    /* the prior of source symbol k, assigned at its vertical
                      * pass from the newest pseudo-posteriors of its chain
-                     * neighbours: Q_{j-1} of this sweep, Q_{j+1} of the last */
-                    double *Pj = Pk + (size_t)j * q;
-                    guards += markov_prior_at(q, K, j, Q, B->markov_M, B->markov_pi, Pj);
-                    for (int a = 0; a < q; ++a) pj[(size_t)j * q + a] = L[(size_t)j * q + a] * Pj[a];
-                    guards += normalise(pj + (size_t)j * q, q);
-                    round32(pj + (size_t)j * q, q, B->precision_model >= 1);
+                     * neighbours (of this sweep if visited already, else of
+                     * the last) */
+                    guards += markov_prior_of(q, K, G, k, Q, B->markov_M, B->markov_pi, Pk + (size_t)k * q);
+                    guards += source_prior(q, L + (size_t)j * q, Pk + (size_t)k * q, pj + (size_t)j * q);
                 }
-                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s) {
+                for (int s = G->col_ptr[j]; s < G->col_ptr[j + 1]; ++s)
                     guards += update_q(q, G, j, G->col_edge[s], pj, rm, qm);
-                    round32(qm + (size_t)G->col_edge[s] * q, q, r32);
-                }
-                if (in_sweep && j < K) {
-                    /* Q_j now, for the next symbol's prior (the same value the
-                     * pass after the sweep computes: neither p_j nor the r of
-                     * column j change later in the sweep) */
+                if (in_sweep && k >= 0) {
+                    /* Q_j now, for its chain neighbours' priors (the same value
+                     * the pass after the sweep computes: neither p_j nor the r
+                     * of column j change later in the sweep) */
                     (void)posterior(q, G, j, pj, rm, Q);
-                    round32(Q + (size_t)j * q, q, r32);
                 }
             }
         }
+        double gap = 2.0;
         for (int j = 0; j < n; ++j) {
             guards += posterior(q, G, j, pj, rm, Q);
-            round32(Q + (size_t)j * q, q, r32);
             x[j] = (uint8_t)clip(Q + (size_t)j * q, q);
+            if (R->gap_trace) {
+                const double g = top_gap(Q + (size_t)j * q, q);
+                gap = g < gap ? g : gap;
+            }
         }
         if (R->xhat_trace) memcpy(R->xhat_trace + ((size_t)f * B->max_iter + (t - 1)) * n, x, (size_t)n);
+        if (R->gap_trace) R->gap_trace[(size_t)f * B->max_iter + (t - 1)] = gap;
         if (t == B->snap_iter) {
             if (R->snap_q) memcpy(R->snap_q + (size_t)f * E * q, qm, sizeof(double) * (size_t)E * q);
             if (R->snap_r) memcpy(R->snap_r + (size_t)f * E * q, rm, sizeof(double) * (size_t)E * q);
@@ -476,11 +576,12 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
         if (last_ok && B->early_stop) break;
         if (t == B->max_iter) break;
         if (markov && !in_sweep) {
-            guards += ref_markov_prior(q, K, Q, B->markov_M, B->markov_pi, Pk);
+            /* Eq. (7) for every source symbol from this iteration's Q */
+            for (int k = 0; k < K; ++k)
+                guards += markov_prior_of(q, K, G, k, Q, B->markov_M, B->markov_pi, Pk + (size_t)k * q);
             for (int k = 0; k < K; ++k) {
-                for (int a = 0; a < q; ++a) pj[(size_t)k * q + a] = L[(size_t)k * q + a] * Pk[(size_t)k * q + a];
-                guards += normalise(pj + (size_t)k * q, q);
-                round32(pj + (size_t)k * q, q, B->precision_model >= 1);
+                const int j = G->source[k];
+                guards += source_prior(q, L + (size_t)j * q, Pk + (size_t)k * q, pj + (size_t)j * q);
             }
         }
     }
@@ -495,10 +596,15 @@ static void decode_frame(const ref_field *F, const ref_code *C, const ref_graph 
 int ref_decode(const ref_code *C, const ref_batch *B, ref_result *R)
 {
     if (C->p < 1 || C->p > 6 || B->n_frames < 0 || B->max_iter < 1) return -1;
+    if (B->prior < 0 || B->prior > 2 || (B->prior == 1 && (!B->markov_M || !B->markov_pi)) ||
+        (B->prior == 2 && !B->static_P))
+        return -1;
+    if (B->evidence == 1 && B->channel == 3) return -1;
     ref_field F;
     field_init(&F, C->p, C->poly);
     ref_graph G;
-    if (graph_build(C, &G)) { graph_free(&G); return -2; }
+    const int gs = graph_build(C, &G);
+    if (gs) { graph_free(&G); return gs == -3 ? -3 : -2; }
 #ifdef _OPENMP
     if (B->n_threads > 0) omp_set_num_threads(B->n_threads);
 #pragma omp parallel for schedule(dynamic, 1)

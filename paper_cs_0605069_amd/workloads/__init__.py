@@ -117,6 +117,8 @@ class Code:
     n_info: int = 0
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    visit_order: np.ndarray | None = None  # int32 [n]: SUS visiting order (None: 0..n-1)
+    source_cols: np.ndarray | None = None  # int32 [n_info]: source chain's columns (None: 0..n_info-1)
 
     def __post_init__(self):
         if self.poly == 0:
@@ -393,6 +395,11 @@ class Frames:
     y: np.ndarray | None = None  # float32 [F][n][p]
     syndrome: np.ndarray | None = None  # uint8 [F][m] (None means z = 0)
     lik: np.ndarray | None = None  # float32 [F][n][q] per-symbol likelihoods (channel "likelihood")
+    # "symbol": the channel output at column j is about symbol x_j; "mn": the
+    # MacKay-Neal syndrome form, where the output at a noise column j is the
+    # received bit pattern of a transmitted symbol whose noise is x_j, and
+    # source columns carry no channel output (their entries are 0)
+    evidence: str = "symbol"
 
     @property
     def F(self) -> int:
@@ -401,7 +408,7 @@ class Frames:
     def subset(self, idx) -> "Frames":
         g = lambda a: None if a is None else np.ascontiguousarray(a[idx])
         return Frames(self.channel, self.param[idx].copy(), g(self.codeword), g(self.rx), g(self.erasure),
-                      g(self.y), g(self.syndrome), g(self.lik))
+                      g(self.y), g(self.syndrome), g(self.lik), self.evidence)
 
 
 def make_frames(code: Code, enc: Encoder, F: int, seed: int, channel: str, param,
@@ -602,14 +609,16 @@ def lift_binary_chain(M2: np.ndarray, p: int) -> tuple[np.ndarray, np.ndarray]:
 
 def make_mn_frames(code: Code, F: int, seed: int, channel: str, param, source: str = "iid",
                    markov: np.ndarray | None = None, start: np.ndarray | None = None) -> Frames:
-    """Frames of the MN syndrome form: sources s [F][N] (i.i.d. uniform or a
-    Markov chain with transition matrix `markov` from `start`), t = B^-1 A s
-    sent over the channel, r the received word (hard decisions for BI-AWGN,
-    erased bits set to 0 for the BEC), z = B r = A s + B n (Eq. (2)) with
-    n = r - t.  The decoder sees z and per-symbol likelihoods: uniform for the
-    source columns (their prior is the source model) and, for noise column
-    j, the probability of each noise symbol given the channel output (for the
-    BSC the paper's f^L (1-f)^(p-L)).  `codeword` holds the true x = (s, n)."""
+    """Frames of the MN syndrome form (Section 2, Eqs. (1)-(2)): sources s
+    [F][N] (i.i.d. uniform or a Markov chain with transition matrix `markov`
+    from `start`), t = B^-1 A s sent over the channel, r the received word
+    (hard decisions for BI-AWGN, erased bits read as 0 for the BEC), and
+    z = B r = A s + B n with n = r - t.  The frames hold only what the
+    receiver has: z and the channel outputs, placed at the noise columns
+    N..N+M-1 (rx = r, erasure masks, y); source columns have no channel output
+    and hold zeros.  Turning the outputs into evidence about the noise symbols
+    is the decoder's work (``evidence = "mn"``).  `codeword` holds the true
+    x = (s, n)."""
     N, M, q, p = code.meta["N"], code.meta["M"], code.q, code.p
     if source == "iid":
         s = iid_source(F, N, q, seed)
@@ -617,33 +626,26 @@ def make_mn_frames(code: Code, F: int, seed: int, channel: str, param, source: s
         s = markov_source(F, N, markov, stationary(markov) if start is None else start, seed)
     t = mn_encode(code, s)
     prm = np.broadcast_to(np.asarray(param, dtype=np.float64), (F,)).copy()
-    a_bits = ((np.arange(q)[:, None] >> np.arange(p)[None, :]) & 1).astype(np.float64)  # [q][p]
+    rx = np.zeros((F, N + M), dtype=np.uint8)
+    er = y = None
     if channel == "bsc":
         r = bsc(t, p, prm, seed)
-        f = prm[:, None, None, None]
-        pbit = np.where(a_bits[None, None] == 1, f, 1.0 - f)  # [F][1][q][p]
-        lik = np.broadcast_to(pbit.prod(axis=3), (F, M, q))
     elif channel == "bec":
-        r, er = bec(t, p, prm, seed)
-        erb = symbol_bits(er, p).astype(bool)[:, :, None, :]  # [F][M][1][p]
-        pbit = np.where(erb, 0.5, np.where(a_bits[None, None] == 1, 0.0, 1.0))
-        lik = pbit.prod(axis=3)
+        r, e = bec(t, p, prm, seed)
+        er = np.zeros((F, N + M), dtype=np.uint8)
+        er[:, N:] = e
     elif channel == "biawgn":
-        y = biawgn(t, p, prm, seed).astype(np.float64)
-        r = pack_bits(y < 0)
-        sg = prm[:, None, None]
-        p0 = 1.0 / (1.0 + np.exp(-2.0 * np.abs(y) / sg ** 2))  # [F][M][p]: noise bit 0
-        pbit = np.where(a_bits[None, None] == 1, (1.0 - p0)[:, :, None, :], p0[:, :, None, :])
-        lik = pbit.prod(axis=3)
+        yt = biawgn(t, p, prm, seed)
+        r = pack_bits(yt < 0)
+        y = np.zeros((F, N + M, p), dtype=np.float32)
+        y[:, N:] = yt
     else:
         raise ValueError(channel)
     r = r.astype(np.uint8)
+    rx[:, N:] = r
     n = (r ^ t).astype(np.uint8)
     x = np.concatenate([s, n], axis=1)
-    L = np.empty((F, N + M, q), dtype=np.float32)
-    L[:, :N] = 1.0 / q
-    L[:, N:] = lik / lik.sum(axis=2, keepdims=True)
     z = syndromes(code, np.concatenate([np.zeros_like(s), r], axis=1))
-    fr = Frames("likelihood", prm, x, lik=L)
+    fr = Frames(channel, prm, x, rx=rx, erasure=er, y=y, evidence="mn")
     fr.syndrome = z
     return fr

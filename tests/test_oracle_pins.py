@@ -564,22 +564,275 @@ def test_sequential_schedule_needs_fewer_iterations():
     assert sus["iters"][both].mean() < 0.85 * pus["iters"][both].mean()
 
 
-def test_precision_instrument_is_off_by_default_and_models_what_it_says():
-    """The reference's precision model (a test instrument for classifying
-    GPU/reference differences) leaves the default decoder untouched; model 1
-    keeps every stored vector in float32, model 2 also zeroes r entries below
-    4e-16 of each r-vector's largest."""
-    code, enc = wl.regular_code(96, 3, 6, 8, seed=41)
-    fr = wl.make_frames(code, enc, 6, 42, "bsc", 0.12)
-    base = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3)
-    m0 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=0)
-    for k in ("snap_q", "snap_r", "snap_Q", "xhat"):
-        assert np.array_equal(base[k], m0[k])
-    m1 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=1)
-    for k in ("snap_q", "snap_r", "snap_Q"):
-        assert np.array_equal(m1[k], m1[k].astype(np.float32).astype(np.float64))  # float32 values
-        assert np.abs(m1[k] - base[k]).max() < 1e-5
-    m2 = oracle.decode(code, fr, schedule=oracle.PUS, max_iter=3, early_stop=False, snap_iter=3, precision_model=2)
-    r = m2["snap_r"]
-    mx = r.max(axis=2, keepdims=True)
-    assert ((r == 0) | (r >= mx * 4e-16 * (1 - 1e-7))).all()
+# ------------------------------------------------------------------ guards and clipping
+def _isolated_code(q, n_extra=0):
+    """Columns 0..1 joined by one check (x0 h0 + x1 h1 = z) and column 2 in
+    no check; ``n_extra`` further columns in no check."""
+    code = _code(q, 3 + n_extra, [[0, 1]], coef_seed=5)
+    return code
+
+
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_zero_evidence_row_becomes_uniform_with_one_guard(schedule):
+    """Reading R13: a column whose evidence is zero for every symbol has no
+    normalisable prior; it is made uniform and one guard event is counted.
+    On a column in no check its pseudo-posterior stays uniform, and the
+    decision is then the smallest symbol (every entry ties)."""
+    q = 4
+    code = _isolated_code(q)
+    L = np.array([[[0.6, 0.2, 0.1, 0.1], [0.1, 0.3, 0.4, 0.2], [0.0, 0.0, 0.0, 0.0]],
+                  [[0.0, 0.0, 0.0, 0.0], [0.1, 0.3, 0.4, 0.2], [0.2, 0.3, 0.4, 0.1]]])
+    out = oracle.decode(code, likelihoods=L, schedule=schedule, max_iter=3, early_stop=False, posterior=True)
+    assert out["guards"].tolist() == [1, 1]
+    np.testing.assert_array_equal(out["posterior"][0, 2], np.full(q, 0.25))
+    assert out["xhat"][0, 2] == 0
+    # a zero row on a column in a check: its prior is uniform, so its
+    # posterior is its check message alone: the other column's evidence
+    # mapped through x0 = h0^-1 (z + h1 x1)
+    h0, h1 = int(code.coef[0]), int(code.coef[1])
+    inv0 = oracle.gf_inv(code.p, code.poly, h0)
+    want = np.zeros(q)
+    for x1 in range(q):
+        want[oracle.gf_mul(code.p, code.poly, inv0, oracle.gf_mul(code.p, code.poly, h1, x1))] += L[1, 1, x1]
+    np.testing.assert_allclose(out["posterior"][1, 0], want / want.sum(), atol=1e-15)
+
+
+@pytest.mark.parametrize("lik,want", [([0.1, 0.4, 0.4, 0.1], 1), ([0.3, 0.2, 0.3, 0.2], 0),
+                                      ([0.2, 0.1, 0.35, 0.35], 2), ([0.25, 0.25, 0.25, 0.25], 0),
+                                      ([0.1, 0.2, 0.3, 0.4], 3)])
+def test_clipping_takes_the_smallest_symbol_among_exact_maxima(lik, want):
+    """Reading R14 on exact ties: a column in no check keeps its prior as
+    its pseudo-posterior, and its decision is the smallest of the symbols
+    sharing the largest value."""
+    q = 4
+    code = _isolated_code(q)
+    L = np.array([[[0.7, 0.1, 0.1, 0.1], [0.7, 0.1, 0.1, 0.1], lik]])
+    for sch in (oracle.PUS, oracle.SUS):
+        out = oracle.decode(code, likelihoods=L, schedule=sch, max_iter=2, early_stop=False, posterior=True)
+        assert out["xhat"][0, 2] == want
+
+
+def test_clipping_tie_through_a_check():
+    """A tie carried through a check: in GF(4) the check x0 + x1 = 0 forces
+    x0 = x1, so with x1 uniform column 0's pseudo-posterior is its own
+    evidence, whose maximum is shared by 1 and 2 (equal inputs through the
+    same arithmetic stay exactly equal): the decision is 1 under both
+    schedules, for both columns."""
+    code = wl.Code(q=4, n=2, m=1, row_ptr=np.array([0, 2], np.int32), col=np.array([0, 1], np.int32),
+                   coef=np.array([1, 1], np.uint8))
+    L = np.array([[[0.05, 0.45, 0.45, 0.05], [0.25, 0.25, 0.25, 0.25]]])
+    for sch in (oracle.PUS, oracle.SUS):
+        out = oracle.decode(code, likelihoods=L, schedule=sch, max_iter=2, early_stop=False, posterior=True)
+        assert out["posterior"][0, 0, 1] == out["posterior"][0, 0, 2]
+        assert out["xhat"][0].tolist() == [1, 1]
+
+
+def test_gap_trace_is_the_smallest_top_two_gap_of_each_iteration(c1_small):
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 3, 44, "bsc", 0.12)
+    g = oracle.decode(code, fr, schedule=oracle.SUS, max_iter=4, early_stop=False, gap_trace=True)["gap_trace"]
+    for t in (1, 2, 4):
+        Q = oracle.decode(code, fr, schedule=oracle.SUS, max_iter=t, early_stop=False, snap_iter=t)["snap_Q"]
+        P = np.sort(Q, axis=2)
+        np.testing.assert_array_equal(g[:, t - 1], (P[:, :, -1] - P[:, :, -2]).min(axis=1))
+
+
+# ------------------------------------------------------------------ MacKay-Neal noise evidence
+@pytest.mark.parametrize("p,f", [(1, 0.11), (2, 0.2), (3, 0.2), (6, 0.155)])
+def test_mn_bsc_noise_evidence_is_the_papers_noise_prior(p, f):
+    """Section 2: for the BSC the noise symbol a has prior f^L (1-f)^(p-L),
+    L the number of ones of a, whatever was received."""
+    N = oracle.noise_evidence(p, "bsc", f)
+    if p == 3 and f == 0.2:  # worked values: 0.8^3, 0.2 * 0.8^2, 0.2^2 * 0.8, 0.2^3
+        assert N[0] == pytest.approx(0.512, rel=1e-14) and N[1] == pytest.approx(0.128, rel=1e-14)
+        assert N[3] == pytest.approx(0.032, rel=1e-14) and N[7] == pytest.approx(0.008, rel=1e-14)
+    for a in range(1 << p):
+        L = bin(a).count("1")
+        assert N[a] == pytest.approx(f ** L * (1 - f) ** (p - L), rel=1e-14)
+    assert N.sum() == pytest.approx(1.0, abs=1e-14)
+
+
+def test_mn_bec_noise_evidence():
+    """A received bit carries no noise; an erased bit (read as 0) carries the
+    unknown sent bit as its noise: 2^-e on the symbols whose unerased bits
+    are 0, for e erased bits, else 0."""
+    p = 3
+    for er in range(8):
+        N = oracle.noise_evidence(p, "bec", 0.4, er=er)
+        e = bin(er).count("1")
+        for a in range(8):
+            assert N[a] == (2.0 ** -e if (a & ~er) == 0 else 0.0)
+
+
+def test_mn_biawgn_noise_evidence_from_gaussian_densities():
+    """P(noise bit 0 | y) is the probability that the sent bit has the sign
+    the receiver decided, from the two Gaussian densities at y: BPSK +1 for
+    bit 0, -1 for bit 1; noise bits independent."""
+    from scipy.stats import norm
+
+    p = 3
+    for sigma in (0.6, 1.0, 1.6):
+        y = np.array([0.9, -0.2, -1.7], dtype=np.float32)
+        N = oracle.noise_evidence(p, "biawgn", sigma, y=y)
+        d0 = norm.pdf(y.astype(np.float64), loc=1.0, scale=sigma)   # density if bit 0 was sent
+        d1 = norm.pdf(y.astype(np.float64), loc=-1.0, scale=sigma)  # if bit 1 was sent
+        decided = (y < 0).astype(int)
+        p_same = np.where(decided == 0, d0, d1) / (d0 + d1)
+        for a in range(8):
+            want = np.prod([p_same[b] if not (a >> b) & 1 else 1 - p_same[b] for b in range(p)])
+            assert N[a] == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.12), ("biawgn", 0.9)])
+def test_mn_noise_evidence_is_calibrated_on_generated_frames(channel, param):
+    """Among generated MN frames, noise symbols to which the evidence gives
+    probability near x occur with frequency near x (binned, five binomial
+    standard deviations): the evidence is the posterior of the noise given
+    the channel output, for the generator's channel."""
+    q, p = 4, 2
+    code = wl.mn_code(40, 120, q, seed=23)
+    fr = wl.make_mn_frames(code, 300, 24, channel, param)
+    N0 = 40
+    probs, hits = [], []
+    for f in range(fr.F):
+        for j in range(N0, code.n):
+            ev = oracle.noise_evidence(p, channel, fr.param[f], y=None if fr.y is None else fr.y[f, j])
+            probs.append(ev)
+            hits.append(np.arange(q) == fr.codeword[f, j])
+    probs, hits = np.array(probs).ravel(), np.array(hits).ravel()
+    edges = np.linspace(0, 1, 11)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (probs >= lo) & (probs < hi)
+        if sel.sum() < 200:
+            continue
+        mean_p = probs[sel].mean()
+        sd = np.sqrt(mean_p * (1 - mean_p) / sel.sum())
+        assert abs(hits[sel].mean() - mean_p) <= 5 * sd + 1e-3, (lo, hi)
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.1), ("bec", 0.45), ("biawgn", 1.0)])
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_mn_evidence_mode_equals_explicit_evidence(channel, param, schedule):
+    """The MN evidence mode gives source columns no channel evidence and each
+    noise column the evidence of its channel output: the same decode as
+    explicit per-column vectors built from the single-symbol routine."""
+    q, p = 4, 2
+    code = wl.mn_code(30, 90, q, seed=25)
+    M, pi = wl.PAPER_MARKOV_4S, wl.stationary(wl.PAPER_MARKOV_4S)
+    fr = wl.make_mn_frames(code, 5, 26, channel, param, source="markov", markov=M)
+    L = np.ones((fr.F, code.n, q))
+    for f in range(fr.F):
+        for j in range(30, code.n):
+            L[f, j] = oracle.noise_evidence(p, channel, fr.param[f], er=0 if fr.erasure is None else fr.erasure[f, j],
+                                            y=None if fr.y is None else fr.y[f, j])
+    kw = dict(schedule=schedule, max_iter=6, early_stop=False, posterior=True, prior="markov", markov_M=M,
+              markov_pi=pi)
+    a = oracle.decode(code, fr, **kw)
+    b = oracle.decode(code, likelihoods=L, syndrome=fr.syndrome, **kw)
+    for k in ("xhat", "iters", "posterior", "guards"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------------ static priors, visiting order, chain order
+@pytest.mark.parametrize("schedule", [oracle.PUS, oracle.SUS])
+def test_static_prior_equals_memoryless_markov_source(c1_small, schedule):
+    """A static prior P on every source symbol is what Eq. (7) gives for a
+    memoryless chain (every row of M equal to P, start P)."""
+    code, enc = c1_small
+    q = code.q
+    P = np.array([0.4, 0.3, 0.2, 0.1])
+    fr = wl.make_frames(code, enc, 4, 45, "bsc", 0.14)
+    kw = dict(schedule=schedule, max_iter=12, early_stop=False, posterior=True)
+    a = oracle.decode(code, fr, prior="static", static_prior=P, **kw)
+    b = oracle.decode(code, fr, prior="markov", markov_M=np.tile(P, (q, 1)), markov_pi=P, **kw)
+    assert np.array_equal(a["xhat"], b["xhat"])
+    np.testing.assert_allclose(a["posterior"], b["posterior"], atol=1e-13)
+
+
+def test_static_prior_per_symbol(c1_small):
+    """A per-symbol static prior P_k multiplies the evidence of source symbol
+    k only (p_j = norm(L_j P_k)); parity columns keep their evidence."""
+    code, enc = c1_small
+    q, K = code.q, code.n_info
+    rng = np.random.default_rng(46)
+    P = rng.dirichlet(np.ones(q), size=K)
+    fr = wl.make_frames(code, enc, 3, 47, "bsc", 0.12)
+    L = _lik(code, fr)
+    Lp = L.copy()
+    Lp[:, :K] *= P
+    for sch in (oracle.PUS, oracle.SUS):
+        a = oracle.decode(code, fr, schedule=sch, max_iter=8, early_stop=False, posterior=True, prior="static",
+                          static_prior=P)
+        b = oracle.decode(code, likelihoods=Lp, schedule=sch, max_iter=8, early_stop=False, posterior=True)
+        np.testing.assert_allclose(a["posterior"], b["posterior"], atol=1e-13)
+
+
+def _relabel(code, perm):
+    """The code with column perm[k] renamed k (edges re-sorted in each row)."""
+    new = np.empty(code.n, dtype=np.int32)
+    new[perm] = np.arange(code.n, dtype=np.int32)
+    col = new[code.col]
+    row = code.row_of_edge()
+    srt = np.lexsort((col, row))
+    return wl.Code(q=code.q, n=code.n, m=code.m, row_ptr=code.row_ptr.copy(), col=col[srt].astype(np.int32),
+                   coef=code.coef[srt].copy(), n_info=code.n_info), srt
+
+
+@pytest.mark.parametrize("tree", range(len(TREES)))
+def test_tree_marginals_are_exact_in_any_visiting_order(tree):
+    """On a cycle-free graph SUS reaches the exact marginals whatever order it
+    visits the columns in."""
+    q, n, rows = TREES[tree]
+    code = _code(q, n, rows, coef_seed=tree)
+    code.visit_order = np.random.default_rng(60 + tree).permutation(n).astype(np.int32)
+    rng = np.random.default_rng(61 + tree)
+    L = rng.random((n, q)) ** 2 + 0.01
+    z = rng.integers(0, q, size=code.m).astype(np.uint8)
+    out = oracle.decode(code, likelihoods=L[None], syndrome=z[None], schedule=oracle.SUS, max_iter=2 * n,
+                        early_stop=False, posterior=True)
+    np.testing.assert_allclose(out["posterior"][0], _exact_marginals(code, L, z), rtol=0, atol=1e-12)
+
+
+def test_visiting_order_equals_relabelled_columns(c1_small):
+    """SUS visiting the columns in an order v equals SUS in column order on
+    the code whose column v[k] is renamed k (inputs renamed alike)."""
+    code, enc = c1_small
+    fr = wl.make_frames(code, enc, 4, 48, "bsc", 0.12)
+    perm = np.random.default_rng(49).permutation(code.n).astype(np.int32)
+    a_code = wl.Code(q=code.q, n=code.n, m=code.m, row_ptr=code.row_ptr, col=code.col, coef=code.coef,
+                     n_info=0, visit_order=perm)
+    b_code, _ = _relabel(code, perm)
+    b_code.n_info = 0
+    L = _lik(code, fr)
+    a = oracle.decode(a_code, likelihoods=L, schedule=oracle.SUS, max_iter=5, early_stop=False, posterior=True)
+    b = oracle.decode(b_code, likelihoods=L[:, perm], schedule=oracle.SUS, max_iter=5, early_stop=False,
+                      posterior=True)
+    np.testing.assert_allclose(a["posterior"][:, perm], b["posterior"], atol=1e-12)
+    assert np.array_equal(a["xhat"][:, perm], b["xhat"])
+    c = oracle.decode(code, likelihoods=L, schedule=oracle.SUS, max_iter=5, early_stop=False, posterior=True)
+    assert np.abs(c["posterior"] - a["posterior"]).max() > 1e-6  # the order matters
+
+
+@pytest.mark.parametrize("schedule,in_sweep", [(oracle.PUS, False), (oracle.SUS, False), (oracle.SUS, True)])
+def test_source_chain_order_equals_relabelled_columns(c1_small, schedule, in_sweep):
+    """A Markov chain over source columns s[0], s[1], ... equals the chain
+    over columns 0, 1, ... of the code whose column s[k] is renamed k (the
+    visiting order renamed alike, so SUS sees the same sequence)."""
+    code, enc = c1_small
+    q, K = code.q, code.n_info
+    M = wl.self_transition_matrix(q, 0.75)
+    pi = wl.stationary(M)
+    fr = wl.make_frames(code, enc, 3, 50, "bsc", 0.13, source="markov", markov=M)
+    rng = np.random.default_rng(51)
+    src = rng.permutation(code.n)[:K].astype(np.int32)
+    rest = np.setdiff1d(np.arange(code.n), src).astype(np.int32)
+    perm = np.concatenate([src, rest])  # new column k = old column perm[k]
+    a_code = wl.Code(q=q, n=code.n, m=code.m, row_ptr=code.row_ptr, col=code.col, coef=code.coef, n_info=K,
+                     source_cols=src, visit_order=perm)
+    b_code, _ = _relabel(code, perm)
+    L = _lik(code, fr)
+    kw = dict(schedule=schedule, max_iter=6, early_stop=False, posterior=True, prior="markov", markov_M=M,
+              markov_pi=pi, prior_in_sweep=in_sweep)
+    a = oracle.decode(a_code, likelihoods=L, **kw)
+    b = oracle.decode(b_code, likelihoods=L[:, perm], **kw)
+    np.testing.assert_allclose(a["posterior"][:, perm], b["posterior"], atol=1e-12)

@@ -57,19 +57,44 @@ def test_mn_code_is_a_then_invertible_b(q):
 
 
 @pytest.mark.parametrize("channel,param", [("bsc", 0.1), ("bec", 0.3), ("biawgn", 0.8)])
-def test_mn_frames_syndrome_and_noise_likelihoods(channel, param):
+def test_mn_frames_hold_only_what_the_receiver_has(channel, param):
+    """z = H (s, n) = B r, and the channel outputs of the transmitted symbols
+    t = B^-1 A s at the noise columns (source columns have none); the noise
+    is what separates r from t."""
     q, p = 8, 3
     code = wl.mn_code(20, 60, q, seed=9)
     fr = wl.make_mn_frames(code, 6, 10, channel, param)
     N = 20
+    assert fr.evidence == "mn" and fr.lik is None
     assert np.array_equal(wl.syndromes(code, fr.codeword), fr.syndrome)  # z = H (s, n)
-    assert np.allclose(fr.lik[:, :N], 1.0 / q) and np.allclose(fr.lik.sum(axis=2), 1.0, atol=1e-6)
-    noise = fr.codeword[:, N:]
-    # the true noise symbol is never excluded by its likelihood
-    assert (np.take_along_axis(fr.lik[:, N:], noise[:, :, None], axis=2) > 0).all()
-    if channel == "bsc":  # the paper's noise prior f^L (1-f)^(p-L), L = ones in a
-        L = np.array([bin(a).count("1") for a in range(q)])
-        assert np.allclose(fr.lik[0, N], param ** L * (1 - param) ** (p - L), rtol=1e-6)
+    s, noise = fr.codeword[:, :N], fr.codeword[:, N:]
+    t = wl.mn_encode(code, s)
+    r = fr.rx[:, N:]
+    assert (fr.rx[:, :N] == 0).all()
+    assert np.array_equal(r ^ t, noise)
+    zr = np.concatenate([np.zeros_like(s), r], axis=1)
+    assert np.array_equal(wl.syndromes(code, zr), fr.syndrome)  # z = B r
+    if channel == "bec":
+        er = fr.erasure[:, N:]
+        assert (fr.erasure[:, :N] == 0).all()
+        assert ((noise & ~er) == 0).all() and ((r & er) == 0).all()  # unerased bits arrive as sent
+    if channel == "biawgn":
+        assert (fr.y[:, :N] == 0).all()
+        assert np.array_equal(r, wl.pack_bits(fr.y[:, N:] < 0))  # hard decisions
+
+
+def test_mn_bsc_noise_follows_the_papers_noise_prior():
+    """The generator's BSC noise symbols have the distribution
+    f^L (1-f)^(p-L) of Section 2 (L = ones in the symbol): empirical
+    frequencies within five binomial standard deviations."""
+    q, p, f = 8, 3, 0.17
+    code = wl.mn_code(30, 90, q, seed=19)
+    fr = wl.make_mn_frames(code, 400, 20, "bsc", f)
+    noise = fr.codeword[:, 30:].ravel()
+    emp = np.bincount(noise, minlength=q) / noise.size
+    L = np.array([bin(a).count("1") for a in range(q)])
+    want = f ** L * (1 - f) ** (p - L)
+    assert (np.abs(emp - want) <= 5 * np.sqrt(want * (1 - want) / noise.size)).all()
 
 
 def test_lifted_binary_chain():
@@ -98,8 +123,8 @@ def test_mn_frames_decode_at_low_noise():
     M = wl.PAPER_MARKOV_4S
     fr = wl.make_mn_frames(code, 8, 13, "bsc", 0.02, source="markov", markov=M)
     for sch in (oracle.PUS, oracle.SUS):
-        out = oracle.decode(code, None, schedule=sch, max_iter=50, prior="markov", markov_M=M,
-                            markov_pi=wl.stationary(M), likelihoods=fr.lik, syndrome=fr.syndrome)
+        out = oracle.decode(code, fr, schedule=sch, max_iter=50, prior="markov", markov_M=M,
+                            markov_pi=wl.stationary(M))
         assert out["converged"].all() and (out["xhat"] == fr.codeword).all()
 
 
