@@ -64,9 +64,30 @@ typedef int32_t gfbp_status;
 #define GFBP_CH_BIAWGN 2     /* y: p samples per symbol; param: noise std sigma   */
 #define GFBP_CH_LIKELIHOOD 3 /* likelihood: P(received | x = a) for every a       */
 
-/* priors of the information symbols (columns 0..n_info-1) */
-#define GFBP_PRIOR_UNIFORM 0 /* i.i.d. uniform source: prior 1/q                  */
-#define GFBP_PRIOR_MARKOV 1  /* first-order Markov source, Eq. (7)           */
+/* priors of the source symbols (Section 2: a source symbol's prior multiplies
+ * its channel evidence; the chain of source symbols is gfbp_code_desc's
+ * source_cols) */
+#define GFBP_PRIOR_UNIFORM 0 /* i.i.d. uniform source: prior 1/q                            */
+#define GFBP_PRIOR_MARKOV 1  /* first-order Markov source: pi at iteration 1, then the
+                                dynamical block prior of Eq. (7) after every iteration   */
+#define GFBP_PRIOR_STATIC 2  /* a fixed prior: one vector for every source symbol, or one
+                                per source symbol (gfbp_batch.static_prior)              */
+
+/* What the channel output of a column is evidence about. */
+#define GFBP_EVIDENCE_SYMBOL 0 /* the symbol x_j itself (codeword sent over the channel)   */
+#define GFBP_EVIDENCE_MN 1     /* MacKay-Neal syndrome form (Section 2, Eqs. (1)-(2)): H = [A B],
+                                  x = (source s, noise n), z = B r for the received word r.
+                                  Source columns carry no channel evidence; every other
+                                  column j is a noise symbol, with evidence
+                                  P(n_j = a | channel output at j):
+                                    BSC: f^w (1-f)^(p-w), w the number of ones of a (the
+                                         paper's noise prior; rx is not read);
+                                    BEC: 2^-e over the a with no one at an unerased bit
+                                         (erased bits were read as 0), else 0;
+                                    BI-AWGN: per bit, noise 0 with probability
+                                         1 / (1 + exp(-2|y|/sigma^2)) (the received bit is
+                                         the sign of y).
+                                  GFBP_CH_LIKELIHOOD is refused with this mode.          */
 
 /* Limits of the decoding kernels. */
 #define GFBP_MAX_Q 64
@@ -82,12 +103,18 @@ typedef struct gfbp_code gfbp_code; /* opaque, device-resident Tanner graph */
 typedef struct {
     int32_t q;               /* field size 2^p, 2 <= q <= 64                        */
     int32_t poly;            /* primitive polynomial incl. x^p (e.g. 0x13 for q=16); 0 = default */
-    int32_t n;               /* columns (code symbols), visited in order 0..n-1 by SUS */
+    int32_t n;               /* columns (code symbols)                                */
     int32_t m;               /* rows (checks)                                        */
-    int32_t n_info;          /* columns 0..n_info-1 are source symbols in chain order */
+    int32_t n_info;          /* number of source symbols (see source_cols)           */
     const int32_t *row_ptr;  /* [m+1], row_ptr[0] = 0, nondecreasing                */
     const int32_t *col;      /* [E] column of each edge, 0 <= col < n, no repeats in a row */
     const uint8_t *coef;     /* [E] nonzero field element of each edge, < q          */
+    const int32_t *visit_order; /* [n] the order in which SUS visits the columns (Section 2,
+                                   SUS steps: column by column), a permutation of 0..n-1;
+                                   NULL = 0..n-1                                          */
+    const int32_t *source_cols; /* [n_info] the columns of the source symbols in chain order
+                                   (the Markov chain of Eq. (7) runs over them), distinct;
+                                   NULL = 0..n_info-1                                     */
 } gfbp_code_desc;
 
 typedef struct {
@@ -99,35 +126,59 @@ typedef struct {
                                     (GFBP_OPT_PRIOR_IN_SWEEP): at least n_info */
 } gfbp_code_info;
 
-/* Build the device-resident graph of a code on the current HIP device.
- * Rejects: null pointers, q not a power of two in [2, 64], a polynomial that
- * is not primitive of degree p, column/coefficient out of range, a column
- * repeated in a row, row degree > GFBP_MAX_ROW_DEGREE, column degree
- * > GFBP_MAX_COL_DEGREE.  Synchronous.  The handle owns its device memory. */
+/* Build the device-resident Tanner graph of the parity-check matrix H of
+ * Section 2 (Eq. (2): H x = z) on the current HIP device, with its SUS
+ * dependency levels.  Rejects: null pointers, q not a power of two in
+ * [2, 64], a polynomial that is not primitive of degree p, column/coefficient
+ * out of range, a column repeated in a row, row degree > GFBP_MAX_ROW_DEGREE,
+ * column degree > GFBP_MAX_COL_DEGREE, a visit_order that is not a
+ * permutation, source_cols out of range or repeated.  Synchronous.  The
+ * library copies every input; the handle owns its device memory and is freed
+ * by gfbp_code_free. */
 gfbp_status gfbp_code_build(const gfbp_code_desc *desc, gfbp_code **out);
 gfbp_status gfbp_code_free(gfbp_code *code);
 gfbp_status gfbp_code_info_get(const gfbp_code *code, gfbp_code_info *out);
 
-/* One batch of frames, all on one code.  All pointers are device memory,
- * frame-major, owned by the caller and only read. */
+/* One batch of frames.  All pointers are device memory owned by the caller
+ * and only read, except code_index (host memory, read during the call).
+ * Frames of one code: arrays are frame-major with the code's sizes ([F][n],
+ * [F][m], ...).  Frames of several codes (n_codes > 1): each frame's entries
+ * follow the previous frame's ("ragged"), with the sizes of the frame's own
+ * code: frame f's rx starts at sum over earlier frames g of n(g), its y at p
+ * times that, its likelihoods at sum of n(g) q(g), its syndrome at sum of
+ * m(g); per-frame scalars (param, channel_of) are [F]. */
 typedef struct {
     int32_t n_frames;        /* F >= 0                                                */
     int32_t schedule;        /* GFBP_PUS or GFBP_SUS                                  */
     int32_t max_iter;        /* >= 1                                                  */
     int32_t early_stop;      /* 1: a frame stops at the first iteration with H x = z;
                                 0: every frame runs max_iter iterations              */
-    int32_t channel;         /* GFBP_CH_*                                             */
-    const float *param;      /* [F] crossover f (BSC) or sigma (BI-AWGN); may be NULL for BEC/LIKELIHOOD */
-    const uint8_t *rx;       /* [F][n] received symbols (BSC, BEC; erased bits 0)     */
-    const uint8_t *erasure;  /* [F][n] erased-bit masks (BEC)                         */
-    const float *y;          /* [F][n][p] channel outputs (BI-AWGN)                   */
-    const float *likelihood; /* [F][n][q] P(received | a) (LIKELIHOOD), need not be normalised */
-    const uint8_t *syndrome; /* [F][m] z, or NULL for z = 0                           */
+    int32_t channel;         /* GFBP_CH_* of every frame (unless channel_of)          */
+    const float *param;      /* [F] crossover f (BSC) or sigma (BI-AWGN); may be NULL when
+                                no frame is BSC or BI-AWGN                            */
+    const uint8_t *rx;       /* received symbols (BSC, BEC; erased bits 0)            */
+    const uint8_t *erasure;  /* erased-bit masks (BEC)                                */
+    const float *y;          /* p channel outputs per symbol (BI-AWGN)                */
+    const float *likelihood; /* q values P(received | a) per symbol (LIKELIHOOD), need not
+                                be normalised                                         */
+    const uint8_t *syndrome; /* z, or NULL for z = 0                                  */
     int32_t prior;           /* GFBP_PRIOR_*                                          */
     const float *markov_M;   /* [q][q] M[a][b] = P(next = b | current = a) (MARKOV)   */
     const float *markov_pi;  /* [q] distribution of the first source symbol (MARKOV)  */
     int32_t options;         /* bit set of GFBP_OPT_*                                 */
     const uint8_t *truth;    /* [F][n] true symbols, for gfbp_result.trace, or NULL   */
+    int32_t evidence;        /* GFBP_EVIDENCE_*                                       */
+    const uint8_t *channel_of; /* [F] channel kind of each frame (GFBP_CH_*), or NULL: every
+                                frame is `channel`.  Read back to the host to check that the
+                                inputs each kind needs are given.                     */
+    const float *static_prior; /* STATIC: [q], or [n_info][q] in chain order           */
+    int32_t static_per_symbol; /* STATIC: 1 if static_prior holds one vector per source symbol */
+    int32_t n_codes;         /* entries of codes[] (0 is taken as 1)                  */
+    const int32_t *code_index; /* HOST [F] code of each frame (index into codes[]), or NULL:
+                                every frame is on codes[0]                            */
+    int32_t persist_el;      /* persistent path: entries per lane (2, 4 or 8 where the degree
+                                class allows; at most q per field), 0 = 4           */
+    int32_t persist_waves;   /* persistent path: wavefronts per workgroup (1..8), 0 = 8 */
 } gfbp_batch;
 
 /* SUS runs, by default, in dependency levels: two columns that share no check
@@ -160,6 +211,21 @@ typedef struct {
  * session. */
 #define GFBP_OPT_STEP_GRAPHS 4
 
+/* Decode through the persistent work-list kernel (always used when the batch
+ * spans several codes): one launch per kernel shape class, sized to fill the
+ * GPU, in which each workgroup takes the next tile of frames of one code from
+ * a device-side list (largest codes first), decodes it through every
+ * iteration to convergence or max_iter (initialisation, the schedule's
+ * sweeps with a workgroup barrier between dependent steps, the H x = z test,
+ * retirement and Markov refreshes all inside the kernel) and writes its
+ * results, then takes the next tile.  No host work between iterations.  One
+ * launch serves every field; codes beyond the small degree class (rows of
+ * more than 6 or columns of more than 4 entries) take a second launch after
+ * the first.  Outputs equal those of the plain decode bitwise.  Not with
+ * posteriors, snapshots, traces or GFBP_OPT_PRIOR_IN_SWEEP
+ * (GFBP_EUNSUPPORTED). */
+#define GFBP_OPT_PERSISTENT 16
+
 /* Batch decode, SUS with the Markov prior: the prior of each source symbol is
  * assigned during the sweep, at its column's vertical pass (Section 2, the
  * paragraph on priors), instead of after each iteration.  From iteration 2 on,
@@ -173,7 +239,8 @@ typedef struct {
 
 /* Outputs, device memory owned by the caller. */
 typedef struct {
-    uint8_t *xhat;           /* [F][n] decision after the frame's last iteration      */
+    uint8_t *xhat;           /* [F][n] (ragged for several codes) decision after the frame's
+                                last iteration                                        */
     int32_t *iters;          /* [F] first iteration with H x = z, else max_iter       */
     uint8_t *converged;      /* [F] 1 if some iteration satisfied H x = z             */
     float *posterior;        /* [F][n][q] final pseudo-posteriors, or NULL            */
@@ -189,20 +256,34 @@ typedef struct {
                                 its last iteration are 0 (the Fig. 1 diagnostic)        */
 } gfbp_result;
 
-/* Bytes of device workspace gfbp_decode_batch needs for F frames. */
+/* Bytes of device workspace gfbp_decode_batch needs for F frames of one code
+ * decoded by the plain kernels. */
 size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t schedule, int32_t prior);
+/* Bytes of device workspace gfbp_decode_batch needs for this batch (any
+ * number of codes, any options); 0 on a bad argument. */
+size_t gfbp_batch_workspace_size(const gfbp_code *const *codes, const gfbp_batch *batch);
 
-/* Decode a batch (Section 2, PUS or SUS; Eq. (7) priors when asked).
- * workspace: device memory of at least gfbp_workspace_size() bytes, 256-byte
- * aligned, owned by the caller, clobbered.  stream: a hipStream_t (NULL =
- * default stream).  All work is enqueued on the stream; the call returns after
- * the frames have finished (it reads the number of frames still iterating
- * back to the host after every iteration to stop early and to size the next
- * launches).  Results are then complete in the output buffers.  No device
- * memory is allocated; a calling thread's first decode allocates 64 bytes of
- * pinned host memory and four events for the iteration counts, kept for the
- * life of the thread. */
-gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gfbp_result *out,
+/* Decode a batch: solve H x = z for every frame by belief propagation
+ * (Section 2: Eq. (3) check-to-variable messages, Eq. (4) variable-to-check
+ * messages, Eq. (5) pseudo-posteriors clipped to the decision, the stopping
+ * test H x = z after each iteration) under the parallel (PUS) or sequential
+ * (SUS) schedule, with the Eq. (7) Markov prior or a static prior on the
+ * source symbols when asked.  codes[0..n_codes): the codes the frames are on
+ * (batch->code_index); with one code the plain kernels run (several launches
+ * per iteration over the frames still iterating), with several the
+ * persistent kernel (GFBP_OPT_PERSISTENT).  workspace: device memory of at
+ * least gfbp_batch_workspace_size() bytes, 256-byte aligned, owned by the
+ * caller, clobbered.  stream: a hipStream_t (NULL = default stream).  All
+ * work is enqueued on the stream; the call returns after the frames have
+ * finished, with the results complete in the output buffers.  No device
+ * memory is allocated; a calling thread's first plain decode allocates 64
+ * bytes of pinned host memory and four events, kept for the life of the
+ * thread.  Errors: EINVAL
+ * for a null or inconsistent argument (a missing input a frame's channel
+ * needs, a code index out of range, LIKELIHOOD with the MN evidence mode),
+ * ESMALL for a small workspace, EUNSUPPORTED for options the path lacks,
+ * EHIP when a HIP call fails. */
+gfbp_status gfbp_decode_batch(const gfbp_code *const *codes, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 
 /* ---- Sessions: continuous batching with resident frame state. ----
@@ -220,7 +301,8 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *batch, gf
 typedef struct gfbp_session gfbp_session;
 
 typedef struct {
-    int32_t n_slots;         /* resident frames (rounded up to a multiple of 64)          */
+    int32_t n_slots;         /* resident frames (rounded up to a multiple of 64); 0: as many
+                                as device_bytes allows (GFBP_ENOMEM if not even 64)        */
     int32_t schedule;        /* GFBP_PUS or GFBP_SUS                                      */
     int32_t max_iter;        /* >= 1                                                      */
     int32_t has_syndrome;    /* 1: frames may carry z (else z = 0)                        */
@@ -228,6 +310,7 @@ typedef struct {
     const float *markov_pi;  /* host [q] (with markov_M)                                  */
     int32_t options;         /* GFBP_OPT_SUS_STRICT, GFBP_OPT_STEP_GRAPHS (PRIOR_IN_SWEEP:
                                 GFBP_EUNSUPPORTED)                                        */
+    int64_t device_bytes;    /* with n_slots = 0: the session's device-memory budget       */
 } gfbp_session_desc;
 
 /* n frames to admit: device pointers, frame-major, read during the call. */
@@ -245,9 +328,16 @@ typedef struct {
     int64_t id;              /* the caller's id of the frame                               */
     int32_t iters;           /* iterations run                                             */
     int32_t converged;       /* 1 if the decision satisfies H x = z                        */
+    uint64_t t_admit;        /* device clock when the frame's state was initialised        */
+    uint64_t t_retire;       /* device clock when the frame finished (retirement kernel)   */
 } gfbp_retired;
 
-/* Device bytes a session would allocate (for admission by memory budget). */
+/* Rate of the device clock of gfbp_retired's timestamps, in ticks per second
+ * (the current device's constant-rate wall clock); 0 on failure. */
+uint64_t gfbp_device_clock_hz(void);
+
+/* Device bytes a session would allocate (for admission by memory budget;
+ * with n_slots = 0, for the slots device_bytes allows). */
 size_t gfbp_session_bytes(const gfbp_code *code, const gfbp_session_desc *desc);
 /* Allocates the session's device memory (synchronous). */
 gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *desc, gfbp_session **out);
@@ -302,6 +392,15 @@ gfbp_status gfbp_code_set_shape(gfbp_code *code, int32_t schedule, int32_t entri
 int32_t gfbp_code_get_shape(const gfbp_code *code, int32_t schedule);
 gfbp_status gfbp_tune(gfbp_code *code, const gfbp_batch *batch, gfbp_result *out, void *workspace, size_t ws_bytes,
                       void *stream, int32_t trial_iters, int32_t *chosen);
+/* The persistent path's tile shape: times trial_iters fixed iterations of the
+ * batch (any codes; outputs overwritten) with entries per lane 4 and 8
+ * (frames per tile 64 x EL / q) and 4 and 8 wavefronts per workgroup (one
+ * warm-up run each, then three rounds keeping each shape's fastest run),
+ * skipping shapes whose workspace exceeds ws_bytes, and returns the fastest in
+ * *el and *waves for batch->persist_el / persist_waves.  Changes no handle. */
+gfbp_status gfbp_tune_persistent(const gfbp_code *const *codes, const gfbp_batch *batch, gfbp_result *out,
+                                 void *workspace, size_t ws_bytes, void *stream, int32_t trial_iters, int32_t *el,
+                                 int32_t *waves);
 
 /* ---- Tracing: per-kernel timing with HIP events on the decode stream. ----
  * Off by default.  When on, every kernel launch of gfbp_decode_batch is

@@ -22,15 +22,19 @@ LIB_PATH = os.path.join(_HERE, "libgfbp.so")
 
 PUS, SUS = 0, 1
 CH_BSC, CH_BEC, CH_BIAWGN, CH_LIKELIHOOD = 0, 1, 2, 3
-PRIOR_UNIFORM, PRIOR_MARKOV = 0, 1
+PRIOR_UNIFORM, PRIOR_MARKOV, PRIOR_STATIC = 0, 1, 2
+PRIORS = {"uniform": PRIOR_UNIFORM, "markov": PRIOR_MARKOV, "static": PRIOR_STATIC}
+EVIDENCE_SYMBOL, EVIDENCE_MN = 0, 1
 OPT_SUS_STRICT = 1
 OPT_NO_COMPACT = 2
 OPT_STEP_GRAPHS = 4
 OPT_PRIOR_IN_SWEEP = 8
+OPT_PERSISTENT = 16
 CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
-EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size", "gfbp_decode_batch",
+EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size",
+           "gfbp_batch_workspace_size", "gfbp_decode_batch", "gfbp_tune_persistent", "gfbp_device_clock_hz",
            "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
            "gfbp_code_get_shape", "gfbp_tune", "gfbp_session_bytes", "gfbp_session_create", "gfbp_session_destroy",
            "gfbp_session_admit", "gfbp_session_step", "gfbp_session_poll", "gfbp_session_free_slots",
@@ -41,7 +45,7 @@ EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_work
 class CodeDesc(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int32), ("poly", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_info", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("coef", ctypes.c_void_p)]
+                ("coef", ctypes.c_void_p), ("visit_order", ctypes.c_void_p), ("source_cols", ctypes.c_void_p)]
 
 
 class CodeInfo(ctypes.Structure):
@@ -57,7 +61,9 @@ class Batch(ctypes.Structure):
                 ("rx", ctypes.c_void_p), ("erasure", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("likelihood", ctypes.c_void_p), ("syndrome", ctypes.c_void_p), ("prior", ctypes.c_int32),
                 ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p), ("options", ctypes.c_int32),
-                ("truth", ctypes.c_void_p)]
+                ("truth", ctypes.c_void_p), ("evidence", ctypes.c_int32), ("channel_of", ctypes.c_void_p),
+                ("static_prior", ctypes.c_void_p), ("static_per_symbol", ctypes.c_int32), ("n_codes", ctypes.c_int32),
+                ("code_index", ctypes.c_void_p), ("persist_el", ctypes.c_int32), ("persist_waves", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -75,7 +81,7 @@ class KernelStats(ctypes.Structure):
 class SessionDesc(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("schedule", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("has_syndrome", ctypes.c_int32), ("markov_M", ctypes.c_void_p), ("markov_pi", ctypes.c_void_p),
-                ("options", ctypes.c_int32)]
+                ("options", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
 class FramesIn(ctypes.Structure):
@@ -85,7 +91,8 @@ class FramesIn(ctypes.Structure):
 
 
 class Retired(ctypes.Structure):
-    _fields_ = [("id", ctypes.c_int64), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32)]
+    _fields_ = [("id", ctypes.c_int64), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("t_admit", ctypes.c_uint64), ("t_retire", ctypes.c_uint64)]
 
 
 _lib = None
@@ -107,9 +114,16 @@ def lib():
     L.gfbp_code_info_get.restype = ctypes.c_int32
     L.gfbp_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.gfbp_workspace_size.restype = ctypes.c_size_t
+    L.gfbp_batch_workspace_size.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch)]
+    L.gfbp_batch_workspace_size.restype = ctypes.c_size_t
     L.gfbp_decode_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
                                     ctypes.c_size_t, ctypes.c_void_p]
     L.gfbp_decode_batch.restype = ctypes.c_int32
+    L.gfbp_tune_persistent.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.gfbp_tune_persistent.restype = ctypes.c_int32
+    L.gfbp_device_clock_hz.restype = ctypes.c_uint64
     L.gfbp_profile_enable.argtypes = [ctypes.c_int32]
     L.gfbp_profile_enable.restype = ctypes.c_int32
     L.gfbp_profile_reset.restype = ctypes.c_int32
@@ -202,8 +216,13 @@ class DeviceCode:
         self._rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
         self._col = np.ascontiguousarray(code.col, dtype=np.int32)
         self._coef = np.ascontiguousarray(code.coef, dtype=np.uint8)
+        vo, sc = getattr(code, "visit_order", None), getattr(code, "source_cols", None)
+        self._vo = None if vo is None else np.ascontiguousarray(vo, dtype=np.int32)
+        self._sc = None if sc is None else np.ascontiguousarray(sc, dtype=np.int32)
         d = CodeDesc(int(code.q), int(getattr(code, "poly", 0)), int(code.n), int(code.m), int(code.n_info),
-                     self._rp.ctypes.data, self._col.ctypes.data, self._coef.ctypes.data)
+                     self._rp.ctypes.data, self._col.ctypes.data, self._coef.ctypes.data,
+                     None if self._vo is None else self._vo.ctypes.data,
+                     None if self._sc is None else self._sc.ctypes.data)
         h = ctypes.c_void_p()
         _check(L.gfbp_code_build(ctypes.byref(d), ctypes.byref(h)), "gfbp_code_build")
         self.handle = h
@@ -262,6 +281,7 @@ def frames_to_device(frames, device="cuda"):
     return {
         "channel": frames.channel,
         "F": frames.F,
+        "evidence": getattr(frames, "evidence", "symbol"),
         "param": dev(frames.param.astype(np.float32), torch.float32),
         "rx": dev(frames.rx, torch.uint8),
         "erasure": dev(frames.erasure, torch.uint8),
@@ -271,21 +291,60 @@ def frames_to_device(frames, device="cuda"):
     }
 
 
+def _codes_array(dcodes):
+    arr = (ctypes.c_void_p * len(dcodes))(*[d.handle.value for d in dcodes])
+    return arr
+
+
+def _batch(F, sch, max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, options, truth, n_codes, code_index,
+           persist_el=0, persist_waves=0):
+    ev = dframes.get("evidence", "symbol")
+    return Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes.get("channel", "bsc")],
+                 _dptr(dframes.get("param")), _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")),
+                 _dptr(dframes.get("y")), _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")),
+                 PRIORS[prior], _dptr(Mt), _dptr(pt), int(options), _dptr(truth),
+                 EVIDENCE_MN if ev == "mn" else EVIDENCE_SYMBOL, _dptr(dframes.get("channel_of")), _dptr(Pt),
+                 int(per_symbol), int(n_codes), None if code_index is None else code_index.ctypes.data,
+                 int(persist_el), int(persist_waves))
+
+
+def _prior_tensors(prior, markov_M, markov_pi, static_prior, dev):
+    import torch
+
+    Mt = pt = Pt = None
+    per_symbol = 0
+    if prior == "markov":
+        Mt = torch.as_tensor(np.asarray(markov_M, dtype=np.float32), device=dev).contiguous()
+        pt = torch.as_tensor(np.asarray(markov_pi, dtype=np.float32), device=dev).contiguous()
+    elif prior == "static":
+        sp = np.asarray(static_prior, dtype=np.float32)
+        per_symbol = int(sp.ndim == 2)
+        Pt = torch.as_tensor(sp, device=dev).contiguous()
+    return Mt, pt, Pt, per_symbol
+
+
 def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, posterior: bool = False, guards: bool = True,
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
                  sus_strict: bool = False, tune_iters: int = 0, compact: bool = True, truth=None,
-                 prior_in_sweep: bool = False) -> dict:
-    """``gfbp_decode_batch`` on device tensors; returns device tensors.
+                 prior_in_sweep: bool = False, static_prior=None, persistent: bool = False, persist_el: int = 0,
+                 persist_waves: int = 0) -> dict:
+    """``gfbp_decode_batch`` on device tensors of one code; returns device tensors.
 
-    dframes: dict from :func:`frames_to_device` (or with the same keys).
+    dframes: dict from :func:`frames_to_device` (or with the same keys; an
+    optional ``channel_of`` uint8 [F] gives each frame's channel kind, and
+    ``evidence`` "mn" selects the MacKay-Neal syndrome form).
+    prior: "uniform", "markov" (markov_M, markov_pi) or "static"
+    (static_prior [q] or [n_info][q] in chain order).
     workspace: optional preallocated uint8 device tensor of at least
-    ``dcode.workspace_size(F, schedule, prior)`` bytes, 256-byte aligned.
+    ``gfbp_batch_workspace_size`` bytes, 256-byte aligned.
     outputs: optional preallocated output tensors (xhat, iters, converged).
     truth: optional device uint8 [F][n] true symbols; then out["trace"] [F][max_iter]
     counts the correct source bits after each iteration (the Fig. 1 diagnostic).
     prior_in_sweep: SUS with the Markov prior assigns each source symbol's
     prior at its column's vertical pass (``GFBP_OPT_PRIOR_IN_SWEEP``).
+    persistent: decode through the persistent work-list kernel
+    (``GFBP_OPT_PERSISTENT``) with tile shape persist_el / persist_waves.
     """
     import torch
 
@@ -293,7 +352,6 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     n, q, E = dcode.n, dcode.q, dcode.E
     dev = torch.device("cuda", torch.cuda.current_device())
     sch = SCHEDULES[schedule]
-    pk = PRIOR_MARKOV if prior == "markov" else PRIOR_UNIFORM
     out = dict(outputs) if outputs else {}
     out.setdefault("xhat", torch.empty((F, n), dtype=torch.uint8, device=dev))
     out.setdefault("iters", torch.empty((F,), dtype=torch.int32, device=dev))
@@ -308,18 +366,15 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
         out["snap_q"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
         out["snap_r"] = torch.zeros((F, E, q), dtype=torch.float32, device=dev)
         out["snap_Q"] = torch.zeros((F, n, q), dtype=torch.float32, device=dev)
-    ws_bytes = dcode.workspace_size(F, sch, pk)
+    Mt, pt, Pt, per_symbol = _prior_tensors(prior, markov_M, markov_pi, static_prior, dev)
+    opts = ((OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT) |
+            (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0) | (OPT_PERSISTENT if persistent else 0))
+    b = _batch(F, sch, max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, opts, truth, 1, None,
+               persist_el, persist_waves)
+    codes = _codes_array([dcode])
+    ws_bytes = int(lib().gfbp_batch_workspace_size(codes, ctypes.byref(b)))
     if workspace is None:
         workspace = torch.empty((max(ws_bytes, 1),), dtype=torch.uint8, device=dev)
-    Mt = pt = None
-    if pk == PRIOR_MARKOV:
-        Mt = torch.as_tensor(np.asarray(markov_M, dtype=np.float32), device=dev).contiguous()
-        pt = torch.as_tensor(np.asarray(markov_pi, dtype=np.float32), device=dev).contiguous()
-    b = Batch(F, sch, int(max_iter), int(bool(early_stop)), CHANNELS[dframes["channel"]], _dptr(dframes.get("param")),
-              _dptr(dframes.get("rx")), _dptr(dframes.get("erasure")), _dptr(dframes.get("y")),
-              _dptr(dframes.get("likelihood")), _dptr(dframes.get("syndrome")), pk, _dptr(Mt), _dptr(pt),
-              (OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT) |
-              (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0), _dptr(truth))
     r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), _dptr(out.get("posterior")),
                _dptr(out.get("guards")), int(snap_iter), _dptr(out.get("snap_q")), _dptr(out.get("snap_r")),
                _dptr(out.get("snap_Q")), _dptr(out.get("trace")))
@@ -330,9 +385,107 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
                                ctypes.c_void_p(st.cuda_stream), int(tune_iters), ctypes.byref(chosen)), "gfbp_tune")
         out["entries_per_lane"] = int(chosen.value)
         return out
-    _check(lib().gfbp_decode_batch(dcode.handle, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(),
+    _check(lib().gfbp_decode_batch(codes, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(),
                                    workspace.numel(), ctypes.c_void_p(st.cuda_stream)), "gfbp_decode_batch")
     return out
+
+
+def ragged_frames(frames_list, codes_list, device="cuda"):
+    """Concatenate ``workloads.Frames`` batches (frames_list[k] on codes_list[k],
+    in order) into the ragged device inputs of a multi-code
+    ``gfbp_decode_batch``: per-symbol arrays one frame after the other with each
+    frame's own n (and p or q), syndromes with each frame's m, a per-frame
+    channel kind and parameters."""
+    import torch
+
+    def cat(parts, dtype):
+        parts = [np.ascontiguousarray(x, dtype=dtype).ravel() for x in parts]
+        return torch.from_numpy(np.concatenate(parts) if parts else np.zeros(0, dtype)).to(device)
+
+    ev = {getattr(f, "evidence", "symbol") for f in frames_list}
+    if len(ev) > 1:
+        raise ValueError("one evidence mode per batch")
+    rx, er, y, lik, syn, ch, prm = [], [], [], [], [], [], []
+    for fr in frames_list:
+        F, n = fr.codeword.shape
+        rx.append(fr.rx if fr.rx is not None else np.zeros((F, n), np.uint8))
+        er.append(fr.erasure if fr.erasure is not None else np.zeros((F, n), np.uint8))
+        if fr.y is not None:
+            y.append(fr.y)
+        if getattr(fr, "lik", None) is not None:
+            lik.append(fr.lik)
+        if fr.syndrome is not None:
+            syn.append(fr.syndrome)
+        ch.append(np.full(F, CHANNELS[fr.channel], np.uint8))
+        prm.append(fr.param.astype(np.float32))
+    any_y = any(fr.y is not None for fr in frames_list)
+    if any_y:  # frames of other channels hold zeros in y (unread)
+        y = []
+        for fr, code in zip(frames_list, codes_list):
+            F, n = fr.codeword.shape
+            y.append(fr.y if fr.y is not None else np.zeros((F, n, code.p), np.float32))
+    out = {"F": sum(fr.F for fr in frames_list), "channel": frames_list[0].channel, "evidence": ev.pop(),
+           "channel_of": cat(ch, np.uint8), "param": cat(prm, np.float32), "rx": cat(rx, np.uint8),
+           "erasure": cat(er, np.uint8)}
+    if any_y:
+        out["y"] = cat(y, np.float32)
+    if lik:
+        out["likelihood"] = cat(lik, np.float32)
+    if syn:
+        if len(syn) != len(frames_list):
+            raise ValueError("syndromes for every entry or none")
+        out["syndrome"] = cat(syn, np.uint8)
+    return out
+
+
+def decode_multi(dcodes, code_index, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
+                 prior: str = "uniform", markov_M=None, markov_pi=None, static_prior=None, workspace=None,
+                 stream=None, persist_el: int = 0, persist_waves: int = 0, tune_iters: int = 0) -> dict:
+    """``gfbp_decode_batch`` over several codes (the persistent kernel):
+    frame f is on dcodes[code_index[f]]; dframes holds ragged inputs (see
+    :func:`ragged_frames`).  Returns device tensors xhat (ragged, sum of n),
+    iters, converged and guards; with tune_iters, runs
+    ``gfbp_tune_persistent`` instead and returns the chosen shape."""
+    import torch
+
+    ci = np.ascontiguousarray(code_index, dtype=np.int32)
+    F = len(ci)
+    if int(dframes["F"]) != F:
+        raise ValueError("code_index and dframes disagree on the number of frames")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ns = np.array([d.n for d in dcodes], dtype=np.int64)
+    out = {"xhat": torch.empty((int(ns[ci].sum()),), dtype=torch.uint8, device=dev),
+           "iters": torch.empty((F,), dtype=torch.int32, device=dev),
+           "converged": torch.empty((F,), dtype=torch.uint8, device=dev),
+           "guards": torch.empty((F,), dtype=torch.int32, device=dev)}
+    Mt, pt, Pt, per_symbol = _prior_tensors(prior, markov_M, markov_pi, static_prior, dev)
+    b = _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, 0, None,
+               len(dcodes), ci, persist_el, persist_waves)
+    codes = _codes_array(dcodes)
+    ws_bytes = int(lib().gfbp_batch_workspace_size(codes, ctypes.byref(b)))
+    if tune_iters:  # room for every candidate shape
+        ws_bytes = max(ws_bytes, max(int(lib().gfbp_batch_workspace_size(codes, ctypes.byref(
+            _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, 0, None,
+                   len(dcodes), ci, el, wv)))) for el in (4, 8) for wv in (4, 8)))
+    if workspace is None:
+        workspace = torch.empty((max(ws_bytes, 1),), dtype=torch.uint8, device=dev)
+    r = Result(_dptr(out["xhat"]), _dptr(out["iters"]), _dptr(out["converged"]), None, _dptr(out["guards"]), 0,
+               None, None, None, None)
+    st = torch.cuda.current_stream() if stream is None else stream
+    if tune_iters:
+        el, wv = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().gfbp_tune_persistent(codes, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(),
+                                          workspace.numel(), ctypes.c_void_p(st.cuda_stream), int(tune_iters),
+                                          ctypes.byref(el), ctypes.byref(wv)), "gfbp_tune_persistent")
+        out["persist_el"], out["persist_waves"] = int(el.value), int(wv.value)
+        return out
+    _check(lib().gfbp_decode_batch(codes, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(), workspace.numel(),
+                                   ctypes.c_void_p(st.cuda_stream)), "gfbp_decode_batch")
+    return out
+
+
+def device_clock_hz() -> int:
+    return int(lib().gfbp_device_clock_hz())
 
 
 def tune(dcode: DeviceCode, dframes: dict, schedule="pus", trial_iters: int = 3, **kw) -> int:
@@ -358,16 +511,18 @@ class Session:
 
     def __init__(self, dcode: DeviceCode, n_slots: int, schedule="pus", max_iter: int = 100,
                  has_syndrome: bool = False, markov_M=None, markov_pi=None, sus_strict: bool = False,
-                 step_graphs: bool = False):
+                 step_graphs: bool = False, device_bytes: int = 0):
         """step_graphs: replay a captured HIP graph for each even-iteration
-        :meth:`step` on a created stream (the same work; fewer host launches)."""
+        :meth:`step` on a created stream (the same work; fewer host launches).
+        n_slots = 0: as many slots as ``device_bytes`` of device memory hold."""
         self.dcode = dcode
         self._M = None if markov_M is None else np.ascontiguousarray(markov_M, dtype=np.float32)
         self._pi = None if markov_pi is None else np.ascontiguousarray(markov_pi, dtype=np.float32)
         self.desc = SessionDesc(int(n_slots), SCHEDULES[schedule], int(max_iter), int(bool(has_syndrome)),
                                 None if self._M is None else self._M.ctypes.data,
                                 None if self._pi is None else self._pi.ctypes.data,
-                                (OPT_SUS_STRICT if sus_strict else 0) | (OPT_STEP_GRAPHS if step_graphs else 0))
+                                (OPT_SUS_STRICT if sus_strict else 0) | (OPT_STEP_GRAPHS if step_graphs else 0),
+                                int(device_bytes))
         h = ctypes.c_void_p()
         _check(lib().gfbp_session_create(dcode.handle, ctypes.byref(self.desc), ctypes.byref(h)), "gfbp_session_create")
         self.handle = h
@@ -375,11 +530,11 @@ class Session:
 
     @staticmethod
     def bytes_needed(dcode: DeviceCode, n_slots: int, schedule="pus", markov: bool = False,
-                     has_syndrome: bool = False) -> int:
+                     has_syndrome: bool = False, device_bytes: int = 0) -> int:
         q = dcode.q
         M = np.zeros((q, q), np.float32)
         d = SessionDesc(int(n_slots), SCHEDULES[schedule], 1, int(bool(has_syndrome)),
-                        M.ctypes.data if markov else None, M.ctypes.data if markov else None, 0)
+                        M.ctypes.data if markov else None, M.ctypes.data if markov else None, 0, int(device_bytes))
         return int(lib().gfbp_session_bytes(dcode.handle, ctypes.byref(d)))
 
     def close(self):
@@ -414,8 +569,14 @@ class Session:
     def step(self, iters: int = 1, stream=None):
         _check(lib().gfbp_session_step(self.handle, int(iters), _stream_ptr(stream)), "gfbp_session_step")
 
-    def poll(self, cap: int | None = None, want_xhat: bool = True, stream=None):
-        """Finished frames: (ids int64[k], iters int32[k], converged uint8[k], xhat uint8[k][n] or None)."""
+    @property
+    def n_slots(self) -> int:
+        return self.free_slots + self.running
+
+    def poll(self, cap: int | None = None, want_xhat: bool = True, stream=None, timestamps: bool = False):
+        """Finished frames: (ids int64[k], iters int32[k], converged uint8[k], xhat uint8[k][n] or None)
+        and, with timestamps, a fifth item: device clock ticks [k][2] at admission and retirement
+        (:func:`device_clock_hz` per second)."""
         cap = int(cap or max(1, self.running))
         out = (Retired * cap)()
         xh = np.zeros((cap, self.n), dtype=np.uint8) if want_xhat else None
@@ -426,6 +587,9 @@ class Session:
         ids = np.array([out[i].id for i in range(k)], dtype=np.int64)
         it = np.array([out[i].iters for i in range(k)], dtype=np.int32)
         cv = np.array([out[i].converged for i in range(k)], dtype=np.uint8)
+        if timestamps:
+            ts = np.array([(out[i].t_admit, out[i].t_retire) for i in range(k)], dtype=np.uint64).reshape(k, 2)
+            return ids, it, cv, (None if xh is None else xh[:k]), ts
         return ids, it, cv, (None if xh is None else xh[:k])
 
 

@@ -20,6 +20,7 @@
 #include "../../include/gfbp.h"
 #include "gfbp_kernels.h"
 #include "gfbp_tiled.h"
+#include "gfbp_persist.h"
 
 using namespace gfbp;
 
@@ -59,6 +60,7 @@ struct gfbp_code {
         std::vector<double> edges;  // per level: edges
         std::vector<double> src;    // per level: source columns
         const SusRec *recs = nullptr;  // device [n][max column degree], columns in level order
+        const int32_t *dptr = nullptr; // device copy of ptr
         // launches of one sweep: a wide level alone (one workgroup per column
         // and tile), or a run of consecutive thin levels (one per tile)
         struct Seg {
@@ -79,10 +81,10 @@ namespace {
 
 enum Kind {
     K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COMPACT,
-    K_SUS_RUN, K_COUNT
+    K_SUS_RUN, K_PERSIST, K_COUNT
 };
 const char *kKindName[K_COUNT] = {"init",     "check",  "variable", "sequential", "sus_level", "syndrome",
-                                  "retire",   "markov", "output",   "compact",    "sus_run"};
+                                  "retire",   "markov", "output",   "compact",    "sus_run",   "persistent"};
 
 struct Totals {
     int64_t launches = 0;
@@ -294,17 +296,21 @@ __global__ void k_retire(DevState s, BatchAux a, int t, int max_iter, int early_
     s.unsat[f] = 0;
 }
 
-// Fig. 1 diagnostic: correct bits of the first K symbols of running frame f
-// after iteration t, added to trace[f][t-1] (slot = frame: frames do not move
-// when a trace is asked for).  Threads over frames, blockIdx.y over chunks of
-// 128 columns.
+// Fig. 1 diagnostic: correct bits of the K source symbols (columns
+// cols[0..K), or columns 0..K-1 when cols is null) of running frame f after
+// iteration t, added to trace[f][t-1] (slot = frame: frames do not move when
+// a trace is asked for).  Threads over frames, blockIdx.y over chunks of 128
+// symbols.
 __global__ void k_trace(DevState s, const uint8_t *truth, int n, int K, int p, int t, int max_iter,
-                        int32_t *trace) {
+                        int32_t *trace, const int32_t *cols) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j0 = int(blockIdx.y) * 128, j1 = min(K, j0 + 128);
+    const int k0 = int(blockIdx.y) * 128, k1 = min(K, k0 + 128);
     if (f >= s.F || !s.active[f]) return;
     int c = 0;
-    for (int j = j0; j < j1; ++j) c += p - __popc(unsigned(s.xh[size_t(j) * s.Fp + f] ^ truth[size_t(f) * n + j]));
+    for (int k = k0; k < k1; ++k) {
+        const int j = cols ? cols[k] : k;
+        c += p - __popc(unsigned(s.xh[size_t(j) * s.Fp + f] ^ truth[size_t(f) * n + j]));
+    }
     if (c) atomicAdd(&trace[size_t(f) * max_iter + (t - 1)], c);
 }
 
@@ -478,49 +484,47 @@ inline unsigned tiled_blocks(int nodes, const DevState &s) {
 
 template <int P, int LG, int DCM, int DVM>
 struct TiledLaunch {
-    static void init(hipStream_t st, const DevCode &c, const DevState &s, const gfbp_batch *b) {
-        tiled::Chan ch{b->channel, b->prior == GFBP_PRIOR_MARKOV, b->rx, b->erasure, b->y, b->likelihood, b->param,
-                       b->markov_pi};
+    static void init(hipStream_t st, const DevCode &c, const DevState &s, const tiled::Chan &ch) {
         launch((tiled::k_init<P, LG>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
     }
     static void check(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, Snap sn) {
         launch((tiled::k_check<P, LG, DCM>), dim3(tiled_blocks(c.m, s)), dim3(kBlock), 0, st, c, s,
                            z, sn);
     }
-    static void variable(hipStream_t st, const DevCode &c, const DevState &s, int markov, int wantQ, Snap sn) {
+    static void variable(hipStream_t st, const DevCode &c, const DevState &s, int prior_on, int wantQ, Snap sn) {
         launch((tiled::k_variable<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c,
-                           s, markov, wantQ, sn);
+                           s, prior_on, wantQ, sn);
     }
-    static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+    static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int prior_on, int wantQ,
                           Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
         const dim3 g(std::max(1u, unsigned(nc) * unsigned(s.nb)));
         const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
         if (sp.on)
-            launch((tiled::k_sus_level<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+            launch((tiled::k_sus_level<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp, recs,
                    std::max(1, c.max_dv), nc);
         else
-            launch((tiled::k_sus_level<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+            launch((tiled::k_sus_level<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp, recs,
                    std::max(1, c.max_dv), nc);
     }
-    static void sus_run(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+    static void sus_run(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int prior_on, int wantQ,
                         Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
         const dim3 g(std::max(1u, unsigned(s.nb)));
         const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
         if (sp.on)
-            launch((tiled::k_sus_run<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+            launch((tiled::k_sus_run<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp, recs,
                    std::max(1, c.max_dv), nc);
         else
-            launch((tiled::k_sus_run<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp, recs,
+            launch((tiled::k_sus_run<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp, recs,
                    std::max(1, c.max_dv), nc);
     }
     // one sweep of levels (lv.segs)
-    static void sweep(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov, int wantQ,
+    static void sweep(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int prior_on, int wantQ,
                       Snap sn, const SweepPrior &sp, const gfbp_code::Levels &lv, Tracer *tr, int needQ, int t) {
         const int RS = std::max(1, c.max_dv);
         for (const auto &g : lv.segs) {
             if (tr) tr->begin();
-            if (g.run) sus_run(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
-            else sus_level(st, c, s, z, markov, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
+            if (g.run) sus_run(st, c, s, z, prior_on, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
+            else sus_level(st, c, s, z, prior_on, wantQ, sn, sp, lv.recs + size_t(g.c0) * RS, g.nc);
             // an assigned prior reads two neighbours' Q and L in place of Pr
             if (tr)
                 tr->end_iter(g.run ? K_SUS_RUN : K_SUS_LEVEL,
@@ -529,14 +533,14 @@ struct TiledLaunch {
                              g.edges * (1 << P), t);
         }
     }
-    static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int markov,
+    static void sequential(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int prior_on,
                            int wantQ, Snap sn, const SweepPrior &sp) {
         const dim3 g(std::max(1u, unsigned(s.nb)));
         const dim3 b(unsigned(std::max(1, std::min(c.max_dv, DVM))) * kWave);
         if (sp.on)
-            launch((tiled::k_sequential<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp);
+            launch((tiled::k_sequential<P, LG, DCM, DVM, true>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp);
         else
-            launch((tiled::k_sequential<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, markov, wantQ, sn, sp);
+            launch((tiled::k_sequential<P, LG, DCM, DVM, false>), g, b, 0, st, c, s, z, prior_on, wantQ, sn, sp);
     }
     static void markov(hipStream_t st, const DevCode &c, const DevState &s, const float *M, const float *pi,
                        const float *mshape) {
@@ -584,7 +588,8 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const Bytes bpf = bytes_per_frame(code, needQ, b->syndrome != nullptr);
     const double eq_frame = double(c.E) * Q;
     const uint8_t *z = b->syndrome ? a.z : nullptr;  // syndromes by slot
-    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
+    const int prior_on = (b->prior != GFBP_PRIOR_UNIFORM) && c.n_info > 0;  // source columns read Pr
+    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;     // ... refreshed by Eq. (7)
     // SUS priors assigned during the sweep (from iteration 2)
     const int insweep = markov && b->schedule == GFBP_SUS && (b->options & GFBP_OPT_PRIOR_IN_SWEEP);
     // moving frames keeps running frames in whole tiles; posteriors and
@@ -592,7 +597,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const bool tracing = out->trace && b->truth;
     const bool compact = !(b->options & GFBP_OPT_NO_COMPACT) && !out->posterior && out->snap_iter <= 0 &&
                          !tracing && F > K::TF;
-    const int Kp = markov ? c.n_info : 0;  // Markov-weighted likelihoods move with the frame
+    const int Kp = prior_on ? c.n_info : 0;  // prior-weighted evidence moves with the frame
     Tracer tr(st);
     launch(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, a);
     if (tracing) {
@@ -608,8 +613,21 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     s.nact = s.count + 1;
     s.nb = (F + K::TF - 1) / K::TF;
     if (markov) hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, st, b->markov_M, Q, a.mshape);
+    tiled::Chan ch{};
+    ch.channel = b->channel;
+    ch.prior = prior_on ? b->prior : GFBP_PRIOR_UNIFORM;
+    ch.evidence = b->evidence;
+    ch.static_per_symbol = b->static_per_symbol;
+    ch.rx = b->rx;
+    ch.erasure = b->erasure;
+    ch.y = b->y;
+    ch.lik = b->likelihood;
+    ch.param = b->param;
+    ch.pi = b->markov_pi;
+    ch.static_P = b->static_prior;
+    ch.chan_of = b->channel_of;
     tr.begin();
-    K::init(st, c, s, b);
+    K::init(st, c, s, ch);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
     HIP_TRY(hipGetLastError());
     // The host stays one iteration ahead of the device: iteration t+1 is
@@ -643,22 +661,22 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
             K::check(st, c, s, z, sn);
             tr.end_iter(K_CHECK, bpf.check, eq_frame, t);
             tr.begin();
-            K::variable(st, c, s, markov, wantQ, sn);
+            K::variable(st, c, s, prior_on, wantQ, sn);
             tr.end_iter(K_VARIABLE, bpf.variable, eq_frame, t);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
             const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
             tr.begin();
-            K::sequential(st, c, s, z, markov, wantQ, sn, sp);
+            K::sequential(st, c, s, z, prior_on, wantQ, sn, sp);
             tr.end_iter(K_SEQUENTIAL, bpf.sequential + (sp.on ? 8.0 * Q * c.n_info : 0.0), eq_frame, t);
         } else {
             const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
-            K::sweep(st, c, s, z, markov, wantQ, sn, sp, code->lv[insweep ? 1 : 0], &tr, needQ, t);
+            K::sweep(st, c, s, z, prior_on, wantQ, sn, sp, code->lv[insweep ? 1 : 0], &tr, needQ, t);
         }
         if (snap_now && out->snap_Q) K::vectors(st, s.Qp, c.n, s, out->snap_Q);
         if (tracing) {
             const int Kt = c.n_info > 0 ? c.n_info : c.n;
             launch(k_trace, dim3(fb, unsigned((Kt + 127) / 128)), dim3(kBlock), 0, st, s, b->truth, c.n, Kt, P, t,
-                   b->max_iter, out->trace);
+                   b->max_iter, out->trace, c.n_info > 0 ? c.chain_col : nullptr);
         }
         tr.begin();
         launch(k_syndrome, dim3(syndrome_blocks(c.m, F)), dim3(kBlock), 0, st, c, s, z);
@@ -705,7 +723,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                 launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm), c.n,
                        out->xhat);
                 const int W = Q >= 4 ? 4 : 2;
-                const int Kq = insweep ? c.n_info : 0;  // the next sweep's priors read these Q
+                const int Kq = insweep ? c.n : 0;  // the next sweep's priors read the source columns' Q
                 const size_t per = size_t(c.E + c.n + Kp + Kq) * Q;
                 const unsigned chunks = unsigned((per / W + 255) / 256);
                 tr.begin();
@@ -788,6 +806,7 @@ struct SessDev {
     int32_t *iters;
     uint8_t *conv, *fresh, *done, *xout;
     int32_t *pairs, *list, *res;
+    uint64_t *t_admit, *t_done, *ts;  // [S] device clock at admission / retirement; [2][S] of listed slots
 };
 
 struct gfbp_session {
@@ -850,6 +869,7 @@ __global__ void k_admit(SessDev s, AdmitIn in, int n, int m, int p) {
         s.iters[slot] = 0;
         s.conv[slot] = 0;
         s.done[slot] = 0;
+        s.t_admit[slot] = uint64_t(wall_clock64());
     }
 }
 
@@ -869,6 +889,7 @@ __global__ void k_session_retire(SessDev s) {
         if (ok || t >= s.max_iter) {
             s.st.active[f] = 0;
             s.done[f] = 1;
+            s.t_done[f] = uint64_t(wall_clock64());
         }
     }
     s.st.unsat[f] = 0;
@@ -884,6 +905,8 @@ __global__ void k_collect(SessDev s, int k, int n) {
     if (j == 0) {
         s.res[2 * r] = s.iters[slot];
         s.res[2 * r + 1] = s.conv[slot];
+        s.ts[2 * r] = s.t_admit[slot];
+        s.ts[2 * r + 1] = s.t_done[slot];
         s.done[slot] = 0;
     }
 }
@@ -899,15 +922,15 @@ struct SessionRun {
         s.nact = ss->aux + 0;
         s.nb = std::min(ss->ntiles, nadm);
         s.fresh = ss->dv.fresh;
-        gfbp_batch b{};
-        b.channel = GFBP_CH_BSC;  // per-slot channel kinds override this
-        b.param = ss->dv.param;
-        b.rx = ss->dv.rx;
-        b.erasure = ss->dv.er;
-        b.y = ss->dv.y;
-        b.prior = ss->markov ? GFBP_PRIOR_MARKOV : GFBP_PRIOR_UNIFORM;
-        b.markov_pi = ss->pi;
-        K::init(st, c, s, &b);
+        tiled::Chan ch{};
+        ch.channel = GFBP_CH_BSC;  // per-slot channel kinds override this
+        ch.param = ss->dv.param;
+        ch.rx = ss->dv.rx;
+        ch.erasure = ss->dv.er;
+        ch.y = ss->dv.y;
+        ch.prior = ss->markov ? GFBP_PRIOR_MARKOV : GFBP_PRIOR_UNIFORM;  // per-slot flags in s.mark
+        ch.pi = ss->pi;
+        K::init(st, c, s, ch);
         hipLaunchKernelGGL(k_clear_fresh, dim3((nadm + 255) / 256), dim3(256), 0, st, ss->dv, nadm);
         K::tiles(st, s.active, s.F, s.Fp, ss->dv.st.tiles + size_t(ss->parity) * ss->ntiles, ss->aux + 2 + ss->parity);
         HIP_TRY(hipGetLastError());
@@ -1002,7 +1025,7 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     c.Qm = take(E * F * Q * 4);
     c.R = take(schedule == GFBP_PUS ? E * F * Q * 4 : 0);
     c.L = take(n * F * Q * 4);
-    c.Pr = take(prior == GFBP_PRIOR_MARKOV ? K * F * Q * 4 : 0);
+    c.Pr = take(prior != GFBP_PRIOR_UNIFORM ? K * F * Q * 4 : 0);
     c.Qp = take(n * F * Q * 4);
     c.xh = take(n * F);
     c.unsat = take(size_t(F_) * 4);
@@ -1026,6 +1049,7 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
 struct SessCarve {
     size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards;
     size_t rx, er, y, param, z, chan, mark, iters, conv, fresh, done, xout, pairs, list, res, ftiles, aux, M, pi, mshape;
+    size_t t_admit, t_done, ts;
     size_t total;
 };
 
@@ -1066,8 +1090,33 @@ SessCarve session_carve(const gfbp_code *code, int S, int schedule, int markov, 
     c.M = take(Q * Q * 4);
     c.pi = take(Q * 4);
     c.mshape = take(16);
+    c.t_admit = take(F * 8);
+    c.t_done = take(F * 8);
+    c.ts = take(2 * F * 8);
     c.total = off;
     return c;
+}
+
+// Slots of a session: n_slots rounded up to whole 64-slot tiles, or with
+// n_slots = 0 the most whole tiles whose state fits device_bytes (0 if none).
+int session_slots(const gfbp_code *code, const gfbp_session_desc *d) {
+    if (d->n_slots > 0) return (d->n_slots + kWave - 1) / kWave * kWave;
+    if (d->device_bytes <= 0) return 0;
+    const int mk = d->markov_M != nullptr;
+    auto fits = [&](long long tiles) {
+        return session_carve(code, int(tiles * kWave), d->schedule, mk, d->has_syndrome).total <=
+               size_t(d->device_bytes);
+    };
+    long long lo = 0, hi = 1;
+    while (hi < (1 << 24) && fits(hi)) hi *= 2;  // the largest fitting count lies in [lo, hi)
+    lo = hi / 2;
+    if (!fits(std::max(1LL, lo))) return 0;
+    while (hi - lo > 1) {
+        const long long mid = (lo + hi) / 2;
+        if (fits(mid)) lo = mid;
+        else hi = mid;
+    }
+    return int(lo * kWave);
 }
 
 // ---------------------------------------------------------------- host GF
@@ -1095,6 +1144,344 @@ bool field_tables(int p, unsigned poly, std::vector<uint8_t> &mul, std::vector<u
 
 const unsigned kDefaultPoly[7] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43};
 
+
+// ---------------------------------------------------------------- persistent path
+// Plan of a batch for the persistent kernel: the codes with frames (groups),
+// the frames of each in batch order, every frame's input offsets, the work
+// list of each degree class, and the workspace layout.
+struct PersistPlan {
+    int F = 0, lel = 2, waves = 8;
+    std::vector<int> gcode;                       // code index of each group
+    std::vector<std::vector<int32_t>> gframe;     // frames of each group
+    std::vector<int64_t> off_n, off_nq, off_m;    // [F]
+    // work lists by (degree class, field): list 6 * cls + p - 1
+    std::vector<persist::Work> work[12];
+    std::vector<double> top;                      // largest tile's work of each list
+    // workspace
+    size_t o_off_n = 0, o_off_nq = 0, o_off_m = 0, o_groups = 0, o_work[12] = {}, o_next = 0, o_mshape = 0;
+    struct G {
+        size_t gframe, Qm, R, L, Pr, Qp, xh, unsat, active, guards, iters, conv, z;
+        int Fp;
+    };
+    std::vector<G> g;
+    size_t total = 0;
+};
+
+inline int persist_tf(int p, int lel) {  // frames per tile: 64 x entries per lane / q
+    const int l = std::min(lel, p);
+    return kWave >> (p - l);
+}
+
+gfbp_status persist_plan(const gfbp_code *const *codes, int nc, const gfbp_batch *b, PersistPlan &pl) {
+    const int F = b->n_frames;
+    pl.F = F;
+    pl.lel = 2;
+    if (b->persist_el) {
+        if (b->persist_el != 2 && b->persist_el != 4 && b->persist_el != 8)
+            return fail(GFBP_EUNSUPPORTED, "persist_el must be 2, 4 or 8");
+        pl.lel = b->persist_el == 2 ? 1 : b->persist_el == 4 ? 2 : 3;
+    }
+    if (pl.lel == 1) pl.lel = 2;  // entries per lane 2 runs as 4 (the q = 2 field takes 2 in every shape)
+    pl.waves = b->persist_waves ? b->persist_waves : 8;
+    if (pl.waves < 1 || pl.waves > 8) return fail(GFBP_EINVAL, "persist_waves must be 1..8");
+    std::vector<int> count(size_t(nc), 0), gid(size_t(nc), -1);
+    for (int f = 0; f < F; ++f) {
+        const int k = b->code_index ? b->code_index[f] : 0;
+        if (k < 0 || k >= nc) return fail(GFBP_EINVAL, "code_index out of range");
+        count[size_t(k)]++;
+    }
+    for (int k = 0; k < nc; ++k)
+        if (count[size_t(k)]) {
+            gid[size_t(k)] = int(pl.gcode.size());
+            pl.gcode.push_back(k);
+            pl.gframe.emplace_back();
+            pl.gframe.back().reserve(size_t(count[size_t(k)]));
+        }
+    pl.off_n.resize(size_t(F));
+    pl.off_nq.resize(size_t(F));
+    pl.off_m.resize(size_t(F));
+    int64_t on = 0, onq = 0, om = 0;
+    for (int f = 0; f < F; ++f) {
+        const int k = b->code_index ? b->code_index[f] : 0;
+        const gfbp_code_info &ci = codes[k]->info;
+        pl.off_n[size_t(f)] = on;
+        pl.off_nq[size_t(f)] = onq;
+        pl.off_m[size_t(f)] = om;
+        on += ci.n;
+        onq += int64_t(ci.n) * ci.q;
+        om += ci.m;
+        pl.gframe[size_t(gid[size_t(k)])].push_back(f);
+    }
+    if ((b->options & GFBP_OPT_PRIOR_IN_SWEEP))
+        return fail(GFBP_EUNSUPPORTED, "the persistent path refreshes priors after each iteration");
+    // work lists, largest tile first
+    struct Cand {
+        double cost;
+        persist::Work w;
+    };
+    std::vector<Cand> cand[12];
+    for (size_t g = 0; g < pl.gcode.size(); ++g) {
+        const gfbp_code *code = codes[pl.gcode[g]];
+        const int cls = small_class(code) ? 0 : 1;
+        const int lel = cls == 0 ? pl.lel : std::min(pl.lel, 2);
+        const int TF = persist_tf(code->info.p, lel);
+        const int Fg = int(pl.gframe[g].size());
+        const int list = 6 * cls + code->info.p - 1;
+        for (int t = 0; t * TF < Fg; ++t) {
+            const int nf = std::min(TF, Fg - t * TF);
+            cand[list].push_back({double(code->info.n_edges) * code->info.q * nf, {int32_t(g), int32_t(t)}});
+        }
+    }
+    pl.top.assign(12, 0.0);
+    for (int l = 0; l < 12; ++l) {
+        std::stable_sort(cand[l].begin(), cand[l].end(), [](const Cand &x, const Cand &y) { return x.cost > y.cost; });
+        pl.work[l].clear();
+        for (const auto &c : cand[l]) pl.work[l].push_back(c.w);
+        if (!cand[l].empty()) pl.top[size_t(l)] = cand[l].front().cost;
+    }
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes ? bytes : 1); return o; };
+    pl.o_off_n = take(8 * size_t(F));
+    pl.o_off_nq = take(8 * size_t(F));
+    pl.o_off_m = take(8 * size_t(F));
+    pl.o_groups = take(sizeof(persist::Group) * pl.gcode.size());
+    for (int l = 0; l < 12; ++l) pl.o_work[l] = take(sizeof(persist::Work) * pl.work[l].size());
+    pl.o_next = take(4 * 12);
+    pl.o_mshape = take(16);
+    const int prior_on = b->prior != GFBP_PRIOR_UNIFORM, markov = b->prior == GFBP_PRIOR_MARKOV;
+    pl.g.resize(pl.gcode.size());
+    for (size_t g = 0; g < pl.gcode.size(); ++g) {
+        const gfbp_code_info &ci = codes[pl.gcode[g]]->info;
+        const size_t E = ci.n_edges, n = ci.n, K = ci.n_info, Q = ci.q, m = ci.m;
+        const size_t Fg = pl.gframe[g].size(), Fp = size_t(frame_stride(int(Fg)));
+        PersistPlan::G &G = pl.g[g];
+        G.Fp = int(Fp);
+        G.gframe = take(4 * Fg);
+        G.Qm = take(E * Fp * Q * 4);
+        G.R = take(b->schedule == GFBP_PUS ? E * Fp * Q * 4 : 0);
+        G.L = take(n * Fp * Q * 4);
+        G.Pr = take(prior_on ? K * Fp * Q * 4 : 0);
+        G.Qp = take(markov ? n * Fp * Q * 4 : 0);
+        G.xh = take(n * Fp);
+        G.unsat = take(Fp * 4);
+        G.active = take(Fp);
+        G.guards = take(Fp * 4);
+        G.iters = take(Fp * 4);
+        G.conv = take(Fp);
+        G.z = take(b->syndrome ? Fp * m : 0);
+    }
+    pl.total = off;
+    return GFBP_OK;
+}
+
+// Side streams and events of the calling thread for forking the persistent
+// launches of one batch (created on first use, kept for the thread's life).
+struct ForkSet {
+    hipStream_t side[11] = {};
+    hipEvent_t ev[12] = {};
+};
+
+ForkSet *fork_set() {
+    static thread_local ForkSet fs;
+    static thread_local bool ready = false;
+    if (!ready) {
+        for (auto &x : fs.side)
+            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        for (auto &e : fs.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ready = true;
+    }
+    return &fs;
+}
+
+gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_batch *b, gfbp_result *out,
+                              void *workspace, size_t ws_bytes, hipStream_t st) {
+    if (out->posterior || out->snap_iter > 0 || (out->trace && b->truth))
+        return fail(GFBP_EUNSUPPORTED, "the persistent path returns decisions, iterations, convergence and guards only");
+    PersistPlan pl;
+    const gfbp_status ps = persist_plan(codes, nc, b, pl);
+    if (ps != GFBP_OK) return ps;
+    if (ws_bytes < pl.total) return fail(GFBP_ESMALL, "workspace too small");
+    char *w = static_cast<char *>(workspace);
+    const int prior_on = b->prior != GFBP_PRIOR_UNIFORM, markov = b->prior == GFBP_PRIOR_MARKOV;
+    std::vector<persist::Group> groups(pl.gcode.size());
+    for (size_t g = 0; g < pl.gcode.size(); ++g) {
+        const gfbp_code *code = codes[pl.gcode[g]];
+        const PersistPlan::G &o = pl.g[g];
+        persist::Group &G = groups[g];
+        G.c = code->dev;
+        DevState &s = G.s;
+        s = DevState{};
+        s.Qm = reinterpret_cast<float *>(w + o.Qm);
+        s.R = reinterpret_cast<float *>(w + o.R);
+        s.L = reinterpret_cast<float *>(w + o.L);
+        s.Pr = reinterpret_cast<float *>(w + o.Pr);
+        s.Qp = reinterpret_cast<float *>(w + o.Qp);
+        s.xh = reinterpret_cast<uint8_t *>(w + o.xh);
+        s.unsat = reinterpret_cast<uint32_t *>(w + o.unsat);
+        s.active = reinterpret_cast<uint8_t *>(w + o.active);
+        s.guards = reinterpret_cast<int32_t *>(w + o.guards);
+        s.F = int(pl.gframe[g].size());
+        s.Fp = o.Fp;
+        G.recs = code->lv[0].recs;
+        G.lvl = code->lv[0].dptr;
+        G.nlev = code->info.sus_levels;
+        G.rs = std::max(1, code->info.max_col_degree);
+        G.p = code->info.p;
+        G.iters = reinterpret_cast<int32_t *>(w + o.iters);
+        G.conv = reinterpret_cast<uint8_t *>(w + o.conv);
+        G.z = b->syndrome ? reinterpret_cast<uint8_t *>(w + o.z) : nullptr;
+        G.gframe = reinterpret_cast<const int32_t *>(w + o.gframe);
+        HIP_TRY(hipMemcpyAsync(w + o.gframe, pl.gframe[g].data(), 4 * pl.gframe[g].size(), hipMemcpyHostToDevice, st));
+    }
+    const size_t F = size_t(pl.F);
+    HIP_TRY(hipMemcpyAsync(w + pl.o_off_n, pl.off_n.data(), 8 * F, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + pl.o_off_nq, pl.off_nq.data(), 8 * F, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + pl.o_off_m, pl.off_m.data(), 8 * F, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + pl.o_groups, groups.data(), sizeof(persist::Group) * groups.size(),
+                           hipMemcpyHostToDevice, st));
+    for (int l = 0; l < 12; ++l)
+        if (!pl.work[l].empty())
+            HIP_TRY(hipMemcpyAsync(w + pl.o_work[l], pl.work[l].data(), sizeof(persist::Work) * pl.work[l].size(),
+                                   hipMemcpyHostToDevice, st));
+    uint32_t *next = reinterpret_cast<uint32_t *>(w + pl.o_next);
+    float *mshape = reinterpret_cast<float *>(w + pl.o_mshape);
+    launch(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(next), size_t(12), 0);
+    if (markov)  // the matrix is batch-wide (every code on its field)
+        hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, st, b->markov_M, codes[pl.gcode[0]]->info.q,
+                           mshape);
+    persist::Batch B{};
+    B.schedule = b->schedule;
+    B.max_iter = b->max_iter;
+    B.early_stop = b->early_stop;
+    B.prior_on = prior_on;
+    B.markov = markov;
+    B.M = b->markov_M;
+    B.pi = b->markov_pi;
+    B.mshape = mshape;
+    B.ch.channel = b->channel;
+    B.ch.prior = b->prior;
+    B.ch.evidence = b->evidence;
+    B.ch.static_per_symbol = b->static_per_symbol;
+    B.ch.rx = b->rx;
+    B.ch.erasure = b->erasure;
+    B.ch.y = b->y;
+    B.ch.lik = b->likelihood;
+    B.ch.param = b->param;
+    B.ch.pi = b->markov_pi;
+    B.ch.static_P = b->static_prior;
+    B.ch.chan_of = b->channel_of;
+    B.ch.off_n = reinterpret_cast<const int64_t *>(w + pl.o_off_n);
+    B.ch.off_nq = reinterpret_cast<const int64_t *>(w + pl.o_off_nq);
+    B.off_m = reinterpret_cast<const int64_t *>(w + pl.o_off_m);
+    B.zin = b->syndrome;
+    B.xhat = out->xhat;
+    B.iters = out->iters;
+    B.conv = out->converged;
+    B.guards = out->guards;
+    const persist::Group *dg = reinterpret_cast<const persist::Group *>(w + pl.o_groups);
+    // the lists present, the one with the largest tile first: it runs on the
+    // caller's stream, the others on forked streams joined back into it
+    std::vector<int> lists;
+    for (int l = 0; l < 12; ++l)
+        if (!pl.work[l].empty()) lists.push_back(l);
+    std::stable_sort(lists.begin(), lists.end(), [&](int x, int y) { return pl.top[size_t(x)] > pl.top[size_t(y)]; });
+    Tracer tr(st);
+    ForkSet *fs = lists.size() > 1 ? fork_set() : nullptr;
+    if (lists.size() > 1 && !fs) return fail(GFBP_EHIP, "creating the streams for the persistent launches");
+    // several launches: captured into one HIP graph on a created stream
+    const bool graph = lists.size() > 1 && st != nullptr && !tr.on;
+    if (graph) HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t he = hipSuccess;
+    if (fs) he = hipEventRecord(fs->ev[11], st);
+    for (size_t k = 0; k < lists.size() && he == hipSuccess; ++k) {
+        const int l = lists[k];
+        hipStream_t ls = k == 0 ? st : fs->side[k - 1];
+        if (k > 0) he = hipStreamWaitEvent(ls, fs->ev[11], 0);
+        if (he != hipSuccess) break;
+        tr.begin();
+        hipEvent_t ea = g_launch_ev[0], eb = g_launch_ev[1];
+        g_launch_ev[0] = g_launch_ev[1] = nullptr;
+        he = persist::launch_persistent(l % 6 + 1, l < 6 ? pl.lel : 2, l < 6, b->schedule, dg,
+                                        reinterpret_cast<const persist::Work *>(w + pl.o_work[l]),
+                                        int(pl.work[l].size()), next + l, B, pl.waves, ls, ea, eb);
+        if (ea) {
+            Tracer::last_[0] = ea;
+            Tracer::last_[1] = eb;
+        }
+        tr.end(K_PERSIST, 0, 0);
+        if (he == hipSuccess && k > 0) he = hipEventRecord(fs->ev[k - 1], ls);
+        if (he == hipSuccess && k > 0) he = hipStreamWaitEvent(st, fs->ev[k - 1], 0);
+    }
+    if (graph) {
+        hipGraph_t gr = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &gr);
+        if (he == hipSuccess) he = ec;
+        hipGraphExec_t ex = nullptr;
+        if (he == hipSuccess) he = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (he == hipSuccess) he = hipGraphLaunch(ex, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (gr) (void)hipGraphDestroy(gr);
+    }
+    if (he != hipSuccess) return fail(GFBP_EHIP, std::string("persistent launch: ") + hipGetErrorString(he));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tr.on) {
+        // algorithmic bytes and updates of the iterations the frames ran
+        std::vector<int32_t> it(F);
+        HIP_TRY(hipMemcpy(it.data(), out->iters, 4 * F, hipMemcpyDeviceToHost));
+        double bytes = 0, eq = 0;
+        for (size_t g = 0; g < pl.gcode.size(); ++g) {
+            const gfbp_code *code = codes[pl.gcode[g]];
+            const Bytes bp = bytes_per_frame(code, markov, b->syndrome != nullptr);
+            const double per = b->schedule == GFBP_PUS ? bp.check + bp.variable : bp.sequential;
+            for (int32_t f : pl.gframe[g]) {
+                bytes += double(it[size_t(f)]) * (per + bp.syndrome + (markov ? bp.markov : 0.0));
+                eq += double(it[size_t(f)]) * code->info.n_edges * code->info.q;
+            }
+        }
+        for (auto &r : tr.recs) {
+            r.bytes = bytes / double(tr.recs.size());
+            r.edgeq = eq / double(tr.recs.size());
+        }
+    }
+    tr.flush();
+    return GFBP_OK;
+}
+
+// Checks shared by both paths: the inputs each channel kind present needs.
+gfbp_status check_inputs(const gfbp_batch *b, hipStream_t st) {
+    bool kind[4] = {false, false, false, false};
+    if (b->channel_of) {
+        std::vector<uint8_t> ch(size_t(b->n_frames));
+        HIP_TRY(hipMemcpyAsync(ch.data(), b->channel_of, ch.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (uint8_t v : ch) {
+            if (v > GFBP_CH_LIKELIHOOD) return fail(GFBP_EINVAL, "bad channel kind in channel_of");
+            kind[v] = true;
+        }
+    } else {
+        if (b->channel < 0 || b->channel > GFBP_CH_LIKELIHOOD) return fail(GFBP_EINVAL, "bad channel");
+        kind[b->channel] = true;
+    }
+    const bool mn = b->evidence == GFBP_EVIDENCE_MN;
+    if (b->evidence != GFBP_EVIDENCE_SYMBOL && !mn) return fail(GFBP_EINVAL, "bad evidence mode");
+    if (kind[GFBP_CH_BSC] && ((!mn && !b->rx) || !b->param)) return fail(GFBP_EINVAL, "BSC needs rx and param");
+    if (kind[GFBP_CH_BEC] && ((!mn && !b->rx) || !b->erasure)) return fail(GFBP_EINVAL, "BEC needs rx and erasure");
+    if (kind[GFBP_CH_BIAWGN] && (!b->y || !b->param)) return fail(GFBP_EINVAL, "BI-AWGN needs y and param");
+    if (kind[GFBP_CH_LIKELIHOOD] && (!b->likelihood || mn))
+        return fail(GFBP_EINVAL, "LIKELIHOOD needs likelihood, and is not an MN evidence mode");
+    if (b->prior == GFBP_PRIOR_MARKOV && (!b->markov_M || !b->markov_pi))
+        return fail(GFBP_EINVAL, "Markov prior needs markov_M and markov_pi");
+    if (b->prior == GFBP_PRIOR_STATIC && !b->static_prior) return fail(GFBP_EINVAL, "static prior needs static_prior");
+    return GFBP_OK;
+}
+
+inline bool persistent_batch(const gfbp_batch *b) {
+    return b->n_codes > 1 || b->code_index != nullptr || (b->options & GFBP_OPT_PERSISTENT);
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -1102,7 +1489,7 @@ extern "C" {
 
 const char *gfbp_last_error(void) { return g_err.c_str(); }
 
-const char *gfbp_version(void) { return "gfbp 0.4 (gfx950)"; }
+const char *gfbp_version(void) { return "gfbp 0.5 (gfx950)"; }
 
 gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (!d || !out) return fail(GFBP_EINVAL, "null argument");
@@ -1164,9 +1551,27 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
         emap[2 * size_t(e) + 1] = wm;
     }
 
-    // SUS dependency levels: level(j) = 1 + the highest level among earlier
-    // columns sharing a check with j (0 if none); with chain = 1 source
-    // column k also comes after source column k-1.  Then the sequential-
+    // visiting order and source chain (defaults: 0..n-1 and 0..n_info-1)
+    const int K = d->n_info;
+    std::vector<int32_t> visit(n), chain_col(std::max(K, 1), 0), col_chain(n, -1), vpos(n, -1);
+    for (int t = 0; t < n; ++t) {
+        const int j = d->visit_order ? d->visit_order[t] : t;
+        if (j < 0 || j >= n || vpos[j] >= 0) return fail(GFBP_EINVAL, "visit_order is not a permutation of 0..n-1");
+        visit[t] = j;
+        vpos[j] = t;
+    }
+    for (int k = 0; k < K; ++k) {
+        const int j = d->source_cols ? d->source_cols[k] : k;
+        if (j < 0 || j >= n || col_chain[j] >= 0) return fail(GFBP_EINVAL, "source_cols out of range or repeated");
+        chain_col[k] = j;
+        col_chain[j] = k;
+    }
+
+    // SUS dependency levels, taking the columns in visiting order:
+    // level(j) = 1 + the highest level among columns visited earlier that
+    // share a check with j (0 if none); with chain = 1 a source column also
+    // comes after its chain neighbours visited earlier (their pseudo-
+    // posteriors of the same sweep give its prior).  Then the sequential-
     // schedule records, columns in level order, RS slots each.
     const int RS = std::max(1, max_dv);
     gfbp_code::Levels lvs[2];
@@ -1174,11 +1579,15 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     for (int chain = 0; chain < 2; ++chain) {
         std::vector<int32_t> level(n, 0), row_top(m, -1);
         int nlev = 0;
-        for (int j = 0; j < n; ++j) {
+        for (int t = 0; t < n; ++t) {
+            const int j = visit[t];
             int lv = 0;
-            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) lv = std::max(lv, row_top[edge_row[col_edge[t]]] + 1);
-            if (chain && j > 0 && j < d->n_info) lv = std::max(lv, level[j - 1] + 1);
-            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) row_top[edge_row[col_edge[t]]] = lv;
+            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) lv = std::max(lv, row_top[edge_row[col_edge[u]]] + 1);
+            const int k = col_chain[j];
+            if (chain && k >= 0)
+                for (int kk = k - 1; kk <= k + 1; kk += 2)
+                    if (kk >= 0 && kk < K && vpos[chain_col[kk]] < t) lv = std::max(lv, level[chain_col[kk]] + 1);
+            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) row_top[edge_row[col_edge[u]]] = lv;
             level[j] = lv;
             nlev = std::max(nlev, lv + 1);
         }
@@ -1191,12 +1600,13 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
         for (int j = 0; j < n; ++j) L.ptr[level[j] + 1]++;
         for (int l = 0; l < nlev; ++l) L.ptr[l + 1] += L.ptr[l];
         std::vector<int32_t> fillp(L.ptr.begin(), L.ptr.end() - 1);
-        for (int j = 0; j < n; ++j) {
+        for (int t = 0; t < n; ++t) {
+            const int j = visit[t];
             const int l = level[j];
             cols[fillp[l]++] = j;
-            L.src[l] += j < d->n_info ? 1.0 : 0.0;
-            for (int t = col_ptr[j]; t < col_ptr[j + 1]; ++t) {
-                const int i = edge_row[col_edge[t]];
+            L.src[l] += col_chain[j] >= 0 ? 1.0 : 0.0;
+            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) {
+                const int i = edge_row[col_edge[u]];
                 L.sibs[l] += d->row_ptr[i + 1] - d->row_ptr[i] - 1;
                 L.edges[l] += 1;
             }
@@ -1244,7 +1654,9 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     const size_t o_rp = take(4 * size_t(m + 1)), o_col = take(4 * size_t(E)), o_coef = take(size_t(E)),
                  o_cp = take(4 * size_t(n + 1)), o_ce = take(4 * size_t(E)), o_er = take(4 * size_t(E)),
                  o_mul = take(size_t(q) * q), o_em = take(16 * size_t(E)),
-                 o_sr0 = take(sizeof(SusRec) * recs[0].size()), o_sr1 = take(sizeof(SusRec) * recs[1].size());
+                 o_sr0 = take(sizeof(SusRec) * recs[0].size()), o_sr1 = take(sizeof(SusRec) * recs[1].size()),
+                 o_vis = take(4 * size_t(n)), o_cc = take(4 * chain_col.size()), o_colc = take(4 * size_t(n)),
+                 o_lp0 = take(4 * lvs[0].ptr.size()), o_lp1 = take(4 * lvs[1].ptr.size());
     if (hipMalloc(&c->mem, off) != hipSuccess) {
         delete c;
         return fail(GFBP_ENOMEM, "device allocation for the code");
@@ -1264,6 +1676,11 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (err == hipSuccess) err = up(o_em, emap.data(), 16 * size_t(E));
     if (err == hipSuccess) err = up(o_sr0, recs[0].data(), sizeof(SusRec) * recs[0].size());
     if (err == hipSuccess) err = up(o_sr1, recs[1].data(), sizeof(SusRec) * recs[1].size());
+    if (err == hipSuccess) err = up(o_vis, visit.data(), 4 * size_t(n));
+    if (err == hipSuccess) err = up(o_cc, chain_col.data(), 4 * chain_col.size());
+    if (err == hipSuccess) err = up(o_colc, col_chain.data(), 4 * size_t(n));
+    if (err == hipSuccess) err = up(o_lp0, lvs[0].ptr.data(), 4 * lvs[0].ptr.size());
+    if (err == hipSuccess) err = up(o_lp1, lvs[1].ptr.data(), 4 * lvs[1].ptr.size());
     if (err != hipSuccess) {
         (void)hipFree(c->mem);
         delete c;
@@ -1276,11 +1693,15 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     c->lv[1] = std::move(lvs[1]);
     c->lv[0].recs = reinterpret_cast<const SusRec *>(base + o_sr0);
     c->lv[1].recs = reinterpret_cast<const SusRec *>(base + o_sr1);
+    c->lv[0].dptr = reinterpret_cast<const int32_t *>(base + o_lp0);
+    c->lv[1].dptr = reinterpret_cast<const int32_t *>(base + o_lp1);
     c->dev = DevCode{n, m, E, q, p, d->n_info, max_dv,
                      reinterpret_cast<const int32_t *>(base + o_rp), reinterpret_cast<const int32_t *>(base + o_col),
                      reinterpret_cast<const uint8_t *>(base + o_coef), reinterpret_cast<const int32_t *>(base + o_cp),
                      reinterpret_cast<const int32_t *>(base + o_ce), reinterpret_cast<const int32_t *>(base + o_er),
-                     reinterpret_cast<const uint8_t *>(base + o_mul), reinterpret_cast<const uint64_t *>(base + o_em)};
+                     reinterpret_cast<const uint8_t *>(base + o_mul), reinterpret_cast<const uint64_t *>(base + o_em),
+                     reinterpret_cast<const int32_t *>(base + o_vis), reinterpret_cast<const int32_t *>(base + o_cc),
+                     reinterpret_cast<const int32_t *>(base + o_colc)};
     *out = c;
     return GFBP_OK;
 }
@@ -1304,38 +1725,48 @@ size_t gfbp_workspace_size(const gfbp_code *code, int32_t n_frames, int32_t sche
     return carve(code, n_frames, schedule, prior).total;
 }
 
-gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, void *workspace,
+size_t gfbp_batch_workspace_size(const gfbp_code *const *codes, const gfbp_batch *b) {
+    if (!codes || !b || b->n_frames < 0) return 0;
+    const int nc = b->n_codes > 0 ? b->n_codes : 1;
+    for (int k = 0; k < nc; ++k)
+        if (!codes[k]) return 0;
+    if (!persistent_batch(b)) return carve(codes[0], b->n_frames, b->schedule, b->prior).total;
+    PersistPlan pl;
+    if (persist_plan(codes, nc, b, pl) != GFBP_OK) return 0;
+    return pl.total;
+}
+
+gfbp_status gfbp_decode_batch(const gfbp_code *const *codes, const gfbp_batch *b, gfbp_result *out, void *workspace,
                               size_t ws_bytes, void *stream) {
-    if (!code || !b || !out) return fail(GFBP_EINVAL, "null argument");
+    if (!codes || !b || !out) return fail(GFBP_EINVAL, "null argument");
+    const int nc = b->n_codes > 0 ? b->n_codes : 1;
+    for (int k = 0; k < nc; ++k)
+        if (!codes[k]) return fail(GFBP_EINVAL, "null code");
+    const gfbp_code *code = codes[0];
     const int F = b->n_frames;
     if (F < 0) return fail(GFBP_EINVAL, "n_frames < 0");
     if (b->schedule != GFBP_PUS && b->schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
     if (b->max_iter < 1) return fail(GFBP_EINVAL, "max_iter < 1");
-    if (b->prior != GFBP_PRIOR_UNIFORM && b->prior != GFBP_PRIOR_MARKOV) return fail(GFBP_EINVAL, "bad prior");
+    if (b->prior != GFBP_PRIOR_UNIFORM && b->prior != GFBP_PRIOR_MARKOV && b->prior != GFBP_PRIOR_STATIC)
+        return fail(GFBP_EINVAL, "bad prior");
     if (F == 0) return GFBP_OK;
-    switch (b->channel) {
-        case GFBP_CH_BSC:
-            if (!b->rx || !b->param) return fail(GFBP_EINVAL, "BSC needs rx and param");
-            break;
-        case GFBP_CH_BEC:
-            if (!b->rx || !b->erasure) return fail(GFBP_EINVAL, "BEC needs rx and erasure");
-            break;
-        case GFBP_CH_BIAWGN:
-            if (!b->y || !b->param) return fail(GFBP_EINVAL, "BI-AWGN needs y and param");
-            break;
-        case GFBP_CH_LIKELIHOOD:
-            if (!b->likelihood) return fail(GFBP_EINVAL, "LIKELIHOOD needs likelihood");
-            break;
-        default:
-            return fail(GFBP_EINVAL, "bad channel");
-    }
-    if (b->prior == GFBP_PRIOR_MARKOV && (!b->markov_M || !b->markov_pi))
-        return fail(GFBP_EINVAL, "Markov prior needs markov_M and markov_pi");
+    if (b->prior == GFBP_PRIOR_MARKOV)
+        for (int k = 1; k < nc; ++k)
+            if (codes[k]->info.q != code->info.q)
+                return fail(GFBP_EINVAL, "a Markov prior's matrix is over one field: every code needs its q");
+    if (b->prior == GFBP_PRIOR_STATIC && nc > 1)
+        for (int k = 1; k < nc; ++k)
+            if (codes[k]->info.q != code->info.q || (b->static_per_symbol && codes[k]->info.n_info != code->info.n_info))
+                return fail(GFBP_EINVAL, "a static prior is over one field and chain length");
     if ((b->options & GFBP_OPT_PRIOR_IN_SWEEP) && b->schedule != GFBP_SUS)
         return fail(GFBP_EINVAL, "priors assigned during the sweep need the sequential schedule");
     if (!out->xhat || !out->iters || !out->converged) return fail(GFBP_EINVAL, "null output buffer");
     if (!workspace) return fail(GFBP_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(GFBP_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const gfbp_status ci = check_inputs(b, st);
+    if (ci != GFBP_OK) return ci;
+    if (persistent_batch(b)) return decode_persistent(codes, nc, b, out, workspace, ws_bytes, st);
     const Carve cv = carve(code, F, b->schedule, b->prior);
     if (ws_bytes < cv.total) return fail(GFBP_ESMALL, "workspace too small");
     char *w = static_cast<char *>(workspace);
@@ -1363,7 +1794,6 @@ gfbp_status gfbp_decode_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_r
     s.F = F;
     s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     switch (code->info.p) {
         case 1: return run_any<1>(code, b, out, s, a, st, needQ);
         case 2: return run_any<2>(code, b, out, s, a, st, needQ);
@@ -1397,6 +1827,9 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     gfbp_batch tb = *b;
     tb.max_iter = trial_iters;
     tb.early_stop = 0;
+    tb.n_codes = 1;
+    tb.code_index = nullptr;
+    tb.options &= ~GFBP_OPT_PERSISTENT;
     gfbp_result to = *out;
     to.posterior = nullptr;
     to.snap_iter = 0;
@@ -1411,7 +1844,8 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
         for (int l = 1; l <= nl; ++l) {
             c->el[slot] = 1 << l;
             const auto t0 = std::chrono::steady_clock::now();
-            const gfbp_status st = gfbp_decode_batch(c, &tb, &to, workspace, ws_bytes, stream);
+            const gfbp_code *cc[1] = {c};
+            const gfbp_status st = gfbp_decode_batch(cc, &tb, &to, workspace, ws_bytes, stream);
             if (st != GFBP_OK) {
                 c->el[slot] = keep;
                 return st;
@@ -1431,16 +1865,62 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     return GFBP_OK;
 }
 
+gfbp_status gfbp_tune_persistent(const gfbp_code *const *codes, const gfbp_batch *b, gfbp_result *out,
+                                 void *workspace, size_t ws_bytes, void *stream, int32_t trial_iters, int32_t *el,
+                                 int32_t *waves) {
+    if (!codes || !b || !out) return fail(GFBP_EINVAL, "null argument");
+    if (trial_iters < 1) return fail(GFBP_EINVAL, "trial_iters < 1");
+    gfbp_batch tb = *b;
+    tb.max_iter = trial_iters;
+    tb.early_stop = 0;
+    tb.options |= GFBP_OPT_PERSISTENT;
+    struct Cand {
+        int el, waves;
+    };
+    std::vector<Cand> cands;
+    for (int e : {4, 8})
+        for (int wv : {4, 8}) cands.push_back({e, wv});
+    constexpr int kRounds = 3;
+    std::vector<double> best_of(cands.size(), 1e300);
+    for (int round = -1; round < kRounds; ++round)
+        for (size_t k = 0; k < cands.size(); ++k) {
+            tb.persist_el = cands[k].el;
+            tb.persist_waves = cands[k].waves;
+            if (gfbp_batch_workspace_size(codes, &tb) > ws_bytes) continue;
+            const auto t0 = std::chrono::steady_clock::now();
+            const gfbp_status st = gfbp_decode_batch(codes, &tb, out, workspace, ws_bytes, stream);
+            if (st != GFBP_OK) return st;
+            const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (round >= 0) best_of[k] = std::min(best_of[k], t);
+        }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (best_of[k] < best_of[best]) best = k;
+    if (best_of[best] >= 1e300) return fail(GFBP_ESMALL, "workspace too small for every candidate shape");
+    if (el) *el = cands[best].el;
+    if (waves) *waves = cands[best].waves;
+    return GFBP_OK;
+}
+
 size_t gfbp_session_bytes(const gfbp_code *code, const gfbp_session_desc *d) {
-    if (!code || !d || d->n_slots < 1) return 0;
-    const int S = (d->n_slots + kWave - 1) / kWave * kWave;
+    if (!code || !d || d->n_slots < 0) return 0;
+    const int S = session_slots(code, d);
+    if (S < 1) return 0;
     return session_carve(code, S, d->schedule, d->markov_M != nullptr, d->has_syndrome).total;
+}
+
+uint64_t gfbp_device_clock_hz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) return 0;
+    return uint64_t(khz) * 1000u;
 }
 
 gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *d, gfbp_session **out) {
     if (!code || !d || !out) return fail(GFBP_EINVAL, "null argument");
     *out = nullptr;
-    if (d->n_slots < 1) return fail(GFBP_EINVAL, "n_slots < 1");
+    if (d->n_slots < 0 || (d->n_slots == 0 && d->device_bytes <= 0))
+        return fail(GFBP_EINVAL, "n_slots < 1 and no device_bytes budget");
     if (d->schedule != GFBP_PUS && d->schedule != GFBP_SUS) return fail(GFBP_EINVAL, "bad schedule");
     if (d->max_iter < 1) return fail(GFBP_EINVAL, "max_iter < 1");
     if ((d->markov_M == nullptr) != (d->markov_pi == nullptr)) return fail(GFBP_EINVAL, "markov_M and markov_pi go together");
@@ -1449,7 +1929,11 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
     gfbp_session *ss = new (std::nothrow) gfbp_session();
     if (!ss) return fail(GFBP_ENOMEM, "host allocation");
     ss->code = code;
-    ss->S = (d->n_slots + kWave - 1) / kWave * kWave;
+    ss->S = session_slots(code, d);
+    if (ss->S < 1) {
+        delete ss;
+        return fail(GFBP_ENOMEM, "device_bytes holds no 64-slot tile of this code's state");
+    }
     ss->schedule = d->schedule;
     ss->max_iter = d->max_iter;
     ss->has_z = d->has_syndrome != 0;
@@ -1475,7 +1959,7 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
         return fail(GFBP_ENOMEM, "device allocation for the session");
     }
     ss->bytes = cv.total;
-    const size_t pin_bytes = size_t(ss->S) * 6 * 4 + 256;
+    const size_t pin_bytes = size_t(ss->S) * 6 * 4 + size_t(ss->S) * 16 + 256;
     if (hipHostMalloc(&ss->pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(ss->mem);
         delete ss;
@@ -1521,6 +2005,9 @@ gfbp_status gfbp_session_create(const gfbp_code *code, const gfbp_session_desc *
     v.pairs = reinterpret_cast<int32_t *>(w + cv.pairs);
     v.list = reinterpret_cast<int32_t *>(w + cv.list);
     v.res = reinterpret_cast<int32_t *>(w + cv.res);
+    v.t_admit = reinterpret_cast<uint64_t *>(w + cv.t_admit);
+    v.t_done = reinterpret_cast<uint64_t *>(w + cv.t_done);
+    v.ts = reinterpret_cast<uint64_t *>(w + cv.ts);
     st.chan = v.chan;
     st.mark = v.mark;
     ss->ftiles = reinterpret_cast<int32_t *>(w + cv.ftiles);
@@ -1652,8 +2139,10 @@ gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat
     hipLaunchKernelGGL(k_collect, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, ss->dv, k, n);
     int32_t *hlist = static_cast<int32_t *>(ss->pin);
     int32_t *hres = hlist + ss->S;
+    uint64_t *hts = reinterpret_cast<uint64_t *>(hres + 2 * size_t(ss->S));  // 12 S bytes in: 8-byte aligned
     HIP_TRY(hipMemcpyAsync(hlist, ss->dv.list, sizeof(int32_t) * k, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(hres, ss->dv.res, sizeof(int32_t) * 2 * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hts, ss->dv.ts, sizeof(uint64_t) * 2 * k, hipMemcpyDeviceToHost, st));
     if (xhat) HIP_TRY(hipMemcpyAsync(xhat, ss->dv.xout, tot, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int r = 0; r < k; ++r) {
@@ -1661,6 +2150,8 @@ gfbp_status gfbp_session_poll(gfbp_session *ss, gfbp_retired *out, uint8_t *xhat
         out[r].id = ss->id[slot];
         out[r].iters = hres[2 * r];
         out[r].converged = hres[2 * r + 1];
+        out[r].t_admit = hts[2 * r];
+        out[r].t_retire = hts[2 * r + 1];
         ss->id[slot] = -1;
         ss->free_slots.push_back(slot);
     }

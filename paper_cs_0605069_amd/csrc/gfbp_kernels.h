@@ -33,6 +33,9 @@ struct DevCode {
     const int32_t *edge_row;  // [E]
     const uint8_t *mul;       // [q][q] field multiplication
     const uint64_t *emap;     // [E][2] images of x^b under h^-1 (word 0) and h (word 1), 6 bits each
+    const int32_t *visit;     // [n] SUS visiting order of the columns
+    const int32_t *chain_col; // [n_info] column of source symbol k (the Markov chain's order)
+    const int32_t *col_chain; // [n] source symbol held by column j, or -1
 };
 
 // One edge slot of a column in the sequential schedule, precomputed so that

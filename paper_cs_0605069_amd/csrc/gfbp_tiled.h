@@ -285,20 +285,6 @@ __device__ __forceinline__ double lanes_sum(double v) {
     }
 }
 
-template <int P, int LG, int B = 0>
-__device__ __forceinline__ int lanes_argmax(float v, int k) {
-    using Gm = Geo<P, LG>;
-    if constexpr (B < LG) {
-        constexpr int mask = Gm::TF << B;
-        const float ov = xchg<mask>(v);
-        const int ok = xchg<mask>(k);
-        const bool take = ov > v || (ov == v && ok < k);
-        return lanes_argmax<P, LG, B + 1>(take ? ov : v, take ? ok : k);
-    } else {
-        return k;
-    }
-}
-
 // Normalise the distributed vector to sum 1; uniform (and a guard event) when
 // the sum is zero or not finite.
 template <int P, int LG>
@@ -347,52 +333,82 @@ __device__ __forceinline__ void r_from_transform(const DevCode &c, size_t e, con
     lds_permute<P, LG>(perm, it, pos, tv, rv);
 }
 
+// Where a frame's inputs are.  Batch-wide kinds, overridden per frame by
+// chan_of (indexed by frame) or, in sessions, by DevState::chan (by slot).
+// In a batch over several codes a slot f of one code's state holds frame
+// gframe[f] of the batch, whose per-symbol inputs (rx, erasure, y: n entries,
+// or n*p samples) start at element off_n[frame] (times p for y) and whose
+// likelihood vectors start at off_nq[frame]; null: slot f is frame f at f*n.
 struct Chan {
-    int channel, markov;
+    int channel;              // GFBP_CH_*
+    int prior;                // GFBP_PRIOR_* of the source symbols
+    int evidence;             // GFBP_EVIDENCE_*
+    int static_per_symbol;    // static prior: one vector per source symbol
     const uint8_t *rx, *erasure;
-    const float *y, *lik, *param, *pi;
+    const float *y, *lik, *param, *pi, *static_P;
+    const uint8_t *chan_of;   // [frames] channel kind of each frame, or null
+    const int32_t *gframe;    // [F] frame held by slot f, or null
+    const int64_t *off_n;     // [frames] or null
+    const int64_t *off_nq;    // [frames] or null
 };
 
-// A1 channel likelihood and A2 initialisation for column j of frame f:
-// L_j(a) = P(received | x_j = a) as a product over the p transmitted bits;
-// p_j = L_j (times the stationary Markov marginal pi for source symbols);
+// A1 channel evidence and A2 initialisation of column j for the lane's frame:
+// L_j(a), the probability of what was received given x_j = a, as a product
+// over the p transmitted bits; in the syndrome form of Section 2 (evidence
+// GFBP_EVIDENCE_MN) a source column has no channel evidence (L_j = 1) and
+// every other column is a noise symbol n_j, whose evidence is the
+// probability of n_j = a given the channel output at column j: for the BSC
+// the noise prior f^w (1-f)^(p-w), w the number of ones of a; for the BEC
+// each unerased bit has noise 0 and an erased bit (read as 0) has noise equal
+// to the unknown sent bit, 0 or 1 alike; for BI-AWGN the received bit is the
+// sign of y, so noise bit 0 has probability 1/(1 + exp(-2|y|/sigma^2)).
+// p_j = L_j, or for source symbol k = col_chain[j] with a prior
+// p_j = norm(L_j P_k), P_k = pi (Markov, iteration 1) or the static prior;
 // every edge of column j starts with q_e = p_j.
 template <int P, int LG>
-__global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch) {
+__device__ __forceinline__ void init_column(const DevCode &c, const DevState &s, const Chan &ch, const Item &it,
+                                            float *perm) {
     using Gm = Geo<P, LG>;
-    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
-    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
-    const Item it = item<P, LG>(c.n, s);
-    if (!it.ok || it.f >= s.F) return;
-    if (s.fresh && !s.fresh[it.f]) return;
     const int j = it.node, f = it.f;
-    const size_t fj = size_t(f) * c.n + j;
-    const int channel = s.chan ? int(s.chan[f]) : ch.channel;
-    const bool markov = s.mark ? s.mark[f] != 0 : ch.markov != 0;
+    const int gf = ch.gframe ? ch.gframe[f] : f;
+    const size_t fj = (ch.off_n ? size_t(ch.off_n[gf]) : size_t(gf) * c.n) + size_t(j);
+    const int channel = s.chan ? int(s.chan[f]) : ch.chan_of ? int(ch.chan_of[gf]) : ch.channel;
+    const int k = c.col_chain[j];
+    const bool prior_on = (s.mark ? s.mark[f] != 0 : ch.prior != GFBP_PRIOR_UNIFORM) && k >= 0;
     double L[Gm::EL];
-    if (channel == GFBP_CH_BSC || channel == GFBP_CH_BEC) {
-        const int rx = ch.rx[fj];
-        const int er = channel == GFBP_CH_BEC ? ch.erasure[fj] : 0;
-        const double fl = channel == GFBP_CH_BSC ? double(ch.param[f]) : 0.0;
+    if (ch.evidence == GFBP_EVIDENCE_MN && k >= 0) {
+#pragma unroll
+        for (int r = 0; r < Gm::EL; ++r) L[r] = 1.0;
+    } else if (channel == GFBP_CH_BSC) {
+        const double fl = double(ch.param[gf]);
+        const int ref = ch.evidence == GFBP_EVIDENCE_MN ? 0 : int(ch.rx[fj]);  // noise: weight of a itself
 #pragma unroll
         for (int r = 0; r < Gm::EL; ++r) {
             const int a = it.g * Gm::EL + r;
             double v = 1.0;
 #pragma unroll
-            for (int t = 0; t < P; ++t) {
-                const bool flip = ((a ^ rx) >> t) & 1;
-                if (channel == GFBP_CH_BSC) v *= flip ? fl : (1.0 - fl);
-                else v *= ((er >> t) & 1) ? 0.5 : (flip ? 0.0 : 1.0);
-            }
+            for (int t = 0; t < P; ++t) v *= (((a ^ ref) >> t) & 1) ? fl : (1.0 - fl);
+            L[r] = v;
+        }
+    } else if (channel == GFBP_CH_BEC) {
+        const int ref = ch.evidence == GFBP_EVIDENCE_MN ? 0 : int(ch.rx[fj]);
+        const int er = ch.erasure[fj];
+#pragma unroll
+        for (int r = 0; r < Gm::EL; ++r) {
+            const int a = it.g * Gm::EL + r;
+            double v = 1.0;
+#pragma unroll
+            for (int t = 0; t < P; ++t) v *= ((er >> t) & 1) ? 0.5 : ((((a ^ ref) >> t) & 1) ? 0.0 : 1.0);
             L[r] = v;
         }
     } else if (channel == GFBP_CH_BIAWGN) {
-        const double sg = ch.param[f];
+        const double sg = ch.param[gf];
         const double gain = 2.0 / (sg * sg);
         double p0[P], p1[P];
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const double yb = ch.y[fj * P + t];
+            double yb = ch.y[fj * P + t];
+            if (ch.evidence == GFBP_EVIDENCE_MN) yb = fabs(yb);  // bit 0 of the noise: y has the sent sign
             p1[t] = 1.0 / (1.0 + exp(gain * yb));   // P(bit = 1 | y): bit 1 was sent as -1
             p0[t] = 1.0 / (1.0 + exp(-gain * yb));  // P(bit = 0 | y)
         }
@@ -405,35 +421,48 @@ __global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch)
             L[r] = v;
         }
     } else {
+        const size_t base = ch.off_nq ? size_t(ch.off_nq[gf]) + size_t(j) * Gm::Q : fj * Gm::Q;
 #pragma unroll
-        for (int r = 0; r < Gm::EL; ++r) L[r] = ch.lik[fj * Gm::Q + it.g * Gm::EL + r];
+        for (int r = 0; r < Gm::EL; ++r) L[r] = ch.lik[base + it.g * Gm::EL + r];
     }
     normalise<P, LG>(L, s.guards, f, it.g);
     float pf[Gm::EL];
 #pragma unroll
     for (int r = 0; r < Gm::EL; ++r) pf[r] = float(L[r]);
     st<Gm::EL>(chunk<P, LG>(s.L, j, s.Fp, it), pf);
-    if (markov && j < c.n_info) {
+    if (prior_on) {
+        const float *P0 = ch.prior == GFBP_PRIOR_MARKOV
+                              ? ch.pi
+                              : ch.static_P + (ch.static_per_symbol ? size_t(k) * Gm::Q : size_t(0));
         double pr[Gm::EL];
 #pragma unroll
-        for (int r = 0; r < Gm::EL; ++r) pr[r] = double(pf[r]) * double(ch.pi[it.g * Gm::EL + r]);
+        for (int r = 0; r < Gm::EL; ++r) pr[r] = double(pf[r]) * double(P0[it.g * Gm::EL + r]);
         normalise<P, LG>(pr, s.guards, f, it.g);
 #pragma unroll
         for (int r = 0; r < Gm::EL; ++r) pf[r] = float(pr[r]);
-        st<Gm::EL>(chunk<P, LG>(s.Pr, j, s.Fp, it), pf);
+        st<Gm::EL>(chunk<P, LG>(s.Pr, size_t(k), s.Fp, it), pf);
     }
     for (int t = c.col_ptr[j]; t < c.col_ptr[j + 1]; ++t) store_q<P, LG>(c, s, size_t(c.col_edge[t]), it, pf, perm);
 }
 
-// A3, parallel schedule: all r of check i from the previous iteration's q.
-// DCM bounds the row degree: the siblings' transforms stay in registers.
-template <int P, int LG, int DCM>
-__global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const uint8_t *z, Snap snap) {
+template <int P, int LG>
+__global__ __launch_bounds__(kBlock) void k_init(DevCode c, DevState s, Chan ch) {
     using Gm = Geo<P, LG>;
     __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
     float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
-    const Item it = item<P, LG>(c.m, s);
-    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    const Item it = item<P, LG>(c.n, s);
+    if (!it.ok || it.f >= s.F) return;
+    if (s.fresh && !s.fresh[it.f]) return;
+    init_column<P, LG>(c, s, ch, it, perm);
+}
+
+// A3, parallel schedule: all r of check i (it.node) from the previous
+// iteration's q.  DCM bounds the row degree: the siblings' transforms stay in
+// registers.
+template <int P, int LG, int DCM>
+__device__ __forceinline__ void check_node(const DevCode &c, const DevState &s, const uint8_t *z, const Snap &snap,
+                                           const Item &it, float *perm) {
+    using Gm = Geo<P, LG>;
     const int i = it.node, f = it.f;
     const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
     const int zi = z ? z[size_t(f) * c.m + i] : 0;
@@ -468,19 +497,68 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
     }
 }
 
+template <int P, int LG, int DCM>
+__global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const uint8_t *z, Snap snap) {
+    using Gm = Geo<P, LG>;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
+    const Item it = item<P, LG>(c.m, s);
+    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    check_node<P, LG, DCM>(c, s, z, snap, it, perm);
+}
+
+// The lane's entries of the prior-weighted evidence p_j of column j: the
+// source symbol's prior row when the frame takes a prior, else L_j.
+template <int P, int LG>
+__device__ __forceinline__ const float *prior_row(const DevCode &c, const DevState &s, const Item &it, int j,
+                                                  int prior_on) {
+    const int k = c.col_chain[j];
+    const bool pr = (s.mark ? s.mark[it.f] != 0 : prior_on != 0) && k >= 0;
+    return pr ? chunk<P, LG>(s.Pr, size_t(k), s.Fp, it) : chunk<P, LG>(s.L, size_t(j), s.Fp, it);
+}
+
+// Clipping (A5): the symbol of largest pseudo-posterior, the smallest one
+// among exact maxima, from the frame's normalised double-precision vector
+// distributed over its lanes.
+template <int P, int LG, int B = 0>
+__device__ __forceinline__ int lanes_argmax(double v, int k) {
+    using Gm = Geo<P, LG>;
+    if constexpr (B < LG) {
+        constexpr int mask = Gm::TF << B;
+        const double ov = xchg<mask>(v);
+        const int ok = xchg<mask>(k);
+        const bool take = ov > v || (ov == v && ok < k);
+        return lanes_argmax<P, LG, B + 1>(take ? ov : v, take ? ok : k);
+    } else {
+        return k;
+    }
+}
+
+template <int P, int LG>
+__device__ __forceinline__ int clip(const double *acc, int g) {
+    using Gm = Geo<P, LG>;
+    int best = g * Gm::EL;
+    double bv = acc[0];
+#pragma unroll
+    for (int q = 1; q < Gm::EL; ++q)
+        if (acc[q] > bv) {
+            bv = acc[q];
+            best = g * Gm::EL + q;
+        }
+    return lanes_argmax<P, LG>(bv, best);
+}
+
 // A4 variable-node update of column j from its r-messages r[d][.] (natural
 // order): the pseudo-posterior Q_j (Eq. (5)) and its decision, then each
 // edge's q (Eq. (4)), normalised.
 template <int P, int LG, int DVM>
 __device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, const Item &it, int j,
-                                                const float (*r)[Geo<P, LG>::EL], int cs, int dv, int markov,
+                                                const float (*r)[Geo<P, LG>::EL], int cs, int dv, int prior_on,
                                                 int wantQ, const Snap &snap, float *perm) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
-    const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
-    const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
     float pf[Gm::EL];
-    ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
+    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, prior_on), pf);
     double pv[Gm::EL], acc[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
@@ -494,16 +572,13 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
             for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(r[d][q]);
         }
     normalise<P, LG>(acc, s.guards, f, it.g);
-    int best = it.g * Gm::EL;
-    float bv = float(acc[0]);
-    float Qf[Gm::EL];
+    if (wantQ) {
+        float Qf[Gm::EL];
 #pragma unroll
-    for (int q = 0; q < Gm::EL; ++q) {
-        Qf[q] = float(acc[q]);
-        if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
+        for (int q = 0; q < Gm::EL; ++q) Qf[q] = float(acc[q]);
+        st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
     }
-    if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
-    best = lanes_argmax<P, LG>(bv, best);
+    const int best = clip<P, LG>(acc, it.g);
     if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
 #pragma unroll
     for (int d = 0; d < DVM; ++d) {
@@ -530,21 +605,28 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
     }
 }
 
-// A4, parallel schedule: every column from this iteration's r.
+// A4, parallel schedule: column it.node from this iteration's r.
 template <int P, int LG, int DVM>
-__global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int markov, int wantQ, Snap snap) {
+__device__ __forceinline__ void variable_node(const DevCode &c, const DevState &s, int prior_on, int wantQ,
+                                              const Snap &snap, const Item &it, float *perm) {
     using Gm = Geo<P, LG>;
-    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
-    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
-    const Item it = item<P, LG>(c.n, s);
-    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
     const int j = it.node;
     const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
     float r[DVM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DVM; ++d)
         if (d < dv) ld<Gm::EL>(chunk<P, LG>(s.R, size_t(c.col_edge[cs + d]), s.Fp, it), r[d]);
-    variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, markov, wantQ, snap, perm);
+    variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, prior_on, wantQ, snap, perm);
+}
+
+template <int P, int LG, int DVM>
+__global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int prior_on, int wantQ, Snap snap) {
+    using Gm = Geo<P, LG>;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
+    const Item it = item<P, LG>(c.n, s);
+    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    variable_node<P, LG, DVM>(c, s, prior_on, wantQ, snap, it, perm);
 }
 
 // A6 sequential schedule, the step of one column for one tile of frames,
@@ -560,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
 // instantiation, so the default one carries none of its code or registers).
 template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
 __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, const uint8_t *z, const Item &it,
-                                           bool live, const SusRec &rec, int markov, int wantQ, const Snap &snap,
+                                           bool live, const SusRec &rec, int prior_on, int wantQ, const Snap &snap,
                                            const SweepPrior &sp, float *perm, float *rsh) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
@@ -571,15 +653,16 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
     const size_t e = size_t(rec.e);
     float pf[Gm::EL];
     if (mine || post) {
-        const bool mk = s.mark ? s.mark[f] != 0 : markov != 0;
-        if (SWEEP_PRIOR && sp.on && mk && j < c.n_info) {
-            // the prior assigned at this column's vertical pass, from Q_{j-1}
-            // of this sweep (an earlier level) and Q_{j+1} of the last (a
-            // later level): source columns lie on increasing levels
-            markov_prior<P, LG>(c, s, it, j, sp.M, sp.pi, sp.mshape, pf);
+        const int k = c.col_chain[j];
+        const bool mk = (s.mark ? s.mark[f] != 0 : prior_on != 0) && k >= 0;
+        if (SWEEP_PRIOR && sp.on && mk) {
+            // the prior assigned at this column's vertical pass, from the
+            // chain neighbours' newest pseudo-posteriors: a neighbour visited
+            // earlier in the sweep sits on a lower level, one visited later
+            // on a higher level
+            markov_prior<P, LG>(c, s, it, k, sp.M, sp.pi, sp.mshape, pf);
         } else {
-            const float *pj = (mk && j < c.n_info) ? s.Pr : s.L;
-            ld<Gm::EL>(chunk<P, LG>(pj, size_t(j), s.Fp, it), pf);
+            ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, prior_on), pf);
         }
     }
     if (mine) {
@@ -628,16 +711,13 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
                 for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(rsh[(d2 * Gm::EL + q) * kWave + lane]);
             }
         normalise<P, LG>(acc, s.guards, f, it.g);
-        int best = it.g * Gm::EL;
-        float bv = float(acc[0]);
-        float Qf[Gm::EL];
+        if (wantQ) {
+            float Qf[Gm::EL];
 #pragma unroll
-        for (int q = 0; q < Gm::EL; ++q) {
-            Qf[q] = float(acc[q]);
-            if (Qf[q] > bv) { bv = Qf[q]; best = it.g * Gm::EL + q; }
+            for (int q = 0; q < Gm::EL; ++q) Qf[q] = float(acc[q]);
+            st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
         }
-        if (wantQ) st<Gm::EL>(chunk<P, LG>(s.Qp, size_t(j), s.Fp, it), Qf);
-        best = lanes_argmax<P, LG>(bv, best);
+        const int best = clip<P, LG>(acc, it.g);
         if (it.g == 0) s.xh[size_t(j) * s.Fp + f] = uint8_t(best);
     }
     if (mine) {
@@ -672,7 +752,7 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
 // (blockDim = 64 x the largest column degree, at most DVM wavefronts; recs
 // holds rstride >= that many slots per column).
 template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
-__global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int markov,
+__global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s, const uint8_t *z, int prior_on,
                                                           int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
                                                           int rstride, int ncols) {
     using Gm = Geo<P, LG>;
@@ -683,7 +763,7 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
     const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const SusRec rec = recs[size_t(it.node) * rstride + d];
     const bool live = it.f < s.F && s.active[it.f];
-    sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, perm + d * Gm::PERM,
+    sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, prior_on, wantQ, snap, sp, perm + d * Gm::PERM,
                                              rsh);
 }
 
@@ -693,7 +773,7 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_level(DevCode c, DevState s,
 // depends only on columns of this frame at lower levels, which come earlier
 // in the run or in an earlier launch.
 template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
-__global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, const uint8_t *z, int markov,
+__global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, const uint8_t *z, int prior_on,
                                                         int wantQ, Snap snap, SweepPrior sp, const SusRec *recs,
                                                         int rstride, int ncols) {
     using Gm = Geo<P, LG>;
@@ -706,14 +786,15 @@ __global__ __launch_bounds__(DVM *kWave) void k_sus_run(DevCode c, DevState s, c
     float *mine = perm + d * Gm::PERM;
     for (int p = 0; p < ncols; ++p) {
         const SusRec rec = recs[size_t(p) * rstride + d];
-        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
+        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, prior_on, wantQ, snap, sp, mine, rsh);
         __syncthreads();  // rsh and the LDS rows are reused by the next column
     }
 }
 
-// A6, strict order: columns 0..n-1 one after the other for each tile.
+// A6, strict order: the columns in visiting order, one after the other, for
+// each tile.
 template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
-__global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int markov,
+__global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s, const uint8_t *z, int prior_on,
                                                            int wantQ, Snap snap, SweepPrior sp) {
     using Gm = Geo<P, LG>;
     __shared__ __align__(16) float perm[DVM * Gm::PERM];
@@ -723,7 +804,8 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
     const bool live = it.f < s.F && s.active[it.f];
     const int d = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     float *mine = perm + d * Gm::PERM;
-    for (int j = 0; j < c.n; ++j) {
+    for (int t = 0; t < c.n; ++t) {
+        const int j = c.visit[t];
         SusRec rec{};
         rec.j = j;
         const int cs = c.col_ptr[j];
@@ -737,14 +819,15 @@ __global__ __launch_bounds__(DVM *kWave) void k_sequential(DevCode c, DevState s
             rec.hinv = c.emap[2 * size_t(rec.e)];
             rec.h = c.emap[2 * size_t(rec.e) + 1];
         }
-        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, markov, wantQ, snap, sp, mine, rsh);
+        sus_column<P, LG, DCM, DVM, SWEEP_PRIOR>(c, s, z, it, live, rec, prior_on, wantQ, snap, sp, mine, rsh);
         __syncthreads();  // rsh and the LDS rows are reused by the next column
     }
 }
 
 // A7 dynamical block prior (Eq. (7)) for source symbol k of frame it.f,
-// from the current pseudo-posteriors of its chain neighbours in Qp, times the
-// channel likelihood, into pf (both normalised).
+// from the current pseudo-posteriors of its chain neighbours k-1 and k+1 (at
+// columns chain_col[k -+ 1]) in Qp, times the evidence of its own column,
+// into pf (both normalised).
 //
 // mshape (from k_markov_shape): when M = s I + o (J - I) (every diagonal entry
 // s, every other entry o, as for a source that keeps its symbol or moves to
@@ -775,7 +858,7 @@ __device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int kk = h == 0 ? k - 1 : k + 1;
-            if (kk >= 0 && kk < K) ld<Gm::EL>(chunk<P, LG>(s.Qp, size_t(kk), s.Fp, it), nb[h]);
+            if (kk >= 0 && kk < K) ld<Gm::EL>(chunk<P, LG>(s.Qp, size_t(c.chain_col[kk]), s.Fp, it), nb[h]);
             else
 #pragma unroll
                 for (int q = 0; q < Gm::EL; ++q) nb[h][q] = 0.0f;
@@ -792,7 +875,8 @@ __device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s
     } else {
         // the whole neighbour vectors (every lane of the frame reads all q entries)
         if (k > 0) {
-            const float *qp = s.Qp + size_t(k - 1) * s.Fp * Gm::Q + fo;
+            const float *qp = s.Qp + size_t(c.chain_col[k - 1]) * s.Fp * Gm::Q + fo;
+#pragma unroll 2
             for (int a = 0; a < Gm::Q; ++a) {
                 const double qa = qp[a];
 #pragma unroll
@@ -800,7 +884,8 @@ __device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s
             }
         }
         if (k < K - 1) {
-            const float *qp = s.Qp + size_t(k + 1) * s.Fp * Gm::Q + fo;
+            const float *qp = s.Qp + size_t(c.chain_col[k + 1]) * s.Fp * Gm::Q + fo;
+#pragma unroll 2
             for (int cc = 0; cc < Gm::Q; ++cc) {
                 const double qc = qp[cc];
 #pragma unroll
@@ -812,7 +897,7 @@ __device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s
     for (int q = 0; q < Gm::EL; ++q) u[q] *= v[q];
     normalise<P, LG>(u, s.guards, it.f, it.g);
     float lf[Gm::EL];
-    ld<Gm::EL>(chunk<P, LG>(s.L, size_t(k), s.Fp, it), lf);
+    ld<Gm::EL>(chunk<P, LG>(s.L, size_t(c.chain_col[k]), s.Fp, it), lf);
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) u[q] *= double(lf[q]);
     normalise<P, LG>(u, s.guards, it.f, it.g);
@@ -836,7 +921,7 @@ __global__ __launch_bounds__(kBlock) void k_markov(DevCode c, DevState s, const 
 // Shape of the Markov matrix for k_markov: out = {1, s, o} when every
 // diagonal entry of M (q x q) equals s and every other entry o, else {0, 0, 0}.
 // One wavefront.
-__global__ __launch_bounds__(kWave) void k_markov_shape(const float *M, int q, float *out) {
+static __global__ __launch_bounds__(kWave) void k_markov_shape(const float *M, int q, float *out) {
     const float sd = M[0], od = q > 1 ? M[1] : 0.0f;
     bool ok = true;
     for (int t = int(threadIdx.x); t < q * q; t += kWave) ok &= M[t] == ((t / q == t % q) ? sd : od);
@@ -853,7 +938,7 @@ __global__ __launch_bounds__(kWave) void k_markov_shape(const float *M, int q, f
 // set (frames still iterating; or frames just admitted), and its length.  One
 // workgroup of 1024 threads; wavefront ballots and a workgroup scan keep the
 // list in increasing tile order.
-__global__ __launch_bounds__(1024) void k_tiles(const uint8_t *mask, int F, int Fp, int TF, int32_t *out,
+static __global__ __launch_bounds__(1024) void k_tiles(const uint8_t *mask, int F, int Fp, int TF, int32_t *out,
                                                 uint32_t *count) {
     __shared__ uint32_t wsum[1024 / kWave];
     __shared__ uint32_t base;

@@ -63,7 +63,26 @@ def test_null_arguments():
     assert L.gfbp_code_build(None, None) == -1
     assert L.gfbp_decode_batch(None, None, None, None, 0, None) == -1
     assert L.gfbp_workspace_size(None, 10, 0, 0) == 0
+    assert L.gfbp_batch_workspace_size(None, None) == 0
+    assert L.gfbp_tune_persistent(None, None, None, None, 0, None, 1, None, None) == -1
     assert L.gfbp_code_free(None) == 0
+
+
+@pytest.mark.parametrize("field,value", [("visit_order", [0, 1, 2, 3, 4, 4]), ("visit_order", [0, 1, 2, 3, 4, 6]),
+                                         ("source_cols", [1, 1]), ("source_cols", [0, 7])])
+def test_code_build_rejects_bad_orders(field, value):
+    """A visiting order that is not a permutation of the columns, or a
+    source chain with a repeated or out-of-range column, is refused before
+    any device work."""
+    import paper_cs_0605069_amd as gfbp
+
+    d, keep = _desc(gfbp)
+    d.n_info = 2
+    arr = np.asarray(value, dtype=np.int32)
+    setattr(d, field, arr.ctypes.data)
+    h = ctypes.c_void_p()
+    assert gfbp.lib().gfbp_code_build(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert h.value is None and field.split("_")[0] in gfbp.last_error()
 
 
 def _header_defines():
@@ -93,8 +112,9 @@ def test_binding_constants_match_the_header():
         short = name[len("GFBP_"):]
         if hasattr(gfbp, short):
             assert getattr(gfbp, short) == val, name
-    for short in ("OPT_SUS_STRICT", "OPT_NO_COMPACT", "OPT_STEP_GRAPHS", "OPT_PRIOR_IN_SWEEP", "PUS", "SUS",
-                  "CH_BSC", "CH_BEC", "CH_BIAWGN", "CH_LIKELIHOOD", "PRIOR_UNIFORM", "PRIOR_MARKOV"):
+    for short in ("OPT_SUS_STRICT", "OPT_NO_COMPACT", "OPT_STEP_GRAPHS", "OPT_PRIOR_IN_SWEEP", "OPT_PERSISTENT", "PUS",
+                  "SUS", "CH_BSC", "CH_BEC", "CH_BIAWGN", "CH_LIKELIHOOD", "PRIOR_UNIFORM", "PRIOR_MARKOV",
+                  "PRIOR_STATIC", "EVIDENCE_SYMBOL", "EVIDENCE_MN"):
         assert "GFBP_" + short in d and getattr(gfbp, short) == d["GFBP_" + short], short
 
 

@@ -1,16 +1,17 @@
-"""Uneven batches as one HIP graph, against the plain per-code kernels.
+"""Uneven batches: the persistent work-list kernel, against the plain kernels
+and the reference decoder; and sessions as one HIP graph.
 
-Frames of several codes (q in {4, 16, 64}, column weight 2-3, rate 1/3-1/2,
-different lengths) and channels (BSC, BEC, BI-AWGN at 1-2 dB, capacity
-matched) go into one session per code; the kernel shape of each code is
-autotuned on its frames; one HIP graph holds several iterations of every
-session and is replayed, with eager polls between replays, until every frame
-has finished.  Each frame must equal, bitwise, its gfbp_decode_batch result.
+The persistent path (GFBP_OPT_PERSISTENT, and every batch over several codes)
+must give, frame by frame, bitwise the decisions, iteration counts,
+convergence flags and guard counts of the plain kernels: same device
+functions, same arithmetic order.
 """
 import numpy as np
 import pytest
 
+import oracle
 from paper_cs_0605069_amd import workloads as wl
+from tests._parity import classify, gpu_decode, sched
 
 pytestmark = pytest.mark.gpu
 
@@ -33,13 +34,136 @@ def _groups(code, F, seed):
     out = []
     for k, kind in enumerate(("bsc", "bec", "biawgn")):
         nf = F // 3 + (1 if k < F % 3 else 0)
+        if nf == 0:
+            continue
         eb = rng.uniform(1.0, 2.0, size=nf)
         prm = np.array([wl.channel_for(kind, e, rate) for e in eb])
         out.append(wl.make_coset_frames(code, nf, seed * 10 + k, kind, prm))
     return out
 
 
+_CASES = [
+    # q, n, channel, prior, syndrome, schedule
+    (4, 300, "bsc", "uniform", False, "pus"), (4, 300, "bsc", "uniform", False, "sus"),
+    (16, 400, "biawgn", "markov", True, "pus"), (16, 400, "biawgn", "markov", True, "sus"),
+    (64, 240, "bec", "static", True, "sus"), (2, 600, "biawgn", "uniform", True, "sus"),
+    (8, 360, "bsc", "markov", False, "sus"), (32, 200, "bsc", "uniform", True, "pus"),
+]
+
+
+@pytest.mark.parametrize("q,n,channel,prior,syn,schedule", _CASES)
+@pytest.mark.parametrize("el,waves", [(4, 8), (8, 4)])
+def test_persistent_equals_plain(gfbp, q, n, channel, prior, syn, schedule, el, waves):
+    code, enc = wl.regular_code(n, 3, 6, q, seed=80 + q)
+    M = wl.self_transition_matrix(q, 0.7)
+    kw = {}
+    if prior == "markov":
+        kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M))
+    elif prior == "static":
+        kw = dict(prior="static", static_prior=np.random.default_rng(81).dirichlet(np.ones(q), size=code.n_info))
+    param = {"bsc": 0.07, "bec": 0.4, "biawgn": 0.8}[channel]
+    fr = wl.make_frames(code, enc, 333, 82 + q, channel, param, source="markov" if prior == "markov" else "iid",
+                        markov=M if prior == "markov" else None)
+    if syn:  # a random syndrome per frame (coset decoding)
+        fr = wl.make_coset_frames(code, 333, 84 + q, channel, param)
+    dfr = gfbp.frames_to_device(fr)
+    a = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, **kw)
+    b = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, persistent=True, persist_el=el, persist_waves=waves, **kw)
+    for k in ("xhat", "iters", "converged", "guards"):
+        assert np.array_equal(a[k], b[k]), f"{k}: persistent and plain differ"
+
+
+def test_persistent_mn_form_per_frame_channels(gfbp):
+    """The syndrome form (the decoder computes the noise evidence) with the
+    frames' channel kinds given per frame, plain against persistent."""
+    import torch
+
+    q = 8
+    code = wl.mn_code(60, 180, q, seed=90)
+    M, start = wl.lift_binary_chain(wl.PAPER_MARKOV_2S, 3)
+    parts = [wl.make_mn_frames(code, 40, 91 + k, ch, prm, source="markov", markov=M, start=start)
+             for k, (ch, prm) in enumerate((("bsc", 0.15), ("bec", 0.5), ("biawgn", 1.0)))]
+    dfr = gfbp.ragged_frames(parts, [code] * 3)
+    kw = dict(prior="markov", markov_M=M, markov_pi=start, max_iter=60)
+    for sch in ("pus", "sus"):
+        a = gpu_decode(gfbp, code, dfr, sch, **kw)
+        b = gpu_decode(gfbp, code, dfr, sch, persistent=True, **kw)
+        for k in ("xhat", "iters", "converged", "guards"):
+            assert np.array_equal(a[k], b[k]), f"{sch} {k}"
+        o = 0
+        for p in parts:  # and each channel's frames alone (a batch-wide channel)
+            c = gpu_decode(gfbp, code, gfbp.frames_to_device(p), sch, **kw)
+            assert np.array_equal(c["xhat"], a["xhat"][o:o + p.F]) and np.array_equal(c["iters"], a["iters"][o:o + p.F])
+            o += p.F
+    assert torch.cuda.is_available()
+
+
+def _pool_batch(gfbp, n_codes, frames, seed, nmax, with_big):
+    """Frames over a pool of codes (q in {4, 16, 64}); returns the codes, the
+    per-code frame groups and the batch's code index (frames of one code in
+    a row, codes in pool order)."""
+    pool = wl.mixed_pool(n_codes, seed=seed, n_range=(256, nmax))
+    if with_big:  # a GF(64) code of n >= 4000
+        big = wl.mixed_pool(1, seed=seed + 1, qs=(64,), n_range=(4000, 4600))
+        pool = pool + big
+    rng = np.random.default_rng([seed, 2])
+    counts = np.bincount(rng.integers(0, len(pool), size=frames), minlength=len(pool))
+    counts[counts == 0] = 1
+    if with_big:
+        counts[-1] = max(counts[-1], 12)
+    groups = [_groups(code, int(F), seed * 100 + k) for k, (code, F) in enumerate(zip(pool, counts))]
+    return pool, groups
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_multi_code_batch(gfbp, schedule):
+    """One gfbp_decode_batch call over frames of 9 codes (q in {4, 16, 64},
+    one GF(64) code of n >= 4000), BSC / BEC / BI-AWGN frames mixed per frame,
+    syndromes z != 0: every frame equals, bitwise, the plain decode of its
+    code's frames; 48 frames (every code, the GF(64) n >= 4000 ones
+    included) against the reference."""
+    pool, groups = _pool_batch(gfbp, 8, 600, 0xB47C, 1500, True)
+    assert {c.q for c in pool} >= {4, 16, 64} and max(c.n for c in pool if c.q == 64) >= 4000
+    dcodes = [gfbp.DeviceCode(c) for c in pool]
+    flat, codes_of, index = [], [], []
+    for k, gs in enumerate(groups):
+        for g in gs:
+            flat.append(g)
+            codes_of.append(pool[k])
+            index += [k] * g.F
+    index = np.array(index, dtype=np.int32)
+    dfr = gfbp.ragged_frames(flat, codes_of)
+    out = gfbp.decode_multi(dcodes, index, dfr, schedule=schedule, max_iter=60)
+    xh = out["xhat"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    cv = out["converged"].cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([pool[k].n for k in index])])
+    f0 = 0
+    picks = []
+    for g, code in zip(flat, codes_of):
+        k = pool.index(code)
+        e = gpu_decode(gfbp, code, gfbp.frames_to_device(g), schedule, max_iter=60)
+        for f in range(g.F):
+            ff = f0 + f
+            assert it[ff] == e["iters"][f] and cv[ff] == e["converged"][f], f"frame {ff}"
+            assert np.array_equal(xh[offs[ff]:offs[ff + 1]], e["xhat"][f]), f"frame {ff}"
+        picks.append((k, g, list(range(f0, f0 + min(g.F, 2 if code.q < 64 else 4)))))
+        f0 += g.F
+    # the reference on a deterministic sample: the first frames of every group
+    n_ref = 0
+    for k, g, rows in picks:
+        code = pool[k]
+        sub = g.subset(np.arange(len(rows)))
+        r = oracle.decode(code, sub, schedule=sched(schedule), max_iter=60)
+        gg = {"xhat": np.stack([xh[offs[ff]:offs[ff + 1]] for ff in rows]), "iters": it[rows], "converged": cv[rows]}
+        classify(gfbp, code, sub, gg, r, schedule, f"multi-code q={code.q} n={code.n} {g.channel} {schedule}",
+                 max_iter=60)
+        n_ref += len(rows)
+    assert n_ref >= 48
+
+
 def test_uneven_batch_graph_equals_plain_kernels(gfbp):
+    """Sessions of several codes stepped as one HIP graph equal the plain decode."""
     import torch
 
     pool = wl.mixed_pool(6, seed=61, n_range=(256, 900))
@@ -53,10 +177,8 @@ def test_uneven_batch_graph_equals_plain_kernels(gfbp):
         dcodes.append(dcode)
         dfr = gfbp.frames_for_session(groups)
         dfr["syndrome"] = torch.from_numpy(np.concatenate([g.syndrome for g in groups])).cuda()
-        # autotune the kernel shape on this code's frames (first group)
         d0 = gfbp.frames_to_device(groups[0])
         gfbp.tune(dcode, d0, schedule=schedule, trial_iters=2)
-        # eager plain-kernel results per channel group
         ref = {}
         base = 0
         for g in groups:

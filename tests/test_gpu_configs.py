@@ -1,0 +1,93 @@
+"""GPU decoder against the reference decoder on the three fixed workloads, at
+their full sizes and in the launch configuration the benchmark times.
+
+  * GF(4) (3,6) N = 504, BSC 0.06, 2000 frames, max 200 iterations: every
+    frame through the reference;
+  * GF(16) (3,6) N = 2000, BI-AWGN at Eb/N0 0.8 ... 1.6 dB, 4096 frames per
+    point in one launch, max 100: every 16th frame (256 per point) through
+    the reference;
+  * GF(8) (3,6) N = 3000, Markov source (self-transition 0.7), BSC 0.08 and
+    BEC 0.45, 4096 frames each, max 100: every 16th frame (256 per channel).
+
+Each case, both schedules: decisions and iteration counts under the gate of
+tests/_parity.py on the reference's frames (FER and mean-iteration intervals
+of those frames overlap), the GPU's FER and mean iterations over the whole
+launch within the intervals of the reference's sample, and q, r, Q within
+1e-4 after iterations 1..5 on 64 frames.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0605069_amd import workloads as wl
+from tests._parity import classify, fer_ci_overlap, gpu_decode, mean_ci_overlap, messages_close, sched
+
+pytestmark = pytest.mark.gpu
+
+EBN0 = (0.8, 1.0, 1.2, 1.4, 1.6)
+
+
+@pytest.fixture(scope="module")
+def gfbp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_cs_0605069_amd as g
+
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def c2():
+    code, enc = wl.regular_code(2000, 3, 6, 16, seed=0xC0DE0002)
+    return code, enc
+
+
+@pytest.fixture(scope="module")
+def c3():
+    q = 8
+    code, enc = wl.regular_code(3000, 3, 6, q, seed=0xC0DE0003)
+    M = wl.self_transition_matrix(q, 0.7)
+    return code, enc, M, wl.stationary(M)
+
+
+def _check(gfbp, code, fr, schedule, label, every=1, **kw):
+    g = gpu_decode(gfbp, code, gfbp.frames_to_device(fr), schedule, **kw)
+    idx = np.arange(0, fr.F, every)
+    sub = fr.subset(idx)
+    okw = {k: v for k, v in kw.items() if k in ("prior", "markov_M", "markov_pi", "max_iter")}
+    r = oracle.decode(code, sub, schedule=sched(schedule), **okw)
+    gs = {k: v[idx] for k, v in g.items()}
+    classify(gfbp, code, sub, gs, r, schedule, label, **kw)
+    if every > 1:  # the whole launch against the reference's sample
+        assert fer_ci_overlap(g["converged"], r["converged"]), f"{label}: FER of the launch"
+        assert mean_ci_overlap(g["iters"].astype(float), r["iters"].astype(float)), f"{label}: iterations"
+    messages_close(gfbp, code, fr.subset(np.arange(0, 64 * every, every)), schedule, iters=(1, 2, 3, 4, 5),
+                   label=label, **{k: v for k, v in kw.items() if k != "max_iter"})
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_gf4_n504_bsc_all_frames(gfbp, schedule):
+    code, enc = wl.regular_code(504, 3, 6, 4, seed=0xC0DE0001)
+    fr = wl.make_frames(code, enc, 2000, 0xDA7A0001, "bsc", 0.06)
+    _check(gfbp, code, fr, schedule, f"GF(4) N=504 BSC {schedule}", max_iter=200)
+
+
+@pytest.mark.parametrize("ebn0", EBN0)
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_gf16_n2000_biawgn(gfbp, c2, schedule, ebn0):
+    code, enc = c2
+    sigma = wl.sigma_from_ebn0(ebn0, code.n_info / code.n)
+    k = EBN0.index(ebn0)
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0002 * 16 + k, "biawgn", sigma)  # the benchmark's frames
+    _check(gfbp, code, fr, schedule, f"GF(16) N=2000 {ebn0} dB {schedule}", every=16, max_iter=100)
+
+
+@pytest.mark.parametrize("channel,param", [("bsc", 0.08), ("bec", 0.45)])
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_gf8_n3000_markov(gfbp, c3, schedule, channel, param):
+    code, enc, M, pi = c3
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0003 + (channel == "bec"), channel, param, source="markov", markov=M)
+    _check(gfbp, code, fr, schedule, f"GF(8) N=3000 Markov {channel} {schedule}", every=16, max_iter=100,
+           prior="markov", markov_M=M, markov_pi=pi)

@@ -1,26 +1,23 @@
-"""GPU decoder against the reference decoder, through the C ABI.
+"""GPU decoder against the reference decoder, through the C ABI, at sizes the
+reference finishes in seconds (the workload-size checks are in
+test_gpu_configs.py).
 
-Same seeded inputs on both sides.  Bars:
+Same seeded inputs on both sides.  Bars (tests/_parity.py):
   * messages (q, r, Q) after the first iterations within 1e-4 absolute;
   * BEC with an i.i.d. source: messages bit-identical (every value is dyadic);
-  * decisions and iteration counts identical on >= 99.9% of frames, the
-    exceptions (logged) being frames the reference itself did not converge
-    on ("chaotic") and frames whose reference outcome changes when its own
-    float64 inputs are rounded to float32 or moved by a relative 1e-6
-    ("precision-sensitive");
+  * decisions and iteration counts identical on >= 99.9% of frames, the only
+    excused (logged) frames being reference near-ties before the two sides
+    diverge and frames neither side decoded;
   * FER and mean iterations within each other's 95% confidence intervals.
 """
-import math
-
 import numpy as np
 import pytest
 
 import oracle
 from paper_cs_0605069_amd import workloads as wl
+from tests._parity import MSG_TOL, classify, gpu_decode, messages_close, sched
 
 pytestmark = pytest.mark.gpu
-
-MSG_TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -35,20 +32,11 @@ def gfbp():
 
 
 def _gpu(gfbp, code, fr, schedule, **kw):
-    import torch
-
-    dcode = gfbp.DeviceCode(code)
-    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, **kw)
-    torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
+    return gpu_decode(gfbp, code, gfbp.frames_to_device(fr), schedule, **kw)
 
 
 def _ref(code, fr, schedule, **kw):
-    return oracle.decode(code, fr, schedule=gfbp_sched(schedule), **kw)
-
-
-def gfbp_sched(s):
-    return {"pus": oracle.PUS, "sus": oracle.SUS}[s]
+    return oracle.decode(code, fr, schedule=sched(schedule), **kw)
 
 
 def _small_code(q, n, seed, d_v=3, d_c=6):
@@ -56,120 +44,10 @@ def _small_code(q, n, seed, d_v=3, d_c=6):
     return wl.systematic(wl.make_code(n, m, d_v, q, seed, reject_4cycles=False))
 
 
-def _precision_sensitive(code, fr, schedule, idx, **kw):
-    """Frames (of idx) whose reference outcome is not determined at float32
-    precision: it changes when the reference's own float64 inputs (channel
-    likelihoods, Markov matrix and start distribution) are rounded to float32,
-    as the GPU decoder stores them, or perturbed by a relative 1e-6 (a few
-    float32 rounding steps) in either of two seeded random directions, or
-    when the reference keeps its messages in float32 (as the GPU does), or
-    also drops r entries below the resolution of a double-precision
-    transform (4e-16 of the largest; the GPU evaluates Eq. (3) through a
-    Walsh-Hadamard transform, whose small outputs are differences of
-    order-one terms)."""
-    if len(idx) == 0:
-        return np.zeros(0, dtype=bool)
-    sub = fr.subset(idx)
-    L = sub.lik.astype(np.float64) if sub.lik is not None else oracle.frame_likelihoods(code, sub)
-    kw = {k: v for k, v in kw.items() if k not in ("snap_iter", "posterior")}
-    sch = gfbp_sched(schedule)
-    a = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=sch, **kw)
-    rnd = dict(kw)
-    if "markov_M" in rnd:
-        rnd["markov_M"] = np.asarray(rnd["markov_M"]).astype(np.float32).astype(np.float64)
-        rnd["markov_pi"] = np.asarray(rnd["markov_pi"]).astype(np.float32).astype(np.float64)
-    variants = [L.astype(np.float32).astype(np.float64)]
-    rng = np.random.default_rng(0x5E45)
-    for _ in range(2):
-        variants.append(L * (1.0 + 1e-6 * rng.uniform(-1, 1, size=L.shape)))
-    moved = np.zeros(len(idx), dtype=bool)
-    for Lv in variants:
-        b = oracle.decode(code, likelihoods=Lv, syndrome=sub.syndrome, schedule=sch, **rnd)
-        moved |= (a["xhat"] != b["xhat"]).any(axis=1) | (a["iters"] != b["iters"])
-    for model in (1, 2):
-        b = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=sch, precision_model=model, **kw)
-        moved |= (a["xhat"] != b["xhat"]).any(axis=1) | (a["iters"] != b["iters"])
-    return moved
-
-
-def _near_tie(code, fr, schedule, idx, upto, gap=1e-3, **kw):
-    """Frames (of idx) with a near tie in the reference: at some iteration
-    t <= upto[k], some symbol's two largest pseudo-posterior entries differ by
-    less than `gap` (the decision there is not determined by the arithmetic's
-    last bits; float32 messages may break the tie the other way)."""
-    if len(idx) == 0:
-        return np.zeros(0, dtype=bool)
-    sub = fr.subset(idx)
-    L = sub.lik.astype(np.float64) if sub.lik is not None else oracle.frame_likelihoods(code, sub)
-    kw = {k: v for k, v in kw.items() if k not in ("snap_iter", "posterior", "max_iter", "early_stop")}
-    sch = gfbp_sched(schedule)
-    tie = np.zeros(len(idx), dtype=bool)
-    for t in range(1, int(max(upto)) + 1):
-        o = oracle.decode(code, likelihoods=L, syndrome=sub.syndrome, schedule=sch, max_iter=t, early_stop=False,
-                          posterior=True, **kw)
-        P = np.sort(o["posterior"], axis=2)
-        tie |= ((P[:, :, -1] - P[:, :, -2]).min(axis=1) < gap) & (t <= np.asarray(upto))
-    return tie
-
-
-def _compare_decisions(g, r, label, min_frac=0.999, recheck=None, near_tie=None):
-    """Identical decisions and iteration counts on >= min_frac of the frames;
-    frames the reference did not converge on (chaotic), frames whose
-    reference outcome is not determined at float32 input precision
-    (recheck(idx) -> bool mask) and near-tie frames (near_tie(idx, upto) ->
-    bool mask, upto = the first iteration at which either side stopped) are
-    logged exceptions."""
-    same = (g["xhat"] == r["xhat"]).all(axis=1) & (g["iters"] == r["iters"])
-    chaotic = r["converged"] == 0
-    bad = ~same & ~chaotic
-    sensitive = np.zeros_like(bad)
-    if recheck is not None and bad.any():
-        bi = np.nonzero(bad)[0]
-        sens = recheck(bi)
-        sensitive[bi[sens]] = True
-        bad &= ~sensitive
-    ties = np.zeros_like(bad)
-    if near_tie is not None and bad.any():
-        bi = np.nonzero(bad)[0]
-        nt = near_tie(bi, np.minimum(g["iters"][bi], r["iters"][bi]))
-        ties[bi[nt]] = True
-        bad &= ~ties
-    F = len(same)
-    print(f"[{label}] frames={F} identical={int(same.sum())} chaotic-differing={int((~same & chaotic).sum())} "
-          f"precision-sensitive={int(sensitive.sum())} near-tie={int(ties.sum())} other-differing={int(bad.sum())} "
-          f"mean_iters gpu={g['iters'].mean():.3f} ref={r['iters'].mean():.3f} "
-          f"FER gpu={1 - g['converged'].mean():.4f} ref={1 - r['converged'].mean():.4f}")
-    for name, mask in (("chaotic", ~same & chaotic), ("precision-sensitive", sensitive), ("near-tie", ties),
-                       ("differing", bad)):
-        if mask.any():
-            idx = np.nonzero(mask)[0][:8]
-            print(f"[{label}] {name} frames {idx.tolist()} iters gpu={g['iters'][idx].tolist()} "
-                  f"ref={r['iters'][idx].tolist()}")
-    assert bad.sum() <= math.floor((1 - min_frac) * F), f"{label}: {int(bad.sum())} frames differ"
-    return same
-
-
-def _wilson(k, n, z=1.96):
-    """95% Wilson score interval of a binomial proportion k/n."""
-    p = k / n
-    c = (p + z * z / (2 * n)) / (1 + z * z / n)
-    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / (1 + z * z / n)
-    return c - h, c + h
-
-
-def _fer_ci_overlap(conv_a, conv_b):
-    """The frame error rates' 95% Wilson intervals overlap."""
-    a = _wilson(int((conv_a == 0).sum()), len(conv_a))
-    b = _wilson(int((conv_b == 0).sum()), len(conv_b))
-    return a[0] <= b[1] and b[0] <= a[1]
-
-
-def _ci_overlap(a, b):
-    """95% CIs of two means (normal approximation) overlap."""
-    ma, mb = a.mean(), b.mean()
-    sa = 1.96 * a.std(ddof=1) / math.sqrt(len(a)) if len(a) > 1 else 0.0
-    sb = 1.96 * b.std(ddof=1) / math.sqrt(len(b)) if len(b) > 1 else 0.0
-    return abs(ma - mb) <= sa + sb + 1e-12
+def _decide(gfbp, code, fr, schedule, label, **kw):
+    g = _gpu(gfbp, code, fr, schedule, **kw)
+    r = _ref(code, fr, schedule, **{k: v for k, v in kw.items() if k not in ("sus_strict", "persistent")})
+    return classify(gfbp, code, fr, g, r, schedule, label, **kw), g, r
 
 
 # --------------------------------------------------------------- messages
@@ -177,14 +55,8 @@ def _ci_overlap(a, b):
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_messages_after_first_iterations(gfbp, q, schedule):
     code, enc = _small_code(q, 72, seed=100 + q)
-    F = 13  # not a multiple of the frames per wavefront: ragged tail
-    fr = wl.make_frames(code, enc, F, 200 + q, "bsc", 0.09)
-    for it in (1, 2, 3):
-        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
-        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
-        for key in ("snap_q", "snap_r", "snap_Q"):
-            err = np.abs(g[key] - r[key]).max()
-            assert err <= MSG_TOL, f"q={q} {schedule} iter {it} {key}: max abs error {err:.3g}"
+    fr = wl.make_frames(code, enc, 13, 200 + q, "bsc", 0.09)  # 13 frames: a ragged tile
+    messages_close(gfbp, code, fr, schedule, iters=(1, 2, 3), label=f"q={q}")
 
 
 @pytest.mark.parametrize("q", [2, 8])
@@ -200,33 +72,14 @@ def test_bec_messages_bit_identical(gfbp, schedule, q):
             assert np.array_equal(g[key], r[key].astype(np.float32)), f"{schedule} iter {it} {key} not bit-identical"
 
 
-# --------------------------------------------------------------- decisions
-@pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_config1_all_frames(gfbp, schedule):
-    """GF(4), (3,6), N=504, BSC 0.06, 2000 frames, max 200 iterations."""
-    code, enc = wl.regular_code(504, 3, 6, 4, seed=0xC0DE0001)
-    fr = wl.make_frames(code, enc, 2000, 0xDA7A0001, "bsc", 0.06)
-    g = _gpu(gfbp, code, fr, schedule, max_iter=200)
-    r = _ref(code, fr, schedule, max_iter=200)
-    _compare_decisions(g, r, f"C1 {schedule}",
-                       recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=200))
-    assert _ci_overlap(g["iters"].astype(float), r["iters"].astype(float))
-    assert _fer_ci_overlap(g["converged"], r["converged"])
-
-
+# --------------------------------------------------------------- decisions, small codes
 @pytest.mark.parametrize("channel,param", [("bec", 0.42), ("biawgn", 0.85)])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_other_channels(gfbp, channel, param, schedule):
     code, enc = wl.regular_code(240, 3, 6, 8, seed=9)
     fr = wl.make_frames(code, enc, 150, 10, channel, param)
-    g = _gpu(gfbp, code, fr, schedule, max_iter=60)
-    r = _ref(code, fr, schedule, max_iter=60)
-    _compare_decisions(g, r, f"{channel} {schedule}",
-                       recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=60))
-    for it in (1, 3):
-        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
-        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it)
-        assert np.abs(g["snap_q"] - r["snap_q"]).max() <= MSG_TOL
+    _decide(gfbp, code, fr, schedule, f"{channel} {schedule}", max_iter=60)
+    messages_close(gfbp, code, fr.subset(range(64)), schedule, iters=(1, 3), label=channel)
 
 
 @pytest.mark.parametrize("q,kind", [(8, "self"), (8, "general"), (64, "self")])
@@ -242,16 +95,30 @@ def test_markov_prior(gfbp, schedule, q, kind):
     pi = wl.stationary(M)
     fr = wl.make_frames(code, enc, 120, 12, "bsc", 0.1, source="markov", markov=M)
     kw = dict(prior="markov", markov_M=M, markov_pi=pi)
-    for it in (1, 2, 4):
-        g = _gpu(gfbp, code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it, **kw)
-        r = _ref(code, fr, schedule, max_iter=it, early_stop=False, snap_iter=it, **kw)
-        for key in ("snap_q", "snap_r", "snap_Q"):
-            err = np.abs(g[key] - r[key]).max()
-            assert err <= MSG_TOL, f"{schedule} iter {it} {key}: {err:.3g}"
-    g = _gpu(gfbp, code, fr, schedule, max_iter=100, **kw)
-    r = _ref(code, fr, schedule, max_iter=100, **kw)
-    _compare_decisions(g, r, f"markov {kind} q={q} {schedule}",
-                       recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=100, **kw))
+    messages_close(gfbp, code, fr.subset(range(64)), schedule, iters=(1, 2, 4), label=f"markov {kind}", **kw)
+    _decide(gfbp, code, fr, schedule, f"markov {kind} q={q} {schedule}", max_iter=100, **kw)
+
+
+@pytest.mark.parametrize("per_symbol", [False, True])
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_static_prior(gfbp, schedule, per_symbol):
+    """A fixed source prior (Section 2: a source symbol's prior multiplies its
+    evidence): one vector for every source symbol, or one per symbol."""
+    q = 16
+    code, enc = wl.regular_code(240, 3, 6, q, seed=15)
+    rng = np.random.default_rng(0x57A7)
+    K, F = code.n_info, 120
+    P = rng.dirichlet(np.full(q, 0.6), size=K if per_symbol else None)
+    cdf = np.cumsum(np.broadcast_to(P, (K, q)), axis=1)
+    u = rng.random((F, K, 1))
+    s = np.minimum((u > cdf[None]).sum(axis=2), q - 1).astype(np.uint8)  # s[f][k] drawn from P_k
+    cw = enc.encode(s)
+    fr = wl.Frames("bsc", np.full(F, 0.11), cw, rx=wl.bsc(cw, code.p, 0.11, 16))
+    kw = dict(prior="static", static_prior=P)
+    messages_close(gfbp, code, fr.subset(range(64)), schedule, iters=(1, 2), label="static", **kw)
+    _, g, r = _decide(gfbp, code, fr, schedule, f"static per_symbol={per_symbol} {schedule}", max_iter=60, **kw)
+    u = _ref(code, fr, schedule, max_iter=60)
+    assert r["converged"].mean() >= u["converged"].mean()  # the prior helps
 
 
 @pytest.mark.parametrize("kind", ["self", "general"])
@@ -271,20 +138,12 @@ def test_prior_in_sweep(gfbp, strict, kind):
     kw = dict(prior="markov", markov_M=M, markov_pi=pi, prior_in_sweep=True)
     dcode = gfbp.DeviceCode(code)
     assert dcode.info.sus_levels_in_sweep >= code.n_info > dcode.info.sus_levels
-    for it in (1, 2, 4):
-        g = _gpu(gfbp, code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, sus_strict=strict, **kw)
-        r = _ref(code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, **kw)
-        for key in ("snap_q", "snap_r", "snap_Q"):
-            err = np.abs(g[key] - r[key]).max()
-            assert err <= MSG_TOL, f"iter {it} {key}: {err:.3g}"
-        if it == 2:  # the timing matters from iteration 2 on
-            d = _gpu(gfbp, code, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, prior="markov",
-                     markov_M=M, markov_pi=pi)
-            assert np.abs(d["snap_Q"] - g["snap_Q"]).max() > 1e-3
-    g = _gpu(gfbp, code, fr, "sus", max_iter=100, sus_strict=strict, **kw)
-    r = _ref(code, fr, "sus", max_iter=100, **kw)
-    _compare_decisions(g, r, f"in-sweep {kind} strict={strict}",
-                       recheck=lambda idx: _precision_sensitive(code, fr, "sus", idx, max_iter=100, **kw))
+    messages_close(gfbp, code, fr.subset(range(64)), "sus", iters=(1, 2, 4), label="in-sweep", sus_strict=strict, **kw)
+    d = _gpu(gfbp, code, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, prior="markov", markov_M=M,
+             markov_pi=pi)
+    g = _gpu(gfbp, code, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, **kw)
+    assert np.abs(d["snap_Q"] - g["snap_Q"]).max() > 1e-3  # the timing matters from iteration 2 on
+    _decide(gfbp, code, fr, "sus", f"in-sweep {kind} strict={strict}", max_iter=100, sus_strict=strict, **kw)
 
 
 def test_prior_in_sweep_levelled_is_bitwise_strict_and_errors(gfbp):
@@ -303,7 +162,7 @@ def test_prior_in_sweep_levelled_is_bitwise_strict_and_errors(gfbp):
     with pytest.raises(gfbp.GfbpError):
         _gpu(gfbp, code, fr, "pus", **kw)
     dcode = gfbp.DeviceCode(code)
-    d = gfbp.SessionDesc(64, gfbp.SCHEDULES["sus"], 10, 0, None, None, gfbp.OPT_PRIOR_IN_SWEEP)
+    d = gfbp.SessionDesc(64, gfbp.SCHEDULES["sus"], 10, 0, None, None, gfbp.OPT_PRIOR_IN_SWEEP, 0)
     h = ctypes.c_void_p()
     assert gfbp.lib().gfbp_session_create(dcode.handle, ctypes.byref(d), ctypes.byref(h)) != 0 and not h.value
 
@@ -318,61 +177,133 @@ def test_nonzero_syndrome_and_given_likelihoods(gfbp, schedule):
     rng = np.random.default_rng(14)
     F = 40
     x = rng.integers(0, q, size=(F, code.n)).astype(np.uint8)
-    H = code.dense()
-    from tests import _gf
-
-    T = _gf.mul_table(code.p)
-    z = np.zeros((F, code.m), dtype=np.uint8)
-    for i in range(code.m):
-        for j in np.nonzero(H[i])[0]:
-            z[:, i] ^= T[H[i, j], x[:, j]].astype(np.uint8)
+    z = wl.syndromes(code, x)
     noisy = wl.bsc(x, code.p, 0.05, 15)
     L = np.stack([oracle.likelihood(code.p, "bsc", 0.05, rx=int(v)) for v in noisy.ravel()]).reshape(F, code.n, q)
+    L32 = L.astype(np.float32)
     dcode = gfbp.DeviceCode(code)
-    dfr = {"channel": "likelihood", "F": F, "likelihood": torch.from_numpy(L.astype(np.float32)).cuda(),
+    dfr = {"channel": "likelihood", "F": F, "likelihood": torch.from_numpy(L32).cuda(),
            "syndrome": torch.from_numpy(z).cuda()}
     out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50)
     g = {k: v.cpu().numpy() for k, v in out.items()}
-    r = oracle.decode(code, likelihoods=L.astype(np.float32).astype(np.float64), syndrome=z,
-                      schedule=gfbp_sched(schedule), max_iter=50)
-    _compare_decisions(g, r, f"coset {schedule}")
+    fr = wl.Frames("likelihood", np.zeros(F), x)
+    fr.lik = L32
+    fr.syndrome = z
+    r = oracle.decode(code, likelihoods=L32.astype(np.float64), syndrome=z, schedule=sched(schedule), max_iter=50)
+    classify(gfbp, code, fr, g, r, schedule, f"coset {schedule}", max_iter=50)
     assert (g["xhat"][g["converged"] == 1] == x[g["converged"] == 1]).mean() > 0.99
 
 
-# --------------------------------------------------------------- full sizes, sampled frames
+# --------------------------------------------------------------- readings R13 and R14
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_config2_full_batch_sampled(gfbp, schedule):
-    """GF(16), (3,6), N=2000, BI-AWGN 1.0 dB, 4096 frames in one launch; the
-    reference decodes every 256th frame."""
-    code, enc = wl.regular_code(2000, 3, 6, 16, seed=0xC0DE0002)
-    sigma = wl.sigma_from_ebn0(1.0, code.n_info / code.n)
-    fr = wl.make_frames(code, enc, 4096, 0xDA7A0002, "biawgn", sigma)
-    g = _gpu(gfbp, code, fr, schedule, max_iter=100)
-    idx = np.arange(0, 4096, 256)
-    r = _ref(code, fr.subset(idx), schedule, max_iter=100)
-    gs = {k: v[idx] for k, v in g.items()}
-    sub = fr.subset(idx)
-    _compare_decisions(gs, r, f"C2 1.0dB {schedule}", min_frac=0.9,
-                       recheck=lambda i: _precision_sensitive(code, sub, schedule, i, max_iter=100))
+def test_zero_evidence_row_is_uniform_with_one_guard(gfbp, schedule):
+    """Reading R13: a likelihood row of zeros normalises to the uniform vector
+    and counts one guard event, on both sides; the frames still decode."""
+    import torch
 
-
-@pytest.mark.parametrize("channel,param", [("bsc", 0.08), ("bec", 0.45)])
-def test_config3_full_batch_sampled(gfbp, channel, param):
-    """GF(8), (3,6), N=3000, Markov source (self-transition 0.7), 4096 frames."""
     q = 8
-    code, enc = wl.regular_code(3000, 3, 6, q, seed=0xC0DE0003)
-    M = wl.self_transition_matrix(q, 0.7)
-    pi = wl.stationary(M)
-    fr = wl.make_frames(code, enc, 4096, 0xDA7A0003, channel, param, source="markov", markov=M)
-    kw = dict(prior="markov", markov_M=M, markov_pi=pi, max_iter=100)
-    idx = np.arange(0, 4096, 512)
-    for schedule in ("pus", "sus"):
-        g = _gpu(gfbp, code, fr, schedule, **kw)
-        r = _ref(code, fr.subset(idx), schedule, **kw)
-        gs = {k: v[idx] for k, v in g.items()}
-        sub = fr.subset(idx)
-        _compare_decisions(gs, r, f"C3 {channel} {schedule}", min_frac=0.875,
-                           recheck=lambda i: _precision_sensitive(code, sub, schedule, i, **kw))
+    code, enc = _small_code(q, 96, seed=51)
+    fr = wl.make_frames(code, enc, 20, 52, "bsc", 0.03)
+    L = oracle.frame_likelihoods(code, fr)
+    zero_cols = [3, 40, 77]
+    L[:, zero_cols, :] = 0.0
+    L32 = L.astype(np.float32)
+    dcode = gfbp.DeviceCode(code)
+    dfr = {"channel": "likelihood", "F": fr.F, "likelihood": torch.from_numpy(L32).cuda()}
+    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=1, early_stop=False, snap_iter=1)
+    r = oracle.decode(code, likelihoods=L32.astype(np.float64), schedule=sched(schedule), max_iter=1,
+                      early_stop=False, snap_iter=1)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert (r["guards"] == len(zero_cols)).all()
+    assert np.array_equal(g["guards"], r["guards"])
+    assert np.abs(g["snap_q"] - r["snap_q"]).max() <= MSG_TOL
+    # the q-messages of a zero row's edges start uniform: after one
+    # iteration they carry the other edges' r only, so they are not zero
+    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=40)
+    torch.cuda.synchronize()
+    assert out["converged"].float().mean().item() > 0.9
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_exact_tie_takes_the_smallest_symbol(gfbp, schedule):
+    """Reading R14: a column whose pseudo-posterior is exactly flat (uniform
+    evidence, in no check) and a column whose evidence ties two symbols
+    exactly are decided as the smallest tied symbol on both sides."""
+    import torch
+
+    q = 8
+    code, enc = _small_code(q, 48, seed=23)
+    ext = wl.Code(code.q, code.n + 2, code.m, code.row_ptr, code.col, code.coef, poly=code.poly,
+                  n_info=code.n_info)
+    fr = wl.make_frames(code, enc, 12, 24, "bsc", 0.02)
+    L = oracle.frame_likelihoods(code, fr)
+    flat = np.full((fr.F, 1, q), 1.0 / q)
+    two = np.zeros((fr.F, 1, q))
+    two[:, 0, 5] = two[:, 0, 3] = 0.5  # symbols 3 and 5 tie exactly
+    Lx = np.concatenate([L, flat, two], axis=1).astype(np.float32)
+    dfr = {"channel": "likelihood", "F": fr.F, "likelihood": torch.from_numpy(Lx).cuda()}
+    out = gfbp.decode_batch(gfbp.DeviceCode(ext), dfr, schedule=schedule, max_iter=20)
+    r = oracle.decode(ext, likelihoods=Lx.astype(np.float64), schedule=sched(schedule), max_iter=20)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert (r["xhat"][:, -2] == 0).all() and (r["xhat"][:, -1] == 3).all()
+    assert np.array_equal(g["xhat"], r["xhat"]) and np.array_equal(g["iters"], r["iters"])
+
+
+# --------------------------------------------------------------- visiting order and source chain
+@pytest.mark.parametrize("prior", ["uniform", "markov"])
+def test_visit_order_and_source_chain(gfbp, prior):
+    """A SUS visiting order other than 0..n-1 and a source chain over
+    scattered columns (gfbp_code_desc visit_order, source_cols), against the
+    reference with the same orders: messages after iterations 1-3, decisions,
+    and the orders matter (the identity orders give other messages)."""
+    q = 8
+    base, enc = wl.regular_code(240, 3, 6, q, seed=61)
+    rng = np.random.default_rng(62)
+    perm = rng.permutation(base.n)  # column j of the new code is column perm[j] of the old
+    inv = np.argsort(perm)
+    code = wl.Code(q, base.n, base.m, base.row_ptr, inv[base.col].astype(np.int32), base.coef, poly=base.poly,
+                   n_info=base.n_info)
+    code.source_cols = inv[np.arange(base.n_info)].astype(np.int32)  # the chain in the old order
+    code.visit_order = rng.permutation(base.n).astype(np.int32)
+    M = wl.self_transition_matrix(q, 0.75)
+    kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M)) if prior == "markov" else {}
+    f0 = wl.make_frames(base, enc, 100, 63, "bsc", 0.1, source="markov" if kw else "iid",
+                        markov=M if kw else None)
+    fr = wl.Frames("bsc", f0.param, f0.codeword[:, perm], rx=f0.rx[:, perm])
+    messages_close(gfbp, code, fr.subset(range(48)), "sus", iters=(1, 2, 3), label="orders", **kw)
+    messages_close(gfbp, code, fr.subset(range(48)), "pus", iters=(1, 2), label="orders", **kw)
+    for sch in ("pus", "sus"):
+        _decide(gfbp, code, fr, sch, f"orders {prior} {sch}", max_iter=60, **kw)
+    plain = wl.Code(q, code.n, code.m, code.row_ptr, code.col, code.coef, poly=code.poly, n_info=code.n_info)
+    plain.source_cols = code.source_cols
+    a = _gpu(gfbp, code, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, **kw)
+    b = _gpu(gfbp, plain, fr, "sus", max_iter=2, early_stop=False, snap_iter=2, **kw)
+    assert np.abs(a["snap_q"] - b["snap_q"]).max() > 1e-3
+
+
+# --------------------------------------------------------------- per-frame channels
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_per_frame_channel_kinds(gfbp, schedule):
+    """One batch mixing BSC, BEC and BI-AWGN frames (gfbp_batch channel_of)
+    equals each channel's frames decoded alone, bitwise."""
+    import torch
+
+    q = 16
+    code, enc = wl.regular_code(200, 3, 6, q, seed=71)
+    parts = [wl.make_frames(code, enc, 30, 72, "bsc", 0.06), wl.make_frames(code, enc, 25, 73, "bec", 0.35),
+             wl.make_frames(code, enc, 35, 74, "biawgn", 0.8)]
+    mix = gfbp.frames_for_session(parts)
+    mix["channel_of"] = mix["channel"]  # per-frame kinds (device uint8)
+    mix["channel"] = "bsc"
+    assert torch.equal(mix["channel_of"].cpu(), torch.from_numpy(
+        np.concatenate([np.full(p.F, gfbp.CHANNELS[p.channel], np.uint8) for p in parts])))
+    g = gpu_decode(gfbp, code, mix, schedule, max_iter=40, posterior=True)
+    o = 0
+    for p in parts:
+        a = _gpu(gfbp, code, p, schedule, max_iter=40, posterior=True)
+        for k in ("xhat", "iters", "converged", "posterior"):
+            assert np.array_equal(g[k][o:o + p.F], a[k]), f"{p.channel} {k}"
+        o += p.F
 
 
 # --------------------------------------------------------------- batching properties
@@ -397,8 +328,6 @@ def test_frame_compaction_changes_nothing(gfbp, schedule, q):
     a syndrome (and, for priors assigned during the sweep, the source symbols'
     pseudo-posteriors the next sweep reads); the batch mixes fast and slow
     frames so that compaction runs several times."""
-    import torch
-
     code, enc = wl.regular_code(240, 3, 6, q, seed=37)
     M = wl.self_transition_matrix(q, 0.7)
     pi = wl.stationary(M)
@@ -406,14 +335,9 @@ def test_frame_compaction_changes_nothing(gfbp, schedule, q):
     z = np.random.default_rng(39).integers(0, q, size=(fr.F, code.m)).astype(np.uint8)
     z[::3] = 0
     fr.syndrome = z
-    dcode = gfbp.DeviceCode(code)
     dfr = gfbp.frames_to_device(fr)
-    outs = []
-    for compact in (False, True):
-        o = gfbp.decode_batch(dcode, dfr, schedule=schedule[:3], max_iter=60, prior="markov", markov_M=M,
-                              markov_pi=pi, compact=compact, prior_in_sweep=schedule.endswith("in-sweep"))
-        torch.cuda.synchronize()
-        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    outs = [gpu_decode(gfbp, code, dfr, schedule[:3], max_iter=60, prior="markov", markov_M=M, markov_pi=pi,
+                       compact=compact, prior_in_sweep=schedule.endswith("in-sweep")) for compact in (False, True)]
     it = outs[0]["iters"]
     assert it.min() < 10 and (it == 60).sum() > 20  # fast and slow frames
     for k in ("xhat", "iters", "converged", "guards"):
@@ -439,6 +363,14 @@ def test_edge_cases(gfbp):
     with pytest.raises(gfbp.GfbpError) as ei:
         gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
     assert ei.value.status == -5
+    # a channel whose input is missing is refused before any launch
+    with pytest.raises(gfbp.GfbpError) as ei:
+        gfbp.decode_batch(dcode, {"channel": "biawgn", "F": 1, "param": torch.ones(1, device="cuda")})
+    assert ei.value.status == -1
+    # LIKELIHOOD with the MN evidence mode is refused
+    with pytest.raises(gfbp.GfbpError):
+        gfbp.decode_batch(dcode, {"channel": "likelihood", "F": 1, "evidence": "mn",
+                                  "likelihood": torch.ones((1, code.n, 4), device="cuda")})
 
 
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
@@ -463,10 +395,13 @@ def test_largest_shape_gf64_n8000_sampled(gfbp, schedule):
     it = out["iters"][idx].cpu().numpy()
     del out
     torch.cuda.empty_cache()
-    r = oracle.decode(code, fr.subset(idx), schedule=gfbp_sched(schedule), max_iter=3, early_stop=False,
-                      posterior=True)
+    r = oracle.decode(code, fr.subset(idx), schedule=sched(schedule), max_iter=3, early_stop=False, posterior=True,
+                      gap_trace=True)
     assert np.abs(post - r["posterior"]).max() <= MSG_TOL
-    assert (xh == r["xhat"]).mean() > 0.999  # decisions off only where two entries nearly tie
+    # decisions differ only where the reference's two largest entries are within the message tolerance
+    P = np.sort(r["posterior"], axis=2)
+    off = xh != r["xhat"]
+    assert (P[:, :, -1] - P[:, :, -2])[off].max(initial=0.0) < 2 * MSG_TOL
     assert np.array_equal(it, r["iters"])
 
 
@@ -506,16 +441,9 @@ def test_random_irregular_codes(gfbp, seed):
     fr = wl.make_coset_frames(code, 70, 500 + seed, channel, param, source="markov" if markov else "iid", markov=M)
     kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M)) if markov else {}
     for sch in ("pus", "sus"):
-        g = _gpu(gfbp, code, fr, sch, max_iter=2, early_stop=False, snap_iter=2, **kw)
-        r = _ref(code, fr, sch, max_iter=2, early_stop=False, snap_iter=2, **kw)
-        for key in ("snap_q", "snap_r", "snap_Q"):
-            err = np.abs(g[key] - r[key]).max()
-            assert err <= MSG_TOL, f"seed {seed} q={q} {sch} {key}: {err:.3g}"
-        g = _gpu(gfbp, code, fr, sch, max_iter=40, **kw)
-        r = _ref(code, fr, sch, max_iter=40, **kw)
-        _compare_decisions(g, r, f"random seed {seed} q={q} n={n} {channel} markov={markov} {sch}",
-                           recheck=lambda idx: _precision_sensitive(code, fr, sch, idx, max_iter=40, **kw),
-                           near_tie=lambda idx, upto: _near_tie(code, fr, sch, idx, upto, **kw))
+        messages_close(gfbp, code, fr, sch, iters=(2,), label=f"random {seed}", **kw)
+        _decide(gfbp, code, fr, sch, f"random seed {seed} q={q} n={n} {channel} markov={markov} {sch}",
+                max_iter=40, **kw)
 
 
 def test_column_without_edges(gfbp):
@@ -556,22 +484,19 @@ _MN_SOURCES = {
 
 @pytest.mark.parametrize("q,source,channel,param", [(2, "iid", "bsc", 0.1), (4, "4s", "bec", 0.55),
                                                     (8, "2s", "biawgn", 1.1), (4, "4s", "bsc", 0.17),
-                                                    (8, "2s", "bec", 0.6)])
+                                                    (8, "2s", "bec", 0.6), (4, "iid", "biawgn", 0.9)])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_mn_syndrome_form(gfbp, q, source, channel, param, schedule):
-    """H = [A B], x = (source, noise), z = B r: the decoder sees only z, the
-    noise symbols' likelihoods and the source model (Section 2)."""
+    """H = [A B], x = (source, noise), z = B r: the decoder sees z and the
+    channel outputs at the noise columns; the GPU computes the noise symbols'
+    evidence itself (GFBP_EVIDENCE_MN), the reference independently."""
     code = wl.mn_code(60, 180, q, seed=400 + q)
     M, start = _MN_SOURCES[source]
     fr = wl.make_mn_frames(code, 300, 401 + q, channel, param, source="iid" if M is None else "markov",
                            markov=M, start=start)
     kw = {} if M is None else dict(prior="markov", markov_M=M, markov_pi=start)
-    g = _gpu(gfbp, code, fr, schedule, max_iter=80, **kw)
-    r = oracle.decode(code, likelihoods=fr.lik.astype(np.float64), syndrome=fr.syndrome,
-                      schedule=gfbp_sched(schedule), max_iter=80, **kw)
-    same = _compare_decisions(g, r, f"MN q={q} {source} {channel} {schedule}",
-                              recheck=lambda idx: _precision_sensitive(code, fr, schedule, idx, max_iter=80, **kw),
-                              near_tie=lambda idx, upto: _near_tie(code, fr, schedule, idx, upto, **kw))
+    messages_close(gfbp, code, fr.subset(range(64)), schedule, iters=(1, 2), label=f"MN {channel}", **kw)
+    _, g, r = _decide(gfbp, code, fr, schedule, f"MN q={q} {source} {channel} {schedule}", max_iter=80, **kw)
     ok = g["converged"].astype(bool)
     assert r["converged"].mean() > 0.5  # a meaningful share of frames decodes
     assert np.array_equal(wl.syndromes(code, g["xhat"][ok]), fr.syndrome[ok])
@@ -580,34 +505,21 @@ def test_mn_syndrome_form(gfbp, q, source, channel, param, schedule):
 @pytest.mark.parametrize("q,source,channel,param", [(4, "4s", "bsc", 0.17), (8, "2s", "biawgn", 1.1)])
 def test_mn_syndrome_form_prior_in_sweep(gfbp, q, source, channel, param):
     """The MN syndrome form with the source priors assigned during the SUS
-    sweep (R7(ii) timing): messages after iterations 2 and 3, then decisions."""
+    sweep (in-sweep timing): messages after iterations 2 and 3, then decisions."""
     code = wl.mn_code(60, 180, q, seed=410 + q)
     M, start = _MN_SOURCES[source]
     fr = wl.make_mn_frames(code, 300, 411 + q, channel, param, source="markov", markov=M, start=start)
     kw = dict(prior="markov", markov_M=M, markov_pi=start, prior_in_sweep=True)
-    L = fr.lik.astype(np.float64)
-    for it in (2, 3):
-        g = _gpu(gfbp, code, fr, "sus", max_iter=it, early_stop=False, snap_iter=it, **kw)
-        r = oracle.decode(code, likelihoods=L, syndrome=fr.syndrome, schedule=oracle.SUS, max_iter=it,
-                          early_stop=False, snap_iter=it, **kw)
-        for key in ("snap_q", "snap_r", "snap_Q"):
-            err = np.abs(g[key] - r[key]).max()
-            assert err <= MSG_TOL, f"iter {it} {key}: {err:.3g}"
-    g = _gpu(gfbp, code, fr, "sus", max_iter=80, **kw)
-    r = oracle.decode(code, likelihoods=L, syndrome=fr.syndrome, schedule=oracle.SUS, max_iter=80, **kw)
-    _compare_decisions(g, r, f"MN in-sweep q={q} {source} {channel}",
-                       recheck=lambda idx: _precision_sensitive(code, fr, "sus", idx, max_iter=80, **kw),
-                       near_tie=lambda idx, upto: _near_tie(code, fr, "sus", idx, upto, **kw))
+    messages_close(gfbp, code, fr.subset(range(64)), "sus", iters=(2, 3), label="MN in-sweep", **kw)
+    _, g, r = _decide(gfbp, code, fr, "sus", f"MN in-sweep q={q} {source} {channel}", max_iter=80, **kw)
     assert r["converged"].mean() > 0.5
 
 
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
 def test_trace_of_correct_source_bits(gfbp, schedule):
     """The per-iteration count of correct source bits (Fig. 1 diagnostic)
-    equals the count from the reference's decisions after each iteration
-    (frames whose decisions match the reference's at every iteration: a
-    near-tie at some iteration may flip a bit there and be corrected later;
-    the test needs such frames to be rare and their final counts equal)."""
+    equals the count from the reference's decisions after each iteration, on
+    frames whose decisions match the reference's at every iteration."""
     import torch
 
     q, p = 4, 2
@@ -620,8 +532,7 @@ def test_trace_of_correct_source_bits(gfbp, schedule):
                             truth=torch.from_numpy(fr.codeword).cuda(), **kw)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
-    r = oracle.decode(code, likelihoods=fr.lik.astype(np.float64), syndrome=fr.syndrome,
-                      schedule=gfbp_sched(schedule), max_iter=60, trace=True, **kw)
+    r = oracle.decode(code, fr, schedule=sched(schedule), max_iter=60, trace=True, **kw)
     K = code.n_info
     same = (g["xhat"] == r["xhat"]).all(axis=1) & (g["iters"] == r["iters"]) & (r["converged"] == 1)
     assert same.mean() > 0.9
@@ -676,8 +587,7 @@ def test_thin_level_runs_are_bitwise_the_strict_sweep(gfbp, q, source):
     """An MN syndrome-form code (B's chain: most levels hold one or two
     columns, walked in runs of levels per tile): levelled SUS, also with the
     priors assigned during the sweep, equals the strict column order."""
-    M, start = (wl.PAPER_MARKOV_4S, wl.stationary(wl.PAPER_MARKOV_4S)) if source == "4s" else \
-        wl.lift_binary_chain(wl.PAPER_MARKOV_2S, 3)
+    M, start = _MN_SOURCES[source]
     code = wl.mn_code(60, 180, q, seed=41 + q)
     fr = wl.make_mn_frames(code, 40, 42 + q, "bsc", 0.12, source="markov", markov=M, start=start)
     for in_sweep in (False, True):
@@ -693,9 +603,7 @@ def test_thin_level_runs_are_bitwise_the_strict_sweep(gfbp, q, source):
 @pytest.mark.parametrize("q", [2, 4, 8, 16, 32, 64])
 def test_every_kernel_shape_matches_the_reference(gfbp, q):
     """Each allowed entries-per-lane choice (EL = 2, 4, 8) is a different
-    register/lane split of the same arithmetic (a different mix of register
-    butterflies, row-swap butterflies and lane exchanges); all must match the
-    oracle."""
+    register/lane split of the same arithmetic; all must match the oracle."""
     import torch
 
     code, enc = _small_code(q, 72, seed=300 + q)
@@ -729,5 +637,4 @@ def test_tuner_keeps_an_allowed_shape_and_decodes_correctly(gfbp):
         out = gfbp.decode_batch(dcode, dfr, schedule=sch, max_iter=50)
         g = {k: v.cpu().numpy() for k, v in out.items()}
         r = _ref(code, fr, sch, max_iter=50)
-        _compare_decisions(g, r, f"tuned EL={el} {sch}",
-                           recheck=lambda idx: _precision_sensitive(code, fr, sch, idx, max_iter=50))
+        classify(gfbp, code, fr, g, r, sch, f"tuned EL={el} {sch}", max_iter=50)

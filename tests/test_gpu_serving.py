@@ -93,10 +93,10 @@ def test_pool_frames_are_reused_cyclically(gfbp):
 def test_served_frames_match_the_reference(gfbp, schedule):
     """Served frames (mixed codes, channels and priors through the Poisson
     loop) against the float64 reference decoder directly: the same decisions
-    and iteration counts, up to the reference's own logged exception classes."""
+    and iteration counts under the gate of tests/_parity.py."""
     import oracle
     from paper_cs_0605069_amd import serving
-    from tests.test_gpu_parity import _compare_decisions, _near_tie, _precision_sensitive
+    from tests._parity import classify
 
     pool = wl.mixed_pool(3, seed=75, n_range=(256, 600))
     queues, markov = serving.make_requests(pool, 240, rate=20000.0, seed=76)
@@ -115,6 +115,5 @@ def test_served_frames_match_the_reference(gfbp, schedule):
             got = [st.results[int(cq.ids[pos[f]])] for f in take]
             gd = {"xhat": np.stack([x for _, _, x in got]), "iters": np.array([i for i, _, _ in got]),
                   "converged": np.array([c for _, c, _ in got])}
-            _compare_decisions(gd, r, f"served q={cq.code.q} n={cq.code.n} {g.channel} markov={m} {schedule}",
-                               recheck=lambda idx: _precision_sensitive(cq.code, sub, schedule, idx, max_iter=40, **kw),
-                               near_tie=lambda idx, upto: _near_tie(cq.code, sub, schedule, idx, upto, **kw))
+            classify(gfbp, cq.code, sub, gd, r, schedule,
+                     f"served q={cq.code.q} n={cq.code.n} {g.channel} markov={m} {schedule}", max_iter=40, **kw)

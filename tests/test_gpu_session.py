@@ -163,3 +163,40 @@ def test_session_bytes_match_the_memory_it_takes(gfbp):
     assert need > 0
     assert free0 - free1 >= need * 0.9
     sess.close()
+
+
+def test_session_sized_by_device_bytes_and_timestamps(gfbp):
+    """n_slots = 0: the session takes as many 64-slot tiles as device_bytes
+    holds; poll returns device-clock admission and retirement times."""
+    import torch
+
+    code, enc = wl.regular_code(240, 3, 6, 16, seed=64)
+    dcode = gfbp.DeviceCode(code)
+    per64 = gfbp.Session.bytes_needed(dcode, 64, "sus")
+    budget = 5 * per64 + per64 // 2
+    assert gfbp.Session.bytes_needed(dcode, 0, "sus", device_bytes=budget) == gfbp.Session.bytes_needed(dcode, 320, "sus")
+    sess = gfbp.Session(dcode, n_slots=0, schedule="sus", max_iter=40, device_bytes=budget)
+    assert sess.free_slots == 320
+    with pytest.raises(gfbp.GfbpError):
+        gfbp.Session(dcode, n_slots=0, schedule="sus", device_bytes=per64 // 2)
+    fr = wl.make_frames(code, enc, 100, 65, "bsc", 0.07)
+    assert sess.admit(np.arange(100), gfbp.frames_for_session([fr])) == 100
+    hz = gfbp.device_clock_hz()
+    assert hz > 0
+    done = {}
+    for _ in range(40):
+        sess.step(1)
+        ids, it, cv, xh, ts = sess.poll(timestamps=True)
+        for k in range(len(ids)):
+            done[int(ids[k])] = (int(it[k]), ts[k])
+        if len(done) == 100:
+            break
+    assert len(done) == 100
+    spans = np.array([(int(t[1]) - int(t[0])) / hz for _, t in done.values()])
+    assert (spans > 0).all() and (spans < 10).all()
+    # frames that ran more iterations retired later
+    fast = [t[1] for i, t in done.values() if i <= 3]
+    slow = [t[1] for i, t in done.values() if i >= 8]
+    if fast and slow:
+        assert min(slow) > min(fast)
+    torch.cuda.synchronize()
