@@ -144,9 +144,10 @@ gfbp_status gfbp_code_info_get(const gfbp_code *code, gfbp_code_info *out);
  * Frames of one code: arrays are frame-major with the code's sizes ([F][n],
  * [F][m], ...).  Frames of several codes (n_codes > 1): each frame's entries
  * follow the previous frame's ("ragged"), with the sizes of the frame's own
- * code: frame f's rx starts at sum over earlier frames g of n(g), its y at p
- * times that, its likelihoods at sum of n(g) q(g), its syndrome at sum of
- * m(g); per-frame scalars (param, channel_of) are [F]. */
+ * code: frame f's rx and erasure start at the sum over earlier frames g of
+ * n(g), its y at the sum of n(g) p(g), its likelihoods at the sum of n(g) q(g),
+ * its syndrome at the sum of m(g), its decisions (xhat) at the sum of n(g);
+ * per-frame scalars (param, channel_of) are [F]. */
 typedef struct {
     int32_t n_frames;        /* F >= 0                                                */
     int32_t schedule;        /* GFBP_PUS or GFBP_SUS                                  */

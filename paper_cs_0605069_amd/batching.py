@@ -1,17 +1,22 @@
-"""Uneven batches: many codes' frames decoded together through one HIP graph.
+"""Uneven batches: many codes' frames decoded together in one call.
 
 Frames of a pool of codes (q in {4, 16, 64}, column weight 2-3, rate 1/3-1/2,
 n uniform in 256..8000) and channels (BSC, BEC, BI-AWGN at Eb/N0 ~ U[1, 2] dB,
-capacity matched) are decoded two ways:
+capacity matched; the channel kind given per frame) are decoded three ways:
 
-* graph: one session per code holds all of that code's frames; each code's
-  kernel shape is autotuned on its frames; one HIP graph holds `iters`
-  iterations of every session (one branch per session) and is replayed, with
-  the finished frames collected between replays, until every frame is done;
-* plain: ``gfbp_decode_batch`` on each (code, channel) group in turn.
+* persistent: one ``gfbp_decode_batch`` call over every frame (a code index
+  per frame): one persistent work-list kernel per field, run concurrently as
+  one HIP graph launch, with its tile shape (entries per lane, i.e. frames per
+  tile, and wavefronts per workgroup) chosen by ``gfbp_tune_persistent``;
+* plain: ``gfbp_decode_batch`` on each (code, channel) group in turn, each
+  code's kernel shape autotuned;
+* sessions (``--sessions``): one session per code, all stepped as one HIP
+  graph replayed until every frame is done.
 
-Both give bitwise the same per-frame results (tests/test_gpu_batching.py);
-this reports the wall time and edge-q update rate of each way.
+The persistent results must equal the plain ones bitwise (checked here and in
+tests/test_gpu_batching.py).  ``--oracle N`` also decodes a deterministic
+sample of N frames (every k-th frame of the batch) with the float64 reference
+decoder and reports how many agree, and both sides' FER and mean iterations.
 
 ``python -m paper_cs_0605069_amd.batching`` prints one JSON line.
 """
@@ -24,7 +29,8 @@ import time
 
 import numpy as np
 
-from . import DeviceCode, Graph, Session, decode_batch, frames_for_session, frames_to_device, tune
+from . import (DeviceCode, Graph, Session, decode_batch, decode_multi, frames_for_session, frames_to_device,
+               ragged_frames, tune)
 from . import workloads as wl
 
 
@@ -42,6 +48,17 @@ def make_groups(code: wl.Code, F: int, seed: int):
     return out
 
 
+def build(frames: int, codes: int, nmax: int):
+    pool = wl.mixed_pool(codes, seed=0xC0DE0004, n_range=(256, nmax))
+    rng = np.random.default_rng([0xDA7A0004, 1])
+    counts = np.bincount(rng.integers(0, len(pool), size=frames), minlength=len(pool))
+    items = []
+    for ci, (code, F) in enumerate(zip(pool, counts)):
+        if F:
+            items.append((ci, code, make_groups(code, int(F), 0xDA7A0004 + ci)))
+    return pool, items
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--frames", type=int, default=10000)
@@ -49,71 +66,149 @@ def main():
     ap.add_argument("--nmax", type=int, default=8000)
     ap.add_argument("--schedule", default="sus")
     ap.add_argument("--max-iter", type=int, default=100)
-    ap.add_argument("--iters", type=int, default=4, help="iterations per graph replay (even)")
+    ap.add_argument("--repeats", type=int, default=2, help="timed runs of each way (the fastest is kept)")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--sessions", action="store_true", help="also time one graph over one session per code")
+    ap.add_argument("--iters", type=int, default=4, help="iterations per session-graph replay (even)")
+    ap.add_argument("--oracle", type=int, default=0, help="reference decoder on this many frames")
     args = ap.parse_args()
     import torch
 
     torch.cuda.set_device(0)
-    pool = wl.mixed_pool(args.codes, seed=0xC0DE0004, n_range=(256, args.nmax))
-    rng = np.random.default_rng([0xDA7A0004, 1])
-    counts = np.bincount(rng.integers(0, len(pool), size=args.frames), minlength=len(pool))
+    pool, items = build(args.frames, args.codes, args.nmax)
+    flat, flat_codes, index = [], [], []
+    for ci, code, groups in items:
+        for g in groups:
+            flat.append(g)
+            flat_codes.append(code)
+            index += [ci] * g.F
+    index = np.array(index, dtype=np.int32)
+    F = len(index)
+    dcodes = [DeviceCode(c) for c in pool]
+    dfr = ragged_frames(flat, flat_codes)
     stream = torch.cuda.Stream()
-    items = []
-    for ci, (code, F) in enumerate(zip(pool, counts)):
-        if F == 0:
-            continue
-        groups = make_groups(code, int(F), 0xDA7A0004 + ci)
-        dcode = DeviceCode(code)
-        tune(dcode, frames_to_device(groups[-1]), schedule=args.schedule, trial_iters=2)
-        items.append((code, dcode, groups))
-    eq_frame = {id(c): c.E * c.q for c, _, _ in items}
+    eq_frame = np.array([c.E * c.q for c in pool], dtype=np.float64)
+    print(f"# {F} frames over {len(items)} codes built", file=sys.stderr, flush=True)
+
+    # persistent: one call
+    el = waves = 0
+    with torch.cuda.stream(stream):
+        if not args.no_tune:
+            t = decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=args.max_iter, stream=stream,
+                             tune_iters=2)
+            el, waves = t["persist_el"], t["persist_waves"]
+        decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=2, stream=stream,
+                     persist_el=el, persist_waves=waves)
     torch.cuda.synchronize()
+    best = None
+    for _ in range(args.repeats):
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            out = decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=args.max_iter, stream=stream,
+                               persist_el=el, persist_waves=waves)
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    p_it = out["iters"].cpu().numpy()
+    p_cv = out["converged"].cpu().numpy()
+    p_xh = out["xhat"].cpu().numpy()
+    pers_eq = float((p_it * eq_frame[index]).sum())
+    print(f"# persistent: {best:.3f} s", file=sys.stderr, flush=True)
 
     # plain kernels, one (code, channel) group after another
-    dev_groups = [(code, dcode, [frames_to_device(g) for g in groups]) for code, dcode, groups in items]
+    dev_groups = []
+    for ci, code, groups in items:
+        dcode = dcodes[ci]
+        tune(dcode, frames_to_device(groups[-1]), schedule=args.schedule, trial_iters=2)
+        dev_groups.append((ci, dcode, [frames_to_device(g) for g in groups]))
     for _, dcode, dg in dev_groups[:2]:  # warm-up
         decode_batch(dcode, dg[0], schedule=args.schedule, max_iter=2)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain_eq = 0.0
-    for code, dcode, dg in dev_groups:
-        for d in dg:
-            o = decode_batch(dcode, d, schedule=args.schedule, max_iter=args.max_iter, stream=stream)
-            plain_eq += float(o["iters"].sum().item()) * eq_frame[id(code)]
-    stream.synchronize()
-    t_plain = time.perf_counter() - t0
+    best_plain, plain_out = None, None
+    for _ in range(args.repeats):
+        outs = []
+        t0 = time.perf_counter()
+        for ci, dcode, dg in dev_groups:
+            for d in dg:
+                outs.append(decode_batch(dcode, d, schedule=args.schedule, max_iter=args.max_iter, stream=stream))
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        if best_plain is None or dt < best_plain:
+            best_plain, plain_out = dt, outs
+    q_it = np.concatenate([o["iters"].cpu().numpy() for o in plain_out])
+    q_cv = np.concatenate([o["converged"].cpu().numpy() for o in plain_out])
+    q_xh = np.concatenate([o["xhat"].cpu().numpy().ravel() for o in plain_out])
+    plain_eq = float((q_it * eq_frame[index]).sum())
+    offs = np.concatenate([[0], np.cumsum([pool[k].n for k in index])])
+    mism = int(((p_it != q_it) | (p_cv != q_cv)).sum())
+    mism_x = int(sum(not np.array_equal(p_xh[offs[f]:offs[f + 1]], q_xh[offs[f]:offs[f + 1]]) for f in range(F)))
+    print(f"# plain: {best_plain:.3f} s", file=sys.stderr, flush=True)
 
-    # one graph over one session per code
-    sessions = []
-    for code, dcode, groups in items:
-        F = sum(g.F for g in groups)
-        dfr = frames_for_session(groups)
-        dfr["syndrome"] = torch.from_numpy(np.concatenate([g.syndrome for g in groups])).cuda()
-        sess = Session(dcode, n_slots=F, schedule=args.schedule, max_iter=args.max_iter, has_syndrome=True)
-        sessions.append((code, sess, F, dfr))
-    torch.cuda.synchronize()
-    graph = Graph([s for _, s, _, _ in sessions], iters=args.iters, stream=stream)
-    t0 = time.perf_counter()
-    for code, sess, F, dfr in sessions:
-        with torch.cuda.stream(stream):
-            assert sess.admit(np.arange(F), dfr, stream=stream) == F
-    done, graph_eq, replays = 0, 0.0, 0
-    while done < args.frames:
-        graph.launch(stream)
-        replays += 1
-        for code, sess, F, _ in sessions:
-            if sess.running:
-                ids, it, cv, xh = sess.poll(want_xhat=False, stream=stream)
-                done += len(ids)
-                graph_eq += float(it.sum()) * eq_frame[id(code)]
-    stream.synchronize()
-    t_graph = time.perf_counter() - t0
-    graph.close()
-    print(json.dumps({
-        "frames": int(args.frames), "codes": len(items), "schedule": args.schedule, "max_iter": args.max_iter,
-        "plain_s": t_plain, "plain_edge_q_per_s": plain_eq / t_plain, "plain_frames_per_s": args.frames / t_plain,
-        "graph_s": t_graph, "graph_edge_q_per_s": graph_eq / t_graph, "graph_frames_per_s": args.frames / t_graph,
-        "graph_replays": replays, "iters_per_replay": args.iters}), flush=True)
+    res = {"frames": int(F), "codes": len(items), "schedule": args.schedule, "max_iter": args.max_iter,
+           "q_counts": {str(q): int(sum(1 for k in index if pool[k].q == q)) for q in sorted({c.q for c in pool})},
+           "n_max": int(max(c.n for c in pool)),
+           "persistent_s": best, "persistent_edge_q_per_s": pers_eq / best, "persistent_frames_per_s": F / best,
+           "persist_el": el, "persist_waves": waves,
+           "plain_s": best_plain, "plain_edge_q_per_s": plain_eq / best_plain, "plain_frames_per_s": F / best_plain,
+           "persistent_vs_plain_frames_differing": max(mism, mism_x),
+           "mean_iters": float(p_it.mean()), "fer": float(1 - p_cv.mean())}
+
+    if args.sessions:
+        sessions = []
+        for ci, code, groups in items:
+            Fc = sum(g.F for g in groups)
+            d = frames_for_session(groups)
+            d["syndrome"] = torch.from_numpy(np.concatenate([g.syndrome for g in groups])).cuda()
+            sessions.append((ci, Session(dcodes[ci], n_slots=Fc, schedule=args.schedule, max_iter=args.max_iter,
+                                         has_syndrome=True), Fc, d))
+        torch.cuda.synchronize()
+        graph = Graph([s for _, s, _, _ in sessions], iters=args.iters, stream=stream)
+        t0 = time.perf_counter()
+        for ci, sess, Fc, d in sessions:
+            with torch.cuda.stream(stream):
+                assert sess.admit(np.arange(Fc), d, stream=stream) == Fc
+        done, g_eq, replays = 0, 0.0, 0
+        while done < F:
+            graph.launch(stream)
+            replays += 1
+            for ci, sess, Fc, _ in sessions:
+                if sess.running:
+                    ids, it, cv, xh = sess.poll(want_xhat=False, stream=stream)
+                    done += len(ids)
+                    g_eq += float(it.sum()) * eq_frame[ci]
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        graph.close()
+        res.update({"sessions_graph_s": dt, "sessions_graph_edge_q_per_s": g_eq / dt,
+                    "sessions_graph_frames_per_s": F / dt, "sessions_graph_replays": replays})
+
+    if args.oracle:
+        import oracle
+
+        step = max(1, F // args.oracle)
+        pick = np.arange(0, F, step)[:args.oracle]
+        t0 = time.perf_counter()
+        same = 0
+        r_it, r_cv = [], []
+        sch = {"pus": oracle.PUS, "sus": oracle.SUS}[args.schedule]
+        base = 0
+        for g, code in zip(flat, flat_codes):
+            rows = pick[(pick >= base) & (pick < base + g.F)]
+            if len(rows):
+                r = oracle.decode(code, g.subset(rows - base), schedule=sch, max_iter=args.max_iter)
+                for k, f in enumerate(rows):
+                    ok = p_it[f] == r["iters"][k] and np.array_equal(p_xh[offs[f]:offs[f + 1]], r["xhat"][k])
+                    same += int(ok)
+                r_it.append(r["iters"])
+                r_cv.append(r["converged"])
+                print(f"# reference: {len(np.concatenate(r_it))} of {len(pick)} frames", file=sys.stderr, flush=True)
+            base += g.F
+        r_it, r_cv = np.concatenate(r_it), np.concatenate(r_cv)
+        res.update({"oracle_frames": int(len(pick)), "oracle_identical": int(same), "oracle_s": time.perf_counter() - t0,
+                    "oracle_threads": oracle.max_threads(),
+                    "oracle_mean_iters": float(r_it.mean()), "gpu_mean_iters_same_frames": float(p_it[pick].mean()),
+                    "oracle_fer": float(1 - r_cv.mean()), "gpu_fer_same_frames": float(1 - p_cv[pick].mean())})
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -1153,12 +1153,12 @@ struct PersistPlan {
     int F = 0, lel = 2, waves = 8;
     std::vector<int> gcode;                       // code index of each group
     std::vector<std::vector<int32_t>> gframe;     // frames of each group
-    std::vector<int64_t> off_n, off_nq, off_m;    // [F]
+    std::vector<int64_t> off_n, off_np, off_nq, off_m;  // [F]
     // work lists by (degree class, field): list 6 * cls + p - 1
     std::vector<persist::Work> work[12];
     std::vector<double> top;                      // largest tile's work of each list
     // workspace
-    size_t o_off_n = 0, o_off_nq = 0, o_off_m = 0, o_groups = 0, o_work[12] = {}, o_next = 0, o_mshape = 0;
+    size_t o_off_n = 0, o_off_np = 0, o_off_nq = 0, o_off_m = 0, o_groups = 0, o_work[12] = {}, o_next = 0, o_mshape = 0;
     struct G {
         size_t gframe, Qm, R, L, Pr, Qp, xh, unsat, active, guards, iters, conv, z;
         int Fp;
@@ -1198,16 +1198,19 @@ gfbp_status persist_plan(const gfbp_code *const *codes, int nc, const gfbp_batch
             pl.gframe.back().reserve(size_t(count[size_t(k)]));
         }
     pl.off_n.resize(size_t(F));
+    pl.off_np.resize(size_t(F));
     pl.off_nq.resize(size_t(F));
     pl.off_m.resize(size_t(F));
-    int64_t on = 0, onq = 0, om = 0;
+    int64_t on = 0, onp = 0, onq = 0, om = 0;
     for (int f = 0; f < F; ++f) {
         const int k = b->code_index ? b->code_index[f] : 0;
         const gfbp_code_info &ci = codes[k]->info;
         pl.off_n[size_t(f)] = on;
+        pl.off_np[size_t(f)] = onp;
         pl.off_nq[size_t(f)] = onq;
         pl.off_m[size_t(f)] = om;
         on += ci.n;
+        onp += int64_t(ci.n) * ci.p;
         onq += int64_t(ci.n) * ci.q;
         om += ci.m;
         pl.gframe[size_t(gid[size_t(k)])].push_back(f);
@@ -1243,6 +1246,7 @@ gfbp_status persist_plan(const gfbp_code *const *codes, int nc, const gfbp_batch
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes ? bytes : 1); return o; };
     pl.o_off_n = take(8 * size_t(F));
+    pl.o_off_np = take(8 * size_t(F));
     pl.o_off_nq = take(8 * size_t(F));
     pl.o_off_m = take(8 * size_t(F));
     pl.o_groups = take(sizeof(persist::Group) * pl.gcode.size());
@@ -1337,6 +1341,7 @@ gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_
     }
     const size_t F = size_t(pl.F);
     HIP_TRY(hipMemcpyAsync(w + pl.o_off_n, pl.off_n.data(), 8 * F, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + pl.o_off_np, pl.off_np.data(), 8 * F, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + pl.o_off_nq, pl.off_nq.data(), 8 * F, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + pl.o_off_m, pl.off_m.data(), 8 * F, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w + pl.o_groups, groups.data(), sizeof(persist::Group) * groups.size(),
@@ -1373,6 +1378,7 @@ gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_
     B.ch.static_P = b->static_prior;
     B.ch.chan_of = b->channel_of;
     B.ch.off_n = reinterpret_cast<const int64_t *>(w + pl.o_off_n);
+    B.ch.off_np = reinterpret_cast<const int64_t *>(w + pl.o_off_np);
     B.ch.off_nq = reinterpret_cast<const int64_t *>(w + pl.o_off_nq);
     B.off_m = reinterpret_cast<const int64_t *>(w + pl.o_off_m);
     B.zin = b->syndrome;

@@ -336,9 +336,10 @@ __device__ __forceinline__ void r_from_transform(const DevCode &c, size_t e, con
 // Where a frame's inputs are.  Batch-wide kinds, overridden per frame by
 // chan_of (indexed by frame) or, in sessions, by DevState::chan (by slot).
 // In a batch over several codes a slot f of one code's state holds frame
-// gframe[f] of the batch, whose per-symbol inputs (rx, erasure, y: n entries,
-// or n*p samples) start at element off_n[frame] (times p for y) and whose
-// likelihood vectors start at off_nq[frame]; null: slot f is frame f at f*n.
+// gframe[f] of the batch, whose per-symbol inputs (rx, erasure: n entries)
+// start at element off_n[frame], whose channel samples (y: n*p) start at
+// off_np[frame] and whose likelihood vectors (n*q) start at off_nq[frame];
+// null: slot f is frame f at f*n (f*n*p, f*n*q).
 struct Chan {
     int channel;              // GFBP_CH_*
     int prior;                // GFBP_PRIOR_* of the source symbols
@@ -349,6 +350,7 @@ struct Chan {
     const uint8_t *chan_of;   // [frames] channel kind of each frame, or null
     const int32_t *gframe;    // [F] frame held by slot f, or null
     const int64_t *off_n;     // [frames] or null
+    const int64_t *off_np;    // [frames] or null
     const int64_t *off_nq;    // [frames] or null
 };
 
@@ -404,10 +406,11 @@ __device__ __forceinline__ void init_column(const DevCode &c, const DevState &s,
     } else if (channel == GFBP_CH_BIAWGN) {
         const double sg = ch.param[gf];
         const double gain = 2.0 / (sg * sg);
+        const size_t ys = (ch.off_np ? size_t(ch.off_np[gf]) : (fj - size_t(j)) * P) + size_t(j) * P;
         double p0[P], p1[P];
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            double yb = ch.y[fj * P + t];
+            double yb = ch.y[ys + t];
             if (ch.evidence == GFBP_EVIDENCE_MN) yb = fabs(yb);  // bit 0 of the noise: y has the sent sign
             p1[t] = 1.0 / (1.0 + exp(gain * yb));   // P(bit = 1 | y): bit 1 was sent as -1
             p0[t] = 1.0 / (1.0 + exp(-gain * yb));  // P(bit = 0 | y)
