@@ -67,7 +67,10 @@ def test_persistent_equals_plain(gfbp, q, n, channel, prior, syn, schedule, el, 
     if syn:  # a random syndrome per frame (coset decoding)
         fr = wl.make_coset_frames(code, 333, 84 + q, channel, param)
     dfr = gfbp.frames_to_device(fr)
-    a = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, **kw)
+    dcode = gfbp.DeviceCode(code)
+    dcode.set_shape(schedule, min(el, q))  # the same lane split (the transforms' rounding order)
+    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50, **kw)
+    a = {k: v.cpu().numpy() for k, v in out.items()}
     b = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, persistent=True, persist_el=el, persist_waves=waves, **kw)
     for k in ("xhat", "iters", "converged", "guards"):
         assert np.array_equal(a[k], b[k]), f"{k}: persistent and plain differ"
