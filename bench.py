@@ -11,8 +11,10 @@ Reported value: edge-q message updates per second over the whole step, where
 a frame that ran t iterations counts t * E * q updates (E = edges, q = field
 size).  Also per schedule: updates/s, frames/s, mean iterations, decode-call
 latency; the roofline of the dominant kernel from HIP events recorded around
-each launch during the timed steps; and the reference decoder timed on a
-bounded sample of the same frames on the host cores.
+each launch during the timed steps; the reference decoder timed on a bounded
+sample of the same frames on the host cores; a GF(64) leg; and a serving leg
+(continuous batching of a Poisson stream of mixed-code frames: throughput and
+p50/p99 frame latency per schedule).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-frames S]
 """
@@ -75,10 +77,11 @@ def cpu_baseline(code, points, n_frames: int):
             "frames_per_s": 2 * fr.F / dt, "mean_iters": iters}
 
 
-def gf64_leg(gfbp, torch, steps: int) -> dict:
+def gf64_leg(gfbp, torch, steps: int, traffic_path: str = "", shapes: dict | None = None) -> dict:
     """GF(64) (3,6) rate-1/2 N=2000, BI-AWGN at 1.6 dB, 4096 frames, max 100
-    iterations, autotuned: per schedule edge-q/s and the roofline of its
-    dominant kernel (not part of `value`)."""
+    iterations, autotuned: per schedule edge-q/s, frames/s and the roofline of
+    its dominant kernel, with the measured HBM traffic of that kernel when a
+    current traffic summary exists (not part of `value`)."""
     from paper_cs_0605069_amd import workloads as wl
 
     code, enc = wl.systematic(wl.make_code(2000, 1000, 3, 64, seed=0xC0DE0040))
@@ -88,7 +91,11 @@ def gf64_leg(gfbp, torch, steps: int) -> dict:
     res = {"workload": "GF(64) regular (3,6) rate-1/2 LDPC, N=2000 symbols, BI-AWGN 1.6 dB, 4096 frames, "
                        "max 100 iterations", "edges": code.E, "q": 64}
     for s in ("pus", "sus"):
-        res[f"{s}_entries_per_lane"] = gfbp.tune(dcode, d, schedule=s, trial_iters=3)
+        if shapes and s in shapes:
+            dcode.set_shape(s, shapes[s])
+            res[f"{s}_entries_per_lane"] = dcode.shape(s)
+        else:
+            res[f"{s}_entries_per_lane"] = gfbp.tune(dcode, d, schedule=s, trial_iters=3)
         gfbp.decode_batch(dcode, d, schedule=s, max_iter=100)
         torch.cuda.synchronize()
         gfbp.profile_reset()
@@ -104,12 +111,23 @@ def gf64_leg(gfbp, torch, steps: int) -> dict:
         prof = gfbp.profile_read()
         it = np.concatenate(its)
         res[f"{s}_edge_q_per_s"] = float(it.sum()) * code.E * code.q / wall
+        res[f"{s}_frames_per_s"] = len(it) / wall
         res[f"{s}_mean_iters"] = float(it.mean())
         ks = {k: v for k, v in prof.items() if k in ("check", "variable", "sus_level")}
         dom = max(ks, key=lambda k: ks[k]["total_ms"])
         ach = ks[dom]["algo_bytes"] / (ks[dom]["total_ms"] / 1e3)
+        algo = ks[dom]["algo_bytes"] / ks[dom]["launches"]
         res[f"{s}_roofline"] = {"kernel": dom, "achieved_GBps": ach / 1e9, "frac": ach / HBM_PEAK,
-                                "avg_launch_ms": ks[dom]["total_ms"] / ks[dom]["launches"]}
+                                "avg_launch_ms": ks[dom]["total_ms"] / ks[dom]["launches"],
+                                "algo_bytes_per_launch": algo, "traffic": None}
+        if traffic_path:
+            from paper_cs_0605069_amd.profiling import read_traffic
+
+            tr = read_traffic(traffic_path)
+            el = res[f"{s}_entries_per_lane"]
+            if tr and dom in tr["kernels"] and int(tr["shapes"].get(s, -1)) == el:
+                res[f"{s}_roofline"]["traffic"] = tr["kernels"][dom]["bytes_per_dispatch"]
+                res[f"{s}_roofline"]["traffic_over_algorithmic"] = tr["kernels"][dom]["bytes_per_dispatch"] / algo
         # the same kernel with every frame running (fixed iterations, no early stop): its
         # bandwidth at full occupancy, without the convergence tail's small launches
         gfbp.profile_reset()
@@ -122,6 +140,67 @@ def gf64_leg(gfbp, torch, steps: int) -> dict:
         res[f"{s}_roofline"]["all_frames_active"] = {"iterations": 4, "achieved_GBps": fa / 1e9, "frac": fa / HBM_PEAK,
                                                      "avg_launch_ms": full["total_ms"] / full["launches"]}
     return res
+
+
+def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus"), oracle_frames: int = 48) -> dict:
+    """Continuous batching of the mixed-code stream: Poisson arrivals at `rate`
+    frames/s for `seconds`, frames from 16 codes of the uneven pool (q in
+    {4, 16, 64} with GF(64) weighted 30%, n up to 8000, BSC / BEC / BI-AWGN at
+    Eb/N0 ~ U[1, 2] dB, half with the Markov source), admitted into resident
+    slots as they arrive, converged frames retired at once; per schedule the
+    sustained throughput and p50/p99 frame latency (arrival to result on the
+    host, and admission to retirement on the device clock), and the reference
+    decoder on a sample of the served frames (agreement and its frames/s)."""
+    import oracle
+    from paper_cs_0605069_amd import serving
+    from paper_cs_0605069_amd import workloads as wl
+
+    pool = wl.mixed_pool(16, seed=0xC0DE0005, n_range=(256, 8000), q_weights=[0.35, 0.35, 0.3])
+    out = {"workload": f"Poisson arrivals at {rate:.0f} frames/s for {seconds:.0f} s over 16 codes "
+                       "(q in {4, 16, 64}, GF(64) 30%, n 256-8000, BSC/BEC/BI-AWGN at 1-2 dB, half Markov), "
+                       "max 100 iterations"}
+    for sch in schedules:
+        n = int(rate * seconds)
+        queues, markov = serving.make_requests(pool, n, rate, seed=0xDA7A0005, pool_max=512)
+        per = max(1, oracle_frames // len(queues))
+        keep = [int(cq.ids[pos[f]]) for cq in queues for g, m, pos in cq.groups
+                for f in range(min(g.F, max(1, per // len(cq.groups))))]
+        srv = serving.Server(queues, 1024, sch, 100, 200 << 30, step_iters=2, markov=markov, keep_ids=keep)
+        st = srv.run(deadline=seconds + 15.0)
+        lat = np.array(st.latency) * 1e3
+        dlat = np.array(st.device_latency) * 1e3
+        res = {"offered_per_s": rate, "offered": st.offered, "answered": st.done, "wall_s": st.wall,
+               "throughput_frames_per_s": st.done / st.wall,
+               "arrival_window_s": seconds,
+               "frame_latency_ms_p50": float(np.percentile(lat, 50)), "frame_latency_ms_p99": float(np.percentile(lat, 99)),
+               "device_latency_ms_p50": float(np.percentile(dlat, 50)),
+               "device_latency_ms_p99": float(np.percentile(dlat, 99)),
+               "mean_iters": float(np.mean(st.iters)), "fer": 1 - st.converged / max(1, st.done)}
+        # the reference decoder on the first few served frames of every code
+        same = tot = 0
+        t0 = time.perf_counter()
+        sch_o = {"pus": oracle.PUS, "sus": oracle.SUS}[sch]
+        for cq in queues:
+            M, pi = markov[cq.code.q]
+            for g, m, pos in cq.groups:
+                take = [f for f in range(g.F) if int(cq.ids[pos[f]]) in st.results][:max(1, per // len(cq.groups))]
+                if not take:
+                    continue
+                kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
+                r = oracle.decode(cq.code, g.subset(take), schedule=sch_o, max_iter=100, **kw)
+                for k, f in enumerate(take):
+                    it, cv, xh = st.results[int(cq.ids[pos[f]])]
+                    same += int(it == r["iters"][k] and np.array_equal(xh, r["xhat"][k]))
+                    tot += 1
+        dt = time.perf_counter() - t0
+        res["reference_sample"] = {"frames": tot, "identical": same, "seconds": dt, "frames_per_s": tot / dt,
+                                   "threads": oracle.max_threads()}
+        out[sch] = res
+        print(f"# serving {sch}: {res['throughput_frames_per_s']:.0f} frames/s, p99 {res['frame_latency_ms_p99']:.0f} ms",
+              file=sys.stderr, flush=True)
+        del queues, srv
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -139,6 +218,13 @@ def main():
     ap.add_argument("--no-gf64", action="store_true", help="skip the GF(64) leg")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_gf16_n2000_bi-awgn.txt"),
                     help="measured HBM traffic summary to report beside the roofline")
+    ap.add_argument("--traffic-gf64", default=os.path.join(ROOT, "profiles", "traffic_gf64_n2000_bi-awgn.txt"),
+                    help="the same for the GF(64) leg")
+    ap.add_argument("--leg", default="", choices=["", "gf64", "serving"],
+                    help="run only this leg and print its JSON (profiling)")
+    ap.add_argument("--serving-seconds", type=float, default=6.0)
+    ap.add_argument("--serving-rate", type=float, default=20000.0)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: frames are independent and this decoder has no multi-GPU path "
@@ -151,6 +237,22 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    fixed = {}
+    if args.shapes:
+        for kv in args.shapes.split(","):
+            k, v = kv.split("=")
+            fixed[k] = int(v)
+    if args.leg == "gf64":
+        res = gf64_leg(gfbp, torch, max(1, args.steps), args.traffic_gf64, fixed)
+        if args.copy_probe:
+            a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps(res), flush=True)
+        return
+    if args.leg == "serving":
+        print(json.dumps(serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)), flush=True)
+        return
     code, points = make_workload()
     dcode = gfbp.DeviceCode(code)
     scheds = [s for s in args.schedules.split(",") if s]
@@ -248,7 +350,8 @@ def main():
                    "frac_of_hbm_peak": (v["algo_bytes"] / (v["total_ms"] / 1e3) / HBM_PEAK) if v["total_ms"] else 0.0}
                for k, v in prof.items()}
 
-    gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps))
+    gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps), args.traffic_gf64)
+    srv = None if args.no_serving else serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, points, args.cpu_frames)
@@ -278,6 +381,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "gf64": gf64,
+        "serving": srv,
     }
     print(json.dumps(line), flush=True)
 

@@ -287,6 +287,25 @@ size_t gfbp_batch_workspace_size(const gfbp_code *const *codes, const gfbp_batch
 gfbp_status gfbp_decode_batch(const gfbp_code *const *codes, const gfbp_batch *batch, gfbp_result *out,
                               void *workspace, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gfbp_decode_batch with the
+ * library's own static device scratch as its workspace instead of a caller's.
+ * The scratch is one array of 256 MiB per GPU the library runs on, held until
+ * the process ends; a batch whose gfbp_batch_workspace_size() exceeds it is
+ * refused with GFBP_ESMALL (and a message giving both sizes).  The call makes
+ * no device, pinned-host, event or stream allocation: the first call on a
+ * device looks up the scratch's address there (hipGetSymbolAddress, not an
+ * allocation); the plain path reads its iteration counts back through
+ * thread-local host memory after a stream synchronisation; the persistent path
+ * runs its kernels one after the other on `stream` (no forked streams, no
+ * graph); tracing is off for the call; the batch plan itself lives in host
+ * heap memory.  Results equal gfbp_decode_batch's.  Every call on a GPU uses
+ * the same scratch, which keeps the last call's contents (each decode
+ * initialises what it reads): calls that overlap on one GPU (other threads,
+ * other streams) race and must not be made. */
+gfbp_status gfbp_decode_batch_noalloc(const gfbp_code *const *codes, const gfbp_batch *batch, gfbp_result *out,
+                                      void *stream);
+
 /* ---- Sessions: continuous batching with resident frame state. ----
  * A session holds n_slots frame slots of one code on the device (message
  * state, staged channel inputs, per-slot iteration counters).  Frames are

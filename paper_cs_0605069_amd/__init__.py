@@ -34,7 +34,8 @@ CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
 EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size",
-           "gfbp_batch_workspace_size", "gfbp_decode_batch", "gfbp_tune_persistent", "gfbp_device_clock_hz",
+           "gfbp_batch_workspace_size", "gfbp_decode_batch", "gfbp_decode_batch_noalloc", "gfbp_tune_persistent",
+           "gfbp_device_clock_hz",
            "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
            "gfbp_code_get_shape", "gfbp_tune", "gfbp_session_bytes", "gfbp_session_create", "gfbp_session_destroy",
            "gfbp_session_admit", "gfbp_session_step", "gfbp_session_poll", "gfbp_session_free_slots",
@@ -119,6 +120,9 @@ def lib():
     L.gfbp_decode_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
                                     ctypes.c_size_t, ctypes.c_void_p]
     L.gfbp_decode_batch.restype = ctypes.c_int32
+    L.gfbp_decode_batch_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result),
+                                            ctypes.c_void_p]
+    L.gfbp_decode_batch_noalloc.restype = ctypes.c_int32
     L.gfbp_tune_persistent.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result), ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -482,6 +486,25 @@ def decode_multi(dcodes, code_index, dframes: dict, schedule="pus", max_iter: in
     _check(lib().gfbp_decode_batch(codes, ctypes.byref(b), ctypes.byref(r), workspace.data_ptr(), workspace.numel(),
                                    ctypes.c_void_p(st.cuda_stream)), "gfbp_decode_batch")
     return out
+
+
+def decode_batch_noalloc(dcodes, dframes: dict, outputs: dict, schedule="pus", max_iter: int = 100,
+                         early_stop: bool = True, prior: str = "uniform", prior_tensors=(None, None, None, 0),
+                         code_index=None, options: int = 0, stream=None):
+    """``gfbp_decode_batch_noalloc``: decode with the library's static device
+    scratch; the caller passes every device buffer (inputs in dframes, outputs
+    xhat / iters / converged / guards in ``outputs``, prior tensors as
+    (markov_M, markov_pi, static_prior, per_symbol)); nothing is allocated."""
+    F = int(dframes["F"])
+    Mt, pt, Pt, per_symbol = prior_tensors
+    ci = None if code_index is None else np.ascontiguousarray(code_index, dtype=np.int32)
+    b = _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, options, None,
+               len(dcodes), ci)
+    r = Result(_dptr(outputs["xhat"]), _dptr(outputs["iters"]), _dptr(outputs["converged"]), None,
+               _dptr(outputs.get("guards")), 0, None, None, None, None)
+    _check(lib().gfbp_decode_batch_noalloc(_codes_array(dcodes), ctypes.byref(b), ctypes.byref(r),
+                                           _stream_ptr(stream)), "gfbp_decode_batch_noalloc")
+    return outputs
 
 
 def device_clock_hz() -> int:

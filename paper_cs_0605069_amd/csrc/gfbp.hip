@@ -28,6 +28,10 @@ namespace {
 
 thread_local std::string g_err;
 
+// Set while gfbp_decode_batch_noalloc runs on this thread: the decode then
+// takes no pinned memory, events or streams of its own (see that entry point).
+thread_local bool g_no_alloc = false;
+
 gfbp_status fail(gfbp_status s, const std::string &msg) {
     g_err = msg;
     return s;
@@ -113,7 +117,7 @@ struct Tracer {
 
     explicit Tracer(hipStream_t s) : st(s) {
         std::lock_guard<std::mutex> g(g_prof_mu);
-        on = g_prof_on;
+        on = g_prof_on && !g_no_alloc;
     }
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -636,14 +640,18 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     // device), while the counts of iteration t come back asynchronously.
     std::vector<double> ran(size_t(b->max_iter) + 2, 0.0);  // frames iteration t ran
     ran[1] = F;
-    uint32_t *pin = pinned_counts();
+    // without allocations (gfbp_decode_batch_noalloc) the counts come back
+    // into thread-local pageable memory, read after a stream synchronisation
+    static thread_local uint32_t tls_counts[16];
+    uint32_t *pin = g_no_alloc ? tls_counts : pinned_counts();
     if (!pin) return fail(GFBP_ENOMEM, "pinned host memory for the iteration counts");
-    hipEvent_t *ev = count_events();
-    if (!ev) return fail(GFBP_EHIP, "events for the iteration counts");
+    hipEvent_t *ev = g_no_alloc ? nullptr : count_events();
+    if (!g_no_alloc && !ev) return fail(GFBP_EHIP, "events for the iteration counts");
     int last_read = 0;  // the latest iteration whose counts the host has read
     uint32_t known_running = uint32_t(F), known_tiles = uint32_t(s.nb);
     auto read_counts = [&](int t) -> gfbp_status {  // counts after iteration t
-        HIP_TRY(hipEventSynchronize(ev[t & 3]));
+        if (ev) HIP_TRY(hipEventSynchronize(ev[t & 3]));
+        else HIP_TRY(hipStreamSynchronize(st));
         known_running = pin[2 * (t & 3)];
         known_tiles = pin[2 * (t & 3) + 1];
         ran[size_t(t) + 1 < ran.size() ? size_t(t) + 1 : ran.size() - 1] = known_running;
@@ -690,7 +698,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         uint32_t *cnt_dev = s.count + 2 * (t & 1);  // [running after t, tiles listed]
         K::tiles(st, s.active, F, s.Fp, s.tiles + size_t(t & 1) * ntiles, cnt_dev + 1);
         HIP_TRY(hipMemcpyAsync(pin + 2 * (t & 3), cnt_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipEventRecord(ev[t & 3], st));
+        if (ev) HIP_TRY(hipEventRecord(ev[t & 3], st));
         if (t >= 2) {
             const gfbp_status rs = read_counts(t - 1);
             if (rs != GFBP_OK) return rs;
@@ -1394,17 +1402,18 @@ gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_
         if (!pl.work[l].empty()) lists.push_back(l);
     std::stable_sort(lists.begin(), lists.end(), [&](int x, int y) { return pl.top[size_t(x)] > pl.top[size_t(y)]; });
     Tracer tr(st);
-    ForkSet *fs = lists.size() > 1 ? fork_set() : nullptr;
-    if (lists.size() > 1 && !fs) return fail(GFBP_EHIP, "creating the streams for the persistent launches");
+    // without allocations the lists run one after the other on the stream
+    ForkSet *fs = lists.size() > 1 && !g_no_alloc ? fork_set() : nullptr;
+    if (lists.size() > 1 && !g_no_alloc && !fs) return fail(GFBP_EHIP, "creating the streams for the persistent launches");
     // several launches: captured into one HIP graph on a created stream
-    const bool graph = lists.size() > 1 && st != nullptr && !tr.on;
+    const bool graph = fs != nullptr && st != nullptr && !tr.on;
     if (graph) HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t he = hipSuccess;
     if (fs) he = hipEventRecord(fs->ev[11], st);
     for (size_t k = 0; k < lists.size() && he == hipSuccess; ++k) {
         const int l = lists[k];
-        hipStream_t ls = k == 0 ? st : fs->side[k - 1];
-        if (k > 0) he = hipStreamWaitEvent(ls, fs->ev[11], 0);
+        hipStream_t ls = k == 0 || !fs ? st : fs->side[k - 1];
+        if (k > 0 && fs) he = hipStreamWaitEvent(ls, fs->ev[11], 0);
         if (he != hipSuccess) break;
         tr.begin();
         hipEvent_t ea = g_launch_ev[0], eb = g_launch_ev[1];
@@ -1417,8 +1426,8 @@ gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_
             Tracer::last_[1] = eb;
         }
         tr.end(K_PERSIST, 0, 0);
-        if (he == hipSuccess && k > 0) he = hipEventRecord(fs->ev[k - 1], ls);
-        if (he == hipSuccess && k > 0) he = hipStreamWaitEvent(st, fs->ev[k - 1], 0);
+        if (he == hipSuccess && k > 0 && fs) he = hipEventRecord(fs->ev[k - 1], ls);
+        if (he == hipSuccess && k > 0 && fs) he = hipStreamWaitEvent(st, fs->ev[k - 1], 0);
     }
     if (graph) {
         hipGraph_t gr = nullptr;
@@ -1809,6 +1818,52 @@ gfbp_status gfbp_decode_batch(const gfbp_code *const *codes, const gfbp_batch *b
         case 6: return run_any<6>(code, b, out, s, a, st, needQ);
         default: return fail(GFBP_EUNSUPPORTED, "bad field");
     }
+}
+
+// ---- decoding without allocations: the library's static device scratch.
+// One array per GPU, held until the process ends.  In host code its name is
+// a host-side stand-in, not a device address: the address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+}  // extern "C"
+
+namespace {
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+extern "C" {
+
+gfbp_status gfbp_decode_batch_noalloc(const gfbp_code *const *codes, const gfbp_batch *b, gfbp_result *out,
+                                      void *stream) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GFBP_EUNSUPPORTED, "device index beyond the scratch table");
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {  // set-up on this device's first call (the device is current)
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(GFBP_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            g_scratch_ptr[dev] = p;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    if (!codes || !b || !out) return fail(GFBP_EINVAL, "null argument");
+    const size_t need = gfbp_batch_workspace_size(codes, b);
+    if (b->n_frames > 0 && need == 0) return fail(GFBP_EINVAL, "bad batch (workspace size 0)");
+    if (need > kScratchBytes)
+        return fail(GFBP_ESMALL, "the batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                     std::to_string(kScratchBytes));
+    g_no_alloc = true;
+    const gfbp_status rs = gfbp_decode_batch(codes, b, out, ptr, kScratchBytes, stream);
+    g_no_alloc = false;
+    return rs;
 }
 
 gfbp_status gfbp_code_set_shape(gfbp_code *c, int32_t schedule, int32_t entries_per_lane) {

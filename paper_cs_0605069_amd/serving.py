@@ -53,7 +53,8 @@ class CodeQueue:
 
 @dataclass
 class Stats:
-    latency: list = field(default_factory=list)
+    latency: list = field(default_factory=list)  # arrival to collection on the host, seconds
+    device_latency: list = field(default_factory=list)  # admission to retirement on the device clock, seconds
     iters: list = field(default_factory=list)
     converged: int = 0
     done: int = 0
@@ -65,7 +66,9 @@ class Stats:
 class Server:
     def __init__(self, queues: list[CodeQueue], slots: int, schedule: str, max_iter: int, budget_bytes: int,
                  step_iters: int = 2, markov: dict | None = None, keep_results: bool = False, autotune: bool = True,
-                 graph: bool = False, step_graphs: bool = False):
+                 graph: bool = False, step_graphs: bool = False, keep_ids=None):
+        """keep_results: keep every answered frame's (iterations, converged,
+        decisions) in Stats.results; keep_ids: keep only those requests'."""
         self.queues = queues
         self.slots = slots
         self.schedule = schedule
@@ -74,7 +77,8 @@ class Server:
         self.used = 0
         self.step_iters = step_iters
         self.markov = markov or {}
-        self.keep = keep_results
+        self.keep_ids = None if keep_ids is None else set(int(i) for i in keep_ids)
+        self.keep = keep_results or self.keep_ids is not None
         self.autotune = autotune
         self.refused = 0
         self.opened = 0
@@ -90,6 +94,9 @@ class Server:
         self.step_graphs = step_graphs
         self.graph = None
         self.gstream = None
+        from . import device_clock_hz
+
+        self.clock_hz = float(device_clock_hz())
 
     def prepare(self, prewarm: bool = True):
         """Before the clock starts: upload every code, (if asked) autotune its
@@ -184,16 +191,19 @@ class Server:
                 for cq in busy:
                     cq.session.step(self.step_iters, stream=cq.stream)
             for cq in busy:
-                ids, it, cv, xh = cq.session.poll(want_xhat=self.keep, stream=cq.stream)
+                ids, it, cv, xh, ts = cq.session.poll(want_xhat=self.keep, stream=cq.stream, timestamps=True)
                 t = time.perf_counter() - t0
                 if len(ids):
                     k = np.searchsorted(cq.ids, ids)
                     st.latency.extend((t - cq.arrival[k]).tolist())
+                    st.device_latency.extend(((ts[:, 1].astype(np.int64) - ts[:, 0].astype(np.int64)) / self.clock_hz)
+                                             .tolist())
                     st.iters.extend(it.tolist())
                     st.converged += int(cv.sum())
                     if self.keep:
                         for r in range(len(ids)):
-                            st.results[int(ids[r])] = (int(it[r]), int(cv[r]), xh[r].copy())
+                            if self.keep_ids is None or int(ids[r]) in self.keep_ids:
+                                st.results[int(ids[r])] = (int(it[r]), int(cv[r]), xh[r].copy())
                     st.done += len(ids)
             for cq in self.queues:
                 # a session whose requests have all been answered gives its memory back
