@@ -74,7 +74,18 @@ def stats(path: str) -> list[dict]:
     return out
 
 
-def stats_markdown(path: str, command: str, bench_line: str | None = None, plain_line: str | None = None) -> str:
+def _roofline(line: dict, key: str) -> dict:
+    """The roofline record `key` of a bench JSON line, in the main line's
+    field names (the GF(64) leg's records use achieved_GBps and no peak)."""
+    r = dict(line[key] if "." not in key else line[key.split(".")[0]][key.split(".")[1]])
+    if "achieved" not in r:
+        r["achieved"] = r["achieved_GBps"]
+        r["peak"] = 8000.0
+    return r
+
+
+def stats_markdown(path: str, command: str, bench_line: str | None = None, plain_line: str | None = None,
+                   key: str = "roofline") -> str:
     rows = stats(path)
     lines = ["# Kernel time: rocprofv3 --kernel-trace --stats", "", "Command:", "", "```", command, "```", "",
              "| kernel | calls | avg µs | total ms | % of GPU time |", "|---|---:|---:|---:|---:|"]
@@ -83,20 +94,22 @@ def stats_markdown(path: str, command: str, bench_line: str | None = None, plain
     if bench_line:
         # the same run's own HIP-event figures for the dominant kernel
         last = [ln for ln in open(bench_line).read().splitlines() if ln.startswith("{")][-1]
-        roof = json.loads(last)["roofline"]
+        roof = _roofline(json.loads(last), key)
         k = roof["kernel"]
         calls = sum(r["calls"] for r in rows if kind_of(r["kernel"]) == k)
         tot = sum(r["total_ms"] for r in rows if kind_of(r["kernel"]) == k)
+        launches = f" over {roof['launches']} launches" if "launches" in roof else ""
         lines += ["", f"Dominant kernel `{k}`: the program's HIP events give {roof['avg_launch_ms'] * 1e3:.2f} µs "
-                      f"average over {roof['launches']} launches; this trace gives {tot / max(calls, 1) * 1e3:.2f} µs "
+                      f"average{launches}; this trace gives {tot / max(calls, 1) * 1e3:.2f} µs "
                       f"over {calls} dispatches.  Algorithmic bytes per launch {roof['algo_bytes_per_launch'] / 1e6:.3f} MB, "
                       f"achieved {roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of {roof['peak']:.0f} GB/s)."]
     if plain_line:
         # the same bench without the profiler attached
         last = [ln for ln in open(plain_line).read().splitlines() if ln.startswith("{")][-1]
-        roof = json.loads(last)["roofline"]
+        roof = _roofline(json.loads(last), key if key == "roofline" else "gf64." + key)
+        launches = f" over {roof['launches']} launches" if "launches" in roof else ""
         lines += ["", f"The same bench without the profiler (its default steps): `{roof['kernel']}` "
-                      f"{roof['avg_launch_ms'] * 1e3:.2f} µs average over {roof['launches']} launches, "
+                      f"{roof['avg_launch_ms'] * 1e3:.2f} µs average{launches}, "
                       f"{roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of {roof['peak']:.0f} GB/s)."]
     return "\n".join(lines) + "\n"
 
@@ -179,6 +192,7 @@ def main():
     a.add_argument("--out", required=True)
     a.add_argument("--bench-line", help="the program's own output (its last JSON line) to compare against")
     a.add_argument("--plain-line", help="output of the same program run without the profiler")
+    a.add_argument("--key", default="roofline", help="roofline record of the JSON line (e.g. sus_roofline)")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -188,7 +202,7 @@ def main():
     b.add_argument("--out", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
-        text = stats_markdown(args.csv, args.command, args.bench_line, args.plain_line)
+        text = stats_markdown(args.csv, args.command, args.bench_line, args.plain_line, args.key)
     else:
         text = traffic_markdown(args.fetch_csv, args.write_csv, args.copy_bytes, args.shapes, args.command)
     with open(args.out, "w") as f:
