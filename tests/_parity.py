@@ -193,3 +193,38 @@ def messages_close(gfbp, code, fr, schedule, iters=(1, 2, 3, 4, 5), label="", **
             worst = max(worst, err)
             assert err <= MSG_TOL, f"{label} {schedule} iter {it} {key}: max abs error {err:.3g}"
     return worst
+
+
+def summary(log_path: str) -> str:
+    """Markdown table of the per-class counts a GPU run appended to
+    GFBP_PARITY_LOG (``python -m tests._parity LOG``)."""
+    rows = [json.loads(ln) for ln in open(log_path) if ln.strip()]
+    out = ["| gate | frames | identical | near-tie | chaotic | differing (allowed) | FER GPU / ref | mean iters GPU / ref |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    tot = dict(frames=0, identical=0, near_tie=0, chaotic=0, differing=0)
+    for d in rows:
+        for k in tot:
+            tot[k] += d[k]
+        out.append(f"| {d['label']} | {d['frames']} | {d['identical']} | {d['near_tie']} | {d['chaotic']} | "
+                   f"{d['differing']} ({d['allowed_differing']}) | {d['fer_gpu']:.4f} / {d['fer_ref']:.4f} | "
+                   f"{d['mean_iters_gpu']:.3f} / {d['mean_iters_ref']:.3f} |")
+    out.append(f"| **all gates** | {tot['frames']} | {tot['identical']} | {tot['near_tie']} | {tot['chaotic']} | "
+               f"{tot['differing']} | | |")
+    drift = [(d["label"], f, v) for d in rows for f, v in d.get("differing_drift", {}).items()]
+    if drift:
+        out += ["", "Differing frames: divergence iteration, the reference's smallest top-two gap before it, the "
+                    "first iteration whose GPU-vs-reference posterior difference exceeds 1e-4, and that difference "
+                    "at the divergence.", "",
+                "| gate | frame | divergence | smallest gap | first > 1e-4 | posterior difference at divergence |",
+                "|---|---:|---:|---:|---:|---:|"]
+        for label, f, v in drift:
+            e = v["posterior_error_by_iteration"]
+            out.append(f"| {label} | {f} | {v['divergence']} | {v['smallest_gap']:.2e} | "
+                       f"{v['first_iteration_above_1e-4']} | {e[-1]:.2e} |")
+    return "\n".join(out) + "\n"
+
+
+if __name__ == "__main__":
+    import sys
+
+    print(summary(sys.argv[1]), end="")
