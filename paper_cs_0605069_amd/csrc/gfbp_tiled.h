@@ -118,18 +118,25 @@ __device__ __forceinline__ T *chunk(T *arr, size_t node, int Fp, const Item &it)
     return arr + (node * size_t(Fp) + size_t(it.f)) * Gm::Q + size_t(it.g * Gm::EL);
 }
 
+// Loads and stores of a lane's EL entries of a vector array.  Every such
+// array is larger than the caches and each access streams (a vector is read
+// again only after the whole family has passed), so the accesses carry the
+// non-temporal hint.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int EL>
 __device__ __forceinline__ void ld(const float *p, float *v) {
     if constexpr (EL == 1) {
-        v[0] = p[0];
+        v[0] = __builtin_nontemporal_load(p);
     } else if constexpr (EL == 2) {
-        const float2 t = *reinterpret_cast<const float2 *>(p);
+        const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
         v[0] = t.x;
         v[1] = t.y;
     } else {
 #pragma unroll
         for (int k = 0; k < EL / 4; ++k) {
-            const float4 t = reinterpret_cast<const float4 *>(p)[k];
+            const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p) + k);
             v[4 * k] = t.x;
             v[4 * k + 1] = t.y;
             v[4 * k + 2] = t.z;
@@ -141,13 +148,16 @@ __device__ __forceinline__ void ld(const float *p, float *v) {
 template <int EL>
 __device__ __forceinline__ void st(float *p, const float *v) {
     if constexpr (EL == 1) {
-        p[0] = v[0];
+        __builtin_nontemporal_store(v[0], p);
     } else if constexpr (EL == 2) {
-        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+        const f32x2 t = {v[0], v[1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(p));
     } else {
 #pragma unroll
-        for (int k = 0; k < EL / 4; ++k)
-            reinterpret_cast<float4 *>(p)[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        for (int k = 0; k < EL / 4; ++k) {
+            const f32x4 t = {v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x4 *>(p) + k);
+        }
     }
 }
 
@@ -181,7 +191,20 @@ __device__ __forceinline__ void lds_permute(float *buf, const Item &it, const in
 #pragma unroll
     for (int r = 0; r < Gm::EL; ++r) row[pos[r]] = in[r];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    ld<Gm::EL>(row + it.g * Gm::EL, out);
+    const float *src = row + it.g * Gm::EL;  // 16-byte aligned rows of EL-entry chunks
+    if constexpr (Gm::EL >= 4) {
+#pragma unroll
+        for (int k = 0; k < Gm::EL / 4; ++k) {
+            const f32x4 t = reinterpret_cast<const f32x4 *>(src)[k];
+            out[4 * k] = t.x;
+            out[4 * k + 1] = t.y;
+            out[4 * k + 2] = t.z;
+            out[4 * k + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < Gm::EL; ++r) out[r] = src[r];
+    }
 }
 
 // ------------------------------------------------------------- transforms

@@ -55,6 +55,7 @@ class CodeQueue:
 class Stats:
     latency: list = field(default_factory=list)  # arrival to collection on the host, seconds
     device_latency: list = field(default_factory=list)  # admission to retirement on the device clock, seconds
+    answer_time: list = field(default_factory=list)  # collection time of each answer since the start, seconds
     iters: list = field(default_factory=list)
     converged: int = 0
     done: int = 0
@@ -196,6 +197,7 @@ class Server:
                 if len(ids):
                     k = np.searchsorted(cq.ids, ids)
                     st.latency.extend((t - cq.arrival[k]).tolist())
+                    st.answer_time.extend([t] * len(ids))
                     st.device_latency.extend(((ts[:, 1].astype(np.int64) - ts[:, 0].astype(np.int64)) / self.clock_hz)
                                              .tolist())
                     st.iters.extend(it.tolist())
