@@ -21,15 +21,22 @@ PUS, SUS = 0, 1
 CHANNELS = {"bsc": 0, "bec": 1, "biawgn": 2, "likelihood": 3}
 
 
-def build(verbose: bool = False) -> str:
+SANITIZED_DIR_ENV = "GFBP_SANITIZED_DIR"  # directory of a sanitizer build (see the sanitizer test)
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build(verbose: bool = False, out_dir: str | None = None, sanitize: bool = False) -> str:
+    """Compile the reference decoder with gcc next to this file (or into
+    out_dir; sanitize: with the address and undefined-behaviour sanitizers)."""
     src = os.path.join(_HERE, "gfbp_oracle.c")
-    tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"]
+    so = os.path.join(out_dir, "liboracle.so") if out_dir else _SO
+    tmp = so + ".tmp"
+    cmd = ["gcc", *(SANITIZE_FLAGS if sanitize else ["-O2"]), "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, so)
+    return so
 
 
 class _Code(ctypes.Structure):
@@ -58,9 +65,11 @@ class _Result(ctypes.Structure):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build()
-        lib = ctypes.CDLL(_SO)
+        san = os.environ.get(SANITIZED_DIR_ENV)
+        so = os.path.join(san, "liboracle.so") if san else _SO
+        if not os.path.exists(so):
+            build(out_dir=san)
+        lib = ctypes.CDLL(so)
         lib.ref_gf_mul.argtypes = [ctypes.c_int, ctypes.c_uint, ctypes.c_int, ctypes.c_int]
         lib.ref_gf_inv.argtypes = [ctypes.c_int, ctypes.c_uint, ctypes.c_int]
         lib.ref_likelihood.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,

@@ -19,6 +19,7 @@
 
 #include "../../include/gfbp.h"
 #include "gfbp_kernels.h"
+#include "gfbp_plan.h"
 #include "gfbp_tiled.h"
 #include "gfbp_persist.h"
 
@@ -46,9 +47,6 @@ gfbp_status fail(gfbp_status s, const std::string &msg) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// SUS levels with at most this many columns are walked in runs (k_sus_run):
-// one launch then costs more than walking a couple of columns in a row
-constexpr int kThinLevel = 2;
 
 }  // namespace
 
@@ -56,22 +54,11 @@ struct gfbp_code {
     gfbp_code_info info;
     DevCode dev;
     double sum_dc2;       // sum over checks of d_c (d_c - 1): sibling vectors read by one SUS sweep
-    // SUS dependency levels, [0]: from shared checks; [1]: also source
-    // symbol k after k-1 (priors assigned during the sweep)
-    struct Levels {
-        std::vector<int32_t> ptr;   // level l: the columns at positions ptr[l]..ptr[l+1]-1 of recs
-        std::vector<double> sibs;   // per level: sibling vectors read (sum over its edges of d_c - 1)
-        std::vector<double> edges;  // per level: edges
-        std::vector<double> src;    // per level: source columns
+    // SUS dependency levels (host plan, gfbp_plan.h) with their device
+    // records: [0] from shared checks; [1] also along the source chain
+    struct Levels : LevelPlan {
         const SusRec *recs = nullptr;  // device [n][max column degree], columns in level order
         const int32_t *dptr = nullptr; // device copy of ptr
-        // launches of one sweep: a wide level alone (one workgroup per column
-        // and tile), or a run of consecutive thin levels (one per tile)
-        struct Seg {
-            int c0, nc, run;
-            double sibs, edges, src;
-        };
-        std::vector<Seg> segs;
     } lv[2];
     int el[2] = {0, 0};   // entries per lane chosen for PUS / SUS (0 = default)
     void *mem = nullptr;  // one device allocation holding every array of dev
@@ -1127,30 +1114,7 @@ int session_slots(const gfbp_code *code, const gfbp_session_desc *d) {
     return int(lo * kWave);
 }
 
-// ---------------------------------------------------------------- host GF
-bool field_tables(int p, unsigned poly, std::vector<uint8_t> &mul, std::vector<uint8_t> &inv) {
-    const int q = 1 << p;
-    if (poly >> p != 1u) return false;
-    std::vector<int> ex(2 * q), lg(q, -1);
-    int v = 1;
-    for (int i = 0; i < q - 1; ++i) {
-        if (lg[v] != -1) return false;  // x is not primitive
-        ex[i] = ex[i + q - 1] = v;
-        lg[v] = i;
-        v <<= 1;
-        if (v & q) v ^= int(poly);
-    }
-    if (v != 1) return false;
-    mul.assign(size_t(q) * q, 0);
-    inv.assign(q, 0);
-    for (int a = 1; a < q; ++a) {
-        for (int b = 1; b < q; ++b) mul[a * q + b] = uint8_t(ex[lg[a] + lg[b]]);
-        inv[a] = uint8_t(ex[(q - 1 - lg[a]) % (q - 1)]);
-    }
-    return true;
-}
 
-const unsigned kDefaultPoly[7] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43};
 
 
 // ---------------------------------------------------------------- persistent path
@@ -1509,159 +1473,19 @@ const char *gfbp_version(void) { return "gfbp 0.5 (gfx950)"; }
 gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (!d || !out) return fail(GFBP_EINVAL, "null argument");
     *out = nullptr;
-    const int q = d->q;
-    int p = 0;
-    while ((1 << p) < q) ++p;
-    if (q < 2 || q > GFBP_MAX_Q || (1 << p) != q) return fail(GFBP_EUNSUPPORTED, "q must be 2^p with 1 <= p <= 6");
-    if (d->n <= 0 || d->m <= 0 || d->n_info < 0 || d->n_info > d->n)
-        return fail(GFBP_EINVAL, "bad n, m or n_info");
-    if (!d->row_ptr || !d->col || !d->coef) return fail(GFBP_EINVAL, "null row_ptr/col/coef");
-    const unsigned poly = d->poly ? unsigned(d->poly) : kDefaultPoly[p];
-    std::vector<uint8_t> mul, inv;
-    if (!field_tables(p, poly, mul, inv)) return fail(GFBP_EINVAL, "polynomial is not primitive of degree p");
-    const int n = d->n, m = d->m;
-    if (d->row_ptr[0] != 0) return fail(GFBP_EINVAL, "row_ptr[0] must be 0");
-    for (int i = 0; i < m; ++i)
-        if (d->row_ptr[i + 1] < d->row_ptr[i]) return fail(GFBP_EINVAL, "row_ptr not nondecreasing");
-    const int E = d->row_ptr[m];
-    int max_dc = 0;
-    double sum_dc2 = 0;
-    std::vector<int> col_deg(n, 0), seen(n, -1);
-    for (int i = 0; i < m; ++i) {
-        const int dc = d->row_ptr[i + 1] - d->row_ptr[i];
-        max_dc = dc > max_dc ? dc : max_dc;
-        sum_dc2 += double(dc) * (dc - 1);
-        for (int e = d->row_ptr[i]; e < d->row_ptr[i + 1]; ++e) {
-            const int j = d->col[e];
-            if (j < 0 || j >= n) return fail(GFBP_EINVAL, "column index out of range");
-            if (d->coef[e] == 0 || d->coef[e] >= q) return fail(GFBP_EINVAL, "coefficient not in GF(q)\\{0}");
-            if (seen[j] == i) return fail(GFBP_EINVAL, "column repeated in a row");
-            seen[j] = i;
-            col_deg[j]++;
-        }
-    }
-    int max_dv = 0;
-    for (int j = 0; j < n; ++j) max_dv = col_deg[j] > max_dv ? col_deg[j] : max_dv;
-    if (max_dc > GFBP_MAX_ROW_DEGREE) return fail(GFBP_EUNSUPPORTED, "row degree above GFBP_MAX_ROW_DEGREE");
-    if (max_dv > GFBP_MAX_COL_DEGREE) return fail(GFBP_EUNSUPPORTED, "column degree above GFBP_MAX_COL_DEGREE");
-
-    std::vector<int32_t> col_ptr(n + 1, 0), col_edge(E), edge_row(E), fill(n, 0);
-    for (int j = 0; j < n; ++j) col_ptr[j + 1] = col_ptr[j] + col_deg[j];
-    for (int i = 0; i < m; ++i)
-        for (int e = d->row_ptr[i]; e < d->row_ptr[i + 1]; ++e) {
-            edge_row[e] = i;
-            const int j = d->col[e];
-            col_edge[col_ptr[j] + fill[j]++] = e;
-        }
-    // per-edge images of the basis x^b under multiplication by h^-1 and h
-    std::vector<uint64_t> emap(2 * size_t(E));
-    for (int e = 0; e < E; ++e) {
-        const int h = d->coef[e], hi = inv[h];
-        uint64_t wi = 0, wm = 0;
-        for (int b = 0; b < p; ++b) {
-            wi |= uint64_t(mul[hi * q + (1 << b)]) << (6 * b);
-            wm |= uint64_t(mul[h * q + (1 << b)]) << (6 * b);
-        }
-        emap[2 * size_t(e)] = wi;
-        emap[2 * size_t(e) + 1] = wm;
-    }
-
-    // visiting order and source chain (defaults: 0..n-1 and 0..n_info-1)
-    const int K = d->n_info;
-    std::vector<int32_t> visit(n), chain_col(std::max(K, 1), 0), col_chain(n, -1), vpos(n, -1);
-    for (int t = 0; t < n; ++t) {
-        const int j = d->visit_order ? d->visit_order[t] : t;
-        if (j < 0 || j >= n || vpos[j] >= 0) return fail(GFBP_EINVAL, "visit_order is not a permutation of 0..n-1");
-        visit[t] = j;
-        vpos[j] = t;
-    }
-    for (int k = 0; k < K; ++k) {
-        const int j = d->source_cols ? d->source_cols[k] : k;
-        if (j < 0 || j >= n || col_chain[j] >= 0) return fail(GFBP_EINVAL, "source_cols out of range or repeated");
-        chain_col[k] = j;
-        col_chain[j] = k;
-    }
-
-    // SUS dependency levels, taking the columns in visiting order:
-    // level(j) = 1 + the highest level among columns visited earlier that
-    // share a check with j (0 if none); with chain = 1 a source column also
-    // comes after its chain neighbours visited earlier (their pseudo-
-    // posteriors of the same sweep give its prior).  Then the sequential-
-    // schedule records, columns in level order, RS slots each.
-    const int RS = std::max(1, max_dv);
-    gfbp_code::Levels lvs[2];
-    std::vector<SusRec> recs[2];
-    for (int chain = 0; chain < 2; ++chain) {
-        std::vector<int32_t> level(n, 0), row_top(m, -1);
-        int nlev = 0;
-        for (int t = 0; t < n; ++t) {
-            const int j = visit[t];
-            int lv = 0;
-            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) lv = std::max(lv, row_top[edge_row[col_edge[u]]] + 1);
-            const int k = col_chain[j];
-            if (chain && k >= 0)
-                for (int kk = k - 1; kk <= k + 1; kk += 2)
-                    if (kk >= 0 && kk < K && vpos[chain_col[kk]] < t) lv = std::max(lv, level[chain_col[kk]] + 1);
-            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) row_top[edge_row[col_edge[u]]] = lv;
-            level[j] = lv;
-            nlev = std::max(nlev, lv + 1);
-        }
-        gfbp_code::Levels &L = lvs[chain];
-        L.ptr.assign(nlev + 1, 0);
-        L.sibs.assign(nlev, 0.0);
-        L.edges.assign(nlev, 0.0);
-        L.src.assign(nlev, 0.0);
-        std::vector<int32_t> cols(n);
-        for (int j = 0; j < n; ++j) L.ptr[level[j] + 1]++;
-        for (int l = 0; l < nlev; ++l) L.ptr[l + 1] += L.ptr[l];
-        std::vector<int32_t> fillp(L.ptr.begin(), L.ptr.end() - 1);
-        for (int t = 0; t < n; ++t) {
-            const int j = visit[t];
-            const int l = level[j];
-            cols[fillp[l]++] = j;
-            L.src[l] += col_chain[j] >= 0 ? 1.0 : 0.0;
-            for (int u = col_ptr[j]; u < col_ptr[j + 1]; ++u) {
-                const int i = edge_row[col_edge[u]];
-                L.sibs[l] += d->row_ptr[i + 1] - d->row_ptr[i] - 1;
-                L.edges[l] += 1;
-            }
-        }
-        // levels of at most kThinLevel columns are walked in runs
-        for (int l = 0; l < nlev; ++l) {
-            const int c0 = L.ptr[l], nc = L.ptr[l + 1] - c0;
-            const bool thin = nc <= kThinLevel;
-            if (thin && !L.segs.empty() && L.segs.back().run) {
-                gfbp_code::Levels::Seg &g = L.segs.back();
-                g.nc += nc;
-                g.sibs += L.sibs[l];
-                g.edges += L.edges[l];
-                g.src += L.src[l];
-            } else {
-                L.segs.push_back({c0, nc, thin ? 1 : 0, L.sibs[l], L.edges[l], L.src[l]});
-            }
-        }
-        recs[chain].resize(size_t(n) * RS);
-        for (int p = 0; p < n; ++p) {
-            const int j = cols[p], dv = col_ptr[j + 1] - col_ptr[j];
-            for (int t = 0; t < RS; ++t) {
-                SusRec r{};
-                r.j = j;
-                r.dv = dv;
-                if (t < dv) {
-                    const int e = col_edge[col_ptr[j] + t], i = edge_row[e];
-                    r.e = e;
-                    r.i = i;
-                    r.rs = d->row_ptr[i];
-                    r.dc = d->row_ptr[i + 1] - d->row_ptr[i];
-                    r.self = e - r.rs;
-                    r.hinv = emap[2 * size_t(e)];
-                    r.h = emap[2 * size_t(e) + 1];
-                }
-                recs[chain][size_t(p) * RS + t] = r;
-            }
-        }
-    }
-
+    CodePlan pl;
+    std::string perr;
+    const gfbp_status ps = build_plan(d, pl, perr);
+    if (ps != GFBP_OK) return fail(ps, perr);
+    const int q = pl.q, p = pl.p, n = pl.n, m = pl.m, E = pl.E, max_dc = pl.max_dc, max_dv = pl.max_dv;
+    const unsigned poly = pl.poly;
+    const double sum_dc2 = pl.sum_dc2;
+    const std::vector<uint8_t> &mul = pl.mul;
+    const std::vector<int32_t> &col_ptr = pl.col_ptr, &col_edge = pl.col_edge, &edge_row = pl.edge_row,
+                               &visit = pl.visit, &chain_col = pl.chain_col, &col_chain = pl.col_chain;
+    const std::vector<uint64_t> &emap = pl.emap;
+    std::vector<SusRec> *recs = pl.recs;
+    LevelPlan *lvs = pl.lv;
     gfbp_code *c = new (std::nothrow) gfbp_code();
     if (!c) return fail(GFBP_ENOMEM, "host allocation");
     size_t off = 0;
@@ -1704,8 +1528,8 @@ gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     c->info = gfbp_code_info{q, p, n, m, d->n_info, E, max_dc, max_dv, int32_t(poly),
                              int32_t(lvs[0].ptr.size()) - 1, int32_t(lvs[1].ptr.size()) - 1};
     c->sum_dc2 = sum_dc2;
-    c->lv[0] = std::move(lvs[0]);
-    c->lv[1] = std::move(lvs[1]);
+    static_cast<LevelPlan &>(c->lv[0]) = std::move(lvs[0]);
+    static_cast<LevelPlan &>(c->lv[1]) = std::move(lvs[1]);
     c->lv[0].recs = reinterpret_cast<const SusRec *>(base + o_sr0);
     c->lv[1].recs = reinterpret_cast<const SusRec *>(base + o_sr1);
     c->lv[0].dptr = reinterpret_cast<const int32_t *>(base + o_lp0);

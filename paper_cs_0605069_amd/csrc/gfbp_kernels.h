@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gfbp_plan.h"
+
 namespace gfbp {
 
 constexpr int kWave = 64;
@@ -36,16 +38,6 @@ struct DevCode {
     const int32_t *visit;     // [n] SUS visiting order of the columns
     const int32_t *chain_col; // [n_info] column of source symbol k (the Markov chain's order)
     const int32_t *col_chain; // [n] source symbol held by column j, or -1
-};
-
-// One edge slot of a column in the sequential schedule, precomputed so that
-// a column step starts from a single wave-uniform load: the column j and its
-// degree dv, and for slots below dv the edge e, its row i, the row's first
-// edge rs, the row degree dc, e's place in its row (self) and the packed
-// images of the basis under h_e^-1 and h_e.
-struct SusRec {
-    int32_t j, dv, e, i, rs, dc, self, pad;
-    uint64_t hinv, h;
 };
 
 struct DevState {

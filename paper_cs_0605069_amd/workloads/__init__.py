@@ -58,11 +58,18 @@ PAPER_MARKOV_4S = PAPER_MARKOV_4S_RAW / PAPER_MARKOV_4S_RAW.sum(axis=1, keepdims
 _lib = None
 
 
+# Directory of a sanitizer-instrumented build of the host libraries (set by
+# the sanitizer test for the process it starts); unset: the in-tree build.
+SANITIZED_DIR_ENV = "GFBP_SANITIZED_DIR"
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    path = os.path.join(_HERE, _LIBNAME)
+    path = os.path.join(os.environ.get(SANITIZED_DIR_ENV) or _HERE, _LIBNAME)
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')"
@@ -80,14 +87,15 @@ def _load():
     return lib
 
 
-def build_native(verbose: bool = False) -> str:
-    """Compile the encoder helper with gcc into this directory."""
+def build_native(verbose: bool = False, out_dir: str | None = None, sanitize: bool = False) -> str:
+    """Compile the encoder helper with gcc into this directory (or out_dir;
+    sanitize: with the address and undefined-behaviour sanitizers)."""
     import subprocess
 
     src = os.path.join(_HERE, "_encoder.c")
-    out = os.path.join(_HERE, _LIBNAME)
+    out = os.path.join(out_dir or _HERE, _LIBNAME)
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src]
+    cmd = ["gcc", *(SANITIZE_FLAGS if sanitize else ["-O2"]), "-fPIC", "-shared", "-o", tmp, src]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
