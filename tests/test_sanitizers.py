@@ -7,9 +7,9 @@
 * The reference decoder (oracle/gfbp_oracle.c) and the workload encoder
   (workloads/_encoder.c), compiled with the sanitizers into a temporary
   directory and loaded, with the sanitizer runtime preloaded, by a child
-  pytest that runs the CPU tests which call them (the oracle pins, the
-  workload tests and the paper-value fixtures).  Leak reports are off in the
-  child (the Python interpreter keeps its own allocations to the end).
+  pytest that runs the whole CPU suite (this file aside).  Leak reports are
+  off in the child (the Python interpreter keeps its own allocations to the
+  end).
 """
 import os
 import shutil
@@ -54,8 +54,8 @@ def test_oracle_and_encoder_under_sanitizers(tmp_path):
     env = dict(os.environ, LD_PRELOAD=asan, GFBP_SANITIZED_DIR=str(tmp_path),
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1",
                OMP_NUM_THREADS="4")
-    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-           "tests/test_oracle_pins.py", "tests/test_workloads.py", "tests/test_golden.py"]
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu", "tests",
+           "--ignore=tests/test_sanitizers.py"]
     out = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, env=env, timeout=900)
     assert out.returncode == 0, out.stdout[-3000:] + out.stderr[-3000:]
     assert "passed" in out.stdout
