@@ -64,7 +64,10 @@ struct Pick {
 
 // A6, one SUS column step by one wavefront: the r-messages of the column's
 // edges (records recs[0..dv)) in edge order from the siblings' current q,
-// then the column's pseudo-posterior, decision and q-messages (A4).
+// then the column's pseudo-posterior, decision and q-messages (A4).  Where
+// registers allow (narrow rows, few entries per lane), the siblings of the
+// next edge are requested before the current edge's arithmetic, so that one
+// edge's loads are always in flight.
 template <int P, int LG, int DCM, int DVM>
 __device__ __forceinline__ void sus_column_wave(const DevCode &c, const DevState &s, const uint8_t *z,
                                                 const tiled::Item &it, const SusRec *recs, int prior_on, int wantQ,
@@ -72,23 +75,26 @@ __device__ __forceinline__ void sus_column_wave(const DevCode &c, const DevState
     using Gm = tiled::Geo<P, LG>;
     const int f = it.f;
     const int j = recs[0].j, dv = recs[0].dv;
+    constexpr bool kAhead = (DCM - 1) * Gm::EL <= 24;
+    constexpr int NB = kAhead ? 2 : 1;
     float r[DVM][Gm::EL];
+    float raw[NB][DCM - 1][Gm::EL];
+    if (kAhead && dv > 0) tiled::sibling_loads<P, LG, DCM>(s, it, recs[0], raw[0]);
 #pragma unroll
     for (int d = 0; d < DVM; ++d) {
         if (d < dv) {
+            if (!kAhead)
+                tiled::sibling_loads<P, LG, DCM>(s, it, recs[d], raw[0]);
+            else if (d + 1 < DVM && d + 1 < dv)
+                tiled::sibling_loads<P, LG, DCM>(s, it, recs[d + 1], raw[(d + 1) % NB]);
             const SusRec rec = recs[d];
-            const int rs = rec.rs, dc = rec.dc, self = rec.self;
-            float raw[DCM][Gm::EL];
-#pragma unroll
-            for (int t = 0; t < DCM; ++t)
-                if (t < dc && t != self) tiled::ld<Gm::EL>(tiled::chunk<P, LG>(s.Qm, size_t(rs + t), s.Fp, it), raw[t]);
             double acc[Gm::EL];
             tiled::syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + rec.i] : 0, it.g, acc);
 #pragma unroll
-            for (int t = 0; t < DCM; ++t) {
-                if (t < dc && t != self) {
+            for (int u = 0; u < DCM - 1; ++u) {
+                if (u < rec.dc - 1) {
                     double w[Gm::EL];
-                    tiled::transform<P, LG>(raw[t], w, it.g);
+                    tiled::transform<P, LG>(raw[d % NB][u], w, it.g);
 #pragma unroll
                     for (int q = 0; q < Gm::EL; ++q) acc[q] *= w[q];
                 }

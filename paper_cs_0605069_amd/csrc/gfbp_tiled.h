@@ -121,22 +121,31 @@ __device__ __forceinline__ T *chunk(T *arr, size_t node, int Fp, const Item &it)
 // Loads and stores of a lane's EL entries of a vector array.  Every such
 // array is larger than the caches and each access streams (a vector is read
 // again only after the whole family has passed), so the accesses carry the
-// non-temporal hint.
+// non-temporal hint, except the stores of 8 or more entries per lane: those
+// take two or more instructions per lane, each covering every other 16 bytes
+// of the wavefront's span, and with the hint the cache writes the partly
+// filled lines out before the next instruction completes them (about 1.4x
+// the written bytes at 8 entries per lane); plain stores let it merge them.
+// The arrays live in global memory; the accesses name that address space, so
+// that they compile to global (not generic) memory instructions also where
+// the pointer was read from memory (the persistent kernels' per-code state),
+// which the compiler cannot trace to a kernel argument.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+#define GFBP_GLOBAL __attribute__((address_space(1)))
 
 template <int EL>
 __device__ __forceinline__ void ld(const float *p, float *v) {
     if constexpr (EL == 1) {
-        v[0] = __builtin_nontemporal_load(p);
+        v[0] = __builtin_nontemporal_load((const GFBP_GLOBAL float *)p);
     } else if constexpr (EL == 2) {
-        const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
+        const f32x2 t = __builtin_nontemporal_load((const GFBP_GLOBAL f32x2 *)p);
         v[0] = t.x;
         v[1] = t.y;
     } else {
 #pragma unroll
         for (int k = 0; k < EL / 4; ++k) {
-            const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p) + k);
+            const f32x4 t = __builtin_nontemporal_load((const GFBP_GLOBAL f32x4 *)p + k);
             v[4 * k] = t.x;
             v[4 * k + 1] = t.y;
             v[4 * k + 2] = t.z;
@@ -148,18 +157,28 @@ __device__ __forceinline__ void ld(const float *p, float *v) {
 template <int EL>
 __device__ __forceinline__ void st(float *p, const float *v) {
     if constexpr (EL == 1) {
-        __builtin_nontemporal_store(v[0], p);
+        __builtin_nontemporal_store(v[0], (GFBP_GLOBAL float *)p);
     } else if constexpr (EL == 2) {
         const f32x2 t = {v[0], v[1]};
-        __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(p));
+        __builtin_nontemporal_store(t, (GFBP_GLOBAL f32x2 *)p);
     } else {
 #pragma unroll
         for (int k = 0; k < EL / 4; ++k) {
             const f32x4 t = {v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
-            __builtin_nontemporal_store(t, reinterpret_cast<f32x4 *>(p) + k);
+            if constexpr (EL == 4)
+                __builtin_nontemporal_store(t, (GFBP_GLOBAL f32x4 *)p + k);
+            else
+                ((GFBP_GLOBAL f32x4 *)p)[k] = t;
         }
     }
 }
+
+// Row degrees up to this bound load every slot of the degree class (the
+// slots past the row's degree repeat an edge of the row, a cache hit whose
+// value is not used): the loads then form one block and are all in flight
+// before the first is used, where loads under a condition each wait for
+// their own result.  Wider classes load only the row's edges.
+constexpr int kAllSlots = 8;
 
 // Images under multiplication by h (basis images packed in `packed`) of the
 // positions y = g*EL + r held by lane g: by linearity h y = h (g*EL) + h r,
@@ -491,11 +510,13 @@ __device__ __forceinline__ void check_node(const DevCode &c, const DevState &s, 
     using Gm = Geo<P, LG>;
     const int i = it.node, f = it.f;
     const int rs = c.row_ptr[i], dc = c.row_ptr[i + 1] - rs;
+    if (dc == 0) return;
     const int zi = z ? z[size_t(f) * c.m + i] : 0;
     float raw[DCM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DCM; ++d)
-        if (d < dc) ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + d), s.Fp, it), raw[d]);
+        if (DCM <= kAllSlots || d < dc)
+            ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + (d < dc ? d : dc - 1)), s.Fp, it), raw[d]);
     double W[DCM][Gm::EL];
 #pragma unroll
     for (int d = 0; d < DCM; ++d)
@@ -535,12 +556,16 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
 
 // The lane's entries of the prior-weighted evidence p_j of column j: the
 // source symbol's prior row when the frame takes a prior, else L_j.
+// frame_prior: the frame takes a prior (frame_prior_of).
+__device__ __forceinline__ bool frame_prior_of(const DevState &s, int f, int prior_on) {
+    return s.mark ? s.mark[f] != 0 : prior_on != 0;
+}
+
 template <int P, int LG>
 __device__ __forceinline__ const float *prior_row(const DevCode &c, const DevState &s, const Item &it, int j,
-                                                  int prior_on) {
+                                                  bool frame_prior) {
     const int k = c.col_chain[j];
-    const bool pr = (s.mark ? s.mark[it.f] != 0 : prior_on != 0) && k >= 0;
-    return pr ? chunk<P, LG>(s.Pr, size_t(k), s.Fp, it) : chunk<P, LG>(s.L, size_t(j), s.Fp, it);
+    return frame_prior && k >= 0 ? chunk<P, LG>(s.Pr, size_t(k), s.Fp, it) : chunk<P, LG>(s.L, size_t(j), s.Fp, it);
 }
 
 // Clipping (A5): the symbol of largest pseudo-posterior, the smallest one
@@ -584,7 +609,7 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
     using Gm = Geo<P, LG>;
     const int f = it.f;
     float pf[Gm::EL];
-    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, prior_on), pf);
+    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, frame_prior_of(s, f, prior_on)), pf);
     double pv[Gm::EL], acc[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
@@ -655,6 +680,38 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
     variable_node<P, LG, DVM>(c, s, prior_on, wantQ, snap, it, perm);
 }
 
+// The current q of the siblings of edge rec in its row, for the lane's frame:
+// sibling u is edge u of the row below the edge itself, u + 1 from it on.
+template <int P, int LG, int DCM>
+__device__ __forceinline__ void sibling_loads(const DevState &s, const Item &it, const SusRec &rec,
+                                              float (&raw)[DCM - 1][Geo<P, LG>::EL]) {
+#pragma unroll
+    for (int u = 0; u < DCM - 1; ++u) {
+        const int t = u < rec.dc - 1 ? (u < rec.self ? u : u + 1) : rec.self;
+        if (DCM <= kAllSlots || u < rec.dc - 1)
+            ld<Geo<P, LG>::EL>(chunk<P, LG>(s.Qm, size_t(rec.rs + t), s.Fp, it), raw[u]);
+    }
+}
+
+// The prior-weighted evidence of column j for the lane's frame (prior_row),
+// or, in the variant that assigns source priors during the sweep, Eq. (7)
+// from the chain neighbours' newest pseudo-posteriors: a neighbour visited
+// earlier in the sweep sits on a lower level, one visited later on a higher
+// level.
+template <int P, int LG, bool SWEEP_PRIOR>
+__device__ __forceinline__ void column_prior(const DevCode &c, const DevState &s, const Item &it, int j,
+                                             bool frame_prior, const SweepPrior &sp,
+                                             float (&pf)[Geo<P, LG>::EL]) {
+    if constexpr (SWEEP_PRIOR) {
+        const int k = c.col_chain[j];
+        if (sp.on && frame_prior && k >= 0) {
+            markov_prior<P, LG>(c, s, it, k, sp.M, sp.pi, sp.mshape, pf);
+            return;
+        }
+    }
+    ld<Geo<P, LG>::EL>(prior_row<P, LG>(c, s, it, j, frame_prior), pf);
+}
+
 // A6 sequential schedule, the step of one column for one tile of frames,
 // done by a workgroup: wavefront d (< column degree) computes the r of the
 // column's d-th edge (record rec) from the siblings' current q (partial
@@ -662,8 +719,8 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
 // column's r into its edge's q and wavefront 0 into the pseudo-posterior and
 // decision (partial vertical pass).  `live`: this lane's frame is still
 // iterating.  perm is the wavefront's LDS rows; rsh holds the column's r as
-// [d][register][lane].  The column's prior is loaded first so that its
-// latency overlaps the check-side work.  SWEEP_PRIOR: the variant whose
+// [d][register][lane].  The siblings' q and then the column's prior are
+// requested before any of them is used.  SWEEP_PRIOR: the variant whose
 // source-symbol priors are assigned during the sweep (a separate
 // instantiation, so the default one carries none of its code or registers).
 template <int P, int LG, int DCM, int DVM, bool SWEEP_PRIOR>
@@ -677,33 +734,23 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
     const bool mine = live && d < dv;
     const bool post = live && d == 0;  // pseudo-posterior and decision (also for a column without edges)
     const size_t e = size_t(rec.e);
+    const bool fprior = (mine || post) && frame_prior_of(s, f, prior_on);
     float pf[Gm::EL];
-    if (mine || post) {
-        const int k = c.col_chain[j];
-        const bool mk = (s.mark ? s.mark[f] != 0 : prior_on != 0) && k >= 0;
-        if (SWEEP_PRIOR && sp.on && mk) {
-            // the prior assigned at this column's vertical pass, from the
-            // chain neighbours' newest pseudo-posteriors: a neighbour visited
-            // earlier in the sweep sits on a lower level, one visited later
-            // on a higher level
-            markov_prior<P, LG>(c, s, it, k, sp.M, sp.pi, sp.mshape, pf);
-        } else {
-            ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, prior_on), pf);
-        }
-    }
     if (mine) {
-        const int rs = rec.rs, dc = rec.dc, self = rec.self;
-        float raw[DCM][Gm::EL];
-#pragma unroll
-        for (int t = 0; t < DCM; ++t)
-            if (t < dc && t != self) ld<Gm::EL>(chunk<P, LG>(s.Qm, size_t(rs + t), s.Fp, it), raw[t]);
+        // the siblings' q and the syndrome symbol, then the prior: all
+        // requested before any is used
+        const int dc = rec.dc;
+        float raw[DCM - 1][Gm::EL];
+        sibling_loads<P, LG, DCM>(s, it, rec, raw);
+        const int zi = z ? z[size_t(f) * c.m + rec.i] : 0;
+        column_prior<P, LG, SWEEP_PRIOR>(c, s, it, j, fprior, sp, pf);
         double acc[Gm::EL];
-        syndrome_signs<P, LG>(z ? z[size_t(f) * c.m + rec.i] : 0, it.g, acc);
+        syndrome_signs<P, LG>(zi, it.g, acc);
 #pragma unroll
-        for (int t = 0; t < DCM; ++t) {
-            if (t < dc && t != self) {
+        for (int u = 0; u < DCM - 1; ++u) {
+            if (u < dc - 1) {
                 double w[Gm::EL];
-                transform<P, LG>(raw[t], w, it.g);
+                transform<P, LG>(raw[u], w, it.g);
 #pragma unroll
                 for (int q = 0; q < Gm::EL; ++q) acc[q] *= w[q];
             }
@@ -720,6 +767,8 @@ __device__ __forceinline__ void sus_column(const DevCode &c, const DevState &s, 
             rsh[(d * Gm::EL + q) * kWave + lane] = rv[q];
             if (snap.r) snap.r[(size_t(f) * c.E + e) * Gm::Q + it.g * Gm::EL + q] = rv[q];
         }
+    } else if (post) {
+        column_prior<P, LG, SWEEP_PRIOR>(c, s, it, j, fprior, sp, pf);  // a column without edges
     }
     __syncthreads();
     double pv[Gm::EL];
