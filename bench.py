@@ -11,7 +11,9 @@ Reported value: edge-q message updates per second over the whole step, where
 a frame that ran t iterations counts t * E * q updates (E = edges, q = field
 size).  Also per schedule: updates/s, frames/s, mean iterations, decode-call
 latency; the roofline of the dominant kernel from HIP events recorded around
-each launch during the timed steps; the reference decoder timed on a bounded
+each launch during the timed steps, beside the bandwidth a plain streaming
+copy reaches on the same device (measured after the timed steps); the
+reference decoder timed on a bounded
 sample of the same frames on the host cores; a GF(64) leg; and a serving leg
 (continuous batching of a Poisson stream of mixed-code frames: throughput and
 p50/p99 frame latency per schedule).
@@ -227,6 +229,7 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-rate", type=float, default=20000.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-copy-rate", action="store_true", help="skip measuring the achievable streaming-copy bandwidth")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: frames are independent and this decoder has no multi-GPU path "
@@ -346,6 +349,15 @@ def main():
             roof["traffic"] = tr["kernels"][dom]["bytes_per_dispatch"]
             roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
             roof["traffic_over_algorithmic"] = roof["traffic"] / algo
+        if not args.no_copy_rate:
+            # what a plain streaming kernel reaches on this device (2 GiB copy,
+            # after the timed steps), beside the nominal peak
+            src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+            dst = torch.empty_like(src)
+            cr = gfbp.stream_copy_rate(dst, src, reps=5)
+            del src, dst
+            roof["achievable_copy"] = cr / 1e9
+            roof["frac_of_achievable_copy"] = ach / cr
     kernels = {k: {"launches": v["launches"], "avg_ms": v["total_ms"] / v["launches"],
                    "share_of_gpu_time": v["total_ms"] / max(1e-9, sum(x["total_ms"] for x in prof.values())),
                    "GBps_algorithmic": (v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9) if v["total_ms"] else 0.0,

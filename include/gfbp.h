@@ -446,6 +446,15 @@ gfbp_status gfbp_profile_reset(void);
  * many kinds have data. */
 int32_t gfbp_profile_read(gfbp_kernel_stats *out, int32_t cap);
 
+/* Measurement: the HBM bandwidth a plain streaming kernel reaches on this
+ * device, to state beside the nominal peak.  Copies `bytes` (> 0, a multiple
+ * of 16) from src to dst (device pointers, 16-byte aligned, not overlapping)
+ * `reps` times (>= 1) on `stream` (a hipStream_t, null for the default
+ * stream) with 16-byte non-temporal loads and stores, four in flight per
+ * lane, and writes the best read + write rate in bytes per second to *rate.
+ * Synchronises the stream; GFBP_EINVAL for bad arguments. */
+gfbp_status gfbp_stream_copy_rate(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *rate);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *gfbp_last_error(void);
 

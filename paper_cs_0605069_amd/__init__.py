@@ -35,7 +35,7 @@ SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
 EXPORTS = ("gfbp_code_build", "gfbp_code_free", "gfbp_code_info_get", "gfbp_workspace_size",
            "gfbp_batch_workspace_size", "gfbp_decode_batch", "gfbp_decode_batch_noalloc", "gfbp_tune_persistent",
-           "gfbp_device_clock_hz",
+           "gfbp_device_clock_hz", "gfbp_stream_copy_rate",
            "gfbp_profile_enable", "gfbp_profile_reset", "gfbp_profile_read", "gfbp_code_set_shape",
            "gfbp_code_get_shape", "gfbp_tune", "gfbp_session_bytes", "gfbp_session_create", "gfbp_session_destroy",
            "gfbp_session_admit", "gfbp_session_step", "gfbp_session_poll", "gfbp_session_free_slots",
@@ -128,6 +128,9 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.gfbp_tune_persistent.restype = ctypes.c_int32
     L.gfbp_device_clock_hz.restype = ctypes.c_uint64
+    L.gfbp_stream_copy_rate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    L.gfbp_stream_copy_rate.restype = ctypes.c_int32
     L.gfbp_profile_enable.argtypes = [ctypes.c_int32]
     L.gfbp_profile_enable.restype = ctypes.c_int32
     L.gfbp_profile_reset.restype = ctypes.c_int32
@@ -509,6 +512,21 @@ def decode_batch_noalloc(dcodes, dframes: dict, outputs: dict, schedule="pus", m
 
 def device_clock_hz() -> int:
     return int(lib().gfbp_device_clock_hz())
+
+
+def stream_copy_rate(dst, src, reps: int = 5, stream=None) -> float:
+    """``gfbp_stream_copy_rate``: best read + write bytes/s of a streaming copy
+    of src (a contiguous device tensor) into dst (same size)."""
+    import torch
+
+    assert dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rate = ctypes.c_double(0.0)
+    _check(lib().gfbp_stream_copy_rate(dst.data_ptr(), src.data_ptr(), nbytes, int(reps), st.cuda_stream,
+                                       ctypes.byref(rate)), "gfbp_stream_copy_rate")
+    return float(rate.value)
 
 
 def tune(dcode: DeviceCode, dframes: dict, schedule="pus", trial_iters: int = 3, **kw) -> int:

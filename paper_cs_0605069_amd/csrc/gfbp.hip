@@ -1461,6 +1461,23 @@ inline bool persistent_batch(const gfbp_batch *b) {
     return b->n_codes > 1 || b->code_index != nullptr || (b->options & GFBP_OPT_PERSISTENT);
 }
 
+// Streaming copy of n 16-byte vectors, four loads in flight per lane (the
+// measurement behind gfbp_stream_copy_rate).
+constexpr int kCopyUnroll = 4;
+__global__ __launch_bounds__(256) void k_stream_copy(const tiled::f32x4 *__restrict__ src,
+                                                     tiled::f32x4 *__restrict__ dst, size_t n) {
+    const size_t stride = size_t(gridDim.x) * 256 * kCopyUnroll;
+    for (size_t base = size_t(blockIdx.x) * 256 * kCopyUnroll + threadIdx.x; base < n; base += stride) {
+        tiled::f32x4 t[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u)
+            if (base + size_t(u) * 256 < n) t[u] = __builtin_nontemporal_load(src + base + size_t(u) * 256);
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u)
+            if (base + size_t(u) * 256 < n) __builtin_nontemporal_store(t[u], dst + base + size_t(u) * 256);
+    }
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -1469,6 +1486,46 @@ extern "C" {
 const char *gfbp_last_error(void) { return g_err.c_str(); }
 
 const char *gfbp_version(void) { return "gfbp 0.5 (gfx950)"; }
+
+gfbp_status gfbp_stream_copy_rate(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *rate) {
+    if (!dst || !src || !rate) return fail(GFBP_EINVAL, "null argument");
+    if (bytes == 0 || bytes % 16 != 0 || reps < 1)
+        return fail(GFBP_EINVAL, "bytes must be a positive multiple of 16, reps >= 1");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 != 0)
+        return fail(GFBP_EINVAL, "buffers must be 16-byte aligned");
+    const auto d = reinterpret_cast<uintptr_t>(dst), sr = reinterpret_cast<uintptr_t>(src);
+    if (d < sr + bytes && sr < d + bytes) return fail(GFBP_EINVAL, "buffers overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t n = bytes / 16;
+    const size_t per_block = size_t(256) * kCopyUnroll;
+    const unsigned grid = unsigned(std::min<size_t>(32768, (n + per_block - 1) / per_block));
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(GFBP_EHIP, "hipEventCreate");
+    }
+    float best = 0.0f;
+    hipError_t e = hipSuccess;
+    for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
+        e = hipEventRecord(a, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st,
+                               static_cast<const tiled::f32x4 *>(src), static_cast<tiled::f32x4 *>(dst), n);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && r >= 0 && (best == 0.0f || ms < best)) best = ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(GFBP_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
+    *rate = best > 0.0f ? 2.0 * double(bytes) / (double(best) * 1e-3) : 0.0;
+    return GFBP_OK;
+}
 
 gfbp_status gfbp_code_build(const gfbp_code_desc *d, gfbp_code **out) {
     if (!d || !out) return fail(GFBP_EINVAL, "null argument");

@@ -66,6 +66,13 @@ def test_null_arguments():
     assert L.gfbp_batch_workspace_size(None, None) == 0
     assert L.gfbp_tune_persistent(None, None, None, None, 0, None, 1, None, None) == -1
     assert L.gfbp_code_free(None) == 0
+    r = ctypes.c_double(0.0)
+    assert L.gfbp_stream_copy_rate(None, None, 16, 1, None, ctypes.byref(r)) == -1
+    # host-side argument checks (no device memory is touched): sizes, alignment, overlap
+    assert L.gfbp_stream_copy_rate(0x10000, 0x20000, 24, 1, None, ctypes.byref(r)) == -1
+    assert L.gfbp_stream_copy_rate(0x10000, 0x20000, 16, 0, None, ctypes.byref(r)) == -1
+    assert L.gfbp_stream_copy_rate(0x10008, 0x20000, 16, 1, None, ctypes.byref(r)) == -1
+    assert L.gfbp_stream_copy_rate(0x10000, 0x10010, 64, 1, None, ctypes.byref(r)) == -1
 
 
 @pytest.mark.parametrize("field,value", [("visit_order", [0, 1, 2, 3, 4, 4]), ("visit_order", [0, 1, 2, 3, 4, 6]),

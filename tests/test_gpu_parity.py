@@ -649,3 +649,17 @@ def test_tuner_keeps_an_allowed_shape_and_decodes_correctly(gfbp):
         g = {k: v.cpu().numpy() for k, v in out.items()}
         r = _ref(code, fr, sch, max_iter=50)
         classify(gfbp, code, fr, g, r, sch, f"tuned EL={el} {sch}", max_iter=50)
+
+
+def test_stream_copy_rate_copies_and_reports_a_rate(gfbp):
+    import torch
+
+    src = torch.randint(0, 256, (64 << 20,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    rate = gfbp.stream_copy_rate(dst, src, reps=2)
+    assert torch.equal(dst, src)
+    assert 1e11 < rate < 1e14  # bytes/s read + write (the buffers fit the last-level cache)
+    tail = torch.randint(0, 256, (4096 + 48,), dtype=torch.uint8, device="cuda")  # not a whole block of vectors
+    out = torch.zeros_like(tail)
+    gfbp.stream_copy_rate(out, tail, reps=1)
+    assert torch.equal(out, tail)
