@@ -181,7 +181,8 @@ def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus
                "frame_latency_ms_p50": float(np.percentile(lat, 50)), "frame_latency_ms_p99": float(np.percentile(lat, 99)),
                "device_latency_ms_p50": float(np.percentile(dlat, 50)),
                "device_latency_ms_p99": float(np.percentile(dlat, 99)),
-               "mean_iters": float(np.mean(st.iters)), "fer": 1 - st.converged / max(1, st.done)}
+               "mean_iters": float(np.mean(st.iters)), "fer": 1 - st.converged / max(1, st.done),
+               "edge_q_per_s": st.edge_q / st.wall}
         # the reference decoder on the kept frames
         same = tot = 0
         t0 = time.perf_counter()

@@ -177,8 +177,10 @@ typedef struct {
     int32_t n_codes;         /* entries of codes[] (0 is taken as 1)                  */
     const int32_t *code_index; /* HOST [F] code of each frame (index into codes[]), or NULL:
                                 every frame is on codes[0]                            */
-    int32_t persist_el;      /* persistent path: entries per lane (2, 4 or 8 where the degree
-                                class allows; at most q per field), 0 = 4           */
+    int32_t persist_el;      /* persistent path: entries per lane (2, 4 or 8), 0 = 4; per
+                                field taken down to max(2, q/4) (a tile then holds at
+                                most 16 frames), to 4 outside the narrow degree class
+                                (rows <= 6, columns <= 4) and to q                    */
     int32_t persist_waves;   /* persistent path: wavefronts per workgroup (1..8), 0 = 8 */
 } gfbp_batch;
 

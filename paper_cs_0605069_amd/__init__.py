@@ -445,6 +445,15 @@ def ragged_frames(frames_list, codes_list, device="cuda"):
     return out
 
 
+def persist_entries_per_lane(q: int, el: int = 0, narrow: bool = True) -> int:
+    """Entries per lane the persistent path gives field q's tiles for the batch
+    shape persist_el = el (0 = 4), as gfbp_batch.persist_el states: at most
+    max(2, q/4) (at most 16 frames per tile), at most 4 outside the narrow
+    degree class, at most q."""
+    e = min(el or 4, 4 if not narrow else 8)
+    return min(e, max(2, q // 4), q)
+
+
 def decode_multi(dcodes, code_index, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, static_prior=None, workspace=None,
                  stream=None, persist_el: int = 0, persist_waves: int = 0, tune_iters: int = 0) -> dict:

@@ -1144,6 +1144,16 @@ inline int persist_tf(int p, int lel) {  // frames per tile: 64 x entries per la
     return kWave >> (p - l);
 }
 
+// log2 entries per lane of field 2^p's tiles in degree class cls (0: narrow)
+// for the batch's shape lel: at most 2 in the general class, and small fields
+// taken down so that a tile holds at most 16 frames (at least 2 entries per
+// lane).  A tile is decoded by one workgroup, so tiles of 64 frames of a long
+// low-order code would set the running time of a whole uneven batch alone.
+inline int persist_lel(int p, int lel, int cls) {
+    const int l = std::min(cls == 0 ? lel : std::min(lel, 2), std::max(1, p - 2));
+    return std::min(l, p);
+}
+
 gfbp_status persist_plan(const gfbp_code *const *codes, int nc, const gfbp_batch *b, PersistPlan &pl) {
     const int F = b->n_frames;
     pl.F = F;
@@ -1198,8 +1208,7 @@ gfbp_status persist_plan(const gfbp_code *const *codes, int nc, const gfbp_batch
     for (size_t g = 0; g < pl.gcode.size(); ++g) {
         const gfbp_code *code = codes[pl.gcode[g]];
         const int cls = small_class(code) ? 0 : 1;
-        const int lel = cls == 0 ? pl.lel : std::min(pl.lel, 2);
-        const int TF = persist_tf(code->info.p, lel);
+        const int TF = persist_tf(code->info.p, persist_lel(code->info.p, pl.lel, cls));
         const int Fg = int(pl.gframe[g].size());
         const int list = 6 * cls + code->info.p - 1;
         for (int t = 0; t * TF < Fg; ++t) {
@@ -1382,7 +1391,8 @@ gfbp_status decode_persistent(const gfbp_code *const *codes, int nc, const gfbp_
         tr.begin();
         hipEvent_t ea = g_launch_ev[0], eb = g_launch_ev[1];
         g_launch_ev[0] = g_launch_ev[1] = nullptr;
-        he = persist::launch_persistent(l % 6 + 1, l < 6 ? pl.lel : 2, l < 6, b->schedule, dg,
+        const int lp = l % 6 + 1;
+        he = persist::launch_persistent(lp, persist_lel(lp, pl.lel, l / 6), l < 6, b->schedule, dg,
                                         reinterpret_cast<const persist::Work *>(w + pl.o_work[l]),
                                         int(pl.work[l].size()), next + l, B, pl.waves, ls, ea, eb);
         if (ea) {

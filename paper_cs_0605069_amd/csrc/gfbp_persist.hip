@@ -37,6 +37,10 @@ hipError_t launch_one(const Group *groups, const Work *work, int n_work, uint32_
 template <int P, int SCH>
 hipError_t launch_p(int lel, bool small, const Group *groups, const Work *work, int n_work, uint32_t *next,
                     const Batch &B, int waves, hipStream_t st, hipEvent_t a, hipEvent_t b) {
+    if constexpr (P == 2 || P == 3) {  // two entries per lane: the small fields' 16- and 32-frame tiles
+        if (lel == 1 && !small) return launch_one<P, 1, 16, 8, SCH>(groups, work, n_work, next, B, waves, st, a, b);
+        if (lel == 1) return launch_one<P, 1, 6, 4, SCH>(groups, work, n_work, next, B, waves, st, a, b);
+    }
     if (!small) return launch_one<P, 2, 16, 8, SCH>(groups, work, n_work, next, B, waves, st, a, b);
     if (lel == 3) return launch_one<P, 3, 6, 4, SCH>(groups, work, n_work, next, B, waves, st, a, b);
     return launch_one<P, 2, 6, 4, SCH>(groups, work, n_work, next, B, waves, st, a, b);
@@ -61,7 +65,7 @@ hipError_t launch_s(int p, int lel, bool small, const Group *groups, const Work 
 hipError_t launch_persistent(int p, int lel, bool small, int sch, const Group *groups, const Work *work, int n_work,
                              uint32_t *next, const Batch &B, int waves, hipStream_t st, hipEvent_t a, hipEvent_t b) {
     if (n_work <= 0) return hipSuccess;
-    if (waves < 1 || waves > 8 || (lel != 2 && lel != 3)) return hipErrorInvalidValue;
+    if (waves < 1 || waves > 8 || lel < 1 || lel > 3) return hipErrorInvalidValue;
     if (sch == GFBP_PUS) return launch_s<GFBP_PUS>(p, lel, small, groups, work, n_work, next, B, waves, st, a, b);
     return launch_s<GFBP_SUS>(p, lel, small, groups, work, n_work, next, B, waves, st, a, b);
 }

@@ -57,6 +57,7 @@ class Stats:
     device_latency: list = field(default_factory=list)  # admission to retirement on the device clock, seconds
     answer_time: list = field(default_factory=list)  # collection time of each answer since the start, seconds
     iters: list = field(default_factory=list)
+    edge_q: float = 0.0  # edge-q updates of the answered frames (iterations x E x q)
     converged: int = 0
     done: int = 0
     offered: int = 0
@@ -201,6 +202,7 @@ class Server:
                     st.device_latency.extend(((ts[:, 1].astype(np.int64) - ts[:, 0].astype(np.int64)) / self.clock_hz)
                                              .tolist())
                     st.iters.extend(it.tolist())
+                    st.edge_q += float(it.sum()) * cq.code.E * cq.code.q
                     st.converged += int(cv.sum())
                     if self.keep:
                         for r in range(len(ids)):
@@ -314,6 +316,7 @@ def main():
                 "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
                 "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
                 "mean_iters": float(np.mean(st.iters)) if st.iters else None,
+                "edge_q_per_s": st.edge_q / st.wall if st.wall else None,
                 "fer": 1 - st.converged / max(1, st.done), "sessions_opened": srv.opened,
                 "codes": args.codes, "slots": args.slots, "step_iters": args.step_iters,
                 "graph": args.graph, "step_graphs": args.step_graphs}), flush=True)

@@ -68,7 +68,7 @@ def test_persistent_equals_plain(gfbp, q, n, channel, prior, syn, schedule, el, 
         fr = wl.make_coset_frames(code, 333, 84 + q, channel, param)
     dfr = gfbp.frames_to_device(fr)
     dcode = gfbp.DeviceCode(code)
-    dcode.set_shape(schedule, min(el, q))  # the same lane split (the transforms' rounding order)
+    dcode.set_shape(schedule, gfbp.persist_entries_per_lane(q, el))  # the same lane split (rounding order)
     out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50, **kw)
     a = {k: v.cpu().numpy() for k, v in out.items()}
     b = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, persistent=True, persist_el=el, persist_waves=waves, **kw)
@@ -88,14 +88,17 @@ def test_persistent_mn_form_per_frame_channels(gfbp):
              for k, (ch, prm) in enumerate((("bsc", 0.15), ("bec", 0.5), ("biawgn", 1.0)))]
     dfr = gfbp.ragged_frames(parts, [code] * 3)
     kw = dict(prior="markov", markov_M=M, markov_pi=start, max_iter=60)
+    dcode = gfbp.DeviceCode(code)
     for sch in ("pus", "sus"):
-        a = gpu_decode(gfbp, code, dfr, sch, **kw)
+        dcode.set_shape(sch, gfbp.persist_entries_per_lane(q))  # the persistent path's lane split
+        a = {k: v.cpu().numpy() for k, v in gfbp.decode_batch(dcode, dfr, schedule=sch, **kw).items()}
         b = gpu_decode(gfbp, code, dfr, sch, persistent=True, **kw)
         for k in ("xhat", "iters", "converged", "guards"):
             assert np.array_equal(a[k], b[k]), f"{sch} {k}"
         o = 0
         for p in parts:  # and each channel's frames alone (a batch-wide channel)
-            c = gpu_decode(gfbp, code, gfbp.frames_to_device(p), sch, **kw)
+            c = {k: v.cpu().numpy() for k, v in gfbp.decode_batch(dcode, gfbp.frames_to_device(p), schedule=sch,
+                                                                   **kw).items()}
             assert np.array_equal(c["xhat"], a["xhat"][o:o + p.F]) and np.array_equal(c["iters"], a["iters"][o:o + p.F])
             o += p.F
     assert torch.cuda.is_available()
