@@ -7,7 +7,10 @@ their full sizes and in the launch configuration the benchmark times.
     point in one launch, max 100: every 16th frame (256 per point) through
     the reference;
   * GF(8) (3,6) N = 3000, Markov source (self-transition 0.7), BSC 0.08 and
-    BEC 0.45, 4096 frames each, max 100: every 16th frame (256 per channel).
+    BEC 0.45, 4096 frames each, max 100: every 16th frame (256 per channel);
+  * the benchmark's GF(64) leg: (3,6) N = 2000, BI-AWGN at 1.6 dB, 4096
+    frames in one launch, max 100: every 128th frame (32) through the
+    reference (a GF(64) reference frame costs about a second per thread).
 
 Each case, both schedules: decisions and iteration counts under the gate of
 tests/_parity.py on the reference's frames (FER and mean-iteration intervals
@@ -66,7 +69,8 @@ def _check(gfbp, code, fr, schedule, label, every=1, **kw):
               f"mean iterations {r['iters'].mean():.3f}; intervals overlap: FER "
               f"{fer_ci_overlap(g['converged'], r['converged'])} iterations "
               f"{mean_ci_overlap(g['iters'].astype(float), r['iters'].astype(float))}")
-    messages_close(gfbp, code, fr.subset(np.arange(0, 64 * every, every)), schedule, iters=(1, 2, 3, 4, 5),
+    stride = max(1, min(every, fr.F // 64))
+    messages_close(gfbp, code, fr.subset(np.arange(0, 64 * stride, stride)), schedule, iters=(1, 2, 3, 4, 5),
                    label=label, **{k: v for k, v in kw.items() if k != "max_iter"})
 
 
@@ -94,3 +98,10 @@ def test_gf8_n3000_markov(gfbp, c3, schedule, channel, param):
     fr = wl.make_frames(code, enc, 4096, 0xDA7A0003 + (channel == "bec"), channel, param, source="markov", markov=M)
     _check(gfbp, code, fr, schedule, f"GF(8) N=3000 Markov {channel} {schedule}", every=16, max_iter=100,
            prior="markov", markov_M=M, markov_pi=pi)
+
+
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_gf64_n2000_biawgn_bench_leg(gfbp, schedule):
+    code, enc = wl.systematic(wl.make_code(2000, 1000, 3, 64, seed=0xC0DE0040))
+    fr = wl.make_frames(code, enc, 4096, 0xDA7A0040, "biawgn", wl.sigma_from_ebn0(1.6, code.n_info / code.n))
+    _check(gfbp, code, fr, schedule, f"GF(64) N=2000 1.6 dB {schedule}", every=128, max_iter=100)
