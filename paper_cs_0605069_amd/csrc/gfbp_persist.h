@@ -80,6 +80,8 @@ __device__ __forceinline__ void sus_column_wave(const DevCode &c, const DevState
     float r[DVM][Gm::EL];
     float raw[NB][DCM - 1][Gm::EL];
     if (kAhead && dv > 0) tiled::sibling_loads<P, LG, DCM>(s, it, recs[0], raw[0]);
+    float pf[Gm::EL];  // the column's prior, requested early: used only at the end
+    tiled::ld<Gm::EL>(tiled::prior_row<P, LG>(c, s, it, j, tiled::frame_prior_of(s, f, prior_on)), pf);
 #pragma unroll
     for (int d = 0; d < DVM; ++d) {
         if (d < dv) {
@@ -108,8 +110,7 @@ __device__ __forceinline__ void sus_column_wave(const DevCode &c, const DevState
             tiled::lds_permute<P, LG>(perm, it, pos, tv, r[d]);
         }
     }
-    tiled::variable_update<P, LG, DVM>(c, s, it, j, r, c.col_ptr[j], dv, prior_on, wantQ, Snap{nullptr, nullptr},
-                                       perm);
+    tiled::variable_update<P, LG, DVM>(c, s, it, j, r, c.col_ptr[j], dv, pf, wantQ, Snap{nullptr, nullptr}, perm);
 }
 
 // Decode tile `tile` of group G to the end.  act/unsat: the tile's

@@ -604,12 +604,10 @@ __device__ __forceinline__ int clip(const double *acc, int g) {
 // edge's q (Eq. (4)), normalised.
 template <int P, int LG, int DVM>
 __device__ __forceinline__ void variable_update(const DevCode &c, const DevState &s, const Item &it, int j,
-                                                const float (*r)[Geo<P, LG>::EL], int cs, int dv, int prior_on,
+                                                const float (*r)[Geo<P, LG>::EL], int cs, int dv, const float *pf,
                                                 int wantQ, const Snap &snap, float *perm) {
     using Gm = Geo<P, LG>;
     const int f = it.f;
-    float pf[Gm::EL];
-    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, frame_prior_of(s, f, prior_on)), pf);
     double pv[Gm::EL], acc[Gm::EL];
 #pragma unroll
     for (int q = 0; q < Gm::EL; ++q) {
@@ -667,7 +665,9 @@ __device__ __forceinline__ void variable_node(const DevCode &c, const DevState &
 #pragma unroll
     for (int d = 0; d < DVM; ++d)
         if (d < dv) ld<Gm::EL>(chunk<P, LG>(s.R, size_t(c.col_edge[cs + d]), s.Fp, it), r[d]);
-    variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, prior_on, wantQ, snap, perm);
+    float pf[Gm::EL];
+    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, frame_prior_of(s, it.f, prior_on)), pf);
+    variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, pf, wantQ, snap, perm);
 }
 
 template <int P, int LG, int DVM>
