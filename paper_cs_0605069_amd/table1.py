@@ -9,7 +9,10 @@ standard deviation of the per-sample ratio, and the bit error rate (Table 1).
 Its codes come from the Kanter-Saad construction, which it does not specify;
 ``workloads.mn_code`` (A with column weight 3, lower-triangular B) stands in,
 so the iteration counts and error rates are not the paper's: the comparison
-is the schedules' ratio.
+is the schedules' ratio.  ``--b-form chain`` (the default) gives B a
+dual-diagonal chain, whose noise columns a sequential sweep must visit one
+after another; ``--b-form pool`` places each column's second entry in a
+random later row, which leaves the sweep a few tens of dependency levels.
 
 ``python -m paper_cs_0605069_amd.table1`` decodes every setting with both
 schedules on the same samples and prints one JSON line per setting;
@@ -51,12 +54,13 @@ def source_model(name: str, q: int):
 
 
 def run_setting(channel: str, q: int, source: str, param: float, samples: int, batch: int, max_iter: int,
-                seed: int, scale: float = 1.0, source_bits: int = 10000, schedules=("pus", "sus")) -> dict:
+                seed: int, scale: float = 1.0, source_bits: int = 10000, schedules=("pus", "sus"),
+                b_form: str = "chain", pool: int = 1000) -> dict:
     import torch
 
     p = int(round(math.log2(q)))
     N = source_bits // p
-    code = wl.mn_code(N, 3 * N, q, seed=seed)
+    code = wl.mn_code(N, 3 * N, q, seed=seed, b_form=b_form, pool=pool)
     M, start = source_model(source, q)
     kw = {} if M is None else dict(prior="markov", markov_M=M, markov_pi=start)
     dcode = DeviceCode(code)
@@ -86,7 +90,7 @@ def run_setting(channel: str, q: int, source: str, param: float, samples: int, b
             diff = xh[:, :N] ^ fr.codeword[:, :N]
             berr[s] += int(np.unpackbits(diff[..., None], axis=-1).sum())
     res = {"channel": channel, "q": q, "source": source, "noise": prm, "N": N, "M": 3 * N, "E": code.E,
-           "samples": samples, "max_iter": max_iter}
+           "samples": samples, "max_iter": max_iter, "b_form": b_form, "sus_levels": dcode.info.sus_levels}
     ti = {s: np.concatenate(it[s]).astype(np.float64) for s in schedules}
     cv = {s: np.concatenate(conv[s]) for s in schedules}
     for s in schedules:
@@ -95,6 +99,7 @@ def run_setting(channel: str, q: int, source: str, param: float, samples: int, b
         res[f"fer_{s}"] = float(1.0 - cv[s].mean())
         res[f"ber_{s}"] = berr[s] / float(samples * N * p)
         res[f"edge_q_per_s_{s}"] = float(ti[s].sum() * code.E * q / gpu_s[s])
+        res[f"seconds_{s}"] = gpu_s[s]
     for s in schedules:
         if s == "pus" or "pus" not in schedules:
             continue
@@ -117,6 +122,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="multiply every noise parameter")
     ap.add_argument("--only", default="", help="comma-separated row numbers (1-9) to run")
     ap.add_argument("--schedules", default="pus,sus")
+    ap.add_argument("--b-form", default="chain", choices=["chain", "pool"], help="form of the stand-in codes' B")
+    ap.add_argument("--pool", type=int, default=1000, help="pool form: rows a column waits on average")
     args = ap.parse_args()
     import torch
 
@@ -125,7 +132,8 @@ def main():
     for k in rows:
         channel, q, source, param = SETTINGS[k - 1]
         res = run_setting(channel, q, source, param, args.samples, args.batch, args.max_iter,
-                          seed=0xC0DE0100 + k, scale=args.scale, schedules=tuple(args.schedules.split(",")))
+                          seed=0xC0DE0100 + k, scale=args.scale, schedules=tuple(args.schedules.split(",")),
+                          b_form=args.b_form, pool=args.pool)
         res["row"] = k
         print(json.dumps(res), flush=True)
 

@@ -535,25 +535,49 @@ def mixed_pool(n_codes: int, seed: int, qs=(4, 16, 64), n_range=(256, 8000), q_w
 # --------------------------------------------------------------------------
 # MacKay-Neal syndrome form (Section 2): H = [A | B], x = (source, noise)
 # --------------------------------------------------------------------------
-def mn_code(N: int, M: int, q: int, seed: int, d_a: int = 3, extra: float = 0.5) -> Code:
+def mn_code(N: int, M: int, q: int, seed: int, d_a: int = 3, extra: float = 0.5, b_form: str = "chain",
+            pool: int = 1000) -> Code:
     """H = [A | B] over GF(q): A (M x N) with column weight d_a (rows balanced,
     no repeated edge, no 4-cycle inside A), B (M x M) lower triangular with a
-    nonzero diagonal, hence invertible: row i holds columns i and i-1 and,
-    with probability `extra`, one random earlier column that has no such
-    extra entry yet (so a column of B has at most 3 entries).  Columns
-    0..N-1 of H are the source symbols (n_info = N), columns N..N+M-1 the
-    noise symbols.  Nonzero coefficients are uniform on GF(q) minus {0}.
-    This is a stand-in for the paper's Kanter-Saad construction, which it
-    does not specify."""
+    nonzero diagonal, hence invertible.  Columns 0..N-1 of H are the source
+    symbols (n_info = N), columns N..N+M-1 the noise symbols.  Nonzero
+    coefficients are uniform on GF(q) minus {0}.  B's form:
+
+    * "chain": row i holds columns i and i-1 and, with probability `extra`,
+      one random earlier column that has no such extra entry yet (a column
+      of B has at most 3 entries).  Every noise column then shares a check
+      with the previous one, so a sequential sweep's dependency levels
+      number about M.
+    * "pool": each column's second entry sits in a random later row: from
+      row `pool` on, every row takes one random column from the columns
+      still waiting (two per row once fewer rows than waiting columns
+      remain), so each column of B has 2 entries (a few at the end 1) and
+      each row at most 3.  Columns then wait about `pool` rows, and a
+      sequential sweep's dependency levels number about M / pool plus a few.
+
+    Both stand in for the paper's Kanter-Saad construction, which it does not
+    specify."""
+    if b_form not in ("chain", "pool"):
+        raise ValueError(f"b_form {b_form!r}")
     A = make_code(N, M, d_a, q, seed)
     rng = np.random.default_rng([seed, 0xB])
     br, bc = [], []
-    avail = []  # columns < i-1 without an extra entry
+    avail = []  # chain: columns < i-1 without an extra entry; pool: columns waiting for their second entry
     for i in range(M):
-        if i >= 2:
-            avail.append(i - 2)
         br.append(i)
         bc.append(N + i)
+        if b_form == "pool":
+            if i >= 1:
+                avail.append(i - 1)
+            take = 2 if len(avail) > M - i else (1 if i >= pool else 0)
+            for _ in range(min(take, len(avail))):
+                k = int(rng.integers(0, len(avail)))
+                avail[k], avail[-1] = avail[-1], avail[k]
+                br.append(i)
+                bc.append(N + avail.pop())
+            continue
+        if i >= 2:
+            avail.append(i - 2)
         if i >= 1:
             br.append(i)
             bc.append(N + i - 1)
@@ -569,7 +593,8 @@ def mn_code(N: int, M: int, q: int, seed: int, d_a: int = 3, extra: float = 0.5)
     row_ptr = np.zeros(M + 1, dtype=np.int32)
     row_ptr[1:] = np.cumsum(np.bincount(r, minlength=M))
     return Code(q=q, n=N + M, m=M, row_ptr=row_ptr, col=c[order].astype(np.int32), coef=h[order], n_info=N,
-                seed=seed, meta={"mn": True, "N": N, "M": M, "d_a": d_a, "extra": extra})
+                seed=seed, meta={"mn": True, "N": N, "M": M, "d_a": d_a, "extra": extra, "b_form": b_form,
+                                 "pool": pool})
 
 
 def mn_encode(code: Code, s: np.ndarray) -> np.ndarray:

@@ -513,6 +513,29 @@ def test_mn_syndrome_form(gfbp, q, source, channel, param, schedule):
 
 
 @pytest.mark.parametrize("q,source,channel,param", [(4, "4s", "bsc", 0.17), (8, "2s", "biawgn", 1.1)])
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_mn_pool_form(gfbp, q, source, channel, param, schedule):
+    """The syndrome form on the pooled-B stand-in (few dependency levels: SUS
+    runs by level launches, not by runs of thin levels): decisions under the
+    gate, messages after iterations 1 and 2, and levelled SUS bitwise the
+    strict column order."""
+    code = wl.mn_code(60, 180, q, seed=430 + q, b_form="pool", pool=12)
+    M, start = _MN_SOURCES[source]
+    fr = wl.make_mn_frames(code, 300, 431 + q, channel, param, source="markov", markov=M, start=start)
+    kw = dict(prior="markov", markov_M=M, markov_pi=start)
+    assert gfbp.DeviceCode(code).info.sus_levels == _sus_levels(code) < 60
+    messages_close(gfbp, code, fr.subset(range(64)), schedule, iters=(1, 2), label="MN pool", **kw)
+    _, g, r = _decide(gfbp, code, fr, schedule, f"MN pool q={q} {source} {channel} {schedule}", max_iter=80,
+                      budget=MN_BUDGET, **kw)
+    assert r["converged"].mean() > 0.5
+    if schedule == "sus":
+        a = _gpu(gfbp, code, fr.subset(range(40)), "sus", max_iter=60, posterior=True, **kw)
+        b = _gpu(gfbp, code, fr.subset(range(40)), "sus", sus_strict=True, max_iter=60, posterior=True, **kw)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), f"levelled and strict SUS differ in {k}"
+
+
+@pytest.mark.parametrize("q,source,channel,param", [(4, "4s", "bsc", 0.17), (8, "2s", "biawgn", 1.1)])
 def test_mn_syndrome_form_prior_in_sweep(gfbp, q, source, channel, param):
     """The MN syndrome form with the source priors assigned during the SUS
     sweep (in-sweep timing): messages after iterations 2 and 3, then decisions."""

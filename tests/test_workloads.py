@@ -42,10 +42,11 @@ def test_mixed_pool_shapes():
         assert c.meta["rate"] in (1 / 3, 1 / 2) and c.m == round((1 - c.meta["rate"]) * c.n)
 
 
+@pytest.mark.parametrize("b_form", ["chain", "pool"])
 @pytest.mark.parametrize("q", [2, 4, 8])
-def test_mn_code_is_a_then_invertible_b(q):
+def test_mn_code_is_a_then_invertible_b(q, b_form):
     N, M = 30, 90
-    code = wl.mn_code(N, M, q, seed=7)
+    code = wl.mn_code(N, M, q, seed=7, b_form=b_form, pool=10)
     H = _dense(code)
     A, B = H[:, :N], H[:, N:]
     assert code.n_info == N and (np.count_nonzero(A, axis=0) == 3).all()
@@ -54,6 +55,41 @@ def test_mn_code_is_a_then_invertible_b(q):
     t = wl.mn_encode(code, s)
     # B t = A s, i.e. H (s, t) = 0 ... checked through the syndrome map
     assert (wl.syndromes(code, np.concatenate([s, t], axis=1)) == 0).all()
+
+
+def _sus_levels(code):
+    """Number of dependency levels of a sequential sweep in column order
+    (1 + the deepest earlier column sharing a check), by a plain loop."""
+    rows_of = [[] for _ in range(code.n)]
+    for e, (i, j) in enumerate(zip(code.row_of_edge(), code.col)):
+        rows_of[int(j)].append(int(i))
+    deepest = np.zeros(code.m, dtype=np.int64)
+    top = 0
+    for j in range(code.n):
+        lv = 1 + max((int(deepest[i]) for i in rows_of[j]), default=0)
+        for i in rows_of[j]:
+            deepest[i] = max(deepest[i], lv)
+        top = max(top, lv)
+    return top
+
+
+def test_mn_pool_form_shape_and_levels():
+    """The pooled B: lower triangular with a nonzero diagonal, every noise
+    column in two rows of B but the last, rows of B of at most 3 entries, and
+    a sequential sweep of far fewer dependency levels than the chain form's
+    (whose every noise column depends on the one before)."""
+    N, M, q = 300, 900, 4
+    chain = wl.mn_code(N, M, q, seed=31)
+    pool = wl.mn_code(N, M, q, seed=31, b_form="pool", pool=60)
+    B = _dense(pool)[:, N:]
+    assert (np.triu(B, 1) == 0).all() and (np.diag(B) != 0).all()
+    col_w = np.count_nonzero(B, axis=0)
+    assert (col_w[:-1] == 2).all() and col_w[-1] == 1
+    assert np.count_nonzero(B, axis=1).max() <= 3
+    assert _sus_levels(chain) > M
+    assert _sus_levels(pool) < M // 10
+    with pytest.raises(ValueError):
+        wl.mn_code(N, M, q, seed=31, b_form="other")
 
 
 @pytest.mark.parametrize("channel,param", [("bsc", 0.1), ("bec", 0.3), ("biawgn", 0.8)])
