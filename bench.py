@@ -14,9 +14,10 @@ latency; the roofline of the dominant kernel from HIP events recorded around
 each launch during the timed steps, beside the bandwidth a plain streaming
 copy reaches on the same device (measured after the timed steps); the
 reference decoder timed on a bounded
-sample of the same frames on the host cores; a GF(64) leg; and a serving leg
+sample of the same frames on the host cores; a GF(64) leg; a serving leg
 (continuous batching of a Poisson stream of mixed-code frames: throughput and
-p50/p99 frame latency per schedule).
+p50/p99 frame latency per schedule); and a Table-1 stand-in leg (both
+schedules' iteration counts and GPU time on a syndrome-form MN code).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-frames S]
 """
@@ -144,6 +145,28 @@ def gf64_leg(gfbp, torch, steps: int, traffic_path: str = "", shapes: dict | Non
     return res
 
 
+def mn_leg(samples: int = 3000) -> dict:
+    """The paper's setting on a stand-in code whose sweep is not serial: Table
+    1's row 9 (BI-AWGN, GF(8), the 2-state Markov source lifted to symbols,
+    rate-1/3 syndrome-form code with 10^4 source bits and a pooled B) at 0.85
+    of the paper's sigma, `samples` frames in one launch per schedule, max 300
+    iterations: mean iterations of both schedules, their ratios (the Table 1
+    quantities) and the GPU time of each schedule (not part of `value`)."""
+    from paper_cs_0605069_amd import table1
+
+    channel, q, source, param = table1.SETTINGS[8]
+    r = table1.run_setting(channel, q, source, param, samples, samples, 300, seed=0xC0DE0100 + 9, scale=0.85,
+                           b_form="pool")
+    keep = ("noise", "N", "M", "E", "samples", "sus_levels", "t_pus", "t_sus", "ratio_of_means", "mean_of_ratios",
+            "stdev_of_ratios", "fer_pus", "fer_sus", "ber_pus", "ber_sus", "seconds_pus", "seconds_sus",
+            "edge_q_per_s_pus", "edge_q_per_s_sus")
+    out = {"workload": "Table 1 row 9 stand-in: BI-AWGN, GF(8), 2-state Markov source, rate-1/3 MN code with "
+                       "10^4 source bits and a pooled B, sigma = 0.85 x 1.66, max 300 iterations"}
+    out.update({k: r[k] for k in keep if k in r})
+    out["sus_over_pus_gpu_time"] = r["seconds_sus"] / r["seconds_pus"]
+    return out
+
+
 def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus")) -> dict:
     """Continuous batching of the mixed-code stream: Poisson arrivals at `rate`
     frames/s for `seconds`, frames from 16 codes of the uneven pool (q in
@@ -225,11 +248,12 @@ def main():
                     help="measured HBM traffic summary to report beside the roofline")
     ap.add_argument("--traffic-gf64", default=os.path.join(ROOT, "profiles", "traffic_gf64_n2000_bi-awgn.txt"),
                     help="the same for the GF(64) leg")
-    ap.add_argument("--leg", default="", choices=["", "gf64", "serving"],
+    ap.add_argument("--leg", default="", choices=["", "gf64", "serving", "mn"],
                     help="run only this leg and print its JSON (profiling)")
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-rate", type=float, default=20000.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-mn", action="store_true", help="skip the Table-1 stand-in leg (SUS and PUS on an MN code)")
     ap.add_argument("--no-copy-rate", action="store_true", help="skip measuring the achievable streaming-copy bandwidth")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -258,6 +282,9 @@ def main():
         return
     if args.leg == "serving":
         print(json.dumps(serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)), flush=True)
+        return
+    if args.leg == "mn":
+        print(json.dumps(mn_leg()), flush=True)
         return
     code, points = make_workload()
     dcode = gfbp.DeviceCode(code)
@@ -367,6 +394,7 @@ def main():
 
     gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps), args.traffic_gf64)
     srv = None if args.no_serving else serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)
+    mn = None if args.no_mn else mn_leg()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, points, args.cpu_frames)
@@ -397,6 +425,7 @@ def main():
         "cpu_baseline": cpu,
         "gf64": gf64,
         "serving": srv,
+        "mn_table1_row9": mn,
     }
     print(json.dumps(line), flush=True)
 
