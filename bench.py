@@ -167,7 +167,7 @@ def mn_leg(samples: int = 3000) -> dict:
     return out
 
 
-def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus")) -> dict:
+def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus")) -> tuple[dict, dict]:
     """Continuous batching of the mixed-code stream: Poisson arrivals at `rate`
     frames/s for `seconds`, frames from 16 codes of the uneven pool (q in
     {4, 16, 64} with GF(64) weighted 30%, n up to 8000, BSC / BEC / BI-AWGN at
@@ -175,14 +175,15 @@ def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus
     slots as they arrive, converged frames retired at once; per schedule the
     sustained throughput and p50/p99 frame latency (arrival to result on the
     host, and admission to retirement on the device clock; throughput both over
-    the whole run and over the arrival window after its first second), and the
-    reference decoder on a sample of the served frames (the first frame of each
-    request group of the codes of n <= 2500: agreement and its frames/s)."""
-    import oracle
+    the whole run and over the arrival window after its first second).  Also
+    returns, per schedule, the served sample that the CPU baseline leg checks
+    with the reference decoder (the first frame of each request group of the
+    codes of n <= 2500)."""
     from paper_cs_0605069_amd import serving
     from paper_cs_0605069_amd import workloads as wl
 
     pool = wl.mixed_pool(16, seed=0xC0DE0005, n_range=(256, 8000), q_weights=[0.35, 0.35, 0.3])
+    samples = {}
     out = {"workload": f"Poisson arrivals at {rate:.0f} frames/s for {seconds:.0f} s over 16 codes "
                        "(q in {4, 16, 64}, GF(64) 30%, n 256-8000, BSC/BEC/BI-AWGN at 1-2 dB, half Markov), "
                        "max 100 iterations"}
@@ -206,29 +207,40 @@ def serving_leg(gfbp, torch, seconds: float, rate: float, schedules=("sus", "pus
                "device_latency_ms_p99": float(np.percentile(dlat, 99)),
                "mean_iters": float(np.mean(st.iters)), "fer": 1 - st.converged / max(1, st.done),
                "edge_q_per_s": st.edge_q / st.wall}
-        # the reference decoder on the kept frames
-        same = tot = 0
-        t0 = time.perf_counter()
-        sch_o = {"pus": oracle.PUS, "sus": oracle.SUS}[sch]
-        for cq in small:
-            M, pi = markov[cq.code.q]
-            for g, m, pos in cq.groups:
-                if int(cq.ids[pos[0]]) not in st.results:
-                    continue
-                kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
-                r = oracle.decode(cq.code, g.subset([0]), schedule=sch_o, max_iter=100, **kw)
-                it, cv, xh = st.results[int(cq.ids[pos[0]])]
-                same += int(it == r["iters"][0] and np.array_equal(xh, r["xhat"][0]))
-                tot += 1
-        dt = time.perf_counter() - t0
-        res["reference_sample"] = {"frames": tot, "identical": same, "seconds": dt, "frames_per_s": tot / dt,
-                                   "threads": oracle.max_threads()}
+        # the served frames the CPU baseline leg decodes with the reference decoder
+        samples[sch] = [(cq.code, markov[cq.code.q], g, m, st.results.get(int(cq.ids[pos[0]])))
+                        for cq in small for g, m, pos in cq.groups]
         out[sch] = res
         print(f"# serving {sch}: {res['throughput_frames_per_s']:.0f} frames/s, p99 {res['frame_latency_ms_p99']:.0f} ms",
               file=sys.stderr, flush=True)
         del queues, srv
         torch.cuda.empty_cache()
-    return out
+    return out, samples
+
+
+def cpu_baseline_serving(samples: dict) -> dict:
+    """Part of the CPU baseline leg: the reference decoder on the served sample
+    (the first frame of every request group of the serving leg's codes of
+    n <= 2500): agreement with the served answers and the reference's rate."""
+    import oracle
+
+    res = {}
+    for sch, items in samples.items():
+        same = tot = 0
+        t0 = time.perf_counter()
+        sch_o = {"pus": oracle.PUS, "sus": oracle.SUS}[sch]
+        for code, (M, pi), g, m, got in items:
+            if got is None:
+                continue
+            kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
+            r = oracle.decode(code, g.subset([0]), schedule=sch_o, max_iter=100, **kw)
+            it, cv, xh = got
+            same += int(it == r["iters"][0] and np.array_equal(xh, r["xhat"][0]))
+            tot += 1
+        dt = time.perf_counter() - t0
+        res[sch] = {"frames": tot, "identical": same, "seconds": dt, "frames_per_s": tot / dt if dt else None,
+                    "threads": oracle.max_threads()}
+    return res
 
 
 def main():
@@ -281,7 +293,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
     if args.leg == "serving":
-        print(json.dumps(serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)), flush=True)
+        print(json.dumps(serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)[0]), flush=True)
         return
     if args.leg == "mn":
         print(json.dumps(mn_leg()), flush=True)
@@ -393,11 +405,16 @@ def main():
                for k, v in prof.items()}
 
     gf64 = None if args.no_gf64 else gf64_leg(gfbp, torch, max(1, args.steps), args.traffic_gf64)
-    srv = None if args.no_serving else serving_leg(gfbp, torch, args.serving_seconds, args.serving_rate)
+    srv, srv_samples = (None, None) if args.no_serving else serving_leg(gfbp, torch, args.serving_seconds,
+                                                                         args.serving_rate)
     mn = None if args.no_mn else mn_leg()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, points, args.cpu_frames)
+        if srv_samples:
+            cpu["serving_sample"] = cpu_baseline_serving(srv_samples)
+            for sch, r in cpu["serving_sample"].items():
+                srv[sch]["reference_sample"] = r
 
     line = {
         "metric": "edge·q message updates/s (PUS and SUS)",

@@ -14,9 +14,9 @@ capacity matched; the channel kind given per frame) are decoded three ways:
   graph replayed until every frame is done.
 
 The persistent results must equal the plain ones bitwise (checked here and in
-tests/test_gpu_batching.py).  ``--oracle N`` also decodes a deterministic
-sample of N frames (every k-th frame of the batch) with the float64 reference
-decoder and reports how many agree, and both sides' FER and mean iterations.
+tests/test_gpu_batching.py).  tests/uneven_batch_reference.py decodes the
+same batch and checks a deterministic sample of its frames against the
+float64 reference decoder.
 
 ``python -m paper_cs_0605069_amd.batching`` prints one JSON line.
 """
@@ -59,6 +59,20 @@ def build(frames: int, codes: int, nmax: int):
     return pool, items
 
 
+def batch_inputs(frames: int, codes: int, nmax: int):
+    """The uneven batch on the host: the code pool, the (code index, code,
+    frame groups) items, the groups in batch order with their codes, and each
+    frame's code index."""
+    pool, items = build(frames, codes, nmax)
+    flat, flat_codes, index = [], [], []
+    for ci, code, groups in items:
+        for g in groups:
+            flat.append(g)
+            flat_codes.append(code)
+            index += [ci] * g.F
+    return pool, items, flat, flat_codes, np.array(index, dtype=np.int32)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--frames", type=int, default=10000)
@@ -70,19 +84,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--sessions", action="store_true", help="also time one graph over one session per code")
     ap.add_argument("--iters", type=int, default=4, help="iterations per session-graph replay (even)")
-    ap.add_argument("--oracle", type=int, default=0, help="reference decoder on this many frames")
     args = ap.parse_args()
     import torch
 
     torch.cuda.set_device(0)
-    pool, items = build(args.frames, args.codes, args.nmax)
-    flat, flat_codes, index = [], [], []
-    for ci, code, groups in items:
-        for g in groups:
-            flat.append(g)
-            flat_codes.append(code)
-            index += [ci] * g.F
-    index = np.array(index, dtype=np.int32)
+    pool, items, flat, flat_codes, index = batch_inputs(args.frames, args.codes, args.nmax)
     F = len(index)
     dcodes = [DeviceCode(c) for c in pool]
     dfr = ragged_frames(flat, flat_codes)
@@ -182,32 +188,6 @@ def main():
         res.update({"sessions_graph_s": dt, "sessions_graph_edge_q_per_s": g_eq / dt,
                     "sessions_graph_frames_per_s": F / dt, "sessions_graph_replays": replays})
 
-    if args.oracle:
-        import oracle
-
-        step = max(1, F // args.oracle)
-        pick = np.arange(0, F, step)[:args.oracle]
-        t0 = time.perf_counter()
-        same = 0
-        r_it, r_cv = [], []
-        sch = {"pus": oracle.PUS, "sus": oracle.SUS}[args.schedule]
-        base = 0
-        for g, code in zip(flat, flat_codes):
-            rows = pick[(pick >= base) & (pick < base + g.F)]
-            if len(rows):
-                r = oracle.decode(code, g.subset(rows - base), schedule=sch, max_iter=args.max_iter)
-                for k, f in enumerate(rows):
-                    ok = p_it[f] == r["iters"][k] and np.array_equal(p_xh[offs[f]:offs[f + 1]], r["xhat"][k])
-                    same += int(ok)
-                r_it.append(r["iters"])
-                r_cv.append(r["converged"])
-                print(f"# reference: {len(np.concatenate(r_it))} of {len(pick)} frames", file=sys.stderr, flush=True)
-            base += g.F
-        r_it, r_cv = np.concatenate(r_it), np.concatenate(r_cv)
-        res.update({"oracle_frames": int(len(pick)), "oracle_identical": int(same), "oracle_s": time.perf_counter() - t0,
-                    "oracle_threads": oracle.max_threads(),
-                    "oracle_mean_iters": float(r_it.mean()), "gpu_mean_iters_same_frames": float(p_it[pick].mean()),
-                    "oracle_fer": float(1 - r_cv.mean()), "gpu_fer_same_frames": float(1 - p_cv[pick].mean())})
     print(json.dumps(res), flush=True)
 
 
