@@ -54,8 +54,10 @@ def make_workload():
     return code, points
 
 
-def cpu_baseline(code, points, n_frames: int):
-    """Reference decoder on every k-th frame of the step (all points), both schedules."""
+def cpu_baseline(code, points, n_frames: int, rec=None):
+    """Reference decoder on every k-th frame of the step (all points), both
+    schedules; with the timed steps' records `rec`, also both sides' FER and
+    mean iterations on those frames and how many ran the same iterations."""
     import oracle
     from paper_cs_0605069_amd import workloads as wl
 
@@ -69,15 +71,29 @@ def cpu_baseline(code, points, n_frames: int):
     eq = 0.0
     t0 = time.perf_counter()
     iters = {}
+    outs = {}
     for name, sch in (("pus", oracle.PUS), ("sus", oracle.SUS)):
         out = oracle.decode(code, fr, schedule=sch, max_iter=MAX_ITER)
         eq += float(out["iters"].sum()) * code.E * code.q
         iters[name] = float(out["iters"].mean())
+        outs[name] = out
     dt = time.perf_counter() - t0
-    return {"value": eq / dt, "unit": "edge·q updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{fr.F} frames (every {stride}th of each of the {len(points)} Eb/N0 points), "
-                      f"PUS and SUS, max {MAX_ITER} iterations, float64, {dt:.1f} s wall",
-            "frames_per_s": 2 * fr.F / dt, "mean_iters": iters}
+    res = {"value": eq / dt, "unit": "edge·q updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{fr.F} frames (every {stride}th of each of the {len(points)} Eb/N0 points), "
+                     f"PUS and SUS, max {MAX_ITER} iterations, float64, {dt:.1f} s wall",
+           "frames_per_s": 2 * fr.F / dt, "mean_iters": iters}
+    if rec:
+        side = {}
+        for name, out in outs.items():
+            g_it = np.concatenate([next(r for r in rec if r["sched"] == name and r["ebn0"] == eb)["iters"][idx]
+                                   for eb, _ in points])
+            g_cv = np.concatenate([next(r for r in rec if r["sched"] == name and r["ebn0"] == eb)["conv"][idx]
+                                   for eb, _ in points])
+            side[name] = {"frames": int(fr.F), "same_iterations": int((g_it == out["iters"]).sum()),
+                          "mean_iters_gpu": float(g_it.mean()), "mean_iters_reference": float(out["iters"].mean()),
+                          "fer_gpu": float(1 - g_cv.mean()), "fer_reference": float(1 - out["converged"].mean())}
+        res["gpu_on_the_same_frames"] = side
+    return res
 
 
 def gf64_leg(gfbp, torch, steps: int, traffic_path: str = "", shapes: dict | None = None) -> dict:
@@ -248,7 +264,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-frames", type=int, default=100)
+    ap.add_argument("--cpu-frames", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedules", default="pus,sus")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shape instead of autotuning")
@@ -330,8 +346,9 @@ def main():
                 dt = time.perf_counter() - t0
                 if record is not None:
                     it = o["iters"].cpu().numpy()
-                    record.append({"sched": s, "ebn0": eb, "ms": dt * 1e3, "iters": it,
-                                   "fer": 1.0 - float(o["converged"].float().mean().item())})
+                    cv = o["converged"].cpu().numpy()
+                    record.append({"sched": s, "ebn0": eb, "ms": dt * 1e3, "iters": it, "conv": cv,
+                                   "fer": 1.0 - float(cv.mean())})
 
     for _ in range(args.warmup):
         step(None)
@@ -410,7 +427,7 @@ def main():
     mn = None if args.no_mn else mn_leg()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(code, points, args.cpu_frames)
+        cpu = cpu_baseline(code, points, args.cpu_frames, rec)
         if srv_samples:
             cpu["serving_sample"] = cpu_baseline_serving(srv_samples)
             for sch, r in cpu["serving_sample"].items():
