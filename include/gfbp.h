@@ -214,8 +214,9 @@ typedef struct {
  * session. */
 #define GFBP_OPT_STEP_GRAPHS 4
 
-/* Decode through the persistent work-list kernel (always used when the batch
- * spans several codes): one launch per kernel shape class, sized to fill the
+/* Decode through the persistent work-list kernel (the no-allocation entry
+ * takes it for every batch over several codes): one launch per kernel shape
+ * class, sized to fill the
  * GPU, in which each workgroup takes the next tile of frames of one code from
  * a device-side list (largest codes first), decodes it through every
  * iteration to convergence or max_iter (initialisation, the schedule's
@@ -273,13 +274,21 @@ size_t gfbp_batch_workspace_size(const gfbp_code *const *codes, const gfbp_batch
  * (SUS) schedule, with the Eq. (7) Markov prior or a static prior on the
  * source symbols when asked.  codes[0..n_codes): the codes the frames are on
  * (batch->code_index); with one code the plain kernels run (several launches
- * per iteration over the frames still iterating), with several the
- * persistent kernel (GFBP_OPT_PERSISTENT).  workspace: device memory of at
- * least gfbp_batch_workspace_size() bytes, 256-byte aligned, owned by the
- * caller, clobbered.  stream: a hipStream_t (NULL = default stream).  All
- * work is enqueued on the stream; the call returns after the frames have
- * finished, with the results complete in the output buffers.  No device
- * memory is allocated; a calling thread's first plain decode allocates 64
+ * per iteration over the frames still iterating).  With several codes,
+ * unless GFBP_OPT_PERSISTENT is set, each code's frames are gathered from the
+ * ragged inputs into contiguous buffers in the workspace, decoded with the
+ * plain kernels as a one-code batch (the code's kernel shape) and their
+ * results scattered back, the codes running concurrently on the library's
+ * four worker threads (created on the first such call and kept for the
+ * process), each with a stream of its own; the results equal, bitwise, each
+ * code's frames decoded alone.  With GFBP_OPT_PERSISTENT the persistent
+ * kernel runs.  workspace: device memory of at least
+ * gfbp_batch_workspace_size() bytes, 256-byte aligned, owned by the caller,
+ * clobbered.  stream: a hipStream_t (NULL = default stream).  All work is
+ * enqueued on the stream (several codes: the caller's stream is synchronised
+ * first, then the workers' streams run the codes); the call returns after the
+ * frames have finished, with the results complete in the output buffers.  No
+ * device memory is allocated; a thread's first plain decode allocates 64
  * bytes of pinned host memory and four events, kept for the life of the
  * thread.  Errors: EINVAL
  * for a null or inconsistent argument (a missing input a frame's channel

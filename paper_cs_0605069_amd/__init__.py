@@ -456,11 +456,15 @@ def persist_entries_per_lane(q: int, el: int = 0, narrow: bool = True) -> int:
 
 def decode_multi(dcodes, code_index, dframes: dict, schedule="pus", max_iter: int = 100, early_stop: bool = True,
                  prior: str = "uniform", markov_M=None, markov_pi=None, static_prior=None, workspace=None,
-                 stream=None, persist_el: int = 0, persist_waves: int = 0, tune_iters: int = 0) -> dict:
-    """``gfbp_decode_batch`` over several codes (the persistent kernel):
-    frame f is on dcodes[code_index[f]]; dframes holds ragged inputs (see
-    :func:`ragged_frames`).  Returns device tensors xhat (ragged, sum of n),
-    iters, converged and guards; with tune_iters, runs
+                 stream=None, persist_el: int = 0, persist_waves: int = 0, tune_iters: int = 0,
+                 persistent: bool = False, prior_in_sweep: bool = False) -> dict:
+    """``gfbp_decode_batch`` over several codes: frame f is on
+    dcodes[code_index[f]]; dframes holds ragged inputs (see
+    :func:`ragged_frames`).  By default the library decodes code by code with
+    the plain kernels, the codes concurrently; persistent=True takes the
+    persistent work-list kernels (``GFBP_OPT_PERSISTENT``, tile shape
+    persist_el / persist_waves).  Returns device tensors xhat (ragged, sum of
+    n), iters, converged and guards; with tune_iters, runs
     ``gfbp_tune_persistent`` instead and returns the chosen shape."""
     import torch
 
@@ -475,13 +479,14 @@ def decode_multi(dcodes, code_index, dframes: dict, schedule="pus", max_iter: in
            "converged": torch.empty((F,), dtype=torch.uint8, device=dev),
            "guards": torch.empty((F,), dtype=torch.int32, device=dev)}
     Mt, pt, Pt, per_symbol = _prior_tensors(prior, markov_M, markov_pi, static_prior, dev)
-    b = _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, 0, None,
+    opts = (OPT_PERSISTENT if persistent or tune_iters else 0) | (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0)
+    b = _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, opts, None,
                len(dcodes), ci, persist_el, persist_waves)
     codes = _codes_array(dcodes)
     ws_bytes = int(lib().gfbp_batch_workspace_size(codes, ctypes.byref(b)))
     if tune_iters:  # room for every candidate shape
         ws_bytes = max(ws_bytes, max(int(lib().gfbp_batch_workspace_size(codes, ctypes.byref(
-            _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, 0, None,
+            _batch(F, SCHEDULES[schedule], max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, opts, None,
                    len(dcodes), ci, el, wv)))) for el in (4, 8) for wv in (4, 8)))
     if workspace is None:
         workspace = torch.empty((max(ws_bytes, 1),), dtype=torch.uint8, device=dev)

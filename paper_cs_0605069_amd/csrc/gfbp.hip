@@ -9,10 +9,13 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <string>
 #include <vector>
@@ -1471,6 +1474,361 @@ inline bool persistent_batch(const gfbp_batch *b) {
     return b->n_codes > 1 || b->code_index != nullptr || (b->options & GFBP_OPT_PERSISTENT);
 }
 
+// One code's batch through the plain kernels (inputs already checked).
+gfbp_status decode_plain(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, void *workspace,
+                         size_t ws_bytes, hipStream_t st) {
+    const int F = b->n_frames;
+    const Carve cv = carve(code, F, b->schedule, b->prior);
+    if (ws_bytes < cv.total) return fail(GFBP_ESMALL, "workspace too small");
+    char *w = static_cast<char *>(workspace);
+    DevState s{};
+    s.Qm = reinterpret_cast<float *>(w + cv.Qm);
+    s.R = reinterpret_cast<float *>(w + cv.R);
+    s.L = reinterpret_cast<float *>(w + cv.L);
+    s.Pr = reinterpret_cast<float *>(w + cv.Pr);
+    s.Qp = reinterpret_cast<float *>(w + cv.Qp);
+    s.xh = reinterpret_cast<uint8_t *>(w + cv.xh);
+    s.unsat = reinterpret_cast<uint32_t *>(w + cv.unsat);
+    s.active = reinterpret_cast<uint8_t *>(w + cv.active);
+    s.count = reinterpret_cast<uint32_t *>(w + cv.count);
+    s.tiles = reinterpret_cast<int32_t *>(w + cv.tiles);
+    s.guards = reinterpret_cast<int32_t *>(w + cv.guards);
+    BatchAux a{};
+    a.orig = reinterpret_cast<int32_t *>(w + cv.orig);
+    a.iters = reinterpret_cast<int32_t *>(w + cv.iters);
+    a.conv = reinterpret_cast<uint8_t *>(w + cv.conv);
+    a.z = reinterpret_cast<uint8_t *>(w + cv.z);
+    a.holes = reinterpret_cast<int32_t *>(w + cv.holes);
+    a.movers = reinterpret_cast<int32_t *>(w + cv.movers);
+    a.pending = reinterpret_cast<uint8_t *>(w + cv.pending);
+    a.mshape = reinterpret_cast<float *>(w + cv.mshape);
+    s.F = F;
+    s.Fp = frame_stride(F);
+    const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
+    switch (code->info.p) {
+        case 1: return run_any<1>(code, b, out, s, a, st, needQ);
+        case 2: return run_any<2>(code, b, out, s, a, st, needQ);
+        case 3: return run_any<3>(code, b, out, s, a, st, needQ);
+        case 4: return run_any<4>(code, b, out, s, a, st, needQ);
+        case 5: return run_any<5>(code, b, out, s, a, st, needQ);
+        case 6: return run_any<6>(code, b, out, s, a, st, needQ);
+        default: return fail(GFBP_EUNSUPPORTED, "bad field");
+    }
+}
+
+// ------------------------------------------------------ several codes, code by code
+// A batch over several codes (without GFBP_OPT_PERSISTENT) is decoded code by
+// code with the plain kernels: each code's frames are gathered into
+// contiguous inputs, decoded as a one-code batch, and their results
+// scattered back to the batch's places.  The codes run concurrently on the
+// library's worker threads, each with a stream of its own (a code with few
+// frames leaves most of the device idle; several together fill it).
+
+// dst[k len + i] = src[off[k] + i] (k < nf, i < len): a frame's ragged segment.
+template <typename T>
+__global__ void k_gather(const T *src, const int64_t *off, int64_t len, int nf, T *dst) {
+    const int64_t total = int64_t(nf) * len;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total; x += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t k = x / len, i = x - k * len;
+        dst[x] = src[off[k] + i];
+    }
+}
+
+// dst[off[k] + i] = src[k len + i]: the inverse, for the decisions.
+template <typename T>
+__global__ void k_scatter(const T *src, const int64_t *off, int64_t len, int nf, T *dst) {
+    const int64_t total = int64_t(nf) * len;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total; x += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t k = x / len, i = x - k * len;
+        dst[off[k] + i] = src[x];
+    }
+}
+
+inline unsigned copy_blocks(int64_t total) {
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(4096, (total + 255) / 256)));
+}
+
+// The library's worker threads: created on first use and kept for the
+// process (their streams, pinned count buffers and events are thread-local
+// and live as long).  run() hands out tasks 0..n-1 and blocks until all end.
+class Workers {
+public:
+    static constexpr int kThreads = 4;  // streams beyond the device's hardware queues add nothing
+    using Task = std::function<gfbp_status(int, hipStream_t, std::string &)>;
+
+    static Workers &get() {
+        static Workers *w = new Workers();  // never destroyed: its threads stay parked until the process ends
+        return *w;
+    }
+
+    gfbp_status run(int n, int dev, const Task &task, std::string &err) {
+        std::unique_lock<std::mutex> lk(mu_);
+        busy_.wait(lk, [&] { return job_ == nullptr; });  // one batch at a time
+        Job job{&task, n, dev};
+        job.status.assign(size_t(n), GFBP_OK);
+        job.errs.assign(size_t(n), std::string());
+        job.left = n;
+        job_ = &job;
+        wake_.notify_all();
+        done_.wait(lk, [&] { return job.left == 0 && job.active == 0; });
+        job_ = nullptr;
+        busy_.notify_all();
+        for (int i = 0; i < n; ++i)
+            if (job.status[size_t(i)] != GFBP_OK) {
+                err = job.errs[size_t(i)];
+                return job.status[size_t(i)];
+            }
+        return GFBP_OK;
+    }
+
+private:
+    struct Job {
+        const Task *task;
+        int n, dev;
+        int next = 0, left = 0, active = 0;
+        std::vector<gfbp_status> status;
+        std::vector<std::string> errs;
+    };
+
+    Workers() {
+        for (int t = 0; t < kThreads; ++t) std::thread([this] { loop(); }).detach();
+    }
+
+    static hipStream_t stream_for(int dev) {
+        static thread_local std::vector<hipStream_t> per_dev;
+        if (size_t(dev) >= per_dev.size()) per_dev.resize(size_t(dev) + 1, nullptr);
+        if (!per_dev[size_t(dev)] && hipStreamCreateWithFlags(&per_dev[size_t(dev)], hipStreamNonBlocking) != hipSuccess)
+            per_dev[size_t(dev)] = nullptr;
+        return per_dev[size_t(dev)];
+    }
+
+    void loop() {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            wake_.wait(lk, [&] { return job_ != nullptr && job_->next < job_->n; });
+            Job &j = *job_;
+            const int i = j.next++;
+            j.active++;
+            lk.unlock();
+            gfbp_status st = GFBP_OK;
+            std::string e;
+            if (hipSetDevice(j.dev) != hipSuccess) {
+                st = GFBP_EHIP;
+                e = "worker: hipSetDevice";
+            } else if (hipStream_t s = stream_for(j.dev)) {
+                st = (*j.task)(i, s, e);
+            } else {
+                st = GFBP_EHIP;
+                e = "worker: creating its stream";
+            }
+            lk.lock();
+            j.status[size_t(i)] = st;
+            j.errs[size_t(i)] = e;
+            j.active--;
+            j.left--;
+            if (j.left == 0 && j.active == 0) done_.notify_all();
+        }
+    }
+
+    std::mutex mu_;
+    std::condition_variable wake_, done_, busy_;
+    Job *job_ = nullptr;
+};
+
+// Workspace of the code-by-code path: per code, its frames' source offsets
+// and batch indices, the gathered inputs, the results before the scatter and
+// the one-code decode's own workspace.
+struct PartPlan {
+    int code = 0;
+    std::vector<int32_t> frames;  // batch frames of this code, in batch order
+    std::vector<int64_t> src_n, src_np, src_nq, src_m, src_one;  // element offsets of each frame's inputs
+    size_t o_src_n = 0, o_src_np = 0, o_src_nq = 0, o_src_m = 0, o_src_one = 0;
+    size_t o_rx = 0, o_er = 0, o_y = 0, o_lik = 0, o_z = 0, o_param = 0, o_chan = 0;
+    size_t o_xhat = 0, o_iters = 0, o_conv = 0, o_guards = 0, o_ws = 0, ws_bytes = 0;
+};
+
+gfbp_status percode_plan(const gfbp_code *const *codes, int nc, const gfbp_batch *b, std::vector<PartPlan> &parts,
+                         size_t &total) {
+    const int F = b->n_frames;
+    std::vector<int> part_of(size_t(nc), -1);
+    parts.clear();
+    int64_t on = 0, onp = 0, onq = 0, om = 0;
+    for (int f = 0; f < F; ++f) {
+        const int k = b->code_index ? b->code_index[f] : 0;
+        if (k < 0 || k >= nc) return fail(GFBP_EINVAL, "code_index out of range");
+        if (part_of[size_t(k)] < 0) {
+            part_of[size_t(k)] = int(parts.size());
+            parts.emplace_back();
+            parts.back().code = k;
+        }
+        PartPlan &pp = parts[size_t(part_of[size_t(k)])];
+        const gfbp_code_info &ci = codes[k]->info;
+        pp.frames.push_back(f);
+        pp.src_n.push_back(on);
+        pp.src_np.push_back(onp);
+        pp.src_nq.push_back(onq);
+        pp.src_m.push_back(om);
+        pp.src_one.push_back(f);
+        on += ci.n;
+        onp += int64_t(ci.n) * ci.p;
+        onq += int64_t(ci.n) * ci.q;
+        om += ci.m;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    for (PartPlan &pp : parts) {
+        const gfbp_code_info &ci = codes[pp.code]->info;
+        const size_t Fg = pp.frames.size(), n = size_t(ci.n);
+        pp.o_src_n = take(8 * Fg);
+        pp.o_src_np = take(8 * Fg);
+        pp.o_src_nq = take(8 * Fg);
+        pp.o_src_m = take(8 * Fg);
+        pp.o_src_one = take(8 * Fg);
+        pp.o_rx = take(b->rx ? Fg * n : 0);
+        pp.o_er = take(b->erasure ? Fg * n : 0);
+        pp.o_y = take(b->y ? Fg * n * size_t(ci.p) * 4 : 0);
+        pp.o_lik = take(b->likelihood ? Fg * n * size_t(ci.q) * 4 : 0);
+        pp.o_z = take(b->syndrome ? Fg * size_t(ci.m) : 0);
+        pp.o_param = take(b->param ? Fg * 4 : 0);
+        pp.o_chan = take(b->channel_of ? Fg : 0);
+        pp.o_xhat = take(Fg * n);
+        pp.o_iters = take(Fg * 4);
+        pp.o_conv = take(Fg);
+        pp.o_guards = take(Fg * 4);
+        pp.ws_bytes = carve(codes[pp.code], int(Fg), b->schedule, b->prior).total;
+        pp.o_ws = take(pp.ws_bytes);
+    }
+    total = off;
+    return GFBP_OK;
+}
+
+gfbp_status decode_percode(const gfbp_code *const *codes, int nc, const gfbp_batch *b, gfbp_result *out,
+                           void *workspace, size_t ws_bytes, hipStream_t st) {
+    if (out->posterior || out->snap_iter > 0 || (out->trace && b->truth))
+        return fail(GFBP_EUNSUPPORTED, "a batch over several codes returns decisions, iterations, convergence and "
+                                       "guards only");
+    std::vector<PartPlan> parts;
+    size_t total = 0;
+    const gfbp_status ps = percode_plan(codes, nc, b, parts, total);
+    if (ps != GFBP_OK) return ps;
+    if (ws_bytes < total) return fail(GFBP_ESMALL, "workspace too small");
+    char *w = static_cast<char *>(workspace);
+    for (const PartPlan &pp : parts) {
+        const size_t Fg = pp.frames.size();
+        HIP_TRY(hipMemcpyAsync(w + pp.o_src_n, pp.src_n.data(), 8 * Fg, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w + pp.o_src_np, pp.src_np.data(), 8 * Fg, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w + pp.o_src_nq, pp.src_nq.data(), 8 * Fg, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w + pp.o_src_m, pp.src_m.data(), 8 * Fg, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w + pp.o_src_one, pp.src_one.data(), 8 * Fg, hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));  // the offsets, and the caller's inputs, are in place
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    // the largest code first: it runs longest
+    std::vector<int> order(parts.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const auto &a = codes[parts[size_t(x)].code]->info, &c = codes[parts[size_t(y)].code]->info;
+        return double(a.n_edges) * a.q * double(parts[size_t(x)].frames.size()) >
+               double(c.n_edges) * c.q * double(parts[size_t(y)].frames.size());
+    });
+    const Workers::Task task = [&](int t, hipStream_t ws, std::string &err) -> gfbp_status {
+        const PartPlan &pp = parts[size_t(order[size_t(t)])];
+        const gfbp_code *code = codes[pp.code];
+        const gfbp_code_info &ci = code->info;
+        const int Fg = int(pp.frames.size());
+        const int64_t n = ci.n;
+        auto at = [&](size_t o) { return w + o; };
+        auto fail_here = [&](const char *what, hipError_t e) {
+            err = std::string(what) + ": " + hipGetErrorString(e);
+            return GFBP_EHIP;
+        };
+        const int64_t *sn = reinterpret_cast<const int64_t *>(at(pp.o_src_n));
+        const int64_t *snp = reinterpret_cast<const int64_t *>(at(pp.o_src_np));
+        const int64_t *snq = reinterpret_cast<const int64_t *>(at(pp.o_src_nq));
+        const int64_t *sm = reinterpret_cast<const int64_t *>(at(pp.o_src_m));
+        const int64_t *s1 = reinterpret_cast<const int64_t *>(at(pp.o_src_one));
+        gfbp_batch bg = *b;
+        bg.n_frames = Fg;
+        bg.n_codes = 1;
+        bg.code_index = nullptr;
+        bg.truth = nullptr;
+        bg.options &= ~GFBP_OPT_PERSISTENT;
+        if (b->rx) {
+            hipLaunchKernelGGL(k_gather<uint8_t>, dim3(copy_blocks(Fg * n)), dim3(256), 0, ws, b->rx, sn, n, Fg,
+                               reinterpret_cast<uint8_t *>(at(pp.o_rx)));
+            bg.rx = reinterpret_cast<const uint8_t *>(at(pp.o_rx));
+        }
+        if (b->erasure) {
+            hipLaunchKernelGGL(k_gather<uint8_t>, dim3(copy_blocks(Fg * n)), dim3(256), 0, ws, b->erasure, sn, n, Fg,
+                               reinterpret_cast<uint8_t *>(at(pp.o_er)));
+            bg.erasure = reinterpret_cast<const uint8_t *>(at(pp.o_er));
+        }
+        if (b->y) {
+            const int64_t len = n * ci.p;
+            hipLaunchKernelGGL(k_gather<float>, dim3(copy_blocks(Fg * len)), dim3(256), 0, ws, b->y, snp, len, Fg,
+                               reinterpret_cast<float *>(at(pp.o_y)));
+            bg.y = reinterpret_cast<const float *>(at(pp.o_y));
+        }
+        if (b->likelihood) {
+            const int64_t len = n * ci.q;
+            hipLaunchKernelGGL(k_gather<float>, dim3(copy_blocks(Fg * len)), dim3(256), 0, ws, b->likelihood, snq, len,
+                               Fg, reinterpret_cast<float *>(at(pp.o_lik)));
+            bg.likelihood = reinterpret_cast<const float *>(at(pp.o_lik));
+        }
+        if (b->syndrome) {
+            hipLaunchKernelGGL(k_gather<uint8_t>, dim3(copy_blocks(Fg * int64_t(ci.m))), dim3(256), 0, ws, b->syndrome,
+                               sm, int64_t(ci.m), Fg, reinterpret_cast<uint8_t *>(at(pp.o_z)));
+            bg.syndrome = reinterpret_cast<const uint8_t *>(at(pp.o_z));
+        }
+        if (b->param) {
+            hipLaunchKernelGGL(k_gather<float>, dim3(copy_blocks(Fg)), dim3(256), 0, ws, b->param, s1, int64_t(1), Fg,
+                               reinterpret_cast<float *>(at(pp.o_param)));
+            bg.param = reinterpret_cast<const float *>(at(pp.o_param));
+        }
+        if (b->channel_of) {
+            hipLaunchKernelGGL(k_gather<uint8_t>, dim3(copy_blocks(Fg)), dim3(256), 0, ws, b->channel_of, s1,
+                               int64_t(1), Fg, reinterpret_cast<uint8_t *>(at(pp.o_chan)));
+            bg.channel_of = reinterpret_cast<const uint8_t *>(at(pp.o_chan));
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_here("gathering a code's inputs", e);
+        gfbp_result og{};
+        og.xhat = reinterpret_cast<uint8_t *>(at(pp.o_xhat));
+        og.iters = reinterpret_cast<int32_t *>(at(pp.o_iters));
+        og.converged = reinterpret_cast<uint8_t *>(at(pp.o_conv));
+        og.guards = out->guards ? reinterpret_cast<int32_t *>(at(pp.o_guards)) : nullptr;
+        const gfbp_status rs = decode_plain(code, &bg, &og, at(pp.o_ws), pp.ws_bytes, ws);
+        if (rs != GFBP_OK) {
+            err = g_err;
+            return rs;
+        }
+        // results back to the batch's places: decisions at the frame's ragged
+        // offset, the per-frame scalars at its index
+        hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(copy_blocks(Fg * n)), dim3(256), 0, ws, og.xhat, sn, n, Fg,
+                           out->xhat);
+        hipLaunchKernelGGL(k_scatter<int32_t>, dim3(copy_blocks(Fg)), dim3(256), 0, ws, og.iters, s1, int64_t(1), Fg,
+                           out->iters);
+        hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(copy_blocks(Fg)), dim3(256), 0, ws, og.converged, s1, int64_t(1),
+                           Fg, out->converged);
+        if (out->guards)
+            hipLaunchKernelGGL(k_scatter<int32_t>, dim3(copy_blocks(Fg)), dim3(256), 0, ws, og.guards, s1, int64_t(1),
+                               Fg, out->guards);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(ws);
+        if (e != hipSuccess) return fail_here("scattering a code's results", e);
+        return GFBP_OK;
+    };
+    std::string err;
+    const gfbp_status rs = Workers::get().run(int(parts.size()), dev, task, err);
+    if (rs != GFBP_OK) return fail(rs, err);
+    return GFBP_OK;
+}
+
 // Streaming copy of n 16-byte vectors, four loads in flight per lane (the
 // measurement behind gfbp_stream_copy_rate).
 constexpr int kCopyUnroll = 4;
@@ -1637,6 +1995,12 @@ size_t gfbp_batch_workspace_size(const gfbp_code *const *codes, const gfbp_batch
     for (int k = 0; k < nc; ++k)
         if (!codes[k]) return 0;
     if (!persistent_batch(b)) return carve(codes[0], b->n_frames, b->schedule, b->prior).total;
+    if (!(b->options & GFBP_OPT_PERSISTENT)) {  // several codes, code by code
+        std::vector<PartPlan> parts;
+        size_t total = 0;
+        if (percode_plan(codes, nc, b, parts, total) != GFBP_OK) return 0;
+        return total;
+    }
     PersistPlan pl;
     if (persist_plan(codes, nc, b, pl) != GFBP_OK) return 0;
     return pl.total;
@@ -1672,43 +2036,12 @@ gfbp_status gfbp_decode_batch(const gfbp_code *const *codes, const gfbp_batch *b
     hipStream_t st = static_cast<hipStream_t>(stream);
     const gfbp_status ci = check_inputs(b, st);
     if (ci != GFBP_OK) return ci;
-    if (persistent_batch(b)) return decode_persistent(codes, nc, b, out, workspace, ws_bytes, st);
-    const Carve cv = carve(code, F, b->schedule, b->prior);
-    if (ws_bytes < cv.total) return fail(GFBP_ESMALL, "workspace too small");
-    char *w = static_cast<char *>(workspace);
-    DevState s{};
-    s.Qm = reinterpret_cast<float *>(w + cv.Qm);
-    s.R = reinterpret_cast<float *>(w + cv.R);
-    s.L = reinterpret_cast<float *>(w + cv.L);
-    s.Pr = reinterpret_cast<float *>(w + cv.Pr);
-    s.Qp = reinterpret_cast<float *>(w + cv.Qp);
-    s.xh = reinterpret_cast<uint8_t *>(w + cv.xh);
-    s.unsat = reinterpret_cast<uint32_t *>(w + cv.unsat);
-    s.active = reinterpret_cast<uint8_t *>(w + cv.active);
-    s.count = reinterpret_cast<uint32_t *>(w + cv.count);
-    s.tiles = reinterpret_cast<int32_t *>(w + cv.tiles);
-    s.guards = reinterpret_cast<int32_t *>(w + cv.guards);
-    BatchAux a{};
-    a.orig = reinterpret_cast<int32_t *>(w + cv.orig);
-    a.iters = reinterpret_cast<int32_t *>(w + cv.iters);
-    a.conv = reinterpret_cast<uint8_t *>(w + cv.conv);
-    a.z = reinterpret_cast<uint8_t *>(w + cv.z);
-    a.holes = reinterpret_cast<int32_t *>(w + cv.holes);
-    a.movers = reinterpret_cast<int32_t *>(w + cv.movers);
-    a.pending = reinterpret_cast<uint8_t *>(w + cv.pending);
-    a.mshape = reinterpret_cast<float *>(w + cv.mshape);
-    s.F = F;
-    s.Fp = frame_stride(F);
-    const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
-    switch (code->info.p) {
-        case 1: return run_any<1>(code, b, out, s, a, st, needQ);
-        case 2: return run_any<2>(code, b, out, s, a, st, needQ);
-        case 3: return run_any<3>(code, b, out, s, a, st, needQ);
-        case 4: return run_any<4>(code, b, out, s, a, st, needQ);
-        case 5: return run_any<5>(code, b, out, s, a, st, needQ);
-        case 6: return run_any<6>(code, b, out, s, a, st, needQ);
-        default: return fail(GFBP_EUNSUPPORTED, "bad field");
+    if (persistent_batch(b)) {
+        if ((b->options & GFBP_OPT_PERSISTENT) || g_no_alloc)
+            return decode_persistent(codes, nc, b, out, workspace, ws_bytes, st);
+        return decode_percode(codes, nc, b, out, workspace, ws_bytes, st);
     }
+    return decode_plain(code, b, out, workspace, ws_bytes, st);
 }
 
 // ---- decoding without allocations: the library's static device scratch.
@@ -1746,13 +2079,17 @@ gfbp_status gfbp_decode_batch_noalloc(const gfbp_code *const *codes, const gfbp_
         ptr = g_scratch_ptr[dev];
     }
     if (!codes || !b || !out) return fail(GFBP_EINVAL, "null argument");
-    const size_t need = gfbp_batch_workspace_size(codes, b);
-    if (b->n_frames > 0 && need == 0) return fail(GFBP_EINVAL, "bad batch (workspace size 0)");
+    // a batch over several codes runs through the persistent kernels here (the
+    // code-by-code path's worker threads and their streams are allocations)
+    gfbp_batch pb = *b;
+    if (persistent_batch(b)) pb.options |= GFBP_OPT_PERSISTENT;
+    const size_t need = gfbp_batch_workspace_size(codes, &pb);
+    if (pb.n_frames > 0 && need == 0) return fail(GFBP_EINVAL, "bad batch (workspace size 0)");
     if (need > kScratchBytes)
         return fail(GFBP_ESMALL, "the batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
                                      std::to_string(kScratchBytes));
     g_no_alloc = true;
-    const gfbp_status rs = gfbp_decode_batch(codes, b, out, ptr, kScratchBytes, stream);
+    const gfbp_status rs = gfbp_decode_batch(codes, &pb, out, ptr, kScratchBytes, stream);
     g_no_alloc = false;
     return rs;
 }

@@ -1,10 +1,11 @@
-"""Uneven batches: the persistent work-list kernel, against the plain kernels
-and the reference decoder; and sessions as one HIP graph.
+"""Uneven batches: one call over several codes (code by code on the plain
+kernels, or the persistent work-list kernel), against the plain kernels and
+the reference decoder; and sessions as one HIP graph.
 
-The persistent path (GFBP_OPT_PERSISTENT, and every batch over several codes)
-must give, frame by frame, bitwise the decisions, iteration counts,
-convergence flags and guard counts of the plain kernels: same device
-functions, same arithmetic order.
+The persistent path (GFBP_OPT_PERSISTENT) must give, frame by frame, bitwise
+the decisions, iteration counts, convergence flags and guard counts of the
+plain kernels at the same lane split: same device functions, same
+arithmetic order.  The code-by-code path runs the plain kernels themselves.
 """
 import numpy as np
 import pytest
@@ -127,7 +128,8 @@ def test_multi_code_batch(gfbp, schedule):
     one GF(64) code of n >= 4000), BSC / BEC / BI-AWGN frames mixed per frame,
     syndromes z != 0: every frame equals, bitwise, the plain decode of its
     code's frames; 48 frames (every code, the GF(64) n >= 4000 ones
-    included) against the reference."""
+    included) against the reference, from this call and from the same call
+    through the persistent kernels."""
     pool, groups = _pool_batch(gfbp, 8, 600, 0xB47C, 1500, True)
     assert {c.q for c in pool} >= {4, 16, 64} and max(c.n for c in pool if c.q == 64) >= 4000
     dcodes = [gfbp.DeviceCode(c) for c in pool]
@@ -143,6 +145,8 @@ def test_multi_code_batch(gfbp, schedule):
     xh = out["xhat"].cpu().numpy()
     it = out["iters"].cpu().numpy()
     cv = out["converged"].cpu().numpy()
+    po = gfbp.decode_multi(dcodes, index, dfr, schedule=schedule, max_iter=60, persistent=True)
+    p_xh, p_it, p_cv = (po[k].cpu().numpy() for k in ("xhat", "iters", "converged"))
     offs = np.concatenate([[0], np.cumsum([pool[k].n for k in index])])
     f0 = 0
     picks = []
@@ -164,6 +168,10 @@ def test_multi_code_batch(gfbp, schedule):
         gg = {"xhat": np.stack([xh[offs[ff]:offs[ff + 1]] for ff in rows]), "iters": it[rows], "converged": cv[rows]}
         classify(gfbp, code, sub, gg, r, schedule, f"multi-code q={code.q} n={code.n} {g.channel} {schedule}",
                  max_iter=60)
+        pg = {"xhat": np.stack([p_xh[offs[ff]:offs[ff + 1]] for ff in rows]), "iters": p_it[rows],
+              "converged": p_cv[rows]}
+        classify(gfbp, code, sub, pg, r, schedule,
+                 f"multi-code persistent q={code.q} n={code.n} {g.channel} {schedule}", max_iter=60)
         n_ref += len(rows)
     assert n_ref >= 48
 

@@ -59,8 +59,10 @@ def test_noalloc_equals_decode_batch_twice(gfbp, schedule):
 
 
 def test_noalloc_multi_code_twice_and_refusal(gfbp):
-    """A batch over two codes of different fields (persistent kernels, run
-    one after the other on the stream), twice, the second smaller."""
+    """A batch over two codes of different fields (the no-allocation entry
+    takes the persistent kernels, run one after the other on the stream,
+    against the persistent path of gfbp_decode_batch), twice, the second
+    smaller."""
     import torch
 
     codes = [wl.regular_code(300, 3, 6, 4, seed=101)[0], wl.regular_code(200, 3, 6, 64, seed=102)[0]]
@@ -70,7 +72,7 @@ def test_noalloc_multi_code_twice_and_refusal(gfbp):
                wl.make_coset_frames(codes[1], F1, seed + 1, "bsc", 0.05)]
         dfr = gfbp.ragged_frames(frs, codes)
         index = np.array([0] * F0 + [1] * F1, dtype=np.int32)
-        ref = _host(gfbp.decode_multi(dcodes, index, dfr, schedule="sus", max_iter=50))
+        ref = _host(gfbp.decode_multi(dcodes, index, dfr, schedule="sus", max_iter=50, persistent=True))
         n_tot = F0 * codes[0].n + F1 * codes[1].n
         outs = _outputs(torch, F0 + F1, 1)
         outs["xhat"] = torch.empty(n_tot, dtype=torch.uint8, device="cuda")

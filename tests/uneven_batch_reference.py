@@ -1,7 +1,8 @@
 """The uneven batch of ``paper_cs_0605069_amd.batching`` (10,000 frames over
 64 codes of the mixed pool: q in {4, 16, 64}, n up to 8000, per-frame
-channels) decoded in one ``gfbp_decode_batch`` call (the persistent path,
-tuned shape), and a deterministic sample of its frames (every k-th frame)
+channels) decoded in one ``gfbp_decode_batch`` call (code by code, or with
+--persistent the persistent kernels at their tuned shape), and a
+deterministic sample of its frames (every k-th frame)
 decoded by the float64 reference decoder: how many frames agree in decisions
 and iteration count, and both sides' FER and mean iterations on the sample.
 Not collected by pytest (a long GPU run); run as
@@ -30,6 +31,7 @@ def main():
     ap.add_argument("--schedule", default="sus")
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--frames-checked", type=int, default=512)
+    ap.add_argument("--persistent", action="store_true")
     args = ap.parse_args()
     import torch
 
@@ -42,9 +44,11 @@ def main():
     F = len(index)
     dcodes = [gfbp.DeviceCode(c) for c in pool]
     dfr = gfbp.ragged_frames(flat, flat_codes)
-    t = gfbp.decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=args.max_iter, tune_iters=2)
+    t = {"persist_el": 0, "persist_waves": 0}
+    if args.persistent:
+        t = gfbp.decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=args.max_iter, tune_iters=2)
     out = gfbp.decode_multi(dcodes, index, dfr, schedule=args.schedule, max_iter=args.max_iter,
-                            persist_el=t["persist_el"], persist_waves=t["persist_waves"])
+                            persistent=args.persistent, persist_el=t["persist_el"], persist_waves=t["persist_waves"])
     torch.cuda.synchronize()
     g_it = out["iters"].cpu().numpy()
     g_cv = out["converged"].cpu().numpy()
@@ -66,7 +70,8 @@ def main():
             print(f"# reference: {len(np.concatenate(r_it))} of {len(pick)} frames", file=sys.stderr, flush=True)
         base += g.F
     r_it, r_cv = np.concatenate(r_it), np.concatenate(r_cv)
-    print(json.dumps({"frames": int(F), "schedule": args.schedule, "persist_el": t["persist_el"],
+    print(json.dumps({"frames": int(F), "schedule": args.schedule, "persistent": args.persistent,
+                      "persist_el": t["persist_el"],
                       "persist_waves": t["persist_waves"], "frames_checked": int(len(pick)),
                       "identical": int(same), "reference_s": time.perf_counter() - t0,
                       "reference_threads": oracle.max_threads(),
