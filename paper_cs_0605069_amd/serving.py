@@ -68,7 +68,7 @@ class Stats:
 class Server:
     def __init__(self, queues: list[CodeQueue], slots: int, schedule: str, max_iter: int, budget_bytes: int,
                  step_iters: int = 2, markov: dict | None = None, keep_results: bool = False, autotune: bool = True,
-                 graph: bool = False, step_graphs: bool = False, keep_ids=None):
+                 graph: bool = False, step_graphs: bool = False, keep_ids=None, independent: bool = False):
         """keep_results: keep every answered frame's (iterations, converged,
         decisions) in Stats.results; keep_ids: keep only those requests'."""
         self.queues = queues
@@ -94,6 +94,10 @@ class Server:
         # cost of a SUS step, but no gain in latency, which the device's time
         # per launch bounds
         self.step_graphs = step_graphs
+        # optionally each session on its own clock: a session is stepped
+        # again as soon as its previous step has finished (an event on its
+        # stream says so), instead of every busy session once per round
+        self.independent = independent and not graph
         self.graph = None
         self.gstream = None
         from . import device_clock_hz
@@ -176,6 +180,7 @@ class Server:
         st = stats or Stats()
         total = sum(len(cq.arrival) for cq in self.queues)
         st.offered = total
+        inflight = {}  # independent sessions: the event after each one's step in flight
         t0 = time.perf_counter()
         while st.done < total:
             now = time.perf_counter() - t0
@@ -183,16 +188,32 @@ class Server:
                 break
             for cq in self.queues:
                 cq.next_arrived = int(np.searchsorted(cq.arrival, now, side="right"))
-                if cq.next_admitted < cq.next_arrived and self._open(cq):
+                # (admission waits on the session's stream: not while its step runs)
+                if cq.next_admitted < cq.next_arrived and id(cq) not in inflight and self._open(cq):
                     self._admit(cq)
             busy = [cq for cq in self.queues if cq.session is not None and cq.session.running > 0]
-            if self.graph is not None:
+            if self.independent:
+                ready = []
+                for cq in busy:
+                    ev = inflight.get(id(cq))
+                    if ev is None:  # idle: start its next step
+                        cq.session.step(self.step_iters, stream=cq.stream)
+                        ev = torch.cuda.Event()
+                        ev.record(cq.stream)
+                        inflight[id(cq)] = ev
+                    elif ev.query():  # its step has finished: collect, then step again
+                        del inflight[id(cq)]
+                        ready.append(cq)
+                polled = ready
+            elif self.graph is not None:
                 if busy:
                     self.graph.launch(self.gstream)
+                polled = busy
             else:
                 for cq in busy:
                     cq.session.step(self.step_iters, stream=cq.stream)
-            for cq in busy:
+                polled = busy
+            for cq in polled:
                 ids, it, cv, xh, ts = cq.session.poll(want_xhat=self.keep, stream=cq.stream, timestamps=True)
                 t = time.perf_counter() - t0
                 if len(ids):
@@ -212,8 +233,10 @@ class Server:
             for cq in self.queues:
                 # a session whose requests have all been answered gives its memory back
                 if self.graph is None and cq.session is not None and cq.session.running == 0 \
-                        and cq.next_admitted == len(cq.arrival):
+                        and cq.next_admitted == len(cq.arrival) and id(cq) not in inflight:
                     self._close(cq)
+            if self.independent and busy and not polled:
+                time.sleep(0.00005)  # every busy session's step still running
             if not busy:
                 if not any(cq.session is not None for cq in self.queues) and any(
                         cq.next_admitted < cq.next_arrived for cq in self.queues):
@@ -296,6 +319,8 @@ def main():
     ap.add_argument("--step-iters", type=int, default=2)
     ap.add_argument("--graph", action="store_true", help="step all sessions as one HIP graph")
     ap.add_argument("--step-graphs", action="store_true", help="replay a captured graph per session step")
+    ap.add_argument("--independent", action="store_true",
+                    help="step each session again as soon as its previous step has finished")
     args = ap.parse_args()
     import torch
 
@@ -307,7 +332,7 @@ def main():
             queues, markov = make_requests(pool, n, rate, seed=0xDA7A0005, pool_max=args.pool)
             srv = Server(queues, args.slots, schedule, args.max_iter, int(args.budget_gb * 2 ** 30),
                          step_iters=args.step_iters, markov=markov, graph=args.graph,
-                         step_graphs=args.step_graphs)
+                         step_graphs=args.step_graphs, independent=args.independent)
             st = srv.run(deadline=args.seconds + args.drain)
             lat = np.array(st.latency) * 1e3
             print(json.dumps({
@@ -319,7 +344,8 @@ def main():
                 "edge_q_per_s": st.edge_q / st.wall if st.wall else None,
                 "fer": 1 - st.converged / max(1, st.done), "sessions_opened": srv.opened,
                 "codes": args.codes, "slots": args.slots, "step_iters": args.step_iters,
-                "graph": args.graph, "step_graphs": args.step_graphs}), flush=True)
+                "graph": args.graph, "step_graphs": args.step_graphs, "independent": args.independent}),
+                flush=True)
             del queues, srv
             torch.cuda.empty_cache()
 

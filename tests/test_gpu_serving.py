@@ -24,16 +24,20 @@ def gfbp():
     return g
 
 
-@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("mode", ["rounds", "graph", "independent"])
 @pytest.mark.parametrize("schedule", ["pus", "sus"])
-def test_served_frames_equal_alone_decoding(gfbp, schedule, graph):
+def test_served_frames_equal_alone_decoding(gfbp, schedule, mode):
+    """In lock-step rounds, as one captured graph per round, and with each
+    session stepped on its own clock."""
     import torch
     from paper_cs_0605069_amd import serving
 
+    graph = mode == "graph"
     pool = wl.mixed_pool(4, seed=71, n_range=(256, 900))
     queues, markov = serving.make_requests(pool, 500, rate=20000.0, seed=72)
     srv = serving.Server(queues, slots=64, schedule=schedule, max_iter=40, budget_bytes=8 << 30,
-                         step_iters=2 if graph else 3, markov=markov, keep_results=True, graph=graph)
+                         step_iters=2 if graph else 3, markov=markov, keep_results=True, graph=graph,
+                         independent=mode == "independent")
     st = srv.run()
     assert srv.opened == len(queues)
     assert st.done == 500 and st.offered == 500 and len(st.results) == 500
