@@ -162,6 +162,104 @@ def gf64_leg(gfbp, torch, steps: int, traffic_path: str = "", shapes: dict | Non
     return res
 
 
+def configs_workloads():
+    """The two other fixed workloads: (label, code, frames, decode keywords)."""
+    from paper_cs_0605069_amd import workloads as wl
+
+    out = []
+    code, enc = wl.regular_code(504, 3, 6, 4, seed=0xC0DE0001)
+    out.append(("gf4_n504_bsc", code, wl.make_frames(code, enc, 2000, 0xDA7A0001, "bsc", 0.06), {"max_iter": 200}))
+    code, enc = wl.regular_code(3000, 3, 6, 8, seed=0xC0DE0003)
+    M = wl.self_transition_matrix(8, 0.7)
+    kw = {"max_iter": 100, "prior": "markov", "markov_M": M, "markov_pi": wl.stationary(M)}
+    for ch, par in (("bsc", 0.08), ("bec", 0.45)):
+        fr = wl.make_frames(code, enc, 4096, 0xDA7A0003 + (ch == "bec"), ch, par, source="markov", markov=M)
+        out.append((f"gf8_n3000_markov_{ch}", code, fr, kw))
+    return out
+
+
+def configs_leg(gfbp, torch, calls: int = 2) -> tuple[dict, list]:
+    """GF(4) (3,6) N=504 over BSC 0.06 (2000 frames, max 200 iterations) and
+    GF(8) (3,6) N=3000 with a Markov source (self-transition 0.7) over BSC 0.08
+    and BEC 0.45 (4096 frames each, max 100), every frame of a workload in one
+    launch, the kernel shape tuned per schedule: edge-q/s, frames/s, mean
+    iterations and FER per schedule over `calls` timed calls, each kernel's
+    algorithmic GB/s (the Markov prior kernel among them) and the SUS/PUS
+    iteration ratios (not part of `value`).  Also returns, per workload, the
+    decoded iterations and convergence for the reference decoder's sample."""
+    out, samples = {}, []
+    for label, code, fr, kw in configs_workloads():
+        dcode = gfbp.DeviceCode(code)
+        d = gfbp.frames_to_device(fr)
+        res = {"workload": f"GF({code.q}) (3,6) N={code.n}, {fr.channel.upper()} {float(fr.param[0])}"
+                           + (", Markov source (self-transition 0.7)" if "prior" in kw else ", i.i.d. source")
+                           + f", {fr.F} frames in one launch, max {kw['max_iter']} iterations",
+               "edges": code.E, "q": code.q}
+        got = {}
+        for s in ("pus", "sus"):
+            res[s] = {"entries_per_lane": gfbp.tune(dcode, d, schedule=s, trial_iters=3, **{k: v for k, v in kw.items()
+                                                                                          if k != "max_iter"})}
+            gfbp.decode_batch(dcode, d, schedule=s, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                o = gfbp.decode_batch(dcode, d, schedule=s, **kw)
+                it, cv = o["iters"].cpu().numpy(), o["converged"].cpu().numpy()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            # the kernels of one more call, timed one by one (events around
+            # each launch: outside the timed calls above)
+            gfbp.profile_reset()
+            gfbp.profile_enable(True)
+            gfbp.decode_batch(dcode, d, schedule=s, **kw)
+            torch.cuda.synchronize()
+            gfbp.profile_enable(False)
+            prof = gfbp.profile_read()
+            res[s].update({"edge_q_per_s": calls * float(it.sum()) * code.E * code.q / wall,
+                           "frames_per_s": calls * fr.F / wall, "mean_iters": float(it.mean()),
+                           "fer": float(1 - cv.mean()),
+                           "kernels": {k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"] * 1e3,
+                                           "GBps_algorithmic": v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9,
+                                           "frac_of_hbm_peak": v["algo_bytes"] / (v["total_ms"] / 1e3) / HBM_PEAK}
+                                       for k, v in prof.items() if v["launches"] and v["total_ms"]}})
+            got[s] = (it, cv)
+        pi, si = got["pus"][0].astype(float), got["sus"][0].astype(float)
+        res["sus_over_pus"] = {"ratio_of_means": si.mean() / pi.mean(), "mean_of_ratios": float(np.mean(si / pi)),
+                               "stdev_of_ratios": float(np.std(si / pi))}
+        out[label] = res
+        samples.append((label, code, fr, kw, got))
+        del dcode, d
+        print(f"# configs leg {label} done", file=sys.stderr, flush=True)
+    return out, samples
+
+
+def cpu_baseline_configs(samples, frames: int = 256) -> dict:
+    """Reference decoder on every k-th frame (`frames` of each workload of the
+    configs leg), both schedules: its edge-q/s and frames/s, and both sides'
+    mean iterations and FER on those frames."""
+    import oracle
+
+    out = {}
+    for label, code, fr, kw, got in samples:
+        stride = max(1, fr.F // frames)
+        idx = np.arange(0, fr.F, stride)[:frames]
+        sub = fr.subset(idx)
+        okw = {k: v for k, v in kw.items() if k in ("prior", "markov_M", "markov_pi", "max_iter")}
+        r = {"frames": int(len(idx)), "stride": int(stride), "cores": oracle.max_threads()}
+        eq, t0 = 0.0, time.perf_counter()
+        for name, sch in (("pus", oracle.PUS), ("sus", oracle.SUS)):
+            o = oracle.decode(code, sub, schedule=sch, **okw)
+            eq += float(o["iters"].sum()) * code.E * code.q
+            g_it, g_cv = got[name][0][idx], got[name][1][idx]
+            r[name] = {"mean_iters_reference": float(o["iters"].mean()), "mean_iters_gpu": float(g_it.mean()),
+                       "fer_reference": float(1 - o["converged"].mean()), "fer_gpu": float(1 - g_cv.mean()),
+                       "same_iterations": int((g_it == o["iters"]).sum())}
+        dt = time.perf_counter() - t0
+        r.update({"edge_q_per_s": eq / dt, "frames_per_s": 2 * len(idx) / dt, "seconds": dt})
+        out[label] = r
+    return out
+
+
 def uneven_leg(gfbp, torch) -> dict:
     """The uneven batch: 10,000 frames over 64 codes of the mixed pool (q in
     {4, 16, 64}, n 256-8000, BSC / BEC / BI-AWGN per frame at Eb/N0 ~ U[1, 2]
@@ -313,13 +411,15 @@ def main():
                     help="measured HBM traffic summary to report beside the roofline")
     ap.add_argument("--traffic-gf64", default=os.path.join(ROOT, "profiles", "traffic_gf64_n2000_bi-awgn.txt"),
                     help="the same for the GF(64) leg")
-    ap.add_argument("--leg", default="", choices=["", "gf64", "serving", "mn", "uneven"],
+    ap.add_argument("--leg", default="", choices=["", "gf64", "serving", "mn", "uneven", "configs"],
                     help="run only this leg and print its JSON (profiling)")
     ap.add_argument("--serving-seconds", type=float, default=6.0)
     ap.add_argument("--serving-rate", type=float, default=20000.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-mn", action="store_true", help="skip the Table-1 stand-in leg (SUS and PUS on an MN code)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg (64 codes in one call)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the GF(4) N=504 and GF(8) N=3000 Markov workloads")
     ap.add_argument("--no-copy-rate", action="store_true", help="skip measuring the achievable streaming-copy bandwidth")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -354,6 +454,9 @@ def main():
         return
     if args.leg == "uneven":
         print(json.dumps(uneven_leg(gfbp, torch)), flush=True)
+        return
+    if args.leg == "configs":
+        print(json.dumps(configs_leg(gfbp, torch)[0]), flush=True)
         return
     code, points = make_workload()
     dcode = gfbp.DeviceCode(code)
@@ -467,9 +570,12 @@ def main():
                                                                          args.serving_rate)
     mn = None if args.no_mn else mn_leg()
     uneven = None if args.no_uneven else uneven_leg(gfbp, torch)
+    cfgs, cfg_samples = (None, None) if args.no_configs else configs_leg(gfbp, torch)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, points, args.cpu_frames, rec)
+        if cfg_samples:
+            cpu["configs_sample"] = cpu_baseline_configs(cfg_samples)
         if srv_samples:
             cpu["serving_sample"] = cpu_baseline_serving(srv_samples)
             for sch, r in cpu["serving_sample"].items():
@@ -503,6 +609,7 @@ def main():
         "serving": srv,
         "mn_table1_row9": mn,
         "uneven_batch": uneven,
+        "configs": cfgs,
     }
     print(json.dumps(line), flush=True)
 

@@ -230,6 +230,18 @@ typedef struct {
  * (GFBP_EUNSUPPORTED). */
 #define GFBP_OPT_PERSISTENT 16
 
+/* Batch decode of one code: decode through the tiled kernels even where the
+ * frames' state fits in LDS.  By default a one-code batch over GF(2), GF(4)
+ * or GF(8) whose frame state (messages, evidence, priors, decisions:
+ * 4 q (E (1 + PUS) + n + K (prior) + K (Markov)) + n + m bytes) fits in the
+ * LDS of a workgroup is decoded in one launch with each workgroup holding up
+ * to four frames in LDS through every iteration (Section 2's schedules, the
+ * H x = z test, retirement and Markov refreshes inside the kernel; HBM only
+ * for the initial state and the results), unless posteriors, snapshots,
+ * traces, GFBP_OPT_SUS_STRICT or GFBP_OPT_PRIOR_IN_SWEEP are asked for.  Its
+ * outputs equal bitwise those of the tiled decode at q entries per lane. */
+#define GFBP_OPT_NO_ONCHIP 32
+
 /* Batch decode, SUS with the Markov prior: the prior of each source symbol is
  * assigned during the sweep, at its column's vertical pass (Section 2, the
  * paragraph on priors), instead of after each iteration.  From iteration 2 on,

@@ -30,6 +30,7 @@ OPT_NO_COMPACT = 2
 OPT_STEP_GRAPHS = 4
 OPT_PRIOR_IN_SWEEP = 8
 OPT_PERSISTENT = 16
+OPT_NO_ONCHIP = 32
 CHANNELS = {"bsc": CH_BSC, "bec": CH_BEC, "biawgn": CH_BIAWGN, "likelihood": CH_LIKELIHOOD}
 SCHEDULES = {"pus": PUS, "sus": SUS, PUS: PUS, SUS: SUS}
 
@@ -335,7 +336,7 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
                  snap_iter: int = 0, workspace=None, stream=None, outputs: dict | None = None,
                  sus_strict: bool = False, tune_iters: int = 0, compact: bool = True, truth=None,
                  prior_in_sweep: bool = False, static_prior=None, persistent: bool = False, persist_el: int = 0,
-                 persist_waves: int = 0) -> dict:
+                 persist_waves: int = 0, onchip: bool = True) -> dict:
     """``gfbp_decode_batch`` on device tensors of one code; returns device tensors.
 
     dframes: dict from :func:`frames_to_device` (or with the same keys; an
@@ -352,6 +353,8 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
     prior at its column's vertical pass (``GFBP_OPT_PRIOR_IN_SWEEP``).
     persistent: decode through the persistent work-list kernel
     (``GFBP_OPT_PERSISTENT``) with tile shape persist_el / persist_waves.
+    onchip=False: the tiled kernels even where the frames' state fits in LDS
+    (``GFBP_OPT_NO_ONCHIP``).
     """
     import torch
 
@@ -375,7 +378,8 @@ def decode_batch(dcode: DeviceCode, dframes: dict, schedule="pus", max_iter: int
         out["snap_Q"] = torch.zeros((F, n, q), dtype=torch.float32, device=dev)
     Mt, pt, Pt, per_symbol = _prior_tensors(prior, markov_M, markov_pi, static_prior, dev)
     opts = ((OPT_SUS_STRICT if sus_strict else 0) | (0 if compact else OPT_NO_COMPACT) |
-            (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0) | (OPT_PERSISTENT if persistent else 0))
+            (OPT_PRIOR_IN_SWEEP if prior_in_sweep else 0) | (OPT_PERSISTENT if persistent else 0) |
+            (0 if onchip else OPT_NO_ONCHIP))
     b = _batch(F, sch, max_iter, early_stop, dframes, prior, Mt, pt, Pt, per_symbol, opts, truth, 1, None,
                persist_el, persist_waves)
     codes = _codes_array([dcode])

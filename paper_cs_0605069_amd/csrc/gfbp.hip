@@ -25,6 +25,7 @@
 #include "gfbp_plan.h"
 #include "gfbp_tiled.h"
 #include "gfbp_persist.h"
+#include "gfbp_onchip.h"
 
 using namespace gfbp;
 
@@ -75,10 +76,11 @@ namespace {
 
 enum Kind {
     K_INIT, K_CHECK, K_VARIABLE, K_SEQUENTIAL, K_SUS_LEVEL, K_SYNDROME, K_RETIRE, K_MARKOV, K_OUTPUT, K_COMPACT,
-    K_SUS_RUN, K_PERSIST, K_COUNT
+    K_SUS_RUN, K_PERSIST, K_ONCHIP, K_COUNT
 };
 const char *kKindName[K_COUNT] = {"init",     "check",  "variable", "sequential", "sus_level", "syndrome",
-                                  "retire",   "markov", "output",   "compact",    "sus_run",   "persistent"};
+                                  "retire",   "markov", "output",   "compact",    "sus_run",   "persistent",
+                                  "onchip"};
 
 struct Totals {
     int64_t launches = 0;
@@ -781,6 +783,188 @@ gfbp_status run_any(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out
         case 3: return run_lel<P, 3>(code, b, out, s, a, st, needQ, sh.small);
         default: return fail(GFBP_EUNSUPPORTED, "bad shape");
     }
+}
+
+// ------------------------------------------------------ whole decodes in LDS
+// LDS a workgroup may use on the current device (queried once per device).
+int lds_limit() {
+    static std::mutex mu;
+    static std::vector<int> per_dev;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    std::lock_guard<std::mutex> g(mu);
+    if (size_t(dev) >= per_dev.size()) per_dev.resize(size_t(dev) + 1, -1);
+    if (per_dev[size_t(dev)] < 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+        per_dev[size_t(dev)] = std::max(0, v);
+    }
+    return per_dev[size_t(dev)];
+}
+
+// Whether a one-code batch may be decoded in LDS: q <= 8, outputs no more
+// than decisions, iterations, convergence and guards, the level sweep for SUS
+// with priors from the previous iteration.
+bool onchip_allowed(const gfbp_code *code, const gfbp_batch *b, const gfbp_result *out) {
+    if (b->options & GFBP_OPT_NO_ONCHIP) return false;
+    if (code->info.p > onchip::kMaxP) return false;
+    // the packed graph: 16-bit edge, column and row indices
+    if (code->info.n_edges >= 65536 || code->info.n >= 65536 || code->info.m >= 65536) return false;
+    if (out->posterior || out->snap_iter > 0 || (out->trace && b->truth)) return false;
+    if (b->schedule == GFBP_SUS && (b->options & (GFBP_OPT_SUS_STRICT | GFBP_OPT_PRIOR_IN_SWEEP))) return false;
+    return true;
+}
+
+// LDS layout of the in-LDS decode of this batch (fw = 0: a frame does not
+// fit).  Frames per workgroup: PUS, as many as fit in half the limit (two
+// workgroups per compute unit: every phase has work for all four wavefronts
+// of each), at least one if one fits in all of it; SUS, as many as fit in the
+// whole limit (a dependency level has work for a few dozen threads per
+// frame, so more frames per workgroup keep more of its wavefronts busy).
+onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int limit) {
+    onchip::Layout ly{};
+    const size_t q = size_t(code->info.q), E = size_t(code->info.n_edges), n = size_t(code->info.n),
+                 m = size_t(code->info.m), K = size_t(code->info.n_info);
+    const bool pus = b->schedule == GFBP_PUS;
+    const bool prior_on = b->prior != GFBP_PRIOR_UNIFORM && K > 0;
+    const bool markov = b->prior == GFBP_PRIOR_MARKOV && K > 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes, bool on) -> int {
+        if (!on) return -1;
+        const size_t o = off;
+        off += (bytes + 15) & ~size_t(15);
+        return int(std::min<size_t>(o, size_t(1) << 30));
+    };
+    ly.qm = take(E * q * 4, true);
+    ly.r = take(E * q * 4, pus);
+    ly.l = take(n * q * 4, true);
+    ly.pr = take(K * q * 4, prior_on);
+    ly.qp = take(K * q * 4, markov);
+    ly.xh = take(n, true);
+    ly.z = take(m, true);
+    const size_t frame = off;
+    // the shared part, offsets from its start
+    off = 0;
+    const int o_mul = take(q * q, true);
+    const int o_flags = take(size_t(onchip::F_NFLAGS) * onchip::kMaxFW * 4, true);
+    const int o_rsh = take(size_t(onchip::kThreads) * q * 4, !pus);
+    const int o_eg = take(E * 4, true);
+    const int o_erow = take(E * 2, true);
+    const int o_ecol = take(E * 2, true);
+    const int o_cedge = take(E * 2, true);
+    const int o_cg = take(n * 4, true);
+    const int o_ck = take(n * 2, true);
+    const int o_rrow = take(m * 4, true);
+    const int o_kcol = take(K * 2, true);
+    const int o_lcol = take(n * 2, !pus);
+    const int o_lptr = take(code->lv[0].ptr.size() * 2, !pus);
+    const int o_mk = take((4 + q + q * q) * 4, markov);
+    const size_t shared = off;
+    const size_t lim = size_t(std::max(0, limit));
+    int fw = 0;
+    for (int k = onchip::kMaxFW; k >= 1 && fw == 0; --k)
+        if (size_t(k) * frame + shared <= (pus ? lim / 2 : lim)) fw = k;
+    if (fw == 0 && frame + shared <= lim) fw = 1;
+    fw = std::min(fw, std::max(1, b->n_frames));
+    if (fw == 0) return onchip::Layout{};
+    ly.fw = fw;
+    ly.frame = int(frame);
+    const int base = int(size_t(fw) * frame);
+    auto at = [&](int o) { return o < 0 ? -1 : base + o; };
+    ly.mul = at(o_mul);
+    ly.flags = at(o_flags);
+    ly.rsh = at(o_rsh);
+    ly.eg = at(o_eg);
+    ly.erow = at(o_erow);
+    ly.ecol = at(o_ecol);
+    ly.cedge = at(o_cedge);
+    ly.cg = at(o_cg);
+    ly.ck = at(o_ck);
+    ly.rrow = at(o_rrow);
+    ly.kcol = at(o_kcol);
+    ly.lcol = at(o_lcol);
+    ly.lptr = at(o_lptr);
+    ly.mk = at(o_mk);
+    ly.total = int(size_t(fw) * frame + shared);
+    return ly;
+}
+
+template <int P>
+gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
+                       hipStream_t st, int needQ, const onchip::Layout &ly) {
+    constexpr int Q = 1 << P;
+    const DevCode &c = code->dev;
+    const int F = s.F;
+    const unsigned fb = unsigned((F + kBlock - 1) / kBlock);
+    const int prior_on = (b->prior != GFBP_PRIOR_UNIFORM) && c.n_info > 0;
+    const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
+    Tracer tr(st);
+    launch(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, a);
+    // the initialisation kernel's tile list: every frame, one lane per frame
+    launch(tiled::k_tiles, dim3(1), dim3(1024), 0, st, s.active, F, s.Fp, kWave, s.tiles, s.count + 1);
+    s.act = s.tiles;
+    s.nact = s.count + 1;
+    s.nb = (F + kWave - 1) / kWave;
+    if (markov) hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, st, b->markov_M, Q, a.mshape);
+    tiled::Chan ch{};
+    ch.channel = b->channel;
+    ch.prior = prior_on ? b->prior : GFBP_PRIOR_UNIFORM;
+    ch.evidence = b->evidence;
+    ch.static_per_symbol = b->static_per_symbol;
+    ch.rx = b->rx;
+    ch.erasure = b->erasure;
+    ch.y = b->y;
+    ch.lik = b->likelihood;
+    ch.param = b->param;
+    ch.pi = b->markov_pi;
+    ch.static_P = b->static_prior;
+    ch.chan_of = b->channel_of;
+    tr.begin();
+    launch((tiled::k_init<P, 0>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
+    tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
+    onchip::Args oa{};
+    oa.c = c;
+    oa.Qm = s.Qm;
+    oa.L = s.L;
+    oa.Pr = s.Pr;
+    oa.guards0 = s.guards;
+    oa.F = F;
+    oa.Fp = s.Fp;
+    oa.z = b->syndrome;
+    oa.schedule = b->schedule;
+    oa.max_iter = b->max_iter;
+    oa.early_stop = b->early_stop;
+    oa.prior_on = prior_on;
+    oa.markov = markov;
+    oa.wantQ = markov ? needQ : 0;  // (posteriors are not decoded in LDS)
+    oa.M = b->markov_M;
+    oa.pi = b->markov_pi;
+    oa.mshape = a.mshape;
+    oa.recs = code->lv[0].recs;
+    oa.lvl = code->lv[0].dptr;
+    oa.nlev = int(code->lv[0].ptr.size()) - 1;
+    oa.rs = std::max(1, c.max_dv);
+    oa.xhat = out->xhat;
+    oa.iters = out->iters;
+    oa.conv = out->converged;
+    oa.guards = out->guards;
+    oa.lay = ly;
+    // HBM: the initial state and syndromes in, the results out
+    const double hbm = double(F) * (4.0 * Q * (c.E + c.n + (prior_on ? c.n_info : 0)) + 4.0 +
+                                    (b->syndrome ? c.m : 0) + c.n + 9.0);
+    // (dynamic LDS beyond the default bound must be allowed per kernel)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&onchip::k_onchip<P>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, ly.total);
+    tr.begin();
+    launch((onchip::k_onchip<P>), dim3(unsigned((F + ly.fw - 1) / ly.fw)), dim3(onchip::kThreads),
+           size_t(ly.total), st, oa);
+    tr.end(K_ONCHIP, hbm, 0);
+    HIP_TRY(hipGetLastError());
+    if (tr.on) {
+        HIP_TRY(hipStreamSynchronize(st));
+        tr.flush();
+    }
+    return GFBP_OK;
 }
 
 // ======================================================================= sessions
@@ -1505,6 +1689,15 @@ gfbp_status decode_plain(const gfbp_code *code, const gfbp_batch *b, gfbp_result
     s.F = F;
     s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
+    if (F > 0 && onchip_allowed(code, b, out)) {
+        const onchip::Layout ly = onchip_layout(code, b, lds_limit());
+        if (ly.fw > 0) switch (code->info.p) {
+                case 1: return run_onchip<1>(code, b, out, s, a, st, needQ, ly);
+                case 2: return run_onchip<2>(code, b, out, s, a, st, needQ, ly);
+                case 3: return run_onchip<3>(code, b, out, s, a, st, needQ, ly);
+                default: break;
+            }
+    }
     switch (code->info.p) {
         case 1: return run_any<1>(code, b, out, s, a, st, needQ);
         case 2: return run_any<2>(code, b, out, s, a, st, needQ);
@@ -2119,6 +2312,7 @@ gfbp_status gfbp_tune(gfbp_code *c, const gfbp_batch *b, gfbp_result *out, void 
     tb.n_codes = 1;
     tb.code_index = nullptr;
     tb.options &= ~GFBP_OPT_PERSISTENT;
+    tb.options |= GFBP_OPT_NO_ONCHIP;  // the shapes are those of the tiled kernels
     gfbp_result to = *out;
     to.posterior = nullptr;
     to.snap_iter = 0;

@@ -70,7 +70,7 @@ def test_persistent_equals_plain(gfbp, q, n, channel, prior, syn, schedule, el, 
     dfr = gfbp.frames_to_device(fr)
     dcode = gfbp.DeviceCode(code)
     dcode.set_shape(schedule, gfbp.persist_entries_per_lane(q, el))  # the same lane split (rounding order)
-    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50, **kw)
+    out = gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=50, onchip=False, **kw)
     a = {k: v.cpu().numpy() for k, v in out.items()}
     b = gpu_decode(gfbp, code, dfr, schedule, max_iter=50, persistent=True, persist_el=el, persist_waves=waves, **kw)
     for k in ("xhat", "iters", "converged", "guards"):
@@ -92,14 +92,14 @@ def test_persistent_mn_form_per_frame_channels(gfbp):
     dcode = gfbp.DeviceCode(code)
     for sch in ("pus", "sus"):
         dcode.set_shape(sch, gfbp.persist_entries_per_lane(q))  # the persistent path's lane split
-        a = {k: v.cpu().numpy() for k, v in gfbp.decode_batch(dcode, dfr, schedule=sch, **kw).items()}
+        a = {k: v.cpu().numpy() for k, v in gfbp.decode_batch(dcode, dfr, schedule=sch, onchip=False, **kw).items()}
         b = gpu_decode(gfbp, code, dfr, sch, persistent=True, **kw)
         for k in ("xhat", "iters", "converged", "guards"):
             assert np.array_equal(a[k], b[k]), f"{sch} {k}"
         o = 0
         for p in parts:  # and each channel's frames alone (a batch-wide channel)
             c = {k: v.cpu().numpy() for k, v in gfbp.decode_batch(dcode, gfbp.frames_to_device(p), schedule=sch,
-                                                                   **kw).items()}
+                                                                   onchip=False, **kw).items()}
             assert np.array_equal(c["xhat"], a["xhat"][o:o + p.F]) and np.array_equal(c["iters"], a["iters"][o:o + p.F])
             o += p.F
     assert torch.cuda.is_available()
@@ -196,7 +196,8 @@ def test_uneven_batch_graph_equals_plain_kernels(gfbp):
         ref = {}
         base = 0
         for g in groups:
-            out = gfbp.decode_batch(dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40)
+            out = gfbp.decode_batch(dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40,
+                                    onchip=False)  # sessions run the tiled kernels
             torch.cuda.synchronize()
             for f in range(g.F):
                 ref[base + f] = (int(out["iters"][f]), int(out["converged"][f]), out["xhat"][f].cpu().numpy())

@@ -337,7 +337,8 @@ def test_frame_compaction_changes_nothing(gfbp, schedule, q):
     fr.syndrome = z
     dfr = gfbp.frames_to_device(fr)
     outs = [gpu_decode(gfbp, code, dfr, schedule[:3], max_iter=60, prior="markov", markov_M=M, markov_pi=pi,
-                       compact=compact, prior_in_sweep=schedule.endswith("in-sweep")) for compact in (False, True)]
+                       compact=compact, prior_in_sweep=schedule.endswith("in-sweep"), onchip=False)
+            for compact in (False, True)]
     it = outs[0]["iters"]
     assert it.min() < 10 and (it == 60).sum() > 20  # fast and slow frames
     for k in ("xhat", "iters", "converged", "guards"):

@@ -47,7 +47,8 @@ def test_served_frames_equal_alone_decoding(gfbp, schedule, mode):
         for g, m, pos in cq.groups:
             gids = cq.ids[pos]  # one request per pool frame here
             kw = dict(prior="markov", markov_M=M, markov_pi=pi) if m else {}
-            out = gfbp.decode_batch(cq.dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40, **kw)
+            out = gfbp.decode_batch(cq.dcode, gfbp.frames_to_device(g), schedule=schedule, max_iter=40,
+                                    onchip=False, **kw)  # sessions run the tiled kernels
             torch.cuda.synchronize()
             it, cv, xh = out["iters"].cpu().numpy(), out["converged"].cpu().numpy(), out["xhat"].cpu().numpy()
             for f, gid in enumerate(gids):

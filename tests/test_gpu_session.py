@@ -49,7 +49,9 @@ def _drain(sess, dfr, F, step_iters=3, max_rounds=10000, stream=None):
 def _batch(gfbp, dcode, fr, schedule, max_iter, **kw):
     import torch
 
-    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, max_iter=max_iter, **kw)
+    # sessions run the tiled kernels: the batch decode through them too
+    out = gfbp.decode_batch(dcode, gfbp.frames_to_device(fr), schedule=schedule, max_iter=max_iter, onchip=False,
+                            **kw)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 
