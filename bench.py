@@ -178,6 +178,25 @@ def configs_workloads():
     return out
 
 
+LDS_PEAK = 256 * 128 * 2.4e9   # MI355X: 256 CUs x 128 bytes per clock x 2.4 GHz
+FP64_PEAK = 78.6e12            # MI355X fp64 vector
+
+
+def onchip_counts(code) -> tuple[float, float]:
+    """Algorithmic LDS bytes and float64 operations of one frame-iteration of
+    the in-LDS decode: each edge reads its row's other q-vectors and writes
+    its r (check side); each column reads its r-vectors and prior and writes
+    its q-vectors (variable side); transforms cost q log2 q additions, every
+    product and normalisation q operations."""
+    q, p = code.q, int(np.log2(code.q))
+    dc = np.diff(code.row_ptr).astype(float)
+    dv = np.bincount(code.col, minlength=code.n).astype(float)
+    lds = 4.0 * q * (float((dc * (dc - 1)).sum()) + 3.0 * code.E + code.n)
+    flops = float((dc * ((dc - 1) * (q * p + q) + q * p + q)).sum()) + \
+        float((q * dv + 2 * q + dv * ((dv - 1) * q + 2 * q)).sum())
+    return lds, flops
+
+
 def configs_leg(gfbp, torch, calls: int = 2) -> tuple[dict, list]:
     """GF(4) (3,6) N=504 over BSC 0.06 (2000 frames, max 200 iterations) and
     GF(8) (3,6) N=3000 with a Markov source (self-transition 0.7) over BSC 0.08
@@ -223,6 +242,32 @@ def configs_leg(gfbp, torch, calls: int = 2) -> tuple[dict, list]:
                                            "frac_of_hbm_peak": v["algo_bytes"] / (v["total_ms"] / 1e3) / HBM_PEAK}
                                        for k, v in prof.items() if v["launches"] and v["total_ms"]}})
             got[s] = (it, cv)
+            if "onchip" in prof:
+                # the whole decode in LDS: what bounds it is latency (the frames
+                # that run to max_iter), not HBM; its LDS and fp64 rates, also
+                # with every frame running a fixed 20 iterations
+                lds_b, flops = onchip_counts(code)
+                k = prof["onchip"]
+                fi = float(it.sum())
+                sec = k["total_ms"] / 1e3
+                full = {}
+                gfbp.profile_reset()
+                gfbp.profile_enable(True)
+                gfbp.decode_batch(dcode, d, schedule=s, **{**kw, "max_iter": 20, "early_stop": False})
+                torch.cuda.synchronize()
+                gfbp.profile_enable(False)
+                k2 = gfbp.profile_read()["onchip"]
+                sec2 = k2["total_ms"] / 1e3
+                full = {"frame_iterations": 20 * fr.F, "kernel_ms": k2["total_ms"],
+                        "lds_GBps": 20 * fr.F * lds_b / sec2 / 1e9, "lds_frac": 20 * fr.F * lds_b / sec2 / LDS_PEAK,
+                        "fp64_TFLOPs": 20 * fr.F * flops / sec2 / 1e12,
+                        "fp64_frac": 20 * fr.F * flops / sec2 / FP64_PEAK}
+                res[s]["onchip"] = {"bound": "latency", "kernel_ms": k["total_ms"], "frame_iterations": fi,
+                                    "lds_bytes_per_frame_iteration": lds_b, "fp64_ops_per_frame_iteration": flops,
+                                    "lds_GBps": fi * lds_b / sec / 1e9, "lds_frac": fi * lds_b / sec / LDS_PEAK,
+                                    "fp64_TFLOPs": fi * flops / sec / 1e12, "fp64_frac": fi * flops / sec / FP64_PEAK,
+                                    "lds_peak_GBps": LDS_PEAK / 1e9, "fp64_peak_TFLOPs": FP64_PEAK / 1e12,
+                                    "every_frame_running": full}
         pi, si = got["pus"][0].astype(float), got["sus"][0].astype(float)
         res["sus_over_pus"] = {"ratio_of_means": si.mean() / pi.mean(), "mean_of_ratios": float(np.mean(si / pi)),
                                "stdev_of_ratios": float(np.std(si / pi))}

@@ -816,11 +816,14 @@ bool onchip_allowed(const gfbp_code *code, const gfbp_batch *b, const gfbp_resul
 }
 
 // LDS layout of the in-LDS decode of this batch (fw = 0: a frame does not
-// fit).  Frames per workgroup: PUS, as many as fit in half the limit (two
-// workgroups per compute unit: every phase has work for all four wavefronts
-// of each), at least one if one fits in all of it; SUS, as many as fit in the
-// whole limit (a dependency level has work for a few dozen threads per
-// frame, so more frames per workgroup keep more of its wavefronts busy).
+// fit).  Frames per workgroup: as many as fit in half the limit (two
+// workgroups per compute unit), at least one if one fits in all of it.  A
+// decode's time is mostly that of its slowest frames (those that run to
+// max_iter), which more frames per workgroup only delay: on GF(4) N = 504,
+// SUS, 2000 frames, the whole LDS (four frames per workgroup) took 15.6 ms
+// and half of it (one) 11.0 ms; with every frame running 200 iterations
+// the four frames per workgroup were faster (137 against 220 us per
+// iteration).
 onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int limit) {
     onchip::Layout ly{};
     const size_t q = size_t(code->info.q), E = size_t(code->info.n_edges), n = size_t(code->info.n),
@@ -858,12 +861,13 @@ onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int lim
     const int o_kcol = take(K * 2, true);
     const int o_lcol = take(n * 2, !pus);
     const int o_lptr = take(code->lv[0].ptr.size() * 2, !pus);
+    const int o_pe = take(n * size_t(std::max(1, code->info.max_col_degree)) * 4, !pus);
     const int o_mk = take((4 + q + q * q) * 4, markov);
     const size_t shared = off;
     const size_t lim = size_t(std::max(0, limit));
     int fw = 0;
     for (int k = onchip::kMaxFW; k >= 1 && fw == 0; --k)
-        if (size_t(k) * frame + shared <= (pus ? lim / 2 : lim)) fw = k;
+        if (size_t(k) * frame + shared <= lim / 2) fw = k;
     if (fw == 0 && frame + shared <= lim) fw = 1;
     fw = std::min(fw, std::max(1, b->n_frames));
     if (fw == 0) return onchip::Layout{};
@@ -884,6 +888,7 @@ onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int lim
     ly.kcol = at(o_kcol);
     ly.lcol = at(o_lcol);
     ly.lptr = at(o_lptr);
+    ly.pe = at(o_pe);
     ly.mk = at(o_mk);
     ly.total = int(size_t(fw) * frame + shared);
     return ly;
@@ -952,12 +957,17 @@ gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *
     // HBM: the initial state and syndromes in, the results out
     const double hbm = double(F) * (4.0 * Q * (c.E + c.n + (prior_on ? c.n_info : 0)) + 4.0 +
                                     (b->syndrome ? c.m : 0) + c.n + 9.0);
-    // (dynamic LDS beyond the default bound must be allowed per kernel)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&onchip::k_onchip<P>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, ly.total);
-    tr.begin();
-    launch((onchip::k_onchip<P>), dim3(unsigned((F + ly.fw - 1) / ly.fw)), dim3(onchip::kThreads),
-           size_t(ly.total), st, oa);
+    // the degree class bounds the rows' siblings and the columns' r-vectors
+    // held in registers; dynamic LDS beyond the default bound must be
+    // allowed per kernel
+    auto go = [&](auto kern) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  ly.total);
+        tr.begin();
+        launch(kern, dim3(unsigned((F + ly.fw - 1) / ly.fw)), dim3(onchip::kThreads), size_t(ly.total), st, oa);
+    };
+    if (small_class(code)) go(onchip::k_onchip<P, 6, 4>);
+    else go(onchip::k_onchip<P, kDcMax, kDvMax>);
     tr.end(K_ONCHIP, hbm, 0);
     HIP_TRY(hipGetLastError());
     if (tr.on) {

@@ -48,6 +48,7 @@ struct Layout {
     int qm, r, l, pr, qp, xh, z;     // offsets within a frame block (-1: absent)
     int mul, flags, rsh;             // shared part (rsh -1 for PUS)
     int eg, erow, ecol, cedge, cg, ck, rrow, kcol, lcol, lptr;  // the graph (lcol, lptr: SUS)
+    int pe;                          // SUS: [n][rs] u32, the edge of each (position, slot) | degree << 16
     int mk;                          // Markov source: shape [4], pi [q], M [q][q] floats (-1: none)
     int total;                       // bytes of LDS per workgroup
 };
@@ -113,29 +114,123 @@ __device__ __forceinline__ int clip_q(const double *acc) {
     return best;
 }
 
+// One q-vector from LDS (its q floats are 4q-byte aligned) in one access.
+template <int Q>
+__device__ __forceinline__ void lds_vec(const float *p, float *v) {
+    if constexpr (Q == 2) {
+        const tiled::f32x2 t = *reinterpret_cast<const tiled::f32x2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < Q / 4; ++k) {
+            const tiled::f32x4 t = reinterpret_cast<const tiled::f32x4 *>(p)[k];
+            v[4 * k] = t.x;
+            v[4 * k + 1] = t.y;
+            v[4 * k + 2] = t.z;
+            v[4 * k + 3] = t.w;
+        }
+    }
+}
+
+// Row a of the multiplication table (a x y for every y), read as one word.
+template <int Q>
+__device__ __forceinline__ void mul_row(const uint8_t *mul, int a, int *out) {
+    const uint8_t *row = mul + a * Q;
+    uint64_t w;
+    if constexpr (Q == 2) w = *reinterpret_cast<const uint16_t *>(row);
+    else if constexpr (Q == 4) w = *reinterpret_cast<const uint32_t *>(row);
+    else w = *reinterpret_cast<const uint64_t *>(row);
+#pragma unroll
+    for (int y = 0; y < Q; ++y) out[y] = int((w >> (8 * y)) & 0xffu);
+}
+
 // A3 for one edge: r from the siblings (row positions 0..dc-1 except `self`)
-// in row order, T = WHT(signs(z) x prod WHT(q~)), r(h^-1 y) = T(y) / q
-// (products by h^-1 from the row `minv` of the multiplication table).
-template <int P>
-__device__ __forceinline__ void edge_r(const float *qm, int rs, int dc, int self, int zi, const uint8_t *minv,
-                                       float *rout) {
+// in row order, T = WHT(signs(z) x prod WHT(q~)), r(h^-1 y) = T(y) / q.
+// Where registers allow (rows of at most DCM entries, few entries), every
+// sibling is requested before the first is used.
+template <int P, int DCM>
+__device__ __forceinline__ void edge_r(const float *qm, int rs, int dc, int self, int zi, const uint8_t *mul,
+                                       int hinv, float *rout) {
     constexpr int Q = 1 << P;
+    constexpr bool kPre = (DCM - 1) * Q <= 40;
+    int pos[Q];
+    mul_row<Q>(mul, hinv, pos);
     double T[Q];
 #pragma unroll
     for (int r = 0; r < Q; ++r) T[r] = (__popc(unsigned(zi & r)) & 1) ? -1.0 : 1.0;
-    for (int u = 0; u < dc; ++u) {
-        if (u == self) continue;
-        const float *src = qm + size_t(rs + u) * Q;
-        double W[Q];
+    if constexpr (kPre) {
+        float raw[DCM - 1][Q];
 #pragma unroll
-        for (int r = 0; r < Q; ++r) W[r] = double(src[r]);
-        tiled::wht_regs<Q>(W);
+        for (int u = 0; u < DCM - 1; ++u)
+            if (u < dc - 1) lds_vec<Q>(qm + size_t(rs + (u < self ? u : u + 1)) * Q, raw[u]);
 #pragma unroll
-        for (int r = 0; r < Q; ++r) T[r] *= W[r];
+        for (int u = 0; u < DCM - 1; ++u)
+            if (u < dc - 1) {
+                double W[Q];
+#pragma unroll
+                for (int r = 0; r < Q; ++r) W[r] = double(raw[u][r]);
+                tiled::wht_regs<Q>(W);
+#pragma unroll
+                for (int r = 0; r < Q; ++r) T[r] *= W[r];
+            }
+    } else {
+        for (int u = 0; u < dc; ++u) {
+            if (u == self) continue;
+            float raw[Q];
+            lds_vec<Q>(qm + size_t(rs + u) * Q, raw);
+            double W[Q];
+#pragma unroll
+            for (int r = 0; r < Q; ++r) W[r] = double(raw[r]);
+            tiled::wht_regs<Q>(W);
+#pragma unroll
+            for (int r = 0; r < Q; ++r) T[r] *= W[r];
+        }
     }
     tiled::wht_regs<Q>(T);
 #pragma unroll
-    for (int y = 0; y < Q; ++y) rout[minv[y]] = float(fmax(T[y] * (1.0 / double(Q)), 0.0));
+    for (int y = 0; y < Q; ++y) rout[pos[y]] = float(fmax(T[y] * (1.0 / double(Q)), 0.0));
+}
+
+// A4/A5 for a column from its r-vectors rv[0..dv) (natural order, column
+// edge order) and its prior row pv: the pseudo-posterior (Eq. (5)), into
+// Qp_k when not null, and the decision.
+template <int P, int DVM>
+__device__ __forceinline__ void posterior_step(const float (&rv)[DVM][1 << P], int dv, const double *pv,
+                                               float *Qp_k, uint8_t *xh_j, int *g) {
+    constexpr int Q = 1 << P;
+    double acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = pv[q];
+#pragma unroll
+    for (int d2 = 0; d2 < DVM; ++d2)
+        if (d2 < dv)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q] *= double(rv[d2][q]);
+    if (!normalise_q<Q>(acc)) ++*g;
+    if (Qp_k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Qp_k[q] = float(acc[q]);
+    *xh_j = uint8_t(clip_q<Q>(acc));
+}
+
+// Eq. (4) for edge slot d of the column: q from the prior and the other
+// edges' r, normalised, stored at position h a (hpos[a]) of its vector.
+template <int P, int DVM>
+__device__ __forceinline__ void edge_q_step(const float (&rv)[DVM][1 << P], int dv, const double *pv, int d,
+                                            float *dst, const int *hpos, int *g) {
+    constexpr int Q = 1 << P;
+    double qv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) qv[q] = pv[q];
+#pragma unroll
+    for (int d2 = 0; d2 < DVM; ++d2)
+        if (d2 < dv && d2 != d)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) qv[q] *= double(rv[d2][q]);
+    if (!normalise_q<Q>(qv)) ++*g;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) dst[hpos[q]] = float(qv[q]);
 }
 
 // A7 for source symbol k (Eq. (7)): the neighbours' pseudo-posteriors
@@ -203,7 +298,7 @@ __device__ __forceinline__ void markov_row(const float *Qp, const float *Lj, int
     for (int q = 0; q < Q; ++q) pr[q] = float(u[q]);
 }
 
-template <int P>
+template <int P, int DCM, int DVM>
 __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
     constexpr int Q = 1 << P;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -264,8 +359,13 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
     if (a.schedule == GFBP_SUS) {
         uint16_t *lcol = reinterpret_cast<uint16_t *>(lds + ly.lcol);
         uint16_t *lptr = reinterpret_cast<uint16_t *>(lds + ly.lptr);
+        uint32_t *pe = reinterpret_cast<uint32_t *>(lds + ly.pe);
         for (int p = tid; p < n; p += kThreads) lcol[p] = uint16_t(a.recs[size_t(p) * a.rs].j);
         for (int l = tid; l <= a.nlev; l += kThreads) lptr[l] = uint16_t(a.lvl[l]);
+        for (int t = tid; t < n * a.rs; t += kThreads) {  // edge of each (position, slot), and the degree
+            const SusRec &r = a.recs[t];
+            pe[t] = uint32_t(t % a.rs < r.dv ? r.e : 0) | (uint32_t(r.dv) << 16);
+        }
     }
     if (a.markov) {
         for (int t = tid; t < 4; t += kThreads) mk[t] = a.mshape[t];
@@ -307,8 +407,8 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
                 const int w = x % fw, e = x / fw;
                 if (!active[w]) continue;
                 const uint32_t ge = eg[e];
-                edge_r<P>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul + eg_hinv(ge) * Q,
-                          Rr(w) + size_t(e) * Q);
+                edge_r<P, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge),
+                               Rr(w) + size_t(e) * Q);
             }
             __syncthreads();
             // A4: every column's pseudo-posterior, decision and q
@@ -317,43 +417,31 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
                 if (!active[w]) continue;
                 const uint32_t gc = cg[j];
                 const int cs = int(gc & 0xffffu), dv = int(gc >> 16);
-                const float *pf = prow(w, j);
                 const float *R = Rr(w);
-                int g = 0;
-                double pv[Q], acc[Q];
+                float rv[DVM][Q];
+                int es[DVM];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    pv[q] = pf[q];
-                    acc[q] = pv[q];
-                }
-                for (int d = 0; d < dv; ++d) {
-                    const float *rv = R + size_t(cedge[cs + d]) * Q;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) acc[q] *= double(rv[q]);
-                }
-                if (!normalise_q<Q>(acc)) ++g;
-                const int k1 = ck[j];
-                if (a.wantQ && k1 > 0)
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) Qp(w)[size_t(k1 - 1) * Q + q] = float(acc[q]);
-                Xh(w)[j] = uint8_t(clip_q<Q>(acc));
-                for (int d = 0; d < dv; ++d) {
-                    double qv[Q];
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) qv[q] = pv[q];
-                    for (int d2 = 0; d2 < dv; ++d2) {
-                        if (d2 == d) continue;
-                        const float *rv = R + size_t(cedge[cs + d2]) * Q;
-#pragma unroll
-                        for (int q = 0; q < Q; ++q) qv[q] *= double(rv[q]);
+                for (int d = 0; d < DVM; ++d)
+                    if (d < dv) {
+                        es[d] = cedge[cs + d];
+                        lds_vec<Q>(R + size_t(es[d]) * Q, rv[d]);
                     }
-                    if (!normalise_q<Q>(qv)) ++g;
-                    const int e = cedge[cs + d];
-                    const uint8_t *mh = mul + eg_h(eg[e]) * Q;
-                    float *dst = Qm(w) + size_t(e) * Q;
+                float pf[Q];
+                lds_vec<Q>(prow(w, j), pf);
+                double pv[Q];
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) dst[mh[q]] = float(qv[q]);
-                }
+                for (int q = 0; q < Q; ++q) pv[q] = pf[q];
+                int g = 0;
+                const int k1 = ck[j];
+                posterior_step<P, DVM>(rv, dv, pv, a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q : nullptr,
+                                       Xh(w) + j, &g);
+#pragma unroll
+                for (int d = 0; d < DVM; ++d)
+                    if (d < dv) {
+                        int hp[Q];
+                        mul_row<Q>(mul, eg_h(eg[es[d]]), hp);
+                        edge_q_step<P, DVM>(rv, dv, pv, d, Qm(w) + size_t(es[d]) * Q, hp, &g);
+                    }
                 if (g) atomicAdd(&gcount[w], g);
             }
             __syncthreads();
@@ -364,6 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
             // many columns as the threads cover.
             const uint16_t *lcol = reinterpret_cast<const uint16_t *>(lds + ly.lcol);
             const uint16_t *lptr = reinterpret_cast<const uint16_t *>(lds + ly.lptr);
+            const uint32_t *pe = reinterpret_cast<const uint32_t *>(lds + ly.pe);
             float *rsh = reinterpret_cast<float *>(lds + ly.rsh);
             const int per = fw * a.rs;
             const int cw = kThreads / per;
@@ -372,59 +461,39 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
                 const int p0 = lptr[l], p1 = lptr[l + 1];
                 for (int c0 = p0; c0 < p1; c0 += cw) {
                     const int nc = min(cw, p1 - c0);
-                    const bool live = tid < nc * per && active[w] != 0;
-                    int j = 0, cs = 0, dv = 0;
-                    if (live) {
-                        j = lcol[c0 + col];
-                        const uint32_t gc = cg[j];
-                        cs = int(gc & 0xffffu);
-                        dv = int(gc >> 16);
-                    }
+                    const bool in = tid < nc * per;
+                    const int p = c0 + (in ? col : 0);
+                    const uint32_t pw = pe[size_t(p) * a.rs + d];
+                    const int e = int(pw & 0xffffu), dv = int(pw >> 16);
+                    const bool live = in && active[w] != 0;
                     if (live && d < dv) {
-                        const int e = cedge[cs + d];
                         const uint32_t ge = eg[e];
-                        edge_r<P>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul + eg_hinv(ge) * Q,
-                                  rsh + size_t(tid) * Q);
+                        edge_r<P, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge),
+                                       rsh + size_t(tid) * Q);
                     }
                     __syncthreads();
                     if (live && (d < dv || d == 0)) {
-                        const float *pf = prow(w, j);
-                        const float *rc = rsh + size_t(tid - d) * Q;  // the column's r, slot by slot
-                        int g = 0;
+                        const int j = lcol[p];
+                        float rv[DVM][Q];
+#pragma unroll
+                        for (int d2 = 0; d2 < DVM; ++d2)
+                            if (d2 < dv) lds_vec<Q>(rsh + size_t(tid - d + d2) * Q, rv[d2]);
+                        float pf[Q];
+                        lds_vec<Q>(prow(w, j), pf);
                         double pv[Q];
 #pragma unroll
                         for (int q = 0; q < Q; ++q) pv[q] = pf[q];
+                        int g = 0;
                         if (d == 0) {
-                            // A4/A5: pseudo-posterior (Eq. (5)) and decision
-                            double acc[Q];
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) acc[q] = pv[q];
-                            for (int d2 = 0; d2 < dv; ++d2)
-#pragma unroll
-                                for (int q = 0; q < Q; ++q) acc[q] *= double(rc[size_t(d2) * Q + q]);
-                            if (!normalise_q<Q>(acc)) ++g;
                             const int k1 = ck[j];
-                            if (a.wantQ && k1 > 0)
-#pragma unroll
-                                for (int q = 0; q < Q; ++q) Qp(w)[size_t(k1 - 1) * Q + q] = float(acc[q]);
-                            Xh(w)[j] = uint8_t(clip_q<Q>(acc));
+                            posterior_step<P, DVM>(rv, dv, pv,
+                                                   a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q : nullptr,
+                                                   Xh(w) + j, &g);
                         }
                         if (d < dv) {
-                            // Eq. (4) for this slot's edge
-                            double qv[Q];
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) qv[q] = pv[q];
-                            for (int d2 = 0; d2 < dv; ++d2) {
-                                if (d2 == d) continue;
-#pragma unroll
-                                for (int q = 0; q < Q; ++q) qv[q] *= double(rc[size_t(d2) * Q + q]);
-                            }
-                            if (!normalise_q<Q>(qv)) ++g;
-                            const int e = cedge[cs + d];
-                            const uint8_t *mh = mul + eg_h(eg[e]) * Q;
-                            float *dst = Qm(w) + size_t(e) * Q;
-#pragma unroll
-                            for (int q = 0; q < Q; ++q) dst[mh[q]] = float(qv[q]);
+                            int hp[Q];
+                            mul_row<Q>(mul, eg_h(eg[e]), hp);
+                            edge_q_step<P, DVM>(rv, dv, pv, d, Qm(w) + size_t(e) * Q, hp, &g);
                         }
                         if (g) atomicAdd(&gcount[w], g);
                     }
