@@ -37,7 +37,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KINDS = {"k_init": "init", "k_check": "check", "k_variable": "variable", "k_sequential": "sequential",
          "k_sus_level": "sus_level", "k_sus_run": "sus_run", "k_syndrome": "syndrome", "k_retire": "retire", "k_markov": "markov",
          "k_out_xhat": "output", "k_out_vectors": "output", "k_tiles": "tiles", "k_state_init": "state_init",
-         "k_move_frames": "compact"}
+         "k_move_frames": "compact", "k_onchip": "onchip"}
 
 
 def source_hash() -> str:
