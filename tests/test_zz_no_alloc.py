@@ -58,6 +58,27 @@ def test_noalloc_equals_decode_batch_twice(gfbp, schedule):
         assert (b["converged"] == 1).mean() > 0.5
 
 
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_noalloc_small_code_in_lds_twice(gfbp, schedule):
+    """A code small enough for the whole decode in LDS (GF(4) N = 504): the
+    no-allocation entry, on the static scratch, equals the allocating one,
+    twice, the second call smaller."""
+    import torch
+
+    code, enc = wl.regular_code(504, 3, 6, 4, seed=107)
+    dcode = gfbp.DeviceCode(code)
+    for F, seed in ((700, 108), (130, 109)):
+        fr = wl.make_frames(code, enc, F, seed, "bsc", 0.07)
+        dfr = gfbp.frames_to_device(fr)
+        ref = _host(gfbp.decode_batch(dcode, dfr, schedule=schedule, max_iter=80))
+        torch.cuda.synchronize()
+        got = _host(gfbp.decode_batch_noalloc([dcode], dfr, _outputs(torch, F, code.n), schedule=schedule,
+                                              max_iter=80))
+        for k in ("xhat", "iters", "converged", "guards"):
+            assert np.array_equal(ref[k], got[k]), f"F={F} {k}"
+        assert (got["converged"] == 1).mean() > 0.5
+
+
 def test_noalloc_multi_code_twice_and_refusal(gfbp):
     """A batch over two codes of different fields (the no-allocation entry
     takes the persistent kernels, run one after the other on the stream,
