@@ -825,73 +825,12 @@ bool onchip_allowed(const gfbp_code *code, const gfbp_batch *b, const gfbp_resul
 // the four frames per workgroup were faster (137 against 220 us per
 // iteration).
 onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int limit) {
-    onchip::Layout ly{};
-    const size_t q = size_t(code->info.q), E = size_t(code->info.n_edges), n = size_t(code->info.n),
-                 m = size_t(code->info.m), K = size_t(code->info.n_info);
     const bool pus = b->schedule == GFBP_PUS;
-    const bool prior_on = b->prior != GFBP_PRIOR_UNIFORM && K > 0;
-    const bool markov = b->prior == GFBP_PRIOR_MARKOV && K > 0;
-    size_t off = 0;
-    auto take = [&](size_t bytes, bool on) -> int {
-        if (!on) return -1;
-        const size_t o = off;
-        off += (bytes + 15) & ~size_t(15);
-        return int(std::min<size_t>(o, size_t(1) << 30));
-    };
-    ly.qm = take(E * q * 4, true);
-    ly.r = take(E * q * 4, pus);
-    ly.l = take(n * q * 4, true);
-    ly.pr = take(K * q * 4, prior_on);
-    ly.qp = take(K * q * 4, markov);
-    ly.xh = take(n, true);
-    ly.z = take(m, true);
-    const size_t frame = off;
-    // the shared part, offsets from its start
-    off = 0;
-    const int o_mul = take(q * q, true);
-    const int o_flags = take(size_t(onchip::F_NFLAGS) * onchip::kMaxFW * 4, true);
-    const int o_rsh = take(size_t(onchip::kThreads) * q * 4, !pus);
-    const int o_eg = take(E * 4, true);
-    const int o_erow = take(E * 2, true);
-    const int o_ecol = take(E * 2, true);
-    const int o_cedge = take(E * 2, true);
-    const int o_cg = take(n * 4, true);
-    const int o_ck = take(n * 2, true);
-    const int o_rrow = take(m * 4, true);
-    const int o_kcol = take(K * 2, true);
-    const int o_lcol = take(n * 2, !pus);
-    const int o_lptr = take(code->lv[0].ptr.size() * 2, !pus);
-    const int o_pe = take(n * size_t(std::max(1, code->info.max_col_degree)) * 4, !pus);
-    const int o_mk = take((4 + q + q * q) * 4, markov);
-    const size_t shared = off;
-    const size_t lim = size_t(std::max(0, limit));
-    int fw = 0;
-    for (int k = onchip::kMaxFW; k >= 1 && fw == 0; --k)
-        if (size_t(k) * frame + shared <= lim / 2) fw = k;
-    if (fw == 0 && frame + shared <= lim) fw = 1;
-    fw = std::min(fw, std::max(1, b->n_frames));
-    if (fw == 0) return onchip::Layout{};
-    ly.fw = fw;
-    ly.frame = int(frame);
-    const int base = int(size_t(fw) * frame);
-    auto at = [&](int o) { return o < 0 ? -1 : base + o; };
-    ly.mul = at(o_mul);
-    ly.flags = at(o_flags);
-    ly.rsh = at(o_rsh);
-    ly.eg = at(o_eg);
-    ly.erow = at(o_erow);
-    ly.ecol = at(o_ecol);
-    ly.cedge = at(o_cedge);
-    ly.cg = at(o_cg);
-    ly.ck = at(o_ck);
-    ly.rrow = at(o_rrow);
-    ly.kcol = at(o_kcol);
-    ly.lcol = at(o_lcol);
-    ly.lptr = at(o_lptr);
-    ly.pe = at(o_pe);
-    ly.mk = at(o_mk);
-    ly.total = int(size_t(fw) * frame + shared);
-    return ly;
+    const int K = code->info.n_info;
+    return onchip_layout_for(code->info.q, code->info.n_edges, code->info.n, code->info.m, K,
+                             code->info.max_col_degree, int(code->lv[0].ptr.size()) - 1, pus,
+                             b->prior != GFBP_PRIOR_UNIFORM && K > 0, b->prior == GFBP_PRIOR_MARKOV && K > 0,
+                             b->n_frames, limit);
 }
 
 template <int P>

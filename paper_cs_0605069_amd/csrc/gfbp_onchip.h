@@ -36,22 +36,12 @@
 namespace gfbp {
 namespace onchip {
 
-constexpr int kThreads = 256;
-constexpr int kMaxFW = 4;   // frames per workgroup, at most
-constexpr int kMaxP = 3;    // q <= 8: a thread's vectors stay in registers
+constexpr int kThreads = kOnchipThreads;
+constexpr int kMaxFW = kOnchipMaxFW;  // frames per workgroup, at most
+constexpr int kMaxP = 3;              // q <= 8: a thread's vectors stay in registers
 
-// Byte offsets of the LDS arrays (in a frame block, or from the start of LDS
-// for the shared part); computed on the host (layout()).
-struct Layout {
-    int fw;                          // frames per workgroup
-    int frame;                       // bytes per frame block (16-byte multiple)
-    int qm, r, l, pr, qp, xh, z;     // offsets within a frame block (-1: absent)
-    int mul, flags, rsh;             // shared part (rsh -1 for PUS)
-    int eg, erow, ecol, cedge, cg, ck, rrow, kcol, lcol, lptr;  // the graph (lcol, lptr: SUS)
-    int pe;                          // SUS: [n][rs] u32, the edge of each (position, slot) | degree << 16
-    int mk;                          // Markov source: shape [4], pi [q], M [q][q] floats (-1: none)
-    int total;                       // bytes of LDS per workgroup
-};
+// Byte offsets of the LDS arrays, computed on the host (onchip_layout_for).
+using Layout = OnchipLayout;
 
 // One edge's word of the packed graph.
 __device__ __forceinline__ uint32_t pack_edge(int rs, int dc, int self, int h, int hinv) {
@@ -66,6 +56,7 @@ __device__ __forceinline__ int eg_hinv(uint32_t w) { return int(w >> 29); }
 
 // Per-frame flags in the shared part: int32 [kMaxFW] each.
 enum { F_ACTIVE = 0, F_UNSAT = 1, F_GUARDS = 2, F_ITERS = 3, F_CONV = 4, F_NFLAGS = 5 };
+static_assert(F_NFLAGS == kOnchipFlags, "the layout's flag words");
 
 struct Args {
     DevCode c;

@@ -262,4 +262,94 @@ inline gfbp_status build_plan(const gfbp_code_desc *d, CodePlan &pl, std::string
     return GFBP_OK;
 }
 
+// LDS layout of a whole decode in LDS (gfbp_onchip.h): byte offsets of every
+// array, in a frame block (qm .. z) or from the start of LDS (mul .. mk);
+// -1 for an array the decode does not use.  fw = 0: one frame does not fit.
+struct OnchipLayout {
+    int fw;                          // frames per workgroup
+    int frame;                       // bytes per frame block (16-byte multiple)
+    int qm, r, l, pr, qp, xh, z;     // frame block: Qm [E][q], R [E][q] (PUS), L [n][q], Pr [K][q] (prior),
+                                     // Qp [K][q] (Markov) floats; xh [n], z [m] bytes
+    int mul, flags, rsh;             // the field table [q][q]; frame flags; SUS r scratch [threads][q]
+    int eg, erow, ecol, cedge, cg, ck, rrow, kcol, lcol, lptr;  // the packed graph (lcol, lptr: SUS)
+    int pe;                          // SUS: [n][rs] u32, the edge of each (position, slot) | degree << 16
+    int mk;                          // Markov source: shape [4], pi [q], M [q][q] floats
+    int total;                       // bytes of LDS per workgroup
+};
+
+constexpr int kOnchipThreads = 256;
+constexpr int kOnchipMaxFW = 4;
+constexpr int kOnchipFlags = 5;  // int32 [kOnchipMaxFW] each: active, unsat, guards, iterations, converged
+
+// The layout for a code (q, E edges, n columns, m rows, K source symbols,
+// column degree up to max_dv, nlev SUS levels), a schedule and prior, a batch
+// of `frames` frames and `limit` bytes of LDS per workgroup.  Frames per
+// workgroup: as many (up to kOnchipMaxFW) as fit in half the limit (two
+// workgroups per compute unit), else one if one fits in all of it.
+inline OnchipLayout onchip_layout_for(int q_, int E_, int n_, int m_, int K_, int max_dv, int nlev, bool pus,
+                                      bool prior_on, bool markov, int frames, int limit) {
+    OnchipLayout ly{};
+    const size_t q = size_t(q_), E = size_t(E_), n = size_t(n_), m = size_t(m_), K = size_t(K_);
+    size_t off = 0;
+    auto take = [&](size_t bytes, bool on) -> int {
+        if (!on) return -1;
+        const size_t o = off;
+        off += (bytes + 15) & ~size_t(15);
+        return int(std::min<size_t>(o, size_t(1) << 30));
+    };
+    ly.qm = take(E * q * 4, true);
+    ly.r = take(E * q * 4, pus);
+    ly.l = take(n * q * 4, true);
+    ly.pr = take(K * q * 4, prior_on);
+    ly.qp = take(K * q * 4, markov);
+    ly.xh = take(n, true);
+    ly.z = take(m, true);
+    const size_t frame = off;
+    off = 0;  // the shared part, offsets from its start
+    const int o_mul = take(q * q, true);
+    const int o_flags = take(size_t(kOnchipFlags) * kOnchipMaxFW * 4, true);
+    const int o_rsh = take(size_t(kOnchipThreads) * q * 4, !pus);
+    const int o_eg = take(E * 4, true);
+    const int o_erow = take(E * 2, true);
+    const int o_ecol = take(E * 2, true);
+    const int o_cedge = take(E * 2, true);
+    const int o_cg = take(n * 4, true);
+    const int o_ck = take(n * 2, true);
+    const int o_rrow = take(m * 4, true);
+    const int o_kcol = take(K * 2, true);
+    const int o_lcol = take(n * 2, !pus);
+    const int o_lptr = take((size_t(std::max(0, nlev)) + 1) * 2, !pus);
+    const int o_pe = take(n * size_t(std::max(1, max_dv)) * 4, !pus);
+    const int o_mk = take((4 + q + q * q) * 4, markov);
+    const size_t shared = off;
+    const size_t lim = size_t(std::max(0, limit));
+    int fw = 0;
+    for (int k = kOnchipMaxFW; k >= 1 && fw == 0; --k)
+        if (size_t(k) * frame + shared <= lim / 2) fw = k;
+    if (fw == 0 && frame + shared <= lim) fw = 1;
+    fw = std::min(fw, std::max(1, frames));
+    if (fw == 0) return OnchipLayout{};
+    ly.fw = fw;
+    ly.frame = int(frame);
+    const int base = int(size_t(fw) * frame);
+    auto at = [&](int o) { return o < 0 ? -1 : base + o; };
+    ly.mul = at(o_mul);
+    ly.flags = at(o_flags);
+    ly.rsh = at(o_rsh);
+    ly.eg = at(o_eg);
+    ly.erow = at(o_erow);
+    ly.ecol = at(o_ecol);
+    ly.cedge = at(o_cedge);
+    ly.cg = at(o_cg);
+    ly.ck = at(o_ck);
+    ly.rrow = at(o_rrow);
+    ly.kcol = at(o_kcol);
+    ly.lcol = at(o_lcol);
+    ly.lptr = at(o_lptr);
+    ly.pe = at(o_pe);
+    ly.mk = at(o_mk);
+    ly.total = int(size_t(fw) * frame + shared);
+    return ly;
+}
+
 }  // namespace gfbp

@@ -6,7 +6,9 @@
 // after every earlier-visited column it shares a check with (and, in the
 // second levelisation, after its earlier-visited chain neighbours), and the
 // records must describe each column's edges; a malformed one must be refused.
+// Also the LDS layout of the whole decode in LDS over random code shapes.
 // Prints "ok <codes checked>" and exits 0, or names the failure and exits 1.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <set>
@@ -160,11 +162,78 @@ static bool check_refusals(int code_id) {
     return true;
 }
 
+// The LDS layout of the whole decode in LDS: every array the decode uses
+// lies inside the workgroup's bytes, 16-byte aligned, apart from every other;
+// the total fits the limit; the frames per workgroup are the most that fit
+// in half the limit (at most four, at most the batch), else one if one fits
+// at all, else none.
+static bool check_onchip_layout(int code_id) {
+    const int q = 2 << (rnd() % 3);
+    const int n = 8 + int(rnd() % 3000), m = 4 + int(rnd() % (n / 2 + 1)), K = int(rnd() % (n + 1));
+    const int max_dv = 1 + int(rnd() % 8), E = n * (1 + int(rnd() % max_dv)), nlev = 1 + int(rnd() % n);
+    const bool pus = rnd() % 2, prior_on = rnd() % 2, markov = prior_on && (rnd() % 2);
+    const int frames = 1 + int(rnd() % 3000), limit = (rnd() % 2) ? 163840 : 65536;
+    const OnchipLayout ly = onchip_layout_for(q, E, n, m, K, max_dv, nlev, pus, prior_on, markov, frames, limit);
+    // the arrays and their sizes, restated from the decode's use of them
+    struct Arr {
+        int off;
+        size_t bytes;
+        bool used;
+        bool per_frame;
+    };
+    const size_t Q = size_t(q);
+    const Arr arrs[] = {
+        {ly.qm, E * Q * 4, true, true},   {ly.r, E * Q * 4, pus, true},        {ly.l, n * Q * 4, true, true},
+        {ly.pr, K * Q * 4, prior_on, true}, {ly.qp, K * Q * 4, markov, true}, {ly.xh, size_t(n), true, true},
+        {ly.z, size_t(m), true, true},     {ly.mul, Q * Q, true, false},      {ly.flags, 5 * 4 * 4, true, false},
+        {ly.rsh, 256 * Q * 4, !pus, false}, {ly.eg, size_t(E) * 4, true, false}, {ly.erow, size_t(E) * 2, true, false},
+        {ly.ecol, size_t(E) * 2, true, false}, {ly.cedge, size_t(E) * 2, true, false},
+        {ly.cg, size_t(n) * 4, true, false}, {ly.ck, size_t(n) * 2, true, false}, {ly.rrow, size_t(m) * 4, true, false},
+        {ly.kcol, size_t(K) * 2, true, false}, {ly.lcol, size_t(n) * 2, !pus, false},
+        {ly.lptr, size_t(nlev + 1) * 2, !pus, false}, {ly.pe, size_t(n) * max_dv * 4, !pus, false},
+        {ly.mk, (4 + Q + Q * Q) * 4, markov, false}};
+    size_t frame = 0, shared = 0;
+    for (const Arr &a : arrs) (a.per_frame ? frame : shared) += a.used ? (a.bytes + 15) / 16 * 16 : 0;
+    const size_t one = frame + shared;
+    if (ly.fw == 0) {
+        CHECK(one > size_t(limit), "no frames per workgroup although one frame fits");
+        return true;
+    }
+    CHECK(ly.fw >= 1 && ly.fw <= 4 && ly.fw <= frames, "frames per workgroup out of range");
+    CHECK(size_t(ly.frame) == frame, "frame block size");
+    CHECK(size_t(ly.total) == ly.fw * frame + shared && ly.total <= limit, "total bytes");
+    const int best_half = [&] {
+        for (int k = 4; k >= 1; --k)
+            if (k * frame + shared <= size_t(limit) / 2) return k;
+        return 0;
+    }();
+    CHECK(ly.fw == std::min(best_half > 0 ? best_half : 1, frames), "frames per workgroup not the most that fit");
+    // every used array inside the workgroup's bytes, aligned, and apart
+    std::vector<std::pair<size_t, size_t>> spans;
+    for (const Arr &a : arrs) {
+        if (!a.used) {
+            CHECK(a.off == -1, "an unused array has an offset");
+            continue;
+        }
+        CHECK(a.off >= 0 && a.off % 16 == 0, "array offset negative or unaligned");
+        for (int w = 0; w < (a.per_frame ? ly.fw : 1); ++w) {
+            const size_t b0 = size_t(a.off) + (a.per_frame ? size_t(w) * frame : 0);
+            CHECK(b0 + a.bytes <= size_t(ly.total), "array beyond the workgroup's LDS");
+            if (a.bytes) spans.push_back({b0, b0 + a.bytes});
+        }
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k) CHECK(spans[k].first >= spans[k - 1].second, "arrays overlap");
+    return true;
+}
+
 int main(int argc, char **argv) {
     const int count = argc > 1 ? std::atoi(argv[1]) : 400;
     if (!check_refusals(-1)) return 1;
     for (int k = 0; k < count; ++k)
         if (!check_valid(k)) return 1;
+    for (int k = 0; k < 4 * count; ++k)
+        if (!check_onchip_layout(k)) return 1;
     std::printf("ok %d\n", count);
     return 0;
 }
