@@ -91,6 +91,28 @@ def test_onchip_equals_tiled(gfbp, q, n, channel, prior, syn, schedule, frames):
         assert np.array_equal(a[k], b[k]), f"fixed iterations, {k}"
 
 
+@pytest.mark.parametrize("q,seed", [(2, 0), (4, 1), (4, 2)])
+def test_onchip_irregular_codes_equal_tiled(gfbp, q, seed):
+    """Irregular codes beyond the small degree class (rows up to 16 entries,
+    columns up to 5), with a column in no check, syndromes and a Markov
+    prior: bitwise the tiled decode."""
+    from tests.test_gpu_parity import _random_irregular_code
+
+    rng = np.random.default_rng([0x0C41, seed])
+    n = int(rng.integers(60, 200))
+    base = _random_irregular_code(rng, q, n, int(n * rng.uniform(0.4, 0.7)))
+    code = wl.Code(q, n + 1, base.m, base.row_ptr, base.col, base.coef, poly=base.poly,
+                   n_info=base.n_info)  # column n: in no check
+    M = 0.5 * wl.self_transition_matrix(q, 0.75) + 0.5 * rng.dirichlet(np.ones(q), size=q)
+    fr = wl.make_coset_frames(code, 90, 720 + seed, "biawgn", 0.75, source="markov", markov=M)
+    kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M))
+    for sch in ("pus", "sus"):
+        a, b, prof = _both(gfbp, code, gfbp.frames_to_device(fr), sch, max_iter=40, **kw)
+        assert prof["onchip"]["launches"] == 1
+        for k in ("xhat", "iters", "converged", "guards"):
+            assert np.array_equal(a[k], b[k]), f"{sch} {k}"
+
+
 def test_guard_events_equal_tiled(gfbp):
     """All-zero likelihood rows (normalisation guards) counted alike."""
     import torch
