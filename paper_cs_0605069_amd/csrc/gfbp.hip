@@ -1995,7 +1995,7 @@ extern "C" {
 
 const char *gfbp_last_error(void) { return g_err.c_str(); }
 
-const char *gfbp_version(void) { return "gfbp 0.5 (gfx950)"; }
+const char *gfbp_version(void) { return "gfbp 0.6 (gfx950)"; }
 
 gfbp_status gfbp_stream_copy_rate(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *rate) {
     if (!dst || !src || !rate) return fail(GFBP_EINVAL, "null argument");

@@ -29,7 +29,8 @@
 // its row, its column and the edges of each column in column order (16 bits
 // each); per column its first edge and degree, and its source symbol + 1;
 // per row its first edge and degree; per source symbol its column; for SUS
-// the columns in level order and the first position of each level.
+// the columns in level order, the first position of each level and, per
+// (position, edge slot), the slot's edge and the column's degree.
 #pragma once
 #include "gfbp_tiled.h"
 
