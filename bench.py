@@ -310,7 +310,8 @@ def uneven_leg(gfbp, torch) -> dict:
     {4, 16, 64}, n 256-8000, BSC / BEC / BI-AWGN per frame at Eb/N0 ~ U[1, 2]
     dB), each code's kernel shape tuned on its frames, then the whole batch in
     one gfbp_decode_batch call per schedule (code by code, the codes
-    concurrent), max 100 iterations; best of two timed calls (not part of
+    concurrent), max 100 iterations; best of two timed calls, and each
+    kernel's algorithmic rate from one more, profiled call (not part of
     `value`)."""
     from paper_cs_0605069_amd.batching import batch_inputs
 
@@ -337,6 +338,18 @@ def uneven_leg(gfbp, torch) -> dict:
                 best, its = dt, o["iters"].cpu().numpy()
         out[s] = {"seconds": best, "frames_per_s": len(index) / best,
                   "edge_q_per_s": float((its * eq_frame[index]).sum()) / best, "mean_iters": float(its.mean())}
+        # the kernels of one more call, each launch timed by the library (HIP
+        # events on the decode streams; the codes' kernels overlap, so these
+        # are per-kernel rates, not shares of the wall time above)
+        gfbp.profile_reset()
+        gfbp.profile_enable(True)
+        gfbp.decode_multi(dcodes, index, dfr, schedule=s, max_iter=100)
+        torch.cuda.synchronize()
+        gfbp.profile_enable(False)
+        prof = gfbp.profile_read()
+        out[s]["kernels"] = {k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"] * 1e3,
+                                 "GBps_algorithmic": v["algo_bytes"] / (v["total_ms"] / 1e3) / 1e9}
+                             for k, v in prof.items() if v["launches"] and v["total_ms"]}
         print(f"# uneven batch {s}: {best:.3f} s", file=sys.stderr, flush=True)
     return out
 
