@@ -206,6 +206,7 @@ struct BatchAux {
     int32_t *movers;  // [Fp] compaction: running slots at or above it
     uint8_t *pending; // [Fp] finished frame whose decision is not yet written out
     float *mshape;    // [4] shape of the Markov matrix (k_markov_shape)
+    float *qp2;       // PUS with a Markov source: the second pseudo-posterior buffer (iterations alternate)
 };
 
 __global__ void k_state_init(DevState s, BatchAux a) {
@@ -491,6 +492,11 @@ struct TiledLaunch {
         launch((tiled::k_variable<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c,
                            s, prior_on, wantQ, sn);
     }
+    static void variable_markov(hipStream_t st, const DevCode &c, const DevState &s, int prior_on, int wantQ,
+                                Snap sn, const SweepPrior &sp) {
+        launch((tiled::k_variable_markov<P, LG, DVM>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s,
+               prior_on, wantQ, sn, sp);
+    }
     static void sus_level(hipStream_t st, const DevCode &c, const DevState &s, const uint8_t *z, int prior_on, int wantQ,
                           Snap sn, const SweepPrior &sp, const SusRec *recs, int nc) {
         const dim3 g(std::max(1u, unsigned(nc) * unsigned(s.nb)));
@@ -588,6 +594,10 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;     // ... refreshed by Eq. (7)
     // SUS priors assigned during the sweep (from iteration 2)
     const int insweep = markov && b->schedule == GFBP_SUS && (b->options & GFBP_OPT_PRIOR_IN_SWEEP);
+    // PUS: the priors formed in the variable step from the previous
+    // iteration's pseudo-posteriors, the two buffers alternating
+    const bool fused = markov && b->schedule == GFBP_PUS;
+    float *const qbuf[2] = {s.Qp, a.qp2};
     // moving frames keeps running frames in whole tiles; posteriors and
     // snapshots are read by slot at the end, so they keep frames in place
     const bool tracing = out->trace && b->truth;
@@ -656,13 +666,23 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         const bool snap_now = (t == out->snap_iter);
         Snap sn{snap_now ? out->snap_q : nullptr, snap_now ? out->snap_r : nullptr};
         const int wantQ = needQ || (snap_now && out->snap_Q);
+        if (fused) {
+            s.Qp = qbuf[t & 1];
+            s.Qprev = t >= 2 ? qbuf[(t - 1) & 1] : nullptr;
+        }
         if (b->schedule == GFBP_PUS) {
             tr.begin();
             K::check(st, c, s, z, sn);
             tr.end_iter(K_CHECK, bpf.check, eq_frame, t);
             tr.begin();
-            K::variable(st, c, s, prior_on, wantQ, sn);
-            tr.end_iter(K_VARIABLE, bpf.variable, eq_frame, t);
+            if (fused) {
+                const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, t >= 2};
+                K::variable_markov(st, c, s, prior_on, wantQ, sn, sp);
+            } else {
+                K::variable(st, c, s, prior_on, wantQ, sn);
+            }
+            // with the priors formed here: two neighbours' Q and L in place of Pr
+            tr.end_iter(K_VARIABLE, bpf.variable + (fused && t >= 2 ? 8.0 * Q * c.n_info : 0.0), eq_frame, t);
         } else if (b->options & GFBP_OPT_SUS_STRICT) {
             const SweepPrior sp{b->markov_M, b->markov_pi, a.mshape, insweep && t >= 2};
             tr.begin();
@@ -699,7 +719,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
         s.act = s.tiles + size_t(t & 1) * ntiles;
         s.nact = cnt_dev + 1;
         s.nb = int(known_tiles);  // counts of iteration t-1 (or the first list): a bound on the list of t
-        if (markov && !insweep) {
+        if (markov && !insweep && !fused) {
             tr.begin();
             K::markov(st, c, s, b->markov_M, b->markov_pi, a.mshape);
             tr.end_iter(K_MARKOV, bpf.markov, 0, t + 1);
@@ -723,7 +743,7 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
                 launch(k_emit, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, s, a, a.holes, int(nm), c.n,
                        out->xhat);
                 const int W = Q >= 4 ? 4 : 2;
-                const int Kq = insweep ? c.n : 0;  // the next sweep's priors read the source columns' Q
+                const int Kq = insweep || fused ? c.n : 0;  // the next step's priors read the source columns' Q
                 const size_t per = size_t(c.E + c.n + Kp + Kq) * Q;
                 const unsigned chunks = unsigned((per / W + 255) / 256);
                 tr.begin();
@@ -1143,8 +1163,8 @@ bool session_bind(gfbp_session *ss) {
 
 // Workspace carving, shared by size query and decode.
 struct Carve {
-    size_t Qm, R, L, Pr, Qp, xh, unsat, active, count, tiles, guards, orig, iters, conv, z, holes, movers, pending,
-        mshape, total;
+    size_t Qm, R, L, Pr, Qp, Qp2, xh, unsat, active, count, tiles, guards, orig, iters, conv, z, holes, movers,
+        pending, mshape, total;
 };
 
 Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
@@ -1158,6 +1178,7 @@ Carve carve(const gfbp_code *code, int F_, int schedule, int prior) {
     c.L = take(n * F * Q * 4);
     c.Pr = take(prior != GFBP_PRIOR_UNIFORM ? K * F * Q * 4 : 0);
     c.Qp = take(n * F * Q * 4);
+    c.Qp2 = take(schedule == GFBP_PUS && prior == GFBP_PRIOR_MARKOV ? n * F * Q * 4 : 0);
     c.xh = take(n * F);
     c.unsat = take(size_t(F_) * 4);
     c.active = take(size_t(F_));
@@ -1635,6 +1656,7 @@ gfbp_status decode_plain(const gfbp_code *code, const gfbp_batch *b, gfbp_result
     a.movers = reinterpret_cast<int32_t *>(w + cv.movers);
     a.pending = reinterpret_cast<uint8_t *>(w + cv.pending);
     a.mshape = reinterpret_cast<float *>(w + cv.mshape);
+    a.qp2 = reinterpret_cast<float *>(w + cv.Qp2);
     s.F = F;
     s.Fp = frame_stride(F);
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;

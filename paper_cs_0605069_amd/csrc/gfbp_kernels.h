@@ -46,6 +46,8 @@ struct DevState {
     float *L;         // [n][F][Q] normalised channel likelihoods
     float *Pr;        // [K][F][Q] normalised likelihood x Markov prior (Markov only)
     float *Qp;        // [n][F][Q] pseudo-posteriors (when needed)
+    const float *Qprev;  // PUS with a Markov source: the previous iteration's pseudo-posteriors, read by
+                         // the variable step for Eq. (7) (null: the source priors in Pr are used as they are)
     uint8_t *xh;      // [n][F] decisions
     uint32_t *unsat;  // [F] some check unsatisfied in this iteration
     uint8_t *active;  // [F] frame still iterating

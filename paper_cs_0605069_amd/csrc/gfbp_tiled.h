@@ -554,6 +554,11 @@ __global__ __launch_bounds__(kBlock) void k_check(DevCode c, DevState s, const u
     check_node<P, LG, DCM>(c, s, z, snap, it, perm);
 }
 
+template <int P, int LG>
+__device__ __forceinline__ void markov_prior(const DevCode &c, const DevState &s, const Item &it, int k,
+                                             const float *M, const float *pi, const float *mshape,
+                                             float (&pf)[Geo<P, LG>::EL]);
+
 // The lane's entries of the prior-weighted evidence p_j of column j: the
 // source symbol's prior row when the frame takes a prior, else L_j.
 // frame_prior: the frame takes a prior (frame_prior_of).
@@ -655,9 +660,10 @@ __device__ __forceinline__ void variable_update(const DevCode &c, const DevState
 }
 
 // A4, parallel schedule: column it.node from this iteration's r.
-template <int P, int LG, int DVM>
+template <int P, int LG, int DVM, bool MARKOV_PRIOR = false>
 __device__ __forceinline__ void variable_node(const DevCode &c, const DevState &s, int prior_on, int wantQ,
-                                              const Snap &snap, const Item &it, float *perm) {
+                                              const Snap &snap, const Item &it, float *perm,
+                                              const SweepPrior &sp = SweepPrior{}) {
     using Gm = Geo<P, LG>;
     const int j = it.node;
     const int cs = c.col_ptr[j], dv = c.col_ptr[j + 1] - cs;
@@ -666,7 +672,20 @@ __device__ __forceinline__ void variable_node(const DevCode &c, const DevState &
     for (int d = 0; d < DVM; ++d)
         if (d < dv) ld<Gm::EL>(chunk<P, LG>(s.R, size_t(c.col_edge[cs + d]), s.Fp, it), r[d]);
     float pf[Gm::EL];
-    ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, frame_prior_of(s, it.f, prior_on)), pf);
+    bool assigned = false;
+    if constexpr (MARKOV_PRIOR) {
+        // A7 for source symbol k of this column from the previous iteration's
+        // pseudo-posteriors (the values a separate refresh after that
+        // iteration would have written to Pr)
+        const int k = c.col_chain[j];
+        if (sp.on && s.Qprev && frame_prior_of(s, it.f, prior_on) && k >= 0) {
+            DevState sq = s;
+            sq.Qp = const_cast<float *>(s.Qprev);
+            markov_prior<P, LG>(c, sq, it, k, sp.M, sp.pi, sp.mshape, pf);
+            assigned = true;
+        }
+    }
+    if (!assigned) ld<Gm::EL>(prior_row<P, LG>(c, s, it, j, frame_prior_of(s, it.f, prior_on)), pf);
     variable_update<P, LG, DVM>(c, s, it, j, r, cs, dv, pf, wantQ, snap, perm);
 }
 
@@ -678,6 +697,20 @@ __global__ __launch_bounds__(kBlock) void k_variable(DevCode c, DevState s, int 
     const Item it = item<P, LG>(c.n, s);
     if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
     variable_node<P, LG, DVM>(c, s, prior_on, wantQ, snap, it, perm);
+}
+
+// A4 with the source symbols' Eq. (7) priors formed in the same step (PUS
+// with a Markov source, from the second iteration on): one launch and 8 K q
+// bytes per frame fewer than a separate refresh after each iteration.
+template <int P, int LG, int DVM>
+__global__ __launch_bounds__(kBlock) void k_variable_markov(DevCode c, DevState s, int prior_on, int wantQ,
+                                                            Snap snap, SweepPrior sp) {
+    using Gm = Geo<P, LG>;
+    __shared__ __align__(16) float perm_all[(kBlock / kWave) * Gm::PERM];
+    float *perm = perm_all + (int(threadIdx.x) / kWave) * Gm::PERM;
+    const Item it = item<P, LG>(c.n, s);
+    if (!it.ok || it.f >= s.F || !s.active[it.f]) return;
+    variable_node<P, LG, DVM, true>(c, s, prior_on, wantQ, snap, it, perm, sp);
 }
 
 // The current q of the siblings of edge rec in its row, for the lane's frame:
