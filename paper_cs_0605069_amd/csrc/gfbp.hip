@@ -853,12 +853,28 @@ onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int lim
                              b->n_frames, limit);
 }
 
+// Allows the in-LDS kernel of this code's degree class `bytes` of dynamic
+// LDS (beyond the default bound this must be set per kernel); false (the
+// runtime's error cleared) when the runtime refuses.
+template <int P>
+bool onchip_allow_lds(const gfbp_code *code, int bytes) {
+    const void *kern = small_class(code) ? reinterpret_cast<const void *>(&onchip::k_onchip<P, 6, 4>)
+                                         : reinterpret_cast<const void *>(&onchip::k_onchip<P, kDcMax, kDvMax>);
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
+}
+
+// The whole decode in LDS; *ran false (nothing launched) when the runtime
+// does not allow the kernel its LDS, and the caller takes the tiled kernels.
 template <int P>
 gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
-                       hipStream_t st, int needQ, const onchip::Layout &ly) {
+                       hipStream_t st, int needQ, const onchip::Layout &ly, bool *ran) {
     constexpr int Q = 1 << P;
     const DevCode &c = code->dev;
     const int F = s.F;
+    *ran = onchip_allow_lds<P>(code, ly.total);
+    if (!*ran) return GFBP_OK;
     const unsigned fb = unsigned((F + kBlock - 1) / kBlock);
     const int prior_on = (b->prior != GFBP_PRIOR_UNIFORM) && c.n_info > 0;
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
@@ -917,11 +933,8 @@ gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *
     const double hbm = double(F) * (4.0 * Q * (c.E + c.n + (prior_on ? c.n_info : 0)) + 4.0 +
                                     (b->syndrome ? c.m : 0) + c.n + 9.0);
     // the degree class bounds the rows' siblings and the columns' r-vectors
-    // held in registers; dynamic LDS beyond the default bound must be
-    // allowed per kernel
+    // held in registers
     auto go = [&](auto kern) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  ly.total);
         tr.begin();
         launch(kern, dim3(unsigned((F + ly.fw - 1) / ly.fw)), dim3(onchip::kThreads), size_t(ly.total), st, oa);
     };
@@ -1662,12 +1675,15 @@ gfbp_status decode_plain(const gfbp_code *code, const gfbp_batch *b, gfbp_result
     const int needQ = (b->prior == GFBP_PRIOR_MARKOV) || out->posterior != nullptr;
     if (F > 0 && onchip_allowed(code, b, out)) {
         const onchip::Layout ly = onchip_layout(code, b, lds_limit());
+        bool ran = false;
+        gfbp_status rs = GFBP_OK;
         if (ly.fw > 0) switch (code->info.p) {
-                case 1: return run_onchip<1>(code, b, out, s, a, st, needQ, ly);
-                case 2: return run_onchip<2>(code, b, out, s, a, st, needQ, ly);
-                case 3: return run_onchip<3>(code, b, out, s, a, st, needQ, ly);
+                case 1: rs = run_onchip<1>(code, b, out, s, a, st, needQ, ly, &ran); break;
+                case 2: rs = run_onchip<2>(code, b, out, s, a, st, needQ, ly, &ran); break;
+                case 3: rs = run_onchip<3>(code, b, out, s, a, st, needQ, ly, &ran); break;
                 default: break;
             }
+        if (ran || rs != GFBP_OK) return rs;
     }
     switch (code->info.p) {
         case 1: return run_any<1>(code, b, out, s, a, st, needQ);
