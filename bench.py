@@ -582,7 +582,9 @@ def main():
                   "mean_iters": float(np.mean([r["iters"].mean() for r in rs])),
                   "decode_call_ms_p50": float(np.percentile(ms, 50)), "decode_call_ms_p99": float(np.percentile(ms, 99)),
                   "fer_by_ebn0": {str(r["ebn0"]): round(r["fer"], 4) for r in rs[:len(EBN0)]},
-                  "mean_iters_by_ebn0": {str(r["ebn0"]): round(float(r["iters"].mean()), 3) for r in rs[:len(EBN0)]}}
+                  "mean_iters_by_ebn0": {str(r["ebn0"]): round(float(r["iters"].mean()), 3) for r in rs[:len(EBN0)]},
+                  "decode_call_ms_by_ebn0": {str(eb): round(float(np.mean([r["ms"] for r in rs if r["ebn0"] == eb])), 3)
+                                             for eb in EBN0}}
     if "pus" in per and "sus" in per:
         pi = np.concatenate([r["iters"] for r in rec if r["sched"] == "pus"]).astype(float)
         si = np.concatenate([r["iters"] for r in rec if r["sched"] == "sus"]).astype(float)
