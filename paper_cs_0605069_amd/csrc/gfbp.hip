@@ -594,9 +594,13 @@ gfbp_status run_batch(const gfbp_code *code, const gfbp_batch *b, gfbp_result *o
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;     // ... refreshed by Eq. (7)
     // SUS priors assigned during the sweep (from iteration 2)
     const int insweep = markov && b->schedule == GFBP_SUS && (b->options & GFBP_OPT_PRIOR_IN_SWEEP);
-    // PUS: the priors formed in the variable step from the previous
-    // iteration's pseudo-posteriors, the two buffers alternating
-    const bool fused = markov && b->schedule == GFBP_PUS;
+    // PUS: the priors formed in the next iteration's variable step from the
+    // previous iteration's pseudo-posteriors, the two buffers alternating;
+    // not where posteriors or snapshots are read back (a frame that stopped
+    // earlier keeps its last ones in the buffer of that iteration).  (For SUS
+    // the same inside the level kernels made them slower than the separate
+    // refresh they replaced: GF(8) N = 3000, 1.43e11 -> 1.33e11 edge-q/s.)
+    const bool fused = markov && b->schedule == GFBP_PUS && !out->posterior && out->snap_iter <= 0;
     float *const qbuf[2] = {s.Qp, a.qp2};
     // moving frames keeps running frames in whole tiles; posteriors and
     // snapshots are read by slot at the end, so they keep frames in place

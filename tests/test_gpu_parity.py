@@ -321,6 +321,25 @@ def test_frame_alone_equals_frame_in_batch_and_runs_repeat(gfbp, schedule):
         assert one["iters"][0] == a["iters"][f]
 
 
+@pytest.mark.parametrize("schedule", ["pus", "sus"])
+def test_markov_posteriors_alone_equal_in_batch(gfbp, schedule):
+    """With a Markov source, frames that stop at different iterations: each
+    frame's posterior, decisions and iteration count in the batch equal those
+    of the frame decoded alone (the posterior read back is the frame's own
+    last one)."""
+    q = 16
+    code, enc = wl.regular_code(200, 3, 6, q, seed=27)
+    M = wl.self_transition_matrix(q, 0.7)
+    kw = dict(prior="markov", markov_M=M, markov_pi=wl.stationary(M), max_iter=40, posterior=True)
+    fr = wl.make_frames(code, enc, 60, 28, "bsc", np.linspace(0.03, 0.12, 60), source="markov", markov=M)
+    a = _gpu(gfbp, code, fr, schedule, **kw)
+    assert len(set(a["iters"].tolist())) > 3  # frames stop at different iterations
+    for f in (0, 7, 30, 59):
+        one = _gpu(gfbp, code, fr.subset([f]), schedule, **kw)
+        assert one["iters"][0] == a["iters"][f] and np.array_equal(one["xhat"][0], a["xhat"][f])
+        assert np.array_equal(one["posterior"][0], a["posterior"][f]), f"frame {f}"
+
+
 @pytest.mark.parametrize("schedule,q", [("pus", 8), ("sus", 8), ("sus-in-sweep", 8), ("pus", 2), ("sus", 2)])
 def test_frame_compaction_changes_nothing(gfbp, schedule, q):
     """Moving running frames into finished slots (on by default) gives bitwise
