@@ -239,7 +239,8 @@ typedef struct {
  * H x = z test, retirement and Markov refreshes inside the kernel; HBM only
  * for the initial state and the results), unless posteriors, snapshots,
  * traces, GFBP_OPT_SUS_STRICT or GFBP_OPT_PRIOR_IN_SWEEP are asked for.  Its
- * outputs equal bitwise those of the tiled decode at q entries per lane. */
+ * outputs equal bitwise those of the tiled decode at q entries per lane (PUS)
+ * or two entries per lane (SUS). */
 #define GFBP_OPT_NO_ONCHIP 32
 
 /* Batch decode, SUS with the Markov prior: the prior of each source symbol is

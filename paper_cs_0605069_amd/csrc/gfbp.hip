@@ -860,10 +860,10 @@ onchip::Layout onchip_layout(const gfbp_code *code, const gfbp_batch *b, int lim
 // Allows the in-LDS kernel of this code's degree class `bytes` of dynamic
 // LDS (beyond the default bound this must be set per kernel); false (the
 // runtime's error cleared) when the runtime refuses.
-template <int P>
+template <int P, int LG>
 bool onchip_allow_lds(const gfbp_code *code, int bytes) {
-    const void *kern = small_class(code) ? reinterpret_cast<const void *>(&onchip::k_onchip<P, 6, 4>)
-                                         : reinterpret_cast<const void *>(&onchip::k_onchip<P, kDcMax, kDvMax>);
+    const void *kern = small_class(code) ? reinterpret_cast<const void *>(&onchip::k_onchip<P, LG, 6, 4>)
+                                         : reinterpret_cast<const void *>(&onchip::k_onchip<P, LG, kDcMax, kDvMax>);
     if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess) return true;
     (void)hipGetLastError();
     return false;
@@ -871,24 +871,26 @@ bool onchip_allow_lds(const gfbp_code *code, int bytes) {
 
 // The whole decode in LDS; *ran false (nothing launched) when the runtime
 // does not allow the kernel its LDS, and the caller takes the tiled kernels.
-template <int P>
+template <int P, int LG>
 gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *out, DevState &s, BatchAux &a,
                        hipStream_t st, int needQ, const onchip::Layout &ly, bool *ran) {
     constexpr int Q = 1 << P;
     const DevCode &c = code->dev;
     const int F = s.F;
-    *ran = onchip_allow_lds<P>(code, ly.total);
+    *ran = onchip_allow_lds<P, LG>(code, ly.total);
     if (!*ran) return GFBP_OK;
     const unsigned fb = unsigned((F + kBlock - 1) / kBlock);
     const int prior_on = (b->prior != GFBP_PRIOR_UNIFORM) && c.n_info > 0;
     const int markov = (b->prior == GFBP_PRIOR_MARKOV) && c.n_info > 0;
     Tracer tr(st);
+    constexpr int TF = kWave >> LG;
     launch(k_state_init, dim3(fb), dim3(kBlock), 0, st, s, a);
-    // the initialisation kernel's tile list: every frame, one lane per frame
-    launch(tiled::k_tiles, dim3(1), dim3(1024), 0, st, s.active, F, s.Fp, kWave, s.tiles, s.count + 1);
+    // the initialisation kernel's tile list (every frame), at the in-LDS
+    // kernel's lanes per vector
+    launch(tiled::k_tiles, dim3(1), dim3(1024), 0, st, s.active, F, s.Fp, TF, s.tiles, s.count + 1);
     s.act = s.tiles;
     s.nact = s.count + 1;
-    s.nb = (F + kWave - 1) / kWave;
+    s.nb = (F + TF - 1) / TF;
     if (markov) hipLaunchKernelGGL(tiled::k_markov_shape, dim3(1), dim3(kWave), 0, st, b->markov_M, Q, a.mshape);
     tiled::Chan ch{};
     ch.channel = b->channel;
@@ -904,7 +906,7 @@ gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *
     ch.static_P = b->static_prior;
     ch.chan_of = b->channel_of;
     tr.begin();
-    launch((tiled::k_init<P, 0>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
+    launch((tiled::k_init<P, LG>), dim3(tiled_blocks(c.n, s)), dim3(kBlock), 0, st, c, s, ch);
     tr.end(K_INIT, double(F) * (4.0 * Q * (c.n + c.E) + c.n * 4.0 * P), 0);
     onchip::Args oa{};
     oa.c = c;
@@ -942,8 +944,8 @@ gfbp_status run_onchip(const gfbp_code *code, const gfbp_batch *b, gfbp_result *
         tr.begin();
         launch(kern, dim3(unsigned((F + ly.fw - 1) / ly.fw)), dim3(onchip::kThreads), size_t(ly.total), st, oa);
     };
-    if (small_class(code)) go(onchip::k_onchip<P, 6, 4>);
-    else go(onchip::k_onchip<P, kDcMax, kDvMax>);
+    if (small_class(code)) go(onchip::k_onchip<P, LG, 6, 4>);
+    else go(onchip::k_onchip<P, LG, kDcMax, kDvMax>);
     tr.end(K_ONCHIP, hbm, 0);
     HIP_TRY(hipGetLastError());
     if (tr.on) {
@@ -1681,10 +1683,18 @@ gfbp_status decode_plain(const gfbp_code *code, const gfbp_batch *b, gfbp_result
         const onchip::Layout ly = onchip_layout(code, b, lds_limit());
         bool ran = false;
         gfbp_status rs = GFBP_OK;
+        const bool sus = b->schedule == GFBP_SUS;
         if (ly.fw > 0) switch (code->info.p) {
-                case 1: rs = run_onchip<1>(code, b, out, s, a, st, needQ, ly, &ran); break;
-                case 2: rs = run_onchip<2>(code, b, out, s, a, st, needQ, ly, &ran); break;
-                case 3: rs = run_onchip<3>(code, b, out, s, a, st, needQ, ly, &ran); break;
+                case 1: rs = run_onchip<1, onchip::lanes_log<1>(GFBP_PUS)>(code, b, out, s, a, st, needQ, ly, &ran);
+                    break;  // (one lane per vector either way)
+                case 2:
+                    rs = sus ? run_onchip<2, onchip::lanes_log<2>(GFBP_SUS)>(code, b, out, s, a, st, needQ, ly, &ran)
+                             : run_onchip<2, onchip::lanes_log<2>(GFBP_PUS)>(code, b, out, s, a, st, needQ, ly, &ran);
+                    break;
+                case 3:
+                    rs = sus ? run_onchip<3, onchip::lanes_log<3>(GFBP_SUS)>(code, b, out, s, a, st, needQ, ly, &ran)
+                             : run_onchip<3, onchip::lanes_log<3>(GFBP_PUS)>(code, b, out, s, a, st, needQ, ly, &ran);
+                    break;
                 default: break;
             }
         if (ran || rs != GFBP_OK) return rs;

@@ -11,11 +11,12 @@
 // trips, which is what bounds such codes on the tiled kernels (a few
 // microseconds of work per launch, dozens of launches per SUS iteration).
 //
-// One thread holds a whole q-vector (q <= 8) in registers.  The arithmetic is
-// that of the tiled kernels at one lane per frame (entries per lane = q): the
-// same transforms, products in the same order, the same normalisation and
-// clipping, float32 storage of every message; so the results are bitwise
-// those of the tiled decode at that shape.
+// A q-vector (q <= 8) is held in registers by the lanes of an item (PUS: one
+// lane; SUS: q/2 lanes of two entries), laid out as the tiled kernels lay out
+// a frame's lanes, and the arithmetic is theirs at that shape: the same
+// transforms and lane exchanges, products in the same order, the same
+// normalisation and clipping, float32 storage of every message; so the
+// results are bitwise those of the tiled decode at the same entries per lane.
 //
 // LDS of a workgroup: FW frame blocks, then the shared part.  A frame block
 // holds (floats, [node][a]) Qm [E][q] (weighted domain, as in global memory),
@@ -43,6 +44,17 @@ constexpr int kMaxP = 3;              // q <= 8: a thread's vectors stay in regi
 
 // Byte offsets of the LDS arrays, computed on the host (onchip_layout_for).
 using Layout = OnchipLayout;
+
+// log2 of the lanes holding one vector.  PUS: one lane per vector (every
+// phase has work for all the workgroup's lanes; spreading a vector over more
+// lanes only adds exchanges: GF(4) N = 504, 2048 frames running, 41 against
+// 69 us per iteration).  SUS: two entries per lane (a dependency level has
+// few columns, and the lanes of a vector shorten each one's dependent chain:
+// 10.3 against 11.0 ms for 2000 frames).
+template <int P>
+constexpr int lanes_log(int schedule) {
+    return schedule == GFBP_SUS ? P - 1 : 0;
+}
 
 // One edge's word of the packed graph.
 __device__ __forceinline__ uint32_t pack_edge(int rs, int dc, int self, int h, int hinv) {
@@ -77,45 +89,44 @@ struct Args {
     Layout lay;
 };
 
-template <int Q>
-__device__ __forceinline__ bool normalise_q(double *v) {
+// Lane geometry (that of the tiled kernels): an item (an edge, a column, a
+// source symbol of one frame) is held by G = 2^LG lanes with EL = q/G entries
+// each; a wavefront holds TF = 64/G items, lane = g*TF + item, and lane g
+// holds entries g*EL .. g*EL + EL - 1 of the item's vectors.
+
+// Normalise the item's distributed vector to sum 1 (the tiled kernels'
+// order: each lane's entries, then across the lanes); uniform and false when
+// the sum is zero or not finite.
+template <int P, int LG>
+__device__ __forceinline__ bool normalise_l(double *v) {
+    using Gm = tiled::Geo<P, LG>;
     double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < Q; ++r) s += v[r];
+    for (int r = 0; r < Gm::EL; ++r) s += v[r];
+    s = tiled::lanes_sum<P, LG>(s);
     if (!(s > 0.0) || !isfinite(s)) {
 #pragma unroll
-        for (int r = 0; r < Q; ++r) v[r] = 1.0 / double(Q);
+        for (int r = 0; r < Gm::EL; ++r) v[r] = 1.0 / double(Gm::Q);
         return false;
     }
     const double inv = 1.0 / s;
 #pragma unroll
-    for (int r = 0; r < Q; ++r) v[r] *= inv;
+    for (int r = 0; r < Gm::EL; ++r) v[r] *= inv;
     return true;
 }
 
-template <int Q>
-__device__ __forceinline__ int clip_q(const double *acc) {
-    int best = 0;
-    double bv = acc[0];
-#pragma unroll
-    for (int r = 1; r < Q; ++r)
-        if (acc[r] > bv) {
-            bv = acc[r];
-            best = r;
-        }
-    return best;
-}
-
-// One q-vector from LDS (its q floats are 4q-byte aligned) in one access.
-template <int Q>
+// This lane's EL entries of a q-vector in LDS, in one access.
+template <int EL>
 __device__ __forceinline__ void lds_vec(const float *p, float *v) {
-    if constexpr (Q == 2) {
+    if constexpr (EL == 1) {
+        v[0] = p[0];
+    } else if constexpr (EL == 2) {
         const tiled::f32x2 t = *reinterpret_cast<const tiled::f32x2 *>(p);
         v[0] = t.x;
         v[1] = t.y;
     } else {
 #pragma unroll
-        for (int k = 0; k < Q / 4; ++k) {
+        for (int k = 0; k < EL / 4; ++k) {
             const tiled::f32x4 t = reinterpret_cast<const tiled::f32x4 *>(p)[k];
             v[4 * k] = t.x;
             v[4 * k + 1] = t.y;
@@ -125,141 +136,149 @@ __device__ __forceinline__ void lds_vec(const float *p, float *v) {
     }
 }
 
-// Row a of the multiplication table (a x y for every y), read as one word.
-template <int Q>
-__device__ __forceinline__ void mul_row(const uint8_t *mul, int a, int *out) {
-    const uint8_t *row = mul + a * Q;
+// a x (g*EL + r) for this lane's entries r, from row a of the multiplication
+// table, read as one word.
+template <int P, int LG>
+__device__ __forceinline__ void mul_pos(const uint8_t *mul, int a, int g, int *out) {
+    using Gm = tiled::Geo<P, LG>;
+    const uint8_t *row = mul + a * Gm::Q + g * Gm::EL;
     uint64_t w;
-    if constexpr (Q == 2) w = *reinterpret_cast<const uint16_t *>(row);
-    else if constexpr (Q == 4) w = *reinterpret_cast<const uint32_t *>(row);
+    if constexpr (Gm::EL == 1) w = row[0];
+    else if constexpr (Gm::EL == 2) w = *reinterpret_cast<const uint16_t *>(row);
+    else if constexpr (Gm::EL == 4) w = *reinterpret_cast<const uint32_t *>(row);
     else w = *reinterpret_cast<const uint64_t *>(row);
+    static_assert(Gm::EL <= 8, "entries per lane");
 #pragma unroll
-    for (int y = 0; y < Q; ++y) out[y] = int((w >> (8 * y)) & 0xffu);
+    for (int r = 0; r < Gm::EL; ++r) out[r] = int((w >> (8 * r)) & 0xffu);
 }
 
 // A3 for one edge: r from the siblings (row positions 0..dc-1 except `self`)
 // in row order, T = WHT(signs(z) x prod WHT(q~)), r(h^-1 y) = T(y) / q.
-// Where registers allow (rows of at most DCM entries, few entries), every
-// sibling is requested before the first is used.
-template <int P, int DCM>
+// Where registers allow, every sibling is requested before the first is used.
+template <int P, int LG, int DCM>
 __device__ __forceinline__ void edge_r(const float *qm, int rs, int dc, int self, int zi, const uint8_t *mul,
-                                       int hinv, float *rout) {
-    constexpr int Q = 1 << P;
-    constexpr bool kPre = (DCM - 1) * Q <= 40;
-    int pos[Q];
-    mul_row<Q>(mul, hinv, pos);
-    double T[Q];
-#pragma unroll
-    for (int r = 0; r < Q; ++r) T[r] = (__popc(unsigned(zi & r)) & 1) ? -1.0 : 1.0;
+                                       int hinv, int g, float *rout) {
+    using Gm = tiled::Geo<P, LG>;
+    constexpr int Q = Gm::Q, EL = Gm::EL;
+    constexpr bool kPre = (DCM - 1) * EL <= 40;
+    int pos[EL];
+    mul_pos<P, LG>(mul, hinv, g, pos);
+    double T[EL];
+    tiled::syndrome_signs<P, LG>(zi, g, T);
+    const float *base = qm + g * EL;
     if constexpr (kPre) {
-        float raw[DCM - 1][Q];
+        float raw[DCM - 1][EL];
 #pragma unroll
         for (int u = 0; u < DCM - 1; ++u)
-            if (u < dc - 1) lds_vec<Q>(qm + size_t(rs + (u < self ? u : u + 1)) * Q, raw[u]);
+            if (u < dc - 1) lds_vec<EL>(base + size_t(rs + (u < self ? u : u + 1)) * Q, raw[u]);
 #pragma unroll
         for (int u = 0; u < DCM - 1; ++u)
             if (u < dc - 1) {
-                double W[Q];
+                double W[EL];
 #pragma unroll
-                for (int r = 0; r < Q; ++r) W[r] = double(raw[u][r]);
-                tiled::wht_regs<Q>(W);
+                for (int r = 0; r < EL; ++r) W[r] = double(raw[u][r]);
+                tiled::wht<P, LG>(W, g);
 #pragma unroll
-                for (int r = 0; r < Q; ++r) T[r] *= W[r];
+                for (int r = 0; r < EL; ++r) T[r] *= W[r];
             }
     } else {
         for (int u = 0; u < dc; ++u) {
             if (u == self) continue;
-            float raw[Q];
-            lds_vec<Q>(qm + size_t(rs + u) * Q, raw);
-            double W[Q];
+            float raw[EL];
+            lds_vec<EL>(base + size_t(rs + u) * Q, raw);
+            double W[EL];
 #pragma unroll
-            for (int r = 0; r < Q; ++r) W[r] = double(raw[r]);
-            tiled::wht_regs<Q>(W);
+            for (int r = 0; r < EL; ++r) W[r] = double(raw[r]);
+            tiled::wht<P, LG>(W, g);
 #pragma unroll
-            for (int r = 0; r < Q; ++r) T[r] *= W[r];
+            for (int r = 0; r < EL; ++r) T[r] *= W[r];
         }
     }
-    tiled::wht_regs<Q>(T);
+    tiled::wht<P, LG>(T, g);
 #pragma unroll
-    for (int y = 0; y < Q; ++y) rout[pos[y]] = float(fmax(T[y] * (1.0 / double(Q)), 0.0));
+    for (int r = 0; r < EL; ++r) rout[pos[r]] = float(fmax(T[r] * (1.0 / double(Q)), 0.0));
 }
 
-// A4/A5 for a column from its r-vectors rv[0..dv) (natural order, column
-// edge order) and its prior row pv: the pseudo-posterior (Eq. (5)), into
-// Qp_k when not null, and the decision.
-template <int P, int DVM>
-__device__ __forceinline__ void posterior_step(const float (&rv)[DVM][1 << P], int dv, const double *pv,
-                                               float *Qp_k, uint8_t *xh_j, int *g) {
-    constexpr int Q = 1 << P;
-    double acc[Q];
+// A4/A5 for a column from its r-vectors rv[0..dv) (this lane's entries,
+// column edge order) and its prior row pv: the pseudo-posterior (Eq. (5)),
+// into Qp_k (this lane's entries) when not null, and the decision (lane 0).
+template <int P, int LG, int DVM>
+__device__ __forceinline__ void posterior_step(const float (&rv)[DVM][tiled::Geo<P, LG>::EL], int dv,
+                                               const double *pv, float *Qp_k, uint8_t *xh_j, int g, int *gd) {
+    using Gm = tiled::Geo<P, LG>;
+    double acc[Gm::EL];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = pv[q];
+    for (int q = 0; q < Gm::EL; ++q) acc[q] = pv[q];
 #pragma unroll
     for (int d2 = 0; d2 < DVM; ++d2)
         if (d2 < dv)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc[q] *= double(rv[d2][q]);
-    if (!normalise_q<Q>(acc)) ++*g;
+            for (int q = 0; q < Gm::EL; ++q) acc[q] *= double(rv[d2][q]);
+    if (!normalise_l<P, LG>(acc)) ++*gd;
     if (Qp_k)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) Qp_k[q] = float(acc[q]);
-    *xh_j = uint8_t(clip_q<Q>(acc));
+        for (int q = 0; q < Gm::EL; ++q) Qp_k[q] = float(acc[q]);
+    const int best = tiled::clip<P, LG>(acc, g);
+    if (g == 0) *xh_j = uint8_t(best);
 }
 
 // Eq. (4) for edge slot d of the column: q from the prior and the other
-// edges' r, normalised, stored at position h a (hpos[a]) of its vector.
-template <int P, int DVM>
-__device__ __forceinline__ void edge_q_step(const float (&rv)[DVM][1 << P], int dv, const double *pv, int d,
-                                            float *dst, const int *hpos, int *g) {
-    constexpr int Q = 1 << P;
-    double qv[Q];
+// edges' r, normalised, this lane's entries stored at positions h (g*EL + r)
+// of the edge's vector dst.
+template <int P, int LG, int DVM>
+__device__ __forceinline__ void edge_q_step(const float (&rv)[DVM][tiled::Geo<P, LG>::EL], int dv, const double *pv,
+                                            int d, float *dst, const int *hpos, int *gd) {
+    using Gm = tiled::Geo<P, LG>;
+    double qv[Gm::EL];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) qv[q] = pv[q];
+    for (int q = 0; q < Gm::EL; ++q) qv[q] = pv[q];
 #pragma unroll
     for (int d2 = 0; d2 < DVM; ++d2)
         if (d2 < dv && d2 != d)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) qv[q] *= double(rv[d2][q]);
-    if (!normalise_q<Q>(qv)) ++*g;
+            for (int q = 0; q < Gm::EL; ++q) qv[q] *= double(rv[d2][q]);
+    if (!normalise_l<P, LG>(qv)) ++*gd;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) dst[hpos[q]] = float(qv[q]);
+    for (int q = 0; q < Gm::EL; ++q) dst[hpos[q]] = float(qv[q]);
 }
 
 // A7 for source symbol k (Eq. (7)): the neighbours' pseudo-posteriors
 // Qp[k -+ 1] through M (O(q) when M is self-transition plus uniform), times
-// the evidence of its column, into pr; guard events counted in *g.
-template <int P>
+// the evidence of its column Lj, into pr (this lane's entries of each);
+// guard events counted in *gd.
+template <int P, int LG>
 __device__ __forceinline__ void markov_row(const float *Qp, const float *Lj, int k, int K, const float *M,
-                                           const float *pi, const float *mshape, float *pr, int *g) {
-    constexpr int Q = 1 << P;
-    double u[Q], v[Q];
+                                           const float *pi, const float *mshape, float *pr, int g, int *gd) {
+    using Gm = tiled::Geo<P, LG>;
+    constexpr int Q = Gm::Q, EL = Gm::EL;
+    double u[EL], v[EL];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        u[q] = k == 0 ? double(pi[q]) : 0.0;
+    for (int q = 0; q < EL; ++q) {
+        u[q] = k == 0 ? double(pi[g * EL + q]) : 0.0;
         v[q] = k == K - 1 ? 1.0 : 0.0;
     }
     if (mshape[0] != 0.0f) {
         const double sd = mshape[1], od = mshape[2];
-        float nb[2][Q];
+        float nb[2][EL];
         double S[2] = {0.0, 0.0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int kk = h == 0 ? k - 1 : k + 1;
             if (kk >= 0 && kk < K)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) nb[h][q] = Qp[size_t(kk) * Q + q];
+                lds_vec<EL>(Qp + size_t(kk) * Q + g * EL, nb[h]);
             else
 #pragma unroll
-                for (int q = 0; q < Q; ++q) nb[h][q] = 0.0f;
+                for (int q = 0; q < EL; ++q) nb[h][q] = 0.0f;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) S[h] += double(nb[h][q]);
+            for (int q = 0; q < EL; ++q) S[h] += double(nb[h][q]);
+            S[h] = tiled::lanes_sum<P, LG>(S[h]);
         }
         if (k > 0)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) u[q] = sd * double(nb[0][q]) + od * (S[0] - double(nb[0][q]));
+            for (int q = 0; q < EL; ++q) u[q] = sd * double(nb[0][q]) + od * (S[0] - double(nb[0][q]));
         if (k < K - 1)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) v[q] = sd * double(nb[1][q]) + od * (S[1] - double(nb[1][q]));
+            for (int q = 0; q < EL; ++q) v[q] = sd * double(nb[1][q]) + od * (S[1] - double(nb[1][q]));
     } else {
         if (k > 0) {
             const float *qp = Qp + size_t(k - 1) * Q;
@@ -267,7 +286,7 @@ __device__ __forceinline__ void markov_row(const float *Qp, const float *Lj, int
             for (int a = 0; a < Q; ++a) {
                 const double qa = qp[a];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) u[q] += qa * double(M[a * Q + q]);
+                for (int q = 0; q < EL; ++q) u[q] += qa * double(M[a * Q + g * EL + q]);
             }
         }
         if (k < K - 1) {
@@ -276,27 +295,34 @@ __device__ __forceinline__ void markov_row(const float *Qp, const float *Lj, int
             for (int cc = 0; cc < Q; ++cc) {
                 const double qc = qp[cc];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) v[q] += double(M[q * Q + cc]) * qc;
+                for (int q = 0; q < EL; ++q) v[q] += double(M[(g * EL + q) * Q + cc]) * qc;
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] *= v[q];
-    if (!normalise_q<Q>(u)) ++*g;
+    for (int q = 0; q < EL; ++q) u[q] *= v[q];
+    if (!normalise_l<P, LG>(u)) ++*gd;
+    float lf[EL];
+    lds_vec<EL>(Lj + g * EL, lf);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) u[q] *= double(Lj[q]);
-    if (!normalise_q<Q>(u)) ++*g;
+    for (int q = 0; q < EL; ++q) u[q] *= double(lf[q]);
+    if (!normalise_l<P, LG>(u)) ++*gd;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pr[q] = float(u[q]);
+    for (int q = 0; q < EL; ++q) pr[g * EL + q] = float(u[q]);
 }
 
-template <int P, int DCM, int DVM>
+template <int P, int LG, int DCM, int DVM>
 __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
-    constexpr int Q = 1 << P;
+    using Gm = tiled::Geo<P, LG>;
+    constexpr int Q = Gm::Q, EL = Gm::EL;
+    constexpr int NI = (kThreads / kWave) * Gm::TF;  // items a pass of the workgroup covers
     extern __shared__ __align__(16) unsigned char lds[];
     const DevCode &c = a.c;
     const Layout &ly = a.lay;
     const int tid = int(threadIdx.x);
+    const int lane = tid % kWave;
+    const int g = lane >> Gm::LTF;                                  // this lane's part of its item
+    const int xi = (tid / kWave) * Gm::TF + (lane & (Gm::TF - 1));  // this lane's item
     const int f0 = int(blockIdx.x) * ly.fw;
     const int fw = min(ly.fw, a.F - f0);  // >= 1: the grid covers F exactly
     const int E = c.E, n = c.n, m = c.m, K = c.n_info;
@@ -395,46 +421,47 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
     for (int t = 1; t <= a.max_iter; ++t) {
         if (a.schedule == GFBP_PUS) {
             // A3: every edge's r from the previous iteration's q
-            for (int x = tid; x < E * fw; x += kThreads) {
+            for (int x = xi; x < E * fw; x += NI) {
                 const int w = x % fw, e = x / fw;
                 if (!active[w]) continue;
                 const uint32_t ge = eg[e];
-                edge_r<P, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge),
-                               Rr(w) + size_t(e) * Q);
+                edge_r<P, LG, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge), g,
+                                   Rr(w) + size_t(e) * Q);
             }
             __syncthreads();
             // A4: every column's pseudo-posterior, decision and q
-            for (int x = tid; x < n * fw; x += kThreads) {
+            for (int x = xi; x < n * fw; x += NI) {
                 const int w = x % fw, j = x / fw;
                 if (!active[w]) continue;
                 const uint32_t gc = cg[j];
                 const int cs = int(gc & 0xffffu), dv = int(gc >> 16);
-                const float *R = Rr(w);
-                float rv[DVM][Q];
+                const float *R = Rr(w) + g * EL;
+                float rv[DVM][EL];
                 int es[DVM];
 #pragma unroll
                 for (int d = 0; d < DVM; ++d)
                     if (d < dv) {
                         es[d] = cedge[cs + d];
-                        lds_vec<Q>(R + size_t(es[d]) * Q, rv[d]);
+                        lds_vec<EL>(R + size_t(es[d]) * Q, rv[d]);
                     }
-                float pf[Q];
-                lds_vec<Q>(prow(w, j), pf);
-                double pv[Q];
+                float pf[EL];
+                lds_vec<EL>(prow(w, j) + g * EL, pf);
+                double pv[EL];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) pv[q] = pf[q];
-                int g = 0;
+                for (int q = 0; q < EL; ++q) pv[q] = pf[q];
+                int gd = 0;
                 const int k1 = ck[j];
-                posterior_step<P, DVM>(rv, dv, pv, a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q : nullptr,
-                                       Xh(w) + j, &g);
+                posterior_step<P, LG, DVM>(rv, dv, pv,
+                                           a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q + g * EL : nullptr,
+                                           Xh(w) + j, g, &gd);
 #pragma unroll
                 for (int d = 0; d < DVM; ++d)
                     if (d < dv) {
-                        int hp[Q];
-                        mul_row<Q>(mul, eg_h(eg[es[d]]), hp);
-                        edge_q_step<P, DVM>(rv, dv, pv, d, Qm(w) + size_t(es[d]) * Q, hp, &g);
+                        int hp[EL];
+                        mul_pos<P, LG>(mul, eg_h(eg[es[d]]), g, hp);
+                        edge_q_step<P, LG, DVM>(rv, dv, pv, d, Qm(w) + size_t(es[d]) * Q, hp, &gd);
                     }
-                if (g) atomicAdd(&gcount[w], g);
+                if (gd && g == 0) atomicAdd(&gcount[w], gd);
             }
             __syncthreads();
         } else {
@@ -447,47 +474,47 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
             const uint32_t *pe = reinterpret_cast<const uint32_t *>(lds + ly.pe);
             float *rsh = reinterpret_cast<float *>(lds + ly.rsh);
             const int per = fw * a.rs;
-            const int cw = kThreads / per;
-            const int col = tid / per, w = (tid % per) / a.rs, d = tid % a.rs;  // this thread's item
+            const int cw = NI / per;
+            const int col = xi / per, w = (xi % per) / a.rs, d = xi % a.rs;  // this lane's item
             for (int l = 0; l < a.nlev; ++l) {
                 const int p0 = lptr[l], p1 = lptr[l + 1];
                 for (int c0 = p0; c0 < p1; c0 += cw) {
                     const int nc = min(cw, p1 - c0);
-                    const bool in = tid < nc * per;
+                    const bool in = xi < nc * per;
                     const int p = c0 + (in ? col : 0);
                     const uint32_t pw = pe[size_t(p) * a.rs + d];
                     const int e = int(pw & 0xffffu), dv = int(pw >> 16);
                     const bool live = in && active[w] != 0;
                     if (live && d < dv) {
                         const uint32_t ge = eg[e];
-                        edge_r<P, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge),
-                                       rsh + size_t(tid) * Q);
+                        edge_r<P, LG, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul,
+                                           eg_hinv(ge), g, rsh + size_t(xi) * Q);
                     }
                     __syncthreads();
                     if (live && (d < dv || d == 0)) {
                         const int j = lcol[p];
-                        float rv[DVM][Q];
+                        float rv[DVM][EL];
 #pragma unroll
                         for (int d2 = 0; d2 < DVM; ++d2)
-                            if (d2 < dv) lds_vec<Q>(rsh + size_t(tid - d + d2) * Q, rv[d2]);
-                        float pf[Q];
-                        lds_vec<Q>(prow(w, j), pf);
-                        double pv[Q];
+                            if (d2 < dv) lds_vec<EL>(rsh + size_t(xi - d + d2) * Q + g * EL, rv[d2]);
+                        float pf[EL];
+                        lds_vec<EL>(prow(w, j) + g * EL, pf);
+                        double pv[EL];
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) pv[q] = pf[q];
-                        int g = 0;
+                        for (int q = 0; q < EL; ++q) pv[q] = pf[q];
+                        int gd = 0;
                         if (d == 0) {
                             const int k1 = ck[j];
-                            posterior_step<P, DVM>(rv, dv, pv,
-                                                   a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q : nullptr,
-                                                   Xh(w) + j, &g);
+                            posterior_step<P, LG, DVM>(
+                                rv, dv, pv, a.wantQ && k1 > 0 ? Qp(w) + size_t(k1 - 1) * Q + g * EL : nullptr,
+                                Xh(w) + j, g, &gd);
                         }
                         if (d < dv) {
-                            int hp[Q];
-                            mul_row<Q>(mul, eg_h(eg[e]), hp);
-                            edge_q_step<P, DVM>(rv, dv, pv, d, Qm(w) + size_t(e) * Q, hp, &g);
+                            int hp[EL];
+                            mul_pos<P, LG>(mul, eg_h(eg[e]), g, hp);
+                            edge_q_step<P, LG, DVM>(rv, dv, pv, d, Qm(w) + size_t(e) * Q, hp, &gd);
                         }
-                        if (g) atomicAdd(&gcount[w], g);
+                        if (gd && g == 0) atomicAdd(&gcount[w], gd);
                     }
                     __syncthreads();
                 }
@@ -526,13 +553,13 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
         if (!any || t == a.max_iter) break;  // uniform: every thread read the same flags
         if (a.markov) {
             // A7: every source symbol's prior for the next iteration
-            for (int x = tid; x < K * fw; x += kThreads) {
+            for (int x = xi; x < K * fw; x += NI) {
                 const int w = x % fw, k = x / fw;
                 if (!active[w]) continue;
-                int g = 0;
-                markov_row<P>(Qp(w), Lv(w) + size_t(kcol[k]) * Q, k, K, mk + 4 + Q, mk + 4, mk, Pr(w) + size_t(k) * Q,
-                              &g);
-                if (g) atomicAdd(&gcount[w], g);
+                int gd = 0;
+                markov_row<P, LG>(Qp(w), Lv(w) + size_t(kcol[k]) * Q, k, K, mk + 4 + Q, mk + 4, mk,
+                                  Pr(w) + size_t(k) * Q, g, &gd);
+                if (gd && g == 0) atomicAdd(&gcount[w], gd);
             }
             __syncthreads();
         }

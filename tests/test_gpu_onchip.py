@@ -1,8 +1,9 @@
 """Whole decodes in LDS (codes over GF(2), GF(4), GF(8) whose frame state fits
 in a workgroup's LDS).
 
-  * bitwise the tiled decode at q entries per lane (one lane per frame, the
-    same arithmetic), over both schedules, every channel, the three priors
+  * bitwise the tiled decode at the same lanes per vector (PUS: one lane, q
+    entries; SUS: two entries per lane; the same arithmetic), over both
+    schedules, every channel, the three priors
     (a general Markov matrix too), syndromes z != 0, frame counts that leave
     a partly filled last workgroup, fixed iteration counts;
   * the launch is the in-LDS kernel (the profiler's kernel kinds), and a
@@ -37,11 +38,12 @@ def _host(o):
 
 
 def _both(gfbp, code, dfr, schedule, **kw):
-    """The in-LDS decode and the tiled decode at q entries per lane."""
+    """The in-LDS decode and the tiled decode at its lanes per vector (PUS:
+    one lane, q entries; SUS: two entries per lane)."""
     import torch
 
     dcode = gfbp.DeviceCode(code)
-    dcode.set_shape(schedule, code.q)
+    dcode.set_shape(schedule, code.q if schedule == "pus" else 2)
     gfbp.profile_reset()
     gfbp.profile_enable(True)
     a = _host(gfbp.decode_batch(dcode, dfr, schedule=schedule, **kw))
