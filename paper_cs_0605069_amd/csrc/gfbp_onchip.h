@@ -199,6 +199,52 @@ __device__ __forceinline__ void edge_r(const float *qm, int rs, int dc, int self
     for (int r = 0; r < EL; ++r) rout[pos[r]] = float(fmax(T[r] * (1.0 / double(Q)), 0.0));
 }
 
+// Two edges at once (independent chains interleaved); the second one's result
+// is stored only when st1.  Rows of at most DCM entries; a missing sibling
+// multiplies by 1 (exact).
+template <int P, int LG, int DCM>
+__device__ __forceinline__ void edge_r_pair(const float *qm0, const float *qm1, uint32_t ge0, uint32_t ge1, int z0,
+                                            int z1, const uint8_t *mul, int g, float *rout0, float *rout1, bool st1) {
+    using Gm = tiled::Geo<P, LG>;
+    constexpr int Q = Gm::Q, EL = Gm::EL;
+    const float *qm[2] = {qm0 + g * EL, qm1 + g * EL};
+    const uint32_t ge[2] = {ge0, ge1};
+    const int zi[2] = {z0, z1};
+    int pos[2][EL];
+    double T[2][EL];
+    float raw[2][DCM - 1][EL];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        mul_pos<P, LG>(mul, eg_hinv(ge[h]), g, pos[h]);
+        tiled::syndrome_signs<P, LG>(zi[h], g, T[h]);
+        const int rs = eg_rs(ge[h]), dc = eg_dc(ge[h]), self = eg_self(ge[h]);
+#pragma unroll
+        for (int u = 0; u < DCM - 1; ++u) {
+            const int t = u < dc - 1 ? (u < self ? u : u + 1) : self;
+            lds_vec<EL>(qm[h] + size_t(rs + t) * Q, raw[h][u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < DCM - 1; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double W[EL];
+#pragma unroll
+            for (int r = 0; r < EL; ++r) W[r] = double(raw[h][u][r]);
+            tiled::wht<P, LG>(W, g);
+            const bool use = u < eg_dc(ge[h]) - 1;
+#pragma unroll
+            for (int r = 0; r < EL; ++r) T[h][r] *= use ? W[r] : 1.0;
+        }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) tiled::wht<P, LG>(T[h], g);
+#pragma unroll
+    for (int r = 0; r < EL; ++r) rout0[pos[0][r]] = float(fmax(T[0][r] * (1.0 / double(Q)), 0.0));
+    if (st1)
+#pragma unroll
+        for (int r = 0; r < EL; ++r) rout1[pos[1][r]] = float(fmax(T[1][r] * (1.0 / double(Q)), 0.0));
+}
+
 // A4/A5 for a column from its r-vectors rv[0..dv) (this lane's entries,
 // column edge order) and its prior row pv: the pseudo-posterior (Eq. (5)),
 // into Qp_k (this lane's entries) when not null, and the decision (lane 0).
@@ -421,12 +467,27 @@ __global__ __launch_bounds__(kThreads) void k_onchip(const Args a) {
     for (int t = 1; t <= a.max_iter; ++t) {
         if (a.schedule == GFBP_PUS) {
             // A3: every edge's r from the previous iteration's q
-            for (int x = xi; x < E * fw; x += NI) {
-                const int w = x % fw, e = x / fw;
-                if (!active[w]) continue;
-                const uint32_t ge = eg[e];
-                edge_r<P, LG, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge), g,
-                                   Rr(w) + size_t(e) * Q);
+            if constexpr (DCM <= 6) {
+                for (int x = xi; x < E * fw; x += 2 * NI) {
+                    const int x1 = min(x + NI, E * fw - 1);
+                    const int w0 = x % fw, e0 = x / fw, w1 = x1 % fw, e1 = x1 / fw;
+                    const bool a0 = active[w0] != 0, a1 = x + NI < E * fw && active[w1] != 0;
+                    if (!a0 && !a1) continue;
+                    // two edges' chains interleaved; an edge of a stopped
+                    // frame (or past the end) is computed but not stored
+                    const uint32_t g0 = eg[e0], g1 = eg[e1];
+                    float scratch[Q];
+                    edge_r_pair<P, LG, DCM>(Qm(w0), Qm(w1), g0, g1, Zs(w0)[erow[e0]], Zs(w1)[erow[e1]], mul, g,
+                                            a0 ? Rr(w0) + size_t(e0) * Q : scratch, Rr(w1) + size_t(e1) * Q, a1);
+                }
+            } else {
+                for (int x = xi; x < E * fw; x += NI) {
+                    const int w = x % fw, e = x / fw;
+                    if (!active[w]) continue;
+                    const uint32_t ge = eg[e];
+                    edge_r<P, LG, DCM>(Qm(w), eg_rs(ge), eg_dc(ge), eg_self(ge), Zs(w)[erow[e]], mul, eg_hinv(ge),
+                                       g, Rr(w) + size_t(e) * Q);
+                }
             }
             __syncthreads();
             // A4: every column's pseudo-posterior, decision and q
