@@ -18,7 +18,8 @@ sample of the same frames on the host cores; a GF(64) leg; a serving leg
 (continuous batching of a Poisson stream of mixed-code frames: throughput and
 p50/p99 frame latency per schedule); a Table-1 stand-in leg (both
 schedules' iteration counts and GPU time on a syndrome-form MN code); and
-an uneven-batch leg (10,000 frames of 64 codes in one call per schedule).
+an uneven-batch leg (10,000 frames of 64 codes in one call per schedule,
+code by code, and the same call as one persistent launch).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-frames S]
 """
@@ -311,8 +312,9 @@ def uneven_leg(gfbp, torch) -> dict:
     dB), each code's kernel shape tuned on its frames, then the whole batch in
     one gfbp_decode_batch call per schedule (code by code, the codes
     concurrent), max 100 iterations; best of two timed calls, and each
-    kernel's algorithmic rate from one more, profiled call (not part of
-    `value`)."""
+    kernel's algorithmic rate from one more, profiled call; then the same call
+    on the persistent work-list kernels in one launch, their tile shape tuned
+    first (none of it part of `value`)."""
     from paper_cs_0605069_amd.batching import batch_inputs
 
     pool, items, flat, flat_codes, index = batch_inputs(10000, 64, 8000)
@@ -338,6 +340,24 @@ def uneven_leg(gfbp, torch) -> dict:
                 best, its = dt, o["iters"].cpu().numpy()
         out[s] = {"seconds": best, "frames_per_s": len(index) / best,
                   "edge_q_per_s": float((its * eq_frame[index]).sum()) / best, "mean_iters": float(its.mean())}
+        # the same call on the persistent work-list kernels (one HIP graph
+        # launch, one kernel per field), their tile shape tuned first
+        t = gfbp.decode_multi(dcodes, index, dfr, schedule=s, max_iter=100, tune_iters=2)
+        el, waves = t["persist_el"], t["persist_waves"]
+        gfbp.decode_multi(dcodes, index, dfr, schedule=s, max_iter=2, persistent=True, persist_el=el,
+                          persist_waves=waves)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = gfbp.decode_multi(dcodes, index, dfr, schedule=s, max_iter=100, persistent=True, persist_el=el,
+                              persist_waves=waves)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pits = o["iters"].cpu().numpy()
+        out[s]["persistent_one_launch"] = {
+            "seconds": dt, "frames_per_s": len(index) / dt,
+            "edge_q_per_s": float((pits * eq_frame[index]).sum()) / dt, "mean_iters": float(pits.mean()),
+            "entries_per_lane": el, "wavefronts_per_workgroup": waves,
+            "frames_with_other_iteration_count": int((pits != its).sum())}
         # the kernels of one more call, each launch timed by the library (HIP
         # events on the decode streams; the codes' kernels overlap, so these
         # are per-kernel rates, not shares of the wall time above)
